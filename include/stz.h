@@ -1,0 +1,122 @@
+/*
+ * stz.h - C ABI of the MI355X (gfx950) STZ streaming-compressor hot path.
+ *
+ * Method (paper: "STZ: A High Quality and High Speed Streaming Lossy
+ * Compression Framework for Scientific Data", SC'25):
+ *   - hierarchical partition of a 3-D field into levels by stride-2 sampling,
+ *     recursively (Sec. 3.1 "Hierarchical partition", Sec. 3.2);
+ *   - prediction of each finer point from already reconstructed coarser points
+ *     by multi-dimensional linear and cubic interpolation (Sec. 3.1,
+ *     Eqs. 3-8), quantization of the prediction difference directly
+ *     (Optimization 3) under per-level error bounds (Optimization 5);
+ *   - Huffman coding of the quantization codes with per-(level, block,
+ *     sub-block) offsets, so levels and blocks decode independently;
+ *   - full, progressive (stop at a level) and random-access (box) decoding
+ *     (Sec. 3.3).
+ *
+ * Conventions for every call:
+ *   - Pointers marked "device" are HIP device pointers on the current device;
+ *     "host" pointers are ordinary host memory. The caller owns every buffer;
+ *     the library keeps no pointer after a call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream).
+ *     Host out-parameters are valid when the call returns; device outputs are
+ *     valid once the stream reaches the end of the call's work. Calls that
+ *     return a host value (sizes, status of device-side checks) synchronize
+ *     the stream once at their end.
+ *   - Dims are {nz, ny, nx}, C order, x fastest.
+ *   - Internal scratch memory is taken from a stream-ordered pool; the call
+ *     returns STZ_ERR_NOMEM when it cannot be obtained.
+ *   - Errors: STZ_ERR_ARG for invalid arguments, STZ_ERR_NONFINITE when the
+ *     input holds NaN or Inf, STZ_ERR_BUFFER when an output capacity is too
+ *     small (nothing meaningful is written), STZ_ERR_CORRUPT when a stream
+ *     fails validation (decoders never read or write out of bounds on corrupt
+ *     input), STZ_ERR_DEVICE on a HIP runtime failure.
+ */
+#ifndef STZ_H
+#define STZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STZ_OK = 0,
+  STZ_ERR_ARG = -1,
+  STZ_ERR_NONFINITE = -2,
+  STZ_ERR_BUFFER = -3,
+  STZ_ERR_CORRUPT = -4,
+  STZ_ERR_DEVICE = -5,
+  STZ_ERR_NOMEM = -6
+} stz_status;
+
+/* Error-bound mode: absolute, or relative to the field's value range
+ * (max - min), as in the paper's problem statement (Sec. 2.1). */
+typedef enum { STZ_EB_ABS = 0, STZ_EB_REL = 1 } stz_eb_mode;
+
+/* Block and level configuration. Zero fields select the defaults. */
+typedef struct {
+  uint32_t block;    /* B: block edge, power of two in [2, 64]; 0 -> 32      */
+  uint32_t levels;   /* L: levels above the anchors, 1..log2(B); 0 -> log2 B */
+  uint32_t radius;   /* R: quantization radius, 1..1024, alphabet 2R; 0->512 */
+  uint32_t reserved; /* must be 0                                            */
+  double eb_ratio;   /* bound ratio between adjacent paper levels (Sec. 3.1,
+                        Optimization 5), >= 1; 0 -> 2.5                      */
+} stz_config;
+
+/* Stream description (parsed header). */
+typedef struct {
+  uint64_t dims[3];
+  uint32_t block, levels, radius, lmax, eb_mode, reserved;
+  double eb, eb_abs, eb_ratio;
+  uint64_t total_bytes;
+} stz_info_t;
+
+/* Upper bound of the compressed size in bytes for `dims` and `cfg` (host
+ * only; no device work). Returns 0 for invalid arguments. */
+uint64_t stz_compress_bound(const uint64_t dims[3], const stz_config* cfg);
+
+/* Compress the float32 field `x` (device, dims[0]*dims[1]*dims[2] values)
+ * under error bound `eb` (> 0) in mode `eb_mode` into `out` (device,
+ * `out_cap` bytes). `*out_size` (host) receives the stream size; on
+ * STZ_ERR_BUFFER it holds the size that would have been needed. Every
+ * reconstructed value differs from the input by at most the resolved absolute
+ * bound. */
+stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+                        const stz_config* cfg, void* out, uint64_t out_cap,
+                        uint64_t* out_size, void* stream);
+
+/* Parse the header of the stream `comp` (device, `size` bytes) into `info`
+ * (host). Copies 512 bytes to the host and synchronizes `stream`. */
+stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* stream);
+
+/* Full decompression into `out` (device, at least dims product floats). */
+stz_status stz_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap_elems,
+                          void* stream);
+
+/* Progressive decompression (Sec. 3.3): reconstruct levels 0..level and write
+ * the stride-2^(L-level) grid, dims floor((n-1)/s)+1 per axis, into `out`
+ * (device). `out_dims` (host) receives its shape. level == L is the full
+ * field; level 0 returns the anchors. */
+stz_status stz_decompress_level(const void* comp, uint64_t size, uint32_t level, float* out,
+                                uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
+
+/* Random-access decompression (Sec. 3.3) of the half-open box [lo, hi)
+ * (full-resolution coordinates, lo < hi <= dims) at progressive level `level`:
+ * writes the points of the stride-2^(L-level) grid inside the box, raster
+ * order, into `out` (device); `out_dims` (host) receives the shape (an axis
+ * with no grid point gives 0 and nothing is written). Only the sub-blocks in
+ * the box's dependency cone are decoded and predicted. */
+stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
+                                 const uint64_t hi[3], uint32_t level, float* out,
+                                 uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
+
+/* Static description of a status code. */
+const char* stz_status_string(stz_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STZ_H */

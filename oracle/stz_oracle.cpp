@@ -486,7 +486,7 @@ extern "C" {
 struct stz_ref_config {
   uint32_t block;   // B: power of two in [2, 64]; 0 selects 32
   uint32_t levels;  // L: 1..log2(B); 0 selects log2(B)
-  uint32_t radius;  // R: 1..2048; 0 selects 512
+  uint32_t radius;  // R: 1..1024; 0 selects 512
   uint32_t reserved;
   double eb_ratio;  // >= 1; 0 selects 2.5
 };
@@ -517,7 +517,7 @@ int resolve_cfg(const stz_ref_config* c, Cfg* out) {
   int L = d.levels ? (int)d.levels : k;
   if (L < 1 || L > k) return ERR_ARG;
   int R = d.radius ? (int)d.radius : 512;
-  if (R < 1 || R > (1 << (kLmax - 1))) return ERR_ARG;
+  if (R < 1 || R > 1024) return ERR_ARG;
   double ratio = d.eb_ratio != 0.0 ? d.eb_ratio : 2.5;
   if (!(ratio >= 1.0) || !std::isfinite(ratio)) return ERR_ARG;
   out->B = B;

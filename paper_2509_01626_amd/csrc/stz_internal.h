@@ -1,0 +1,191 @@
+// Internal definitions of the HIP library: format constants, geometry
+// descriptors passed to kernels, the device parameter block and the kernel
+// launchers. Host code and kernels include this file; nothing outside the
+// library does.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stz {
+
+// ---- format constants (compressed-stream specification) --------------------
+constexpr uint32_t kMagic = 0x315A5453u;  // 'S','T','Z','1'
+constexpr uint32_t kVersion = 1;
+constexpr uint64_t kHeaderBytes = 512;
+constexpr int kLmax = 12;             // longest Huffman code
+constexpr int kLutBits = kLmax;       // decoder table indexed by the next 12 bits
+constexpr int kMaxLevels = 6;         // B <= 64
+constexpr int kMaxRadius = 1024;      // alphabet 2R <= 2048
+constexpr uint64_t kLevelTable = 128;
+constexpr uint64_t kLevelRec = 48;
+
+// Device-side error flags.
+constexpr uint32_t kFlagNonfinite = 1u;
+constexpr uint32_t kFlagOverflow = 2u;   // output capacity exceeded
+constexpr uint32_t kFlagCorrupt = 4u;
+constexpr uint32_t kFlagBadBound = 8u;   // resolved bound not positive and finite
+constexpr uint32_t kFlagTooLarge = 16u;  // a per-level count exceeds 32 bits
+
+__host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
+
+// ---- geometry --------------------------------------------------------------
+struct Geo {
+  int64_t n[3];    // nz, ny, nx
+  int64_t nb[3];   // blocks per axis
+  int32_t B, logB, L, R;
+};
+
+// Class sub-grid extent along axis d of block b, class parity o, stride 2^logs.
+__host__ __device__ inline int64_t axis_M(const Geo& g, int d, int64_t b, int o, int logs) {
+  const int64_t lo = b << g.logB;
+  const int64_t rest = g.n[d] - lo;
+  const int64_t len = rest < int64_t(g.B) ? rest : int64_t(g.B);
+  const int64_t U = (len + (int64_t(1) << logs) - 1) >> logs;
+  return o ? (U >> 1) : ((U + 1) >> 1);
+}
+// Sum of axis_M over blocks b' < b (all of them full blocks).
+__host__ __device__ inline int64_t axis_P(const Geo& g, int64_t b, int logs) {
+  return b * (int64_t(g.B) >> (logs + 1));
+}
+// Sum of axis_M over all blocks along axis d.
+__host__ __device__ inline int64_t axis_T(const Geo& g, int d, int o, int logs) {
+  return axis_P(g, g.nb[d] - 1, logs) + axis_M(g, d, g.nb[d] - 1, o, logs);
+}
+
+// Symbols of level 2^logs that precede unit u in stream order (blocks raster,
+// classes 1..7, rank order inside a unit), in closed form.
+__host__ __device__ inline int64_t unit_sym_off(const Geo& g, int logs, int64_t u) {
+  const int64_t blk = u / 7;
+  const int c = int(u - blk * 7) + 1;
+  const int64_t bx = blk % g.nb[2], t = blk / g.nb[2], by = t % g.nb[1], bz = t / g.nb[1];
+  int64_t sum = 0;
+  for (int k = 1; k <= 7; ++k) {
+    const int oz = (k >> 2) & 1, oy = (k >> 1) & 1, ox = k & 1;
+    const int64_t Mz = axis_M(g, 0, bz, oz, logs), My = axis_M(g, 1, by, oy, logs),
+                  Mx = axis_M(g, 2, bx, ox, logs);
+    const int64_t Ty = axis_T(g, 1, oy, logs), Tx = axis_T(g, 2, ox, logs);
+    sum += axis_P(g, bz, logs) * Ty * Tx + Mz * axis_P(g, by, logs) * Tx +
+           Mz * My * axis_P(g, bx, logs);
+    if (k < c) sum += Mz * My * Mx;
+  }
+  return sum;
+}
+
+// Lane streams (one per x-column of a unit) that precede unit u.
+__host__ __device__ inline int64_t unit_lane_off(const Geo& g, int logs, int64_t u) {
+  const int64_t blk = u / 7;
+  const int c = int(u - blk * 7) + 1;
+  const int64_t bx = blk % g.nb[2], t = blk / g.nb[2], by = t % g.nb[1], bz = t / g.nb[1];
+  int64_t sum = 0;
+  for (int k = 1; k <= 7; ++k) {
+    const int ox = k & 1;
+    sum += (bz * g.nb[1] + by) * axis_T(g, 2, ox, logs) + axis_P(g, bx, logs);
+    if (k < c) sum += axis_M(g, 2, bx, ox, logs);
+  }
+  return sum;
+}
+
+// Level totals: symbols and lanes.
+__host__ __device__ inline int64_t level_nsym(const Geo& g, int logs) {
+  int64_t sum = 0;
+  for (int k = 1; k <= 7; ++k)
+    sum += axis_T(g, 0, (k >> 2) & 1, logs) * axis_T(g, 1, (k >> 1) & 1, logs) *
+           axis_T(g, 2, k & 1, logs);
+  return sum;
+}
+__host__ __device__ inline int64_t level_nlanes(const Geo& g, int logs) {
+  int64_t sum = 0;
+  for (int k = 1; k <= 7; ++k) sum += g.nb[0] * g.nb[1] * axis_T(g, 2, k & 1, logs);
+  return sum;
+}
+
+// Points of one level's grid inside a box: coordinates first[d] + i*s,
+// i < cnt[d]. The full domain is first = 0, cnt = (n-1)/s + 1.
+struct Grid {
+  int64_t first[3];
+  int64_t cnt[3];
+  int32_t logs;
+};
+
+// Half-open box in full-resolution coordinates.
+struct Box {
+  int64_t lo[3];
+  int64_t hi[3];
+};
+
+// Parameters resolved on the device (error bounds) and the stream layout.
+struct DevParams {
+  double eb_abs;
+  double e[kMaxLevels + 1];
+  float E2[kMaxLevels + 1];
+  float INV[kMaxLevels + 1];
+  float mn, mx;
+  uint32_t flags;
+  uint32_t pad;
+  uint64_t total;                          // stream bytes
+  uint64_t sec[kMaxLevels + 1];            // level section offset
+  uint64_t off_outl[kMaxLevels + 1];       // unit_outl array offset (absolute)
+  uint64_t off_lane[kMaxLevels + 1];       // lane_len array offset (absolute)
+  uint64_t off_pay[kMaxLevels + 1];        // payload offset (absolute)
+  uint64_t off_out[kMaxLevels + 1];        // outlier values offset (absolute)
+  uint64_t words[kMaxLevels + 1];          // payload words per level
+  uint64_t outl[kMaxLevels + 1];           // outliers per level
+};
+
+// Per-level constants known on the host (geometry only).
+struct LevelConst {
+  uint64_t nu;     // units
+  uint64_t nl;     // lanes
+  uint64_t nsym;   // symbols
+};
+
+// ---- launchers (defined with the kernels) ----------------------------------
+struct CompressArgs {
+  const float* x;
+  Geo geo;
+  int eb_mode;
+  double eb, ratio;
+  uint8_t* out;
+  uint64_t out_cap;
+  DevParams* params;
+  // scratch
+  float2* part;            // min/max partials
+  uint32_t nparts;
+  float* rec[kMaxLevels];  // compact grids of levels 0..L-1
+  uint16_t* sym[kMaxLevels + 1];
+  LevelConst lc[kMaxLevels + 1];
+  unsigned long long* hist;   // 2R counters
+  uint8_t* lens;              // 2R
+  uint16_t* codes;            // 2R
+  uint16_t* lane_len;         // per level, at lane_base[l]
+  uint64_t lane_base[kMaxLevels + 1];
+  uint32_t* cnt;              // [2L segments][nu]: unit words, unit outliers
+  uint32_t* scan;             // [2L segments][nu+1]
+  uint64_t* scan_part;        // block partials for the segmented scan
+  uint64_t n_anchor;
+};
+
+hipError_t launch_compress(const CompressArgs& a, hipStream_t st);
+
+struct DecodeArgs {
+  const uint8_t* comp;
+  uint64_t size;
+  Geo geo;
+  int level_out;
+  Box box[kMaxLevels + 1];    // R_k per level
+  float* rec[kMaxLevels + 1]; // box grids of levels 0..level_out (last = output)
+  uint64_t sec[kMaxLevels + 1];
+  uint64_t off_outl[kMaxLevels + 1], off_lane[kMaxLevels + 1], off_pay[kMaxLevels + 1],
+      off_out[kMaxLevels + 1];
+  uint64_t words[kMaxLevels + 1], outl[kMaxLevels + 1];
+  LevelConst lc[kMaxLevels + 1];
+  uint64_t anchor_off;
+  float E2[kMaxLevels + 1];
+  const uint16_t* lut;   // 2^kLutBits entries: symbol | length << 12
+  uint32_t* flags;       // device word
+};
+
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+
+}  // namespace stz

@@ -1,0 +1,207 @@
+"""ctypes binding of the C ABI in include/stz.h (argument marshalling only).
+
+Every step of the compressor runs in the HIP library ``libstz.so``; this
+module passes device pointers taken from torch tensors and the current HIP
+stream. Importing it never falls back to a CPU path: if the library is missing
+or fails to load, every call raises.
+"""
+import ctypes as C
+import os
+
+import torch
+
+from . import build as _build
+
+OK, ERR_ARG, ERR_NONFINITE, ERR_BUFFER, ERR_CORRUPT, ERR_DEVICE, ERR_NOMEM = 0, -1, -2, -3, -4, -5, -6
+EB_ABS, EB_REL = 0, 1
+
+
+class Config(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("levels", C.c_uint32), ("radius", C.c_uint32),
+                ("reserved", C.c_uint32), ("eb_ratio", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("dims", C.c_uint64 * 3), ("block", C.c_uint32), ("levels", C.c_uint32),
+                ("radius", C.c_uint32), ("lmax", C.c_uint32), ("eb_mode", C.c_uint32),
+                ("reserved", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
+                ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64)]
+
+
+class StzError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {_status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libstz.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError(f"HIP library not built: {_build.LIB} is missing "
+                               "(run __graft_entry__.build())")
+        L = C.CDLL(_build.LIB)
+        u64p = C.POINTER(C.c_uint64)
+        L.stz_compress_bound.restype = C.c_uint64
+        L.stz_compress_bound.argtypes = [u64p, C.POINTER(Config)]
+        L.stz_compress.restype = C.c_int
+        L.stz_compress.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double, C.POINTER(Config),
+                                   C.c_void_p, C.c_uint64, u64p, C.c_void_p]
+        L.stz_info.restype = C.c_int
+        L.stz_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Info), C.c_void_p]
+        L.stz_decompress.restype = C.c_int
+        L.stz_decompress.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p]
+        L.stz_decompress_level.restype = C.c_int
+        L.stz_decompress_level.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p,
+                                           C.c_uint64, u64p, C.c_void_p]
+        L.stz_decompress_region.restype = C.c_int
+        L.stz_decompress_region.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32,
+                                            C.c_void_p, C.c_uint64, u64p, C.c_void_p]
+        L.stz_status_string.restype = C.c_char_p
+        L.stz_status_string.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _status_string(st):
+    try:
+        return lib().stz_status_string(st).decode()
+    except Exception:  # pragma: no cover
+        return "status"
+
+
+def _dims(shape):
+    return (C.c_uint64 * 3)(*[int(v) for v in shape])
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def config(block=32, levels=0, radius=0, eb_ratio=0.0):
+    return Config(block, levels, radius, 0, eb_ratio)
+
+
+def _check_dev(t, dtype):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor on a GPU")
+
+
+def stz_compress_bound(shape, cfg):
+    return int(lib().stz_compress_bound(_dims(shape), C.byref(cfg)))
+
+
+def stz_compress(x, eb_mode, eb, cfg, out=None, stream=None):
+    """Compress device tensor x (float32, shape (nz, ny, nx)). Returns a uint8
+    device tensor holding the stream (a view of `out` when given)."""
+    _check_dev(x, torch.float32)
+    assert x.dim() == 3
+    if out is None:
+        out = torch.empty(stz_compress_bound(x.shape, cfg), dtype=torch.uint8, device=x.device)
+    _check_dev(out, torch.uint8)
+    size = C.c_uint64(0)
+    st = lib().stz_compress(C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
+                            C.c_void_p(out.data_ptr()), out.numel(), C.byref(size),
+                            _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_compress")
+    return out[: size.value]
+
+
+def stz_compress_status(x, eb_mode, eb, cfg, out_cap=None, stream=None):
+    """Status code and reported size of a compress call (never raises)."""
+    cap = stz_compress_bound(x.shape, cfg) if out_cap is None else out_cap
+    out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
+    size = C.c_uint64(0)
+    st = lib().stz_compress(C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
+                            C.c_void_p(out.data_ptr()), cap, C.byref(size), _stream(stream))
+    return st, size.value
+
+
+def stz_info(comp, stream=None):
+    _check_dev(comp, torch.uint8)
+    inf = Info()
+    st = lib().stz_info(C.c_void_p(comp.data_ptr()), comp.numel(), C.byref(inf), _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_info")
+    return inf
+
+
+def stz_decompress(comp, out=None, stream=None):
+    inf = stz_info(comp, stream)
+    shape = tuple(int(v) for v in inf.dims)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=comp.device)
+    _check_dev(out, torch.float32)
+    st = lib().stz_decompress(C.c_void_p(comp.data_ptr()), comp.numel(),
+                              C.c_void_p(out.data_ptr()), out.numel(), _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_decompress")
+    return out.view(shape)
+
+
+def level_shape(inf, level):
+    s = 1 << (inf.levels - level)
+    return tuple((int(n) - 1) // s + 1 for n in inf.dims)
+
+
+def region_shape(inf, lo, hi, level):
+    s = 1 << (inf.levels - level)
+    out = []
+    for d in range(3):
+        first = -(-int(lo[d]) // s) * s
+        out.append((int(hi[d]) - 1 - first) // s + 1 if first < int(hi[d]) else 0)
+    return tuple(out)
+
+
+def stz_decompress_level(comp, level, out=None, stream=None, info=None):
+    inf = info if info is not None else stz_info(comp, stream)
+    shape = level_shape(inf, level)
+    n = shape[0] * shape[1] * shape[2]
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=comp.device)
+    _check_dev(out, torch.float32)
+    od = (C.c_uint64 * 3)()
+    st = lib().stz_decompress_level(C.c_void_p(comp.data_ptr()), comp.numel(), level,
+                                    C.c_void_p(out.data_ptr()), out.numel(), od, _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_decompress_level")
+    assert tuple(od) == shape
+    return out.reshape(-1)[:n].view(shape)
+
+
+def stz_decompress_region(comp, lo, hi, level, out=None, stream=None, info=None):
+    inf = info if info is not None else stz_info(comp, stream)
+    shape = region_shape(inf, lo, hi, level)
+    n = shape[0] * shape[1] * shape[2]
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.float32, device=comp.device)
+    _check_dev(out, torch.float32)
+    od = (C.c_uint64 * 3)()
+    st = lib().stz_decompress_region(C.c_void_p(comp.data_ptr()), comp.numel(), _dims(lo),
+                                     _dims(hi), level, C.c_void_p(out.data_ptr()), out.numel(),
+                                     od, _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_decompress_region")
+    assert tuple(od) == shape, (tuple(od), shape)
+    return out.reshape(-1)[:n].view(shape)
+
+
+def decode_status(comp, fn="decompress", level=0, lo=None, hi=None, stream=None):
+    """Status of a decode call on possibly corrupt bytes (never raises)."""
+    out = torch.empty(1 << 22, dtype=torch.float32, device=comp.device)
+    od = (C.c_uint64 * 3)()
+    L = lib()
+    p, n = C.c_void_p(comp.data_ptr()), comp.numel()
+    if fn == "decompress":
+        return L.stz_decompress(p, n, C.c_void_p(out.data_ptr()), out.numel(), _stream(stream))
+    if fn == "level":
+        return L.stz_decompress_level(p, n, level, C.c_void_p(out.data_ptr()), out.numel(), od,
+                                      _stream(stream))
+    return L.stz_decompress_region(p, n, _dims(lo), _dims(hi), level, C.c_void_p(out.data_ptr()),
+                                   out.numel(), od, _stream(stream))

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for
+bit (compressed bytes, full / progressive / region reconstructions)."""
+import numpy as np
+import pytest
+
+from paper_2509_01626_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2509_01626_amd import stz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    stz.lib()
+    return torch.device("cuda:0")
+
+
+def _stz():
+    from paper_2509_01626_amd import stz
+    return stz
+
+
+def _run(gpu, oracle, x, mode, eb, B, L=0, R=0, ratio=0.0, tag=""):
+    import torch
+    stz = _stz()
+    print(f"[case] {tag} shape={x.shape} mode={mode} eb={eb} B={B} L={L} R={R}", flush=True)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(gpu)
+    comp = stz.stz_compress(xd, mode, eb, stz.config(block=B, levels=L, radius=R, eb_ratio=ratio))
+    torch.cuda.synchronize()
+    want = oracle.compress(x, mode, eb, oracle.config(block=B, levels=L, radius=R, eb_ratio=ratio))
+    got = comp.cpu().numpy().tobytes()
+    assert len(got) == len(want), (tag, len(got), len(want))
+    if got != want:
+        a = np.frombuffer(got, np.uint8)
+        b = np.frombuffer(want, np.uint8)
+        i = int(np.nonzero(a != b)[0][0])
+        raise AssertionError(f"{tag}: first differing byte {i} of {len(got)}")
+    return comp, want
+
+
+CASES = [
+    ((64, 64, 64), 16, 0, 0),
+    ((33, 17, 29), 8, 0, 0),
+    ((40, 40, 40), 16, 3, 0),
+    ((1, 1, 100), 8, 0, 0),
+    ((5, 70, 1), 4, 2, 0),
+    ((23, 31, 47), 32, 0, 0),
+    ((70, 66, 65), 64, 0, 0),
+    ((17, 18, 19), 2, 1, 0),
+    ((30, 30, 30), 8, 3, 8),
+]
+
+
+@pytest.mark.parametrize("shape,B,L,R", CASES)
+@pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4])
+def test_compress_and_decode_match_oracle(gpu, oracle, shape, B, L, R, eb):
+    x = fields.bumps(shape, seed=sum(shape) + B, n_bumps=12) if B % 2 == 0 and shape[0] % 2 else \
+        fields.spectral(shape, 5 / 3, seed=sum(shape))
+    comp, want = _run(gpu, oracle, x, 1, eb, B, L, R, tag="roundtrip")
+    stz = _stz()
+    full = stz.stz_decompress(comp).cpu().numpy()
+    ref = oracle.decompress(want)
+    assert np.array_equal(full.view(np.uint32), ref.view(np.uint32))
+    inf = stz.stz_info(comp)
+    for lv in range(inf.levels + 1):
+        g = stz.stz_decompress_level(comp, lv).cpu().numpy()
+        assert np.array_equal(g, oracle.decompress_level(want, lv)), lv
+
+
+def test_abs_mode_and_ratio(gpu, oracle):
+    x = fields.spectral((48, 40, 36), 5 / 3, seed=3)
+    _run(gpu, oracle, x, 0, 0.05, 16, tag="abs")
+    _run(gpu, oracle, x, 1, 1e-3, 8, ratio=1.0, tag="ratio1")
+    _run(gpu, oracle, x, 1, 1e-3, 8, ratio=4.25, tag="ratio4.25")
+
+
+def test_outlier_heavy(gpu, oracle):
+    """Tiny radius: most symbols are verbatim outliers."""
+    x = fields.spectral((36, 36, 36), 5 / 3, seed=5) * 100
+    comp, want = _run(gpu, oracle, x, 0, 1e-3, 8, R=2, tag="outliers")
+    stz = _stz()
+    assert np.array_equal(stz.stz_decompress(comp).cpu().numpy(), oracle.decompress(want))
+
+
+def test_constant_and_linear(gpu, oracle):
+    z, y, xx = np.meshgrid(np.arange(40), np.arange(33), np.arange(35), indexing="ij")
+    for f in [np.full((40, 33, 35), 7.0), 3 * z - 2 * y + 5 * xx + 7]:
+        x = f.astype(np.float32)
+        comp, want = _run(gpu, oracle, x, 0, 0.25, 8, tag="linear")
+        assert np.array_equal(_stz().stz_decompress(comp).cpu().numpy(), x)
+
+
+def test_regions_match_oracle(gpu, oracle):
+    rng = np.random.default_rng(11)
+    x = fields.spectral((50, 45, 61), 5 / 3, seed=8)
+    stz = _stz()
+    for B in (8, 16):
+        comp, want = _run(gpu, oracle, x, 1, 1e-3, B, tag=f"region B={B}")
+        L = stz.stz_info(comp).levels
+        for i in range(25):
+            lo = [int(rng.integers(0, n)) for n in x.shape]
+            hi = [int(rng.integers(a + 1, min(n, a + 30) + 1)) for a, n in zip(lo, x.shape)]
+            lv = int(rng.integers(0, L + 1))
+            print(f"[region] B={B} lo={lo} hi={hi} level={lv}", flush=True)
+            r = stz.stz_decompress_region(comp, lo, hi, lv).cpu().numpy()
+            ref = oracle.decompress_region(want, lo, hi, lv)
+            assert r.shape == ref.shape
+            assert np.array_equal(r, ref), (lo, hi, lv)
+
+
+def test_config1_one_block_decodes(gpu, oracle):
+    """64^3 bumps, relative 1e-3, 16^3 blocks: blocks (1,1,1) and (3,3,3)."""
+    x = fields.bumps((64, 64, 64), seed=1)
+    comp, want = _run(gpu, oracle, x, 1, 1e-3, 16, tag="config1")
+    stz = _stz()
+    for b in [(1, 1, 1), (3, 3, 3)]:
+        lo = [16 * v for v in b]
+        hi = [16 * v + 16 for v in b]
+        r = stz.stz_decompress_region(comp, lo, hi, 4).cpu().numpy()
+        assert np.array_equal(r, oracle.decompress_region(want, lo, hi, 4))
+    g = stz.stz_decompress_level(comp, 2).cpu().numpy()
+    assert g.shape == (16, 16, 16)
+    assert np.array_equal(g, oracle.decompress_level(want, 2))
+
+
+def test_determinism(gpu):
+    import torch
+    stz = _stz()
+    x = torch.from_numpy(fields.spectral((64, 64, 64), 5 / 3, seed=1)).to(gpu)
+    a = stz.stz_compress(x, 1, 1e-3, stz.config(block=16)).cpu()
+    b = stz.stz_compress(x, 1, 1e-3, stz.config(block=16)).cpu()
+    assert torch.equal(a, b)
+
+
+def test_error_codes(gpu, oracle):
+    import torch
+    stz = _stz()
+    x = torch.from_numpy(fields.bumps((20, 20, 20), seed=2, n_bumps=4)).to(gpu)
+    cfg = stz.config(block=8)
+    assert stz.stz_compress_status(x, 1, 0.0, cfg)[0] == stz.ERR_ARG
+    assert stz.stz_compress_status(x, 3, 1e-3, cfg)[0] == stz.ERR_ARG
+    assert stz.stz_compress_status(x, 1, 1e-3, stz.config(block=12))[0] == stz.ERR_ARG
+    st, need = stz.stz_compress_status(x, 1, 1e-3, cfg, out_cap=600)
+    assert st == stz.ERR_BUFFER
+    comp = stz.stz_compress(x, 1, 1e-3, cfg)
+    assert need == comp.numel()
+    bad = x.clone()
+    bad[3, 4, 5] = float("nan")
+    assert stz.stz_compress_status(bad, 1, 1e-3, cfg)[0] == stz.ERR_NONFINITE
+    bad[3, 4, 5] = float("inf")
+    assert stz.stz_compress_status(bad, 0, 1e-3, cfg)[0] == stz.ERR_NONFINITE
+    assert stz.decode_status(comp[:-16]) == stz.ERR_CORRUPT
+    assert stz.decode_status(comp[:100]) == stz.ERR_CORRUPT
+    assert stz.decode_status(comp, "region", 3, (0, 0, 0), (21, 5, 5)) == stz.ERR_ARG
+    assert stz.decode_status(comp, "level", 9) == stz.ERR_ARG
+
+
+def test_corrupt_streams_match_oracle_status(gpu, oracle):
+    """Byte flips: the GPU decoder returns OK or STZ_ERR_CORRUPT like the
+    oracle, and equal outputs when both succeed."""
+    import torch
+    stz = _stz()
+    x = fields.spectral((24, 24, 24), 5 / 3, seed=1)
+    want = oracle.compress(x, 1, 1e-3, oracle.config(block=8))
+    rng = np.random.default_rng(0)
+    for i in range(60):
+        c = bytearray(want)
+        k = int(rng.integers(0, len(c)))
+        c[k] ^= 1 << int(rng.integers(0, 8))
+        print(f"[corrupt] byte {k}", flush=True)
+        d = torch.frombuffer(bytes(c), dtype=torch.uint8).to(gpu)
+        st_gpu = stz.decode_status(d)
+        st_ref = oracle.decode_status(bytes(c))
+        assert (st_gpu == stz.OK) == (st_ref == oracle.OK), (k, st_gpu, st_ref)

@@ -97,7 +97,8 @@ def test_error_codes(oracle):
     assert oracle.compress_status(x, 1, 1e-3, oracle.config(block=12)) == oracle.ERR_ARG
     assert oracle.compress_status(x, 1, 1e-3, oracle.config(block=8, levels=4)) == oracle.ERR_ARG
     assert oracle.compress_status(x, 1, 1e-3, oracle.config(block=128)) == oracle.ERR_ARG
-    assert oracle.compress_status(x, 1, 1e-3, oracle.config(block=8, radius=4096)) == oracle.ERR_ARG
+    assert oracle.compress_status(x, 1, 1e-3, oracle.config(block=8, radius=2048)) == oracle.ERR_ARG
+    assert oracle.compress_status(x, 1, 1e-3, oracle.config(block=8, radius=1024)) == oracle.OK
     bad = x.copy()
     bad[3, 4, 5] = np.nan
     assert oracle.compress_status(bad, 1, 1e-3, cfg) == oracle.ERR_NONFINITE
