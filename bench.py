@@ -1,0 +1,264 @@
+"""Benchmark of the STZ hot path on one MI355X.
+
+Default workload: one 512^3 float32 turbulence-like field (random-phase
+isotropic k^-5/3 spectrum, unit variance), value-range-relative error bound
+1e-3, 32^3 blocks (5 levels). One step is the whole hot path over that field:
+compress, full decompression, progressive decompression at every coarser level
+and one random-access box decode. Inputs are resident in HBM before timing.
+
+Prints one JSON line. `value` is field GB/s of a step (field bytes / step
+time); per-operation rates, the dominant kernel's roofline and the CPU oracle
+baseline are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "comp/decomp GB/s & % HBM peak at rel eb 1e-3; batched vs plain; p99 ROI latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not record per-kernel events in the timed region")
+    return ap.parse_args()
+
+
+def kernel_bytes(name, level, info, lvl_tab, N):
+    """Algorithmic bytes one launch of a kernel must move (see the design
+    notes): inputs it has to read and outputs it has to write, counted once."""
+    L = info.levels
+    dims = [int(v) for v in info.dims]
+
+    def grid(l):
+        s = 1 << (L - l)
+        n = 1
+        for d in dims:
+            n *= (d - 1) // s + 1
+        return n
+
+    if name == "minmax":
+        return 4 * N
+    if level is None:
+        return None
+    n_l = grid(level) - grid(level - 1)
+    coarse = grid(level - 1)
+    words = lvl_tab[level]["words"]
+    outl = lvl_tab[level]["outl"]
+    if name == "predict":
+        return 4 * n_l + 4 * coarse + 2 * n_l
+    if name == "decode":
+        return 4 * coarse + 4 * words + 4 * outl + 4 * n_l
+    if name == "pack":
+        return 2 * n_l + 4 * words + 4 * outl
+    if name == "lanelen":
+        return 2 * n_l
+    if name == "upcopy":
+        return 8 * grid(level - 2) if level >= 2 else None
+    return None
+
+
+def level_table(comp_host):
+    import struct
+    L = struct.unpack_from("<I", comp_host, 36)[0]
+    tab = {}
+    for l in range(1, L + 1):
+        off, nu, nl, ns, w, o = struct.unpack_from("<6Q", comp_host, 128 + 48 * (l - 1))
+        tab[l] = dict(off=off, units=nu, lanes=nl, syms=ns, words=w, outl=o)
+    return tab
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2509_01626_amd import fields, stz
+
+    lib = stz.lib()
+    dev = torch.device("cuda:0")
+    dims = (args.n, args.n, args.n)
+    t0 = time.time()
+    x = fields.spectral(dims, 5.0 / 3.0, seed=args.seed)
+    print(f"[bench] field {dims} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    N = x.size
+    field_bytes = 4 * N
+    xd = torch.from_numpy(x).to(dev)
+    cfg = stz.config(block=args.block)
+    cap = stz.stz_compress_bound(dims, cfg)
+    comp_buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    out_full = torch.empty(dims, dtype=torch.float32, device=dev)
+    comp = stz.stz_compress(xd, stz.EB_REL, args.eb, cfg, out=comp_buf)
+    info = stz.stz_info(comp)
+    L = info.levels
+    lvl_out = [torch.empty(stz.level_shape(info, l), dtype=torch.float32, device=dev)
+               for l in range(L)]
+    rng = np.random.default_rng(7)
+    edge = min(64, args.n)
+    lo = [int(rng.integers(0, n - edge + 1)) for n in dims]
+    hi = [a + edge for a in lo]
+    reg_out = torch.empty(edge ** 3, dtype=torch.float32, device=dev)
+    timings = {"compress": 0.0, "decompress": 0.0, "levels": 0.0, "region": 0.0}
+
+    def step(record):
+        t = time.perf_counter()
+        c = stz.stz_compress(xd, stz.EB_REL, args.eb, cfg, out=comp_buf)
+        t1 = time.perf_counter()
+        stz.stz_decompress(c, out=out_full, info=info)
+        t2 = time.perf_counter()
+        for l in range(L):
+            stz.stz_decompress_level(c, l, out=lvl_out[l], info=info)
+        t3 = time.perf_counter()
+        stz.stz_decompress_region(c, lo, hi, L, out=reg_out, info=info)
+        t4 = time.perf_counter()
+        if record:
+            timings["compress"] += t1 - t
+            timings["decompress"] += t2 - t1
+            timings["levels"] += t3 - t2
+            timings["region"] += t4 - t3
+        return c
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        lib.stz_profile_reset()
+        lib.stz_profile_enable(1)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        comp = step(True)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    lib.stz_profile_enable(0)
+    ms_per_step = (te - ts) * 1e3 / args.steps
+    K = args.steps
+
+    comp_host = comp.cpu().numpy().tobytes()
+    tab = level_table(comp_host)
+    full = out_full.cpu().numpy()
+    err = float(np.abs(full.astype(np.float64) - x.astype(np.float64)).max())
+    rng_v = float(x.max()) - float(x.min())
+    mse = float(np.mean((full.astype(np.float64) - x.astype(np.float64)) ** 2))
+    psnr = 20 * np.log10(rng_v) - 10 * np.log10(mse) if mse > 0 else float("inf")
+
+    # Per-kernel device time (HIP events on the library's stream, timed region).
+    import ctypes as C
+    prof = {}
+    for i in range(lib.stz_profile_count()):
+        name = C.create_string_buffer(64)
+        n = C.c_uint64(0)
+        ms = C.c_double(0)
+        lib.stz_profile_entry(i, name, 64, C.byref(n), C.byref(ms))
+        prof[name.value.decode()] = (n.value, ms.value)
+    roofline = None
+    kernels = {}
+    if prof:
+        for key, (n, ms) in prof.items():
+            nm, _, lv = key.partition("@")
+            lvl = int(lv) if lv else None
+            b = kernel_bytes(nm, lvl, info, tab, N)
+            avg = ms / n
+            kernels[key] = {"launches": n, "avg_us": round(avg * 1e3, 2),
+                            "share": None,
+                            "gbs": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
+        tot = sum(ms for (_, ms) in prof.values())
+        for key in kernels:
+            kernels[key]["share"] = round(prof[key][1] / tot, 4)
+        dom = max(prof, key=lambda k: prof[k][1])
+        nm, _, lv = dom.partition("@")
+        b = kernel_bytes(nm, int(lv) if lv else None, info, tab, N)
+        n, ms = prof[dom]
+        if b:
+            ach = b / (ms / n * 1e-3) / 1e9
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": None, "bytes_per_launch": int(b),
+                        "avg_us": round(ms / n * 1e3, 2), "device_ms_per_step": round(tot / K, 3)}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        ocfg = O.config(block=args.block)
+        t = time.perf_counter()
+        want = O.compress(x, O.EB_REL, args.eb, ocfg)
+        t1 = time.perf_counter()
+        ref = O.decompress(want)
+        t2 = time.perf_counter()
+        for l in range(L):
+            O.decompress_level(want, l)
+        O.decompress_region(want, lo, hi, L)
+        t3 = time.perf_counter()
+        parity = (want == comp_host) and bool(np.array_equal(ref.view(np.uint32),
+                                                             full.view(np.uint32)))
+        cpu = {"value": round(field_bytes / (t3 - t) / 1e9, 4), "unit": "GB/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one full step on the same {dims[0]}^3 field (single thread): "
+                         f"compress {t1 - t:.2f}s, full decode {t2 - t1:.2f}s, "
+                         f"levels+region {t3 - t2:.2f}s",
+               "cpu": _cpu_model(), "host_cores": os.cpu_count()}
+
+    res = {
+        "metric": METRIC,
+        "value": round(field_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{dims[0]}^3 k^-5/3 spectral float32, rel eb {args.eb:g}, "
+                               f"B={args.block}: compress + full + progressive(0..{L - 1}) + "
+                               f"{edge}^3 region decode",
+                   "dims": list(dims), "eb_rel": args.eb, "block": args.block, "levels": L},
+        "compress_gbps": round(field_bytes * K / timings["compress"] / 1e9, 2),
+        "decompress_gbps": round(field_bytes * K / timings["decompress"] / 1e9, 2),
+        "levels_ms": round(timings["levels"] * 1e3 / K, 3),
+        "region_ms": round(timings["region"] * 1e3 / K, 3),
+        "compression_ratio": round(field_bytes / len(comp_host), 3),
+        "max_err_over_eb": round(err / info.eb_abs, 6),
+        "psnr_db": round(float(psnr), 2),
+        "parity_with_oracle": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

@@ -112,6 +112,17 @@ stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t
                                  const uint64_t hi[3], uint32_t level, float* out,
                                  uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
 
+/* Stage profiler (auxiliary; off by default, or on with STZ_PROFILE=1):
+ * records HIP events on the call's stream around every kernel and
+ * accumulates the elapsed time per kernel name and level ("predict@5") when
+ * the call synchronizes. stz_profile_entry copies entry i's name (at most
+ * name_cap bytes, NUL-terminated) and totals; returns -1 when i is out of
+ * range. Intended for single-threaded measurement runs. */
+void stz_profile_enable(int enable);
+void stz_profile_reset(void);
+int stz_profile_count(void);
+int stz_profile_entry(int i, char* name, int name_cap, uint64_t* launches, double* total_ms);
+
 /* Static description of a status code. */
 const char* stz_status_string(stz_status st);
 

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstz.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stz_api.hip", "stz_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stz_api.hip", "stz_kernels.hip", "stz_profile.hip")]
 HEADERS = [os.path.join(ROOT, "include", "stz.h"), os.path.join(HERE, "csrc", "stz_internal.h")]
 
 FLAGS = [

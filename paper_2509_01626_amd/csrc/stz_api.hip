@@ -9,6 +9,9 @@
 #include "stz_internal.h"
 
 namespace stz {
+
+void prof_flush();
+
 namespace {
 
 struct Cfg {
@@ -317,6 +320,7 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   if (hipMemcpyAsync(&flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
+  prof_flush();
   return flags ? STZ_ERR_CORRUPT : STZ_OK;
 }
 
@@ -396,6 +400,7 @@ stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, dou
   if (hipMemcpyAsync(&P, a.params, sizeof(P), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
+  prof_flush();
   *out_size = P.total;
   if (P.flags & kFlagNonfinite) return STZ_ERR_NONFINITE;
   if (P.flags & (kFlagBadBound | kFlagTooLarge)) return STZ_ERR_ARG;

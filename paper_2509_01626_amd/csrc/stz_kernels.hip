@@ -15,6 +15,10 @@
 #include "stz_internal.h"
 
 namespace stz {
+
+void prof_begin(hipStream_t st, const char* name, int level);
+void prof_end(hipStream_t st);
+
 namespace {
 
 constexpr int kWave = 64;
@@ -1068,21 +1072,31 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   const int nsym = 2 * g.R;
   const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
   const uint64_t nu = a.lc[1].nu;
+  prof_begin(st, "init", -1);
   hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, a.params, a.hist, nsym);
+  prof_end(st);
   if (a.eb_mode == 1) {
+    prof_begin(st, "minmax", -1);
     hipLaunchKernelGGL(k_minmax, dim3(a.nparts), dim3(256), 0, st, a.x, N, a.part, a.params);
+    prof_end(st);
   }
+  prof_begin(st, "resolve", -1);
   hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, st, a.params, a.part, a.nparts, a.eb_mode,
                      a.eb, a.ratio, L);
+  prof_end(st);
+  prof_begin(st, "anchor", -1);
   hipLaunchKernelGGL(k_anchor, dim3(grid_for(a.n_anchor, 256, 4096)), dim3(256), 0, st, a.x, g,
                      a.rec[0], a.params);
+  prof_end(st);
   for (int l = 1; l <= L; ++l) {
     const int logs = L - l;
     if (l >= 2) {
       const Grid gs = full_grid(g, logs + 2), gd = full_grid(g, logs + 1);
       const uint64_t n = uint64_t(gs.cnt[0]) * gs.cnt[1] * gs.cnt[2];
+      prof_begin(st, "upcopy", l);
       hipLaunchKernelGGL(k_upcopy, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, a.rec[l - 2], gs,
                          a.rec[l - 1], gd);
+      prof_end(st);
     }
     PredictArgs p;
     p.x = a.x;
@@ -1099,9 +1113,13 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     p.Pw = a.params;
     p.hist = a.hist;
     p.nsym = nsym;
+    prof_begin(st, "predict", l);
     hipLaunchKernelGGL(k_predict, dim3(grid_for(nu, 4, 2048)), dim3(256), 0, st, p);
+    prof_end(st);
   }
+  prof_begin(st, "codebook", -1);
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kCbThreads), 0, st, a.hist, nsym, a.lens, a.codes);
+  prof_end(st);
   for (int l = 1; l <= L; ++l) {
     LaneLenArgs q;
     q.g = g;
@@ -1113,13 +1131,21 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     q.lane_len = a.lane_len + a.lane_base[l];
     q.cnt_words = a.cnt + uint64_t(2 * (l - 1)) * nu;
     q.cnt_outl = a.cnt + uint64_t(2 * (l - 1) + 1) * nu;
+    prof_begin(st, "lanelen", l);
     hipLaunchKernelGGL(k_lanelen, dim3(grid_for(nu, 4, 2048)), dim3(256), 0, st, q);
+    prof_end(st);
   }
   const int nblk = int((nu + kScanBlock - 1) / kScanBlock);
+  prof_begin(st, "scan_a", -1);
   hipLaunchKernelGGL(k_scan_a, dim3(nblk, 2 * L), dim3(256), 0, st, a.cnt, nu, a.scan_part, nblk);
+  prof_end(st);
+  prof_begin(st, "scan_b", -1);
   hipLaunchKernelGGL(k_scan_b, dim3(2 * L), dim3(256), 0, st, a.scan_part, nblk);
+  prof_end(st);
+  prof_begin(st, "scan_c", -1);
   hipLaunchKernelGGL(k_scan_c, dim3(nblk, 2 * L), dim3(256), 0, st, a.cnt, nu, a.scan_part, nblk,
                      a.scan, a.params);
+  prof_end(st);
   LayoutArgs la;
   la.g = g;
   la.eb_mode = a.eb_mode;
@@ -1132,10 +1158,16 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   la.nu = nu;
   for (int l = 0; l <= kMaxLevels; ++l) la.lc[l] = a.lc[l];
   la.n_anchor = a.n_anchor;
+  prof_begin(st, "layout", -1);
   hipLaunchKernelGGL(k_layout, dim3(1), dim3(64), 0, st, la);
+  prof_end(st);
+  prof_begin(st, "zero", -1);
   hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, a.out, kHeaderBytes, a.params);
+  prof_end(st);
+  prof_begin(st, "fill_head", -1);
   hipLaunchKernelGGL(k_fill_head, dim3(grid_for(a.n_anchor + nsym, 256, 4096)), dim3(256), 0, st,
                      a.out, a.lens, nsym, a.rec[0], a.n_anchor, a.params);
+  prof_end(st);
   for (int l = 1; l <= L; ++l) {
     PackArgs p;
     p.x = a.x;
@@ -1152,7 +1184,9 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     p.scan_outl = a.scan + uint64_t(2 * (l - 1) + 1) * (nu + 1);
     p.out = a.out;
     p.P = a.params;
+    prof_begin(st, "pack", l);
     hipLaunchKernelGGL(k_pack, dim3(grid_for(nu, 4, 4096)), dim3(256), 0, st, p);
+    prof_end(st);
   }
   return hipGetLastError();
 }
@@ -1163,15 +1197,19 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
   const int lo = a.level_out;
   const Grid g0 = box_grid(a.box[0], L);
   const uint64_t n0 = uint64_t(g0.cnt[0]) * g0.cnt[1] * g0.cnt[2];
+  prof_begin(st, "dec_anchor", -1);
   hipLaunchKernelGGL(k_dec_anchor, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
                      a.anchor_off, g, a.rec[0], g0);
+  prof_end(st);
   for (int k = 1; k <= lo; ++k) {
     const int logs = L - k;
     const Grid gp = box_grid(a.box[k - 1], logs + 1);
     const Grid gc = box_grid(a.box[k], logs);
     const uint64_t ncopy = uint64_t(gc.cnt[0]) * gc.cnt[1] * gc.cnt[2];
+    prof_begin(st, "upcopy", k);
     hipLaunchKernelGGL(k_upcopy, dim3(grid_for(ncopy / 8 + 1, 256, 8192)), dim3(256), 0, st,
                        a.rec[k - 1], gp, a.rec[k], gc);
+    prof_end(st);
     DecLevelArgs d;
     d.comp = a.comp;
     d.g = g;
@@ -1199,7 +1237,9 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
     d.lut = a.lut;
     d.flags = a.flags;
     const uint64_t nwork = uint64_t(d.bb_n[0]) * d.bb_n[1] * d.bb_n[2] * 7;
+    prof_begin(st, "decode", k);
     hipLaunchKernelGGL(k_decode, dim3(grid_for(nwork, 4, 4096)), dim3(256), 0, st, d);
+    prof_end(st);
   }
   return hipGetLastError();
 }

@@ -132,8 +132,8 @@ def stz_info(comp, stream=None):
     return inf
 
 
-def stz_decompress(comp, out=None, stream=None):
-    inf = stz_info(comp, stream)
+def stz_decompress(comp, out=None, stream=None, info=None):
+    inf = info if info is not None else stz_info(comp, stream)
     shape = tuple(int(v) for v in inf.dims)
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=comp.device)
