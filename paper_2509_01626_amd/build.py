@@ -11,8 +11,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstz.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stz_api.hip", "stz_kernels.hip", "stz_profile.hip")]
-HEADERS = [os.path.join(ROOT, "include", "stz.h"), os.path.join(HERE, "csrc", "stz_internal.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in
+           ("stz_api.hip", "stz_compress.hip", "stz_codebook.hip", "stz_decode.hip",
+            "stz_profile.hip")]
+HEADERS = [os.path.join(ROOT, "include", "stz.h")] + [
+    os.path.join(HERE, "csrc", f) for f in ("stz_internal.h", "stz_device.h", "stz_slab.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -390,6 +390,7 @@ stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, dou
   a.hist = ws.get<unsigned long long>(nsym);
   a.lens = ws.get<uint8_t>(nsym);
   a.codes = ws.get<uint16_t>(nsym);
+  a.cb_scratch = ws.get<uint8_t>(codebook_scratch_bytes(nsym));
   a.cnt = ws.get<uint32_t>(2 * L * nu);
   a.scan = ws.get<uint32_t>(2 * L * (nu + 1));
   const uint64_t nblk = (nu + 2047) / 2048;

@@ -1,0 +1,229 @@
+// Canonical Huffman code book on the device (format section 2.4).
+//
+// The format limits code lengths to kLmax by repeatedly replacing every
+// nonzero count c with (c+1)>>1 and rebuilding. Applying that k times gives
+// ceil(c / 2^k), so the rule is: the smallest k >= 0 whose Huffman code for
+// the counts ceil(c / 2^k) has no code longer than kLmax. Counts never exceed
+// 2^40, so k <= 40 always succeeds (all counts 1, at most 2048 symbols). The
+// device builds the trees for every k in parallel, one work-group per k, and a
+// second kernel picks the first k that fits: the latency of one build instead
+// of one build per halving.
+#include "stz_device.h"
+
+namespace stz {
+using namespace dev;
+namespace {
+
+constexpr int kCbThreads = 1024;
+constexpr int kCbMax = 2 * kMaxRadius;  // largest alphabet
+constexpr int kCbScales = 42;           // k = 0..41
+constexpr uint64_t kInf = ~uint64_t(0);
+
+// Ascending bitonic sort of n (power of two) 64-bit keys in LDS.
+__device__ void bitonic_sort(uint64_t* key, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const uint64_t a = key[lo], b = key[hi];
+        if ((a > b) == up) {
+          key[lo] = b;
+          key[hi] = a;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Code lengths for counts ceil(hist / 2^k), k = blockIdx.x: two queues over the
+// leaves sorted by (count, symbol), ties to the leaf queue, merged nodes in
+// creation order; depths by pointer jumping.
+__global__ __launch_bounds__(kCbThreads) void k_cb_build(const unsigned long long* hist, int nsym,
+                                                         uint8_t* lens_k, int* maxlen_k) {
+  __shared__ uint64_t W[2 * kCbMax];
+  __shared__ uint16_t par[2 * kCbMax];
+  __shared__ uint16_t dep[2 * kCbMax];
+  __shared__ uint16_t leaf[kCbMax];
+  __shared__ int s_m, s_max;
+  const int t = threadIdx.x;
+  const int k = blockIdx.x;
+  uint8_t* lens = lens_k + size_t(k) * nsym;
+  int np2 = 1;
+  while (np2 < nsym) np2 <<= 1;
+  if (t == 0) {
+    s_m = 0;
+    s_max = 0;
+  }
+  __syncthreads();
+  const uint64_t add = (uint64_t(1) << k) - 1;
+  for (int i = t; i < np2; i += blockDim.x) {
+    const uint64_t c = i < nsym ? uint64_t(hist[i]) : 0;
+    if (c) {
+      W[i] = (((c + add) >> k) << 11) | uint64_t(i);
+      atomicAdd(&s_m, 1);
+    } else {
+      W[i] = kInf;
+    }
+  }
+  for (int i = t; i < nsym; i += blockDim.x) lens[i] = 0;
+  bitonic_sort(W, np2);
+  const int m = s_m;
+  if (m <= 1) {
+    if (m == 1 && t == 0) lens[W[0] & 2047] = 1;
+    if (t == 0) maxlen_k[k] = m;
+    return;
+  }
+  for (int i = t; i < m; i += blockDim.x) {
+    leaf[i] = uint16_t(W[i] & 2047);
+    W[i] = W[i] >> 11;
+  }
+  __syncthreads();
+  if (t == 0) {
+    // Two-queue merge with a two-deep register lookahead on both queues:
+    // leaves are W[li..m), merged nodes W[ii..next).
+    int li = 0, ii = m, next = m;
+    uint64_t l0 = W[0], l1 = W[1], i0 = kInf, i1 = kInf;
+    for (int it = 0; it < m - 1; ++it) {
+      int a, b;
+      uint64_t wa, wb;
+      if (li < m && (ii == next || l0 <= i0)) {
+        a = li;
+        wa = l0;
+        ++li;
+        l0 = l1;
+        l1 = li + 1 < m ? W[li + 1] : kInf;
+      } else {
+        a = ii;
+        wa = i0;
+        ++ii;
+        i0 = i1;
+        i1 = ii + 1 < next ? W[ii + 1] : kInf;
+      }
+      if (li < m && (ii == next || l0 <= i0)) {
+        b = li;
+        wb = l0;
+        ++li;
+        l0 = l1;
+        l1 = li + 1 < m ? W[li + 1] : kInf;
+      } else {
+        b = ii;
+        wb = i0;
+        ++ii;
+        i0 = i1;
+        i1 = ii + 1 < next ? W[ii + 1] : kInf;
+      }
+      const uint64_t nw = wa + wb;
+      W[next] = nw;
+      par[a] = uint16_t(next);
+      par[b] = uint16_t(next);
+      if (ii == next)
+        i0 = nw;
+      else if (ii + 1 == next)
+        i1 = nw;
+      ++next;
+    }
+    par[2 * m - 2] = uint16_t(2 * m - 2);
+  }
+  __syncthreads();
+  const int nn = 2 * m - 1;
+  for (int i = t; i < nn; i += blockDim.x) dep[i] = (i == nn - 1) ? 0 : 1;
+  __syncthreads();
+  for (int round = 0; (1 << round) < nn; ++round) {
+    uint16_t nd[2 * kCbMax / kCbThreads], np[2 * kCbMax / kCbThreads];
+    int j = 0;
+    for (int i = t; i < nn; i += blockDim.x, ++j) {
+      const int p = par[i];
+      nd[j] = dep[i] + dep[p];
+      np[j] = par[p];
+    }
+    __syncthreads();
+    j = 0;
+    for (int i = t; i < nn; i += blockDim.x, ++j) {
+      dep[i] = nd[j];
+      par[i] = np[j];
+    }
+    __syncthreads();
+  }
+  int mx = 0;
+  for (int i = t; i < m; i += blockDim.x) {
+    lens[leaf[i]] = uint8_t(dep[i] > 255 ? 255 : dep[i]);
+    mx = max(mx, int(dep[i]));
+  }
+  atomicMax(&s_max, mx);
+  __syncthreads();
+  if (t == 0) maxlen_k[k] = s_max;
+}
+
+// Pick the first scale whose code fits in kLmax bits; canonical codes.
+__global__ __launch_bounds__(kCbThreads) void k_cb_final(const uint8_t* lens_k, const int* maxlen_k,
+                                                         int nsym, uint8_t* lens_out,
+                                                         uint16_t* codes_out) {
+  __shared__ uint64_t key[kCbMax];
+  __shared__ uint32_t bl[kLmax + 2], first[kLmax + 1], start[kLmax + 1];
+  __shared__ int s_k;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int kk = kCbScales - 1;
+    for (int k = 0; k < kCbScales; ++k)
+      if (maxlen_k[k] <= kLmax) {
+        kk = k;
+        break;
+      }
+    s_k = kk;
+  }
+  if (t < kLmax + 2) bl[t] = 0;
+  __syncthreads();
+  const uint8_t* lens = lens_k + size_t(s_k) * nsym;
+  int np2 = 1;
+  while (np2 < nsym) np2 <<= 1;
+  for (int i = t; i < np2; i += blockDim.x) {
+    const int l = i < nsym ? lens[i] : 0;
+    key[i] = l ? ((uint64_t(l) << 11) | uint64_t(i)) : kInf;
+    if (l) atomicAdd(&bl[l], 1u);
+    if (i < nsym) {
+      lens_out[i] = uint8_t(l);
+      codes_out[i] = 0;
+    }
+  }
+  bitonic_sort(key, np2);
+  if (t == 0) {
+    uint32_t code = 0, st = 0;
+    for (int l = 1; l <= kLmax; ++l) {
+      code = (code + bl[l - 1]) << 1;
+      first[l] = code;
+      start[l] = st;
+      st += bl[l];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < np2; i += blockDim.x) {
+    const uint64_t k = key[i];
+    if (k == kInf) continue;
+    const int l = int(k >> 11), sy = int(k & 2047);
+    codes_out[sy] = uint16_t(first[l] + (uint32_t(i) - start[l]));
+  }
+}
+
+}  // namespace
+
+size_t codebook_scratch_bytes(int nsym) { return size_t(kCbScales) * (size_t(nsym) + 4) + 64; }
+
+void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, uint16_t* codes,
+                     void* scratch, hipStream_t st) {
+  uint8_t* lens_k = static_cast<uint8_t*>(scratch);
+  int* maxlen_k = reinterpret_cast<int*>(lens_k + ((size_t(kCbScales) * nsym + 15) & ~size_t(15)));
+  prof_begin(st, "cb_build", -1);
+  hipLaunchKernelGGL(k_cb_build, dim3(kCbScales), dim3(kCbThreads), 0, st, hist, nsym, lens_k,
+                     maxlen_k);
+  prof_end(st);
+  prof_begin(st, "cb_final", -1);
+  hipLaunchKernelGGL(k_cb_final, dim3(1), dim3(kCbThreads), 0, st, lens_k, maxlen_k, nsym, lens,
+                     codes);
+  prof_end(st);
+}
+
+}  // namespace stz

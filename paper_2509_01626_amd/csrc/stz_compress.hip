@@ -1,0 +1,645 @@
+// Compression kernels (gfx950): range reduction and error-bound resolution,
+// anchors, per-level predict+quantize (Sec. 3.1, Eqs. 3-8, Optimizations 3
+// and 5) with the code histogram, per-lane code lengths, segmented scans for
+// the stream layout, bit packing and outlier compaction.
+#include "stz_slab.h"
+
+namespace stz {
+using namespace dev;
+namespace {
+
+// ---------------------------------------------------------------------------
+// Compression kernels
+// ---------------------------------------------------------------------------
+__global__ void k_init(DevParams* P, unsigned long long* hist, int nsym) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    P->flags = 0;
+    P->total = 0;
+  }
+  for (int i = t; i < nsym; i += blockDim.x) hist[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N,
+                                                float2* part, DevParams* P) {
+  float mn = INFINITY, mx = -INFINITY;
+  bool bad = false;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const float v = x[i];
+    bad |= !isfinite(v);
+    mn = fminf(mn, v);
+    mx = fmaxf(mx, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, o, kWave));
+    mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+  }
+  __shared__ float smn[4], smx[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smn[w] = mn;
+    smx[w] = mx;
+  }
+  if (bad) atomicOr(&P->flags, kFlagNonfinite);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      mn = fminf(mn, smn[i]);
+      mx = fmaxf(mx, smx[i]);
+    }
+    part[blockIdx.x] = make_float2(mn, mx);
+  }
+}
+
+// Resolve the absolute bound and the per-level constants (format 2.3).
+__global__ void k_resolve(DevParams* P, const float2* part, uint32_t nparts, int mode, double eb,
+                          double ratio, int L) {
+  if (threadIdx.x != 0) return;
+  double eb_abs = eb;
+  if (mode == 1) {
+    float mn = part[0].x, mx = part[0].y;
+    for (uint32_t i = 1; i < nparts; ++i) {
+      mn = fminf(mn, part[i].x);
+      mx = fmaxf(mx, part[i].y);
+    }
+    P->mn = mn;
+    P->mx = mx;
+    const double range = (double)mx - (double)mn;
+    if (range > 0.0)
+      eb_abs = eb * range;
+    else
+      eb_abs = eb * (fabs((double)mn) > 0.0 ? fabs((double)mn) : 1.0);
+  }
+  if (!(eb_abs > 0.0) || !isfinite(eb_abs)) P->flags |= kFlagBadBound;
+  P->eb_abs = eb_abs;
+  for (int l = 1; l <= L; ++l) {
+    double e;
+    if (l == L)
+      e = eb_abs;
+    else if (l == L - 1)
+      e = eb_abs / ratio;
+    else
+      e = (eb_abs / ratio) / ratio;
+    P->e[l] = e;
+    P->E2[l] = (float)(2.0 * e);
+    P->INV[l] = (float)(1.0 / (2.0 * e));
+  }
+}
+
+// Anchors: the stride-2^L grid, copied verbatim into the level-0 grid.
+__global__ void k_anchor(const float* __restrict__ x, Geo g, float* rec0, DevParams* P) {
+  const int logs = g.L;
+  const int64_t c0 = ((g.n[0] - 1) >> logs) + 1, c1 = ((g.n[1] - 1) >> logs) + 1,
+                c2 = ((g.n[2] - 1) >> logs) + 1;
+  const int64_t na = c0 * c1 * c2;
+  bool bad = false;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < na;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t ix = i % c2, t = i / c2, iy = t % c1, iz = t / c1;
+    const float v = x[((iz << logs) * g.n[1] + (iy << logs)) * g.n[2] + (ix << logs)];
+    bad |= !isfinite(v);
+    rec0[i] = v;
+  }
+  if (bad) atomicOr(&P->flags, kFlagNonfinite);
+}
+
+struct PredSlabArgs {
+  const float* x;
+  Geo g;
+  int level, logs;
+  int64_t n[3];      // level grid extents
+  int64_t nc[3];     // previous level's grid extents
+  const float* prev; // level-(l-1) grid, complete
+  float* cur;        // level-l grid; null at the finest level
+  uint16_t* sym;
+  DevParams* P;
+  unsigned long long* hist;
+  int nsym;
+};
+
+// Predict and quantize every level-l point of one block (format 2.2, 2.3);
+// also writes the block's part of the level-l grid (coarse points copied,
+// level points reconstructed) for the next level's prediction.
+template <int E>
+__global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
+  using S = SlabShape<E>;
+  constexpr int m = S::m;
+  __shared__ uint32_t h[2 * kMaxRadius];
+  __shared__ float tile[S::TILE];
+  __shared__ uint64_t ubase[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
+  const int64_t nblk = a.g.nb[0] * a.g.nb[1] * a.g.nb[2];
+  const int64_t blk = wg_block(blockIdx.x, nblk, true);
+  const int64_t bx = blk % a.g.nb[2], by = (blk / a.g.nb[2]) % a.g.nb[1],
+                bz = blk / (a.g.nb[2] * a.g.nb[1]);
+  const int64_t oz = bz * E, oy = by * E, ox = bx * E;
+  const int Ez = int(min<int64_t>(E, a.n[0] - oz)), Ey = int(min<int64_t>(E, a.n[1] - oy)),
+            Ex = int(min<int64_t>(E, a.n[2] - ox));
+  if (tid >= 1 && tid <= 7) ubase[tid] = uint64_t(unit_sym_off(a.g, a.logs, blk * 7 + tid - 1));
+  const float E2 = a.P->E2[a.level], INV = a.P->INV[a.level];
+  const double e = a.P->e[a.level];
+  const int R = a.g.R;
+  const int64_t sf[3] = {0, 0, 0};
+  const int ls = a.logs;
+  bool bad = false;
+  for (int z0 = 0; z0 < Ez; z0 += S::H) {
+    const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;
+    load_tile<E>(tile, a.prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    __syncthreads();
+    const int hs = min(S::H, Ez - z0);
+    const int ntask = hs * S::TASKS_PER_Z;
+    for (int task = wave; task < ntask; task += 4) {
+      const int lz = z0 + task / S::TASKS_PER_Z;
+      const int rem = task % S::TASKS_PER_Z, par = rem / S::G, g = rem % S::G;
+      const int ly = par + 2 * (g * S::RW + lane / S::P);
+      const int q = lane % S::P;
+      if (lane / S::P >= S::RW || ly >= Ey) continue;
+      for (int hh = 0; hh < 2; ++hh) {
+        const int lx = 2 * q + hh;
+        if (lx >= Ex) continue;
+        const int o[3] = {lz & 1, ly & 1, hh};
+        const int cc = 4 * o[0] + 2 * o[1] + o[2];
+        const int64_t gi = ((oz + lz) * a.n[1] + (oy + ly)) * a.n[2] + (ox + lx);
+        if (cc == 0) {
+          if (a.cur)
+            a.cur[gi] = tile[((((lz - z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
+          continue;
+        }
+        const int64_t p[3] = {oz + lz, oy + ly, ox + lx};
+        const float xv =
+            a.x[(((p[0] << ls) * a.g.n[1]) + (p[1] << ls)) * a.g.n[2] + (p[2] << ls)];
+        bad |= !isfinite(xv);
+        const float pred = tile_predict<E>(tile, p, a.n, o, tz0, ty0, tx0);
+        float rv;
+        const int sy = quantize(xv, pred, E2, INV, e, R, &rv);
+        // rank inside the unit: class sub-grid raster
+        const int oy_ = o[1], ox_ = o[2];
+        const int My = oy_ ? Ey >> 1 : (Ey + 1) >> 1, Mx = ox_ ? Ex >> 1 : (Ex + 1) >> 1;
+        a.sym[ubase[cc] + ((uint64_t(lz >> 1) * My + (ly >> 1)) * Mx + (lx >> 1))] = uint16_t(sy);
+        if (a.cur) a.cur[gi] = rv;
+        atomicAdd(&h[sy], 1u);
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(&a.P->flags, kFlagNonfinite);
+  for (int i = tid; i < a.nsym; i += blockDim.x)
+    if (h[i]) atomicAdd(&a.hist[i], (unsigned long long)h[i]);
+}
+
+template <int E>
+void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, p);
+}
+
+struct LaneLenArgs {
+  Geo g;
+  int logs;
+  const uint16_t* sym;
+  uint64_t nu;
+  const uint8_t* lens;
+  int nsym;
+  uint16_t* lane_len;  // this level's lanes
+  uint32_t* cnt_words;
+  uint32_t* cnt_outl;
+};
+
+// Bit length of every lane stream and per-unit totals.
+__global__ __launch_bounds__(256) void k_lanelen(LaneLenArgs a) {
+  __shared__ uint8_t L[2 * kMaxRadius];
+  for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t u = int64_t(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); u < int64_t(a.nu);
+       u += nwaves) {
+    const UnitGeo ug = unit_geo(a.g, u, a.logs);
+    const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1], Mx = ug.M[2];
+    const uint64_t base = unit_sym_off(a.g, a.logs, u);
+    uint32_t bits = 0, no = 0;
+    if (lane < int(Mx)) {
+      for (uint32_t t = 0; t < rows; ++t) {
+        const uint16_t s = a.sym[base + uint64_t(t) * Mx + lane];
+        bits += L[s];
+        no += (s == 0);
+      }
+      a.lane_len[unit_lane_off(a.g, a.logs, u) + lane] = uint16_t(bits);
+    }
+    const uint32_t tb = wave_sum(bits), to = wave_sum(no);
+    if (lane == 0) {
+      a.cnt_words[u] = (tb + 31) >> 5;
+      a.cnt_outl[u] = to;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segmented exclusive scan: `nseg` segments of n u32 values, out[seg][n+1].
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256 * kScanItems;
+
+__device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
+  __shared__ uint64_t ws[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t inc = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t t = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) pre += ws[i];
+    tot += ws[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_a(const uint32_t* in, uint64_t n, uint64_t* part,
+                                                int nblk) {
+  const int seg = blockIdx.y;
+  const uint32_t* src = in + uint64_t(seg) * n;
+  const uint64_t base = uint64_t(blockIdx.x) * kScanBlock + uint64_t(threadIdx.x) * kScanItems;
+  uint64_t s = 0;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += src[base + i];
+  uint64_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) part[uint64_t(seg) * nblk + blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_b(uint64_t* part, int nblk) {
+  uint64_t* p = part + uint64_t(blockIdx.x) * nblk;
+  uint64_t carry = 0;
+  for (int b0 = 0; b0 < nblk; b0 += 256) {
+    const int i = b0 + threadIdx.x;
+    const uint64_t v = i < nblk ? p[i] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan(v, &tot);
+    if (i < nblk) p[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_c(const uint32_t* in, uint64_t n, const uint64_t* part,
+                                                int nblk, uint32_t* out, DevParams* P) {
+  const int seg = blockIdx.y;
+  const uint32_t* src = in + uint64_t(seg) * n;
+  uint32_t* dst = out + uint64_t(seg) * (n + 1);
+  const uint64_t base = uint64_t(blockIdx.x) * kScanBlock + uint64_t(threadIdx.x) * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? src[base + i] : 0;
+    s += v[i];
+  }
+  uint64_t tot;
+  uint64_t run = part[uint64_t(seg) * nblk + blockIdx.x] + block_excl_scan(s, &tot);
+  bool over = false;
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) {
+      over |= run > 0xFFFFFFFFull;
+      dst[base + i] = uint32_t(run);
+    }
+    run += v[i];
+    if (base + i + 1 == n) {
+      over |= run > 0xFFFFFFFFull;
+      dst[n] = uint32_t(run);
+    }
+  }
+  if (over) atomicOr(&P->flags, kFlagTooLarge);
+}
+
+struct LayoutArgs {
+  Geo g;
+  int eb_mode;
+  double eb, ratio;
+  uint64_t out_cap;
+  uint8_t* out;
+  DevParams* P;
+  const uint32_t* scan;   // [2L][nu+1]
+  uint64_t nu;
+  LevelConst lc[kMaxLevels + 1];
+  uint64_t n_anchor;
+};
+
+__device__ inline void st32(uint8_t* p, uint32_t v) { *reinterpret_cast<uint32_t*>(p) = v; }
+__device__ inline void st64(uint8_t* p, uint64_t v) {
+  st32(p, uint32_t(v));
+  st32(p + 4, uint32_t(v >> 32));
+}
+
+// Stream layout (format 2.5) from the scanned totals; writes the header.
+__global__ void k_layout(LayoutArgs a) {
+  if (threadIdx.x != 0) return;
+  DevParams* P = a.P;
+  const int L = a.g.L;
+  const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(2 * a.g.R));
+  uint64_t pos = anchor_off + align16(4 * a.n_anchor);
+  for (int l = 1; l <= L; ++l) {
+    const uint64_t W = a.scan[uint64_t(2 * (l - 1)) * (a.nu + 1) + a.nu];
+    const uint64_t O = a.scan[uint64_t(2 * (l - 1) + 1) * (a.nu + 1) + a.nu];
+    P->words[l] = W;
+    P->outl[l] = O;
+    P->sec[l] = pos;
+    P->off_outl[l] = pos + align16(4 * (a.nu + 1));
+    P->off_lane[l] = P->off_outl[l] + align16(4 * (a.nu + 1));
+    P->off_pay[l] = P->off_lane[l] + align16(2 * a.lc[l].nl);
+    P->off_out[l] = P->off_pay[l] + align16(4 * W);
+    pos = P->off_out[l] + align16(4 * O);
+  }
+  P->total = pos;
+  if (pos > a.out_cap) P->flags |= kFlagOverflow;
+  if (P->flags) return;
+  uint8_t* o = a.out;
+  for (int i = 0; i < int(kHeaderBytes); i += 4) st32(o + i, 0);
+  st32(o + 0, kMagic);
+  st32(o + 4, kVersion);
+  for (int d = 0; d < 3; ++d) st64(o + 8 + 8 * d, uint64_t(a.g.n[d]));
+  st32(o + 32, uint32_t(a.g.B));
+  st32(o + 36, uint32_t(L));
+  st32(o + 40, uint32_t(a.g.R));
+  st32(o + 44, uint32_t(kLmax));
+  st32(o + 48, uint32_t(a.eb_mode));
+  st64(o + 56, __double_as_longlong(a.eb));
+  st64(o + 64, __double_as_longlong(P->eb_abs));
+  st64(o + 72, __double_as_longlong(a.ratio));
+  st64(o + 80, pos);
+  st64(o + 88, kHeaderBytes);
+  st64(o + 96, anchor_off);
+  st64(o + 104, a.n_anchor);
+  for (int l = 1; l <= L; ++l) {
+    uint8_t* e = o + kLevelTable + kLevelRec * uint64_t(l - 1);
+    st64(e + 0, P->sec[l]);
+    st64(e + 8, a.nu);
+    st64(e + 16, a.lc[l].nl);
+    st64(e + 24, a.lc[l].nsym);
+    st64(e + 32, P->words[l]);
+    st64(e + 40, P->outl[l]);
+  }
+}
+
+// Zero [from, total) of the stream (padding and the words packed with atomics).
+__global__ void k_zero(uint8_t* out, uint64_t from, const DevParams* P) {
+  if (P->flags) return;
+  const uint64_t to = P->total;
+  uint4* p = reinterpret_cast<uint4*>(out);
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  for (uint64_t i = from / 16 + uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < to / 16;
+       i += uint64_t(gridDim.x) * blockDim.x)
+    p[i] = z;
+}
+
+// Code lengths and anchors into the stream.
+__global__ void k_fill_head(uint8_t* out, const uint8_t* lens, int nsym, const float* rec0,
+                            uint64_t na, const DevParams* P) {
+  if (P->flags) return;
+  const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(nsym));
+  float* an = reinterpret_cast<float*>(out + anchor_off);
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < na + uint64_t(nsym);
+       i += uint64_t(gridDim.x) * blockDim.x) {
+    if (i < uint64_t(nsym))
+      out[kHeaderBytes + i] = lens[i];
+    else
+      an[i - nsym] = rec0[i - nsym];
+  }
+}
+
+struct PackArgs {
+  const float* x;
+  Geo g;
+  int level, logs;
+  const uint16_t* sym;
+  uint64_t nu;
+  const uint8_t* lens;
+  const uint16_t* codes;
+  int nsym;
+  const uint16_t* lane_len;
+  const uint32_t* scan_words;  // nu+1
+  const uint32_t* scan_outl;   // nu+1
+  uint8_t* out;
+  const DevParams* P;
+};
+
+__device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_t start,
+                                 uint64_t end) {
+  if (wi * 32 >= start && wi * 32 + 32 <= end)
+    pay[wi] = w;
+  else if (w)
+    atomicOr(&pay[wi], w);
+}
+
+// Bit-pack every lane stream, write the unit index and the outliers.
+__global__ __launch_bounds__(256) void k_pack(PackArgs a) {
+  const DevParams* P = a.P;
+  if (P->flags) return;
+  __shared__ uint8_t Ls[2 * kMaxRadius];
+  __shared__ uint16_t Cs[2 * kMaxRadius];
+  for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) {
+    Ls[i] = a.lens[i];
+    Cs[i] = a.codes[i];
+  }
+  __syncthreads();
+  const int l = a.level;
+  uint32_t* unit_word = reinterpret_cast<uint32_t*>(a.out + P->sec[l]);
+  uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
+  uint16_t* lane_arr = reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]);
+  uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
+  float* outv = reinterpret_cast<float*>(a.out + P->off_out[l]);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+  const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t u = int64_t(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); u < int64_t(a.nu);
+       u += nwaves) {
+    const UnitGeo ug = unit_geo(a.g, u, a.logs);
+    const uint32_t M1 = ug.M[1], Mx = ug.M[2], rows = uint32_t(ug.M[0]) * M1;
+    const bool act = lane < int(Mx);
+    const uint64_t lane0 = unit_lane_off(a.g, a.logs, u);
+    const uint32_t lb = act ? a.lane_len[lane0 + lane] : 0;
+    const uint32_t pre = wave_excl_scan(lb, lane);
+    const uint32_t uw = a.scan_words[u], uo = a.scan_outl[u];
+    if (lane == 0) {
+      unit_word[u] = uw;
+      unit_outl[u] = uo;
+      if (u == int64_t(a.nu) - 1) {
+        unit_word[a.nu] = a.scan_words[a.nu];
+        unit_outl[a.nu] = a.scan_outl[a.nu];
+      }
+    }
+    if (act) lane_arr[lane0 + lane] = uint16_t(lb);
+    const uint64_t start = uint64_t(uw) * 32 + pre, end = start + lb;
+    uint64_t pos = start;
+    uint32_t cur = 0;
+    uint32_t run = 0;
+    const uint64_t base = unit_sym_off(a.g, a.logs, u);
+    for (uint32_t t = 0; t < rows; ++t) {
+      const uint16_t s = act ? a.sym[base + uint64_t(t) * Mx + lane] : uint16_t(1);
+      if (act) {
+        const uint32_t len = Ls[s], c = Cs[s];
+        const uint32_t o = uint32_t(pos & 31);
+        if (o + len <= 32) {
+          cur |= c << (32 - o - len);
+          pos += len;
+          if ((pos & 31) == 0) {
+            emit_word(pay, (pos >> 5) - 1, cur, start, end);
+            cur = 0;
+          }
+        } else {
+          const uint32_t hi = len - (32 - o);
+          cur |= c >> hi;
+          emit_word(pay, pos >> 5, cur, start, end);
+          cur = c << (32 - hi);
+          pos += len;
+        }
+      }
+      const bool is_out = act && s == 0;
+      const uint64_t m = __ballot(is_out);
+      if (is_out) {
+        const uint32_t vy = t % M1, vz = t / M1;
+        const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
+        const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
+        const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * lane + ug.o[2]) << a.logs);
+        outv[uo + run + __popcll(m & lt_mask)] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
+      }
+      run += __popcll(m);
+    }
+    if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launch sequences
+// ---------------------------------------------------------------------------
+hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
+  const Geo& g = a.geo;
+  const int L = g.L;
+  const int nsym = 2 * g.R;
+  const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
+  const uint64_t nu = a.lc[1].nu;
+  prof_begin(st, "init", -1);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, a.params, a.hist, nsym);
+  prof_end(st);
+  if (a.eb_mode == 1) {
+    prof_begin(st, "minmax", -1);
+    hipLaunchKernelGGL(k_minmax, dim3(a.nparts), dim3(256), 0, st, a.x, N, a.part, a.params);
+    prof_end(st);
+  }
+  prof_begin(st, "resolve", -1);
+  hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, st, a.params, a.part, a.nparts, a.eb_mode,
+                     a.eb, a.ratio, L);
+  prof_end(st);
+  prof_begin(st, "anchor", -1);
+  hipLaunchKernelGGL(k_anchor, dim3(grid_for(a.n_anchor, 256, 4096)), dim3(256), 0, st, a.x, g,
+                     a.rec[0], a.params);
+  prof_end(st);
+  for (int l = 1; l <= L; ++l) {
+    const int logs = L - l;
+    PredSlabArgs p;
+    p.x = a.x;
+    p.g = g;
+    p.level = l;
+    p.logs = logs;
+    for (int q = 0; q < 3; ++q) {
+      p.n[q] = ((g.n[q] - 1) >> logs) + 1;
+      p.nc[q] = ((g.n[q] - 1) >> (logs + 1)) + 1;
+    }
+    p.prev = a.rec[l - 1];
+    p.cur = l < L ? a.rec[l] : nullptr;
+    p.sym = a.sym[l];
+    p.P = a.params;
+    p.hist = a.hist;
+    p.nsym = nsym;
+    const int64_t nblk = g.nb[0] * g.nb[1] * g.nb[2];
+    const int E = g.B >> logs;
+    prof_begin(st, "predict", l);
+    switch (E) {
+      case 2: launch_pred<2>(p, nblk, st); break;
+      case 4: launch_pred<4>(p, nblk, st); break;
+      case 8: launch_pred<8>(p, nblk, st); break;
+      case 16: launch_pred<16>(p, nblk, st); break;
+      case 32: launch_pred<32>(p, nblk, st); break;
+      default: launch_pred<64>(p, nblk, st); break;
+    }
+    prof_end(st);
+  }
+  launch_codebook(a.hist, nsym, a.lens, a.codes, a.cb_scratch, st);
+  for (int l = 1; l <= L; ++l) {
+    LaneLenArgs q;
+    q.g = g;
+    q.logs = L - l;
+    q.sym = a.sym[l];
+    q.nu = nu;
+    q.lens = a.lens;
+    q.nsym = nsym;
+    q.lane_len = a.lane_len + a.lane_base[l];
+    q.cnt_words = a.cnt + uint64_t(2 * (l - 1)) * nu;
+    q.cnt_outl = a.cnt + uint64_t(2 * (l - 1) + 1) * nu;
+    prof_begin(st, "lanelen", l);
+    hipLaunchKernelGGL(k_lanelen, dim3(grid_for(nu, 4, 2048)), dim3(256), 0, st, q);
+    prof_end(st);
+  }
+  const int nblk = int((nu + kScanBlock - 1) / kScanBlock);
+  prof_begin(st, "scan_a", -1);
+  hipLaunchKernelGGL(k_scan_a, dim3(nblk, 2 * L), dim3(256), 0, st, a.cnt, nu, a.scan_part, nblk);
+  prof_end(st);
+  prof_begin(st, "scan_b", -1);
+  hipLaunchKernelGGL(k_scan_b, dim3(2 * L), dim3(256), 0, st, a.scan_part, nblk);
+  prof_end(st);
+  prof_begin(st, "scan_c", -1);
+  hipLaunchKernelGGL(k_scan_c, dim3(nblk, 2 * L), dim3(256), 0, st, a.cnt, nu, a.scan_part, nblk,
+                     a.scan, a.params);
+  prof_end(st);
+  LayoutArgs la;
+  la.g = g;
+  la.eb_mode = a.eb_mode;
+  la.eb = a.eb;
+  la.ratio = a.ratio;
+  la.out_cap = a.out_cap;
+  la.out = a.out;
+  la.P = a.params;
+  la.scan = a.scan;
+  la.nu = nu;
+  for (int l = 0; l <= kMaxLevels; ++l) la.lc[l] = a.lc[l];
+  la.n_anchor = a.n_anchor;
+  prof_begin(st, "layout", -1);
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(64), 0, st, la);
+  prof_end(st);
+  prof_begin(st, "zero", -1);
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, a.out, kHeaderBytes, a.params);
+  prof_end(st);
+  prof_begin(st, "fill_head", -1);
+  hipLaunchKernelGGL(k_fill_head, dim3(grid_for(a.n_anchor + nsym, 256, 4096)), dim3(256), 0, st,
+                     a.out, a.lens, nsym, a.rec[0], a.n_anchor, a.params);
+  prof_end(st);
+  for (int l = 1; l <= L; ++l) {
+    PackArgs p;
+    p.x = a.x;
+    p.g = g;
+    p.level = l;
+    p.logs = L - l;
+    p.sym = a.sym[l];
+    p.nu = nu;
+    p.lens = a.lens;
+    p.codes = a.codes;
+    p.nsym = nsym;
+    p.lane_len = a.lane_len + a.lane_base[l];
+    p.scan_words = a.scan + uint64_t(2 * (l - 1)) * (nu + 1);
+    p.scan_outl = a.scan + uint64_t(2 * (l - 1) + 1) * (nu + 1);
+    p.out = a.out;
+    p.P = a.params;
+    prof_begin(st, "pack", l);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(nu, 4, 4096)), dim3(256), 0, st, p);
+    prof_end(st);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace stz

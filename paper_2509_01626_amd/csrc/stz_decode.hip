@@ -1,0 +1,326 @@
+// Decoding kernels (gfx950): per-level decode + reconstruct over the
+// dependency cone of a box (Sec. 3.3), which covers full, progressive and
+// region decoding.
+//
+// One work-group per block of the level. Its 7 sub-block units are decoded by
+// one lane per x-column stream (units never straddle a wave), a z-slab of rows
+// at a time into LDS; outliers get their rank-order index from a per-row
+// ballot over the unit's lanes. The slab's coarse halo is staged in LDS, and
+// the whole slab of the level grid (coarse points copied, level points
+// predicted and dequantized) is written with coalesced rows.
+#include "stz_slab.h"
+
+namespace stz {
+using namespace dev;
+namespace {
+
+struct DecSlabArgs {
+  Geo g;
+  int level;
+  int logs;                     // L - level
+  int64_t n[3];                 // level grid extents
+  int64_t bb_lo[3], bb_n[3];    // blocks to process
+  bool xcd_remap;
+  const float* prev;            // level-(l-1) box grid
+  int64_t in_first[3], in_cnt[3];  // (coarse coordinates)
+  float* cur;                   // level-l box grid (output)
+  int64_t out_first[3], out_cnt[3];
+  const uint32_t* unit_word;
+  const uint32_t* unit_outl;
+  const uint16_t* lane_len;
+  const uint32_t* pay;
+  const float* outv;
+  uint64_t words, noutl, nlanes, nu;
+  float E2;
+  const uint16_t* lut;
+  uint32_t* flags;
+};
+
+template <int E>
+__global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
+  using S = SlabShape<E>;
+  constexpr int m = S::m;
+  __shared__ uint16_t lut[1 << kLutBits];
+  __shared__ uint16_t symb[7 * S::HZ * m * m];
+  __shared__ float tile[S::TILE];
+  __shared__ uint32_t lanelen_s[7 * m];
+  __shared__ uint32_t uo0[8], uo1[8];
+  __shared__ int uok[8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut[i] = a.lut[i];
+
+  const int64_t nblk = a.bb_n[0] * a.bb_n[1] * a.bb_n[2];
+  const int64_t bl = wg_block(blockIdx.x, nblk, a.xcd_remap);
+  const int64_t bx = a.bb_lo[2] + bl % a.bb_n[2];
+  const int64_t by = a.bb_lo[1] + (bl / a.bb_n[2]) % a.bb_n[1];
+  const int64_t bz = a.bb_lo[0] + bl / (a.bb_n[2] * a.bb_n[1]);
+  const int64_t blk = (bz * a.g.nb[1] + by) * a.g.nb[2] + bx;
+  const int64_t oz = bz * E, oy = by * E, ox = bx * E;  // block origin, level coordinates
+  const int Ez = int(min<int64_t>(E, a.n[0] - oz)), Ey = int(min<int64_t>(E, a.n[1] - oy)),
+            Ex = int(min<int64_t>(E, a.n[2] - ox));
+  // Output box (level coordinates) clipped to the block, block-local.
+  const int rz0 = int(max<int64_t>(0, a.out_first[0] - oz));
+  const int rz1 = int(min<int64_t>(Ez, a.out_first[0] + a.out_cnt[0] - oz));
+  const int ry0 = int(max<int64_t>(0, a.out_first[1] - oy));
+  const int ry1 = int(min<int64_t>(Ey, a.out_first[1] + a.out_cnt[1] - oy));
+  const int rx0 = int(max<int64_t>(0, a.out_first[2] - ox));
+  const int rx1 = int(min<int64_t>(Ex, a.out_first[2] + a.out_cnt[2] - ox));
+
+  // ---- decode setup: lane t < 7m handles class c = t/m + 1, column j ------
+  const int c = tid / m + 1, j = tid % m;
+  const bool is_lane = tid < 7 * m;
+  const int ocz = (c >> 2) & 1, ocy = (c >> 1) & 1, ocx = c & 1;
+  const int Mz = ocz ? Ez >> 1 : (Ez + 1) >> 1;
+  const int My = ocy ? Ey >> 1 : (Ey + 1) >> 1;
+  const int Mx = ocx ? Ex >> 1 : (Ex + 1) >> 1;
+  // Does the unit have a point inside the output box? (v range per axis)
+  bool needed = Mz > 0 && My > 0 && Mx > 0;
+  {
+    const int lo[3] = {rz0, ry0, rx0}, hi[3] = {rz1, ry1, rx1}, oo[3] = {ocz, ocy, ocx};
+    for (int d = 0; d < 3; ++d) {
+      // v with 2v+o in [lo, hi)
+      const int v0 = lo[d] - oo[d] <= 0 ? 0 : (lo[d] - oo[d] + 1) >> 1;
+      const int v1 = hi[d] - oo[d] <= 0 ? 0 : ((hi[d] - 1 - oo[d]) >> 1) + 1;
+      needed = needed && v0 < v1;
+    }
+  }
+  const int64_t u = blk * 7 + (c - 1);
+  uint32_t lb = 0;
+  uint64_t pos = 0;
+  if (is_lane && needed && j < Mx) {
+    const uint64_t lane0 = uint64_t(unit_lane_off(a.g, a.logs, u));
+    lb = lane0 + j < a.nlanes ? a.lane_len[lane0 + j] : 0;
+  }
+  if (is_lane) lanelen_s[tid] = lb;
+  if (tid < 8) uok[tid] = 1;
+  __syncthreads();
+  bool alive = false;
+  if (is_lane && needed && j < Mx) {
+    uint32_t pre = 0, tot = 0;
+    for (int k = 0; k < Mx; ++k) {
+      const uint32_t v = lanelen_s[(c - 1) * m + k];
+      if (k < j) pre += v;
+      tot += v;
+    }
+    const uint32_t w0 = a.unit_word[u], w1 = a.unit_word[u + 1];
+    const uint32_t o0 = a.unit_outl[u], o1 = a.unit_outl[u + 1];
+    const bool ok = w0 <= w1 && w1 <= a.words && o0 <= o1 && o1 <= a.noutl &&
+                    (uint64_t(tot) + 31) / 32 == uint64_t(w1 - w0);
+    if (j == 0) {
+      uo0[c] = o0;
+      uo1[c] = o1;
+      uok[c] = ok;
+    }
+    if (!ok) atomicOr(a.flags, kFlagCorrupt);
+    alive = ok;
+    pos = uint64_t(w0) * 32 + pre;
+  }
+  // Bit window: `buf` holds `nb` valid bits, left aligned; `wi` = next word.
+  uint64_t wi = pos >> 5, buf = 0;
+  int nb = 0;
+  if (alive) {
+    const uint32_t w = wi < a.words ? a.pay[wi] : 0;
+    ++wi;
+    const int sk = int(pos & 31);
+    buf = (uint64_t(w) << 32) << sk;
+    nb = 32 - sk;
+  }
+  uint32_t used = 0, run = 0;
+  bool bad = false;
+  // Lanes of this unit inside the wave (units never straddle a wave).
+  const int seg = lane - j;
+  const uint64_t segmask = (m >= 64 ? ~uint64_t(0) : ((uint64_t(1) << m) - 1)) << seg;
+  const uint64_t ltmask = (uint64_t(1) << lane) - 1;
+  const bool lane_active = is_lane && needed && j < Mx;
+
+  const int zlast = min(Ez, rz1);  // no output needed beyond this level plane
+  bool complete = true;
+  for (int z0 = 0; z0 < Ez; z0 += S::H) {
+    if (z0 >= zlast) {
+      complete = false;
+      break;
+    }
+    const int a0 = z0 >> 1;
+    // ---- decode this slab's rows into LDS -----------------------------------
+    if (lane_active) {
+      const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
+      for (int r = r0; r < r1; ++r) {
+        int sy = 1;
+        if (alive) {
+          if (nb < kLmax) {
+            const uint32_t w = wi < a.words ? a.pay[wi] : 0;
+            ++wi;
+            buf |= uint64_t(w) << (32 - nb);
+            nb += 32;
+          }
+          const uint16_t e = lut[buf >> (64 - kLutBits)];
+          const int len = e >> 12;
+          if (len == 0 || used + len > lb) {
+            alive = false;
+            bad = true;
+          } else {
+            sy = e & 4095;
+            buf <<= len;
+            nb -= len;
+            used += len;
+          }
+        }
+        const bool is_out = alive && sy == 0;
+        const uint64_t mk = __ballot(is_out) & segmask;
+        uint16_t st = uint16_t(sy);
+        if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
+        run += __popcll(mk);
+        const int vz = r / My, vy = r - vz * My;
+        symb[((c - 1) * S::HZ + (vz - a0)) * m * m + vy * m + j] = st;
+      }
+    }
+    // ---- coarse tile of the slab ----------------------------------------------
+    const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;  // level coords, even
+    load_tile<E>(tile, a.prev, a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    __syncthreads();
+    // ---- reconstruct the slab ------------------------------------------------------
+    const int hs = min(S::H, Ez - z0);
+    const int ntask = hs * S::TASKS_PER_Z;
+    for (int task = wave; task < ntask; task += 4) {
+      const int lz = z0 + task / S::TASKS_PER_Z;
+      const int rem = task % S::TASKS_PER_Z, par = rem / S::G, g = rem % S::G;
+      const int ly = par + 2 * (g * S::RW + lane / S::P);
+      const int q = lane % S::P;
+      if (lane / S::P >= S::RW || ly >= Ey || lz < rz0 || lz >= rz1 || ly < ry0 || ly >= ry1)
+        continue;
+      for (int h = 0; h < 2; ++h) {
+        const int lx = 2 * q + h;
+        if (lx >= Ex || lx < rx0 || lx >= rx1) continue;
+        const int o[3] = {lz & 1, ly & 1, h};
+        const int cc = 4 * o[0] + 2 * o[1] + o[2];
+        float val;
+        if (cc == 0) {
+          val = tile[((((lz - z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
+        } else {
+          const uint16_t e =
+              symb[((cc - 1) * S::HZ + (lz >> 1) - a0) * m * m + (ly >> 1) * m + (lx >> 1)];
+          if (e & 0x8000u) {
+            const uint64_t oi = uint64_t(uo0[cc]) + (e & 0x7FFFu);
+            if (oi < uo1[cc]) {
+              val = a.outv[oi];
+            } else {
+              val = 0.0f;
+              atomicOr(a.flags, kFlagCorrupt);
+            }
+          } else {
+            const int64_t p[3] = {oz + lz, oy + ly, ox + lx};
+            const float pred = tile_predict<E>(tile, p, a.n, o, tz0, ty0, tx0);
+            const float prod = (float)(int(e) - a.g.R) * a.E2;
+            val = pred + prod;
+          }
+        }
+        a.cur[((oz + lz - a.out_first[0]) * a.out_cnt[1] + (oy + ly - a.out_first[1])) *
+                  a.out_cnt[2] +
+              (ox + lx - a.out_first[2])] = val;
+      }
+    }
+    __syncthreads();
+  }
+  if (lane_active && alive && complete) {
+    if (used != lb) bad = true;
+    if (j == 0 && uok[c] && run != uo1[c] - uo0[c]) bad = true;
+  }
+  if (bad) atomicOr(a.flags, kFlagCorrupt);
+}
+
+// Anchors of the box R_0 from the stream into the level-0 box grid.
+__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, float* rec0,
+                             Grid g0) {
+  const int logs = g.L;
+  const int64_t c1 = ((g.n[1] - 1) >> logs) + 1, c2 = ((g.n[2] - 1) >> logs) + 1;
+  const float* an = reinterpret_cast<const float*>(comp + anchor_off);
+  const int64_t n = g0.cnt[0] * g0.cnt[1] * g0.cnt[2];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t ix = i % g0.cnt[2], t = i / g0.cnt[2], iy = t % g0.cnt[1], iz = t / g0.cnt[1];
+    const int64_t z = g0.first[0] + (iz << logs), y = g0.first[1] + (iy << logs),
+                  x = g0.first[2] + (ix << logs);
+    rec0[i] = an[((z >> logs) * c1 + (y >> logs)) * c2 + (x >> logs)];
+  }
+}
+
+// Sentinel entries of a level's unit index (first offsets 0, last = totals).
+__global__ void k_dec_check(const uint32_t* unit_word, const uint32_t* unit_outl, uint64_t nu,
+                            uint64_t words, uint64_t noutl, uint32_t* flags) {
+  if (threadIdx.x == 0 && (unit_word[0] != 0 || unit_outl[0] != 0 || unit_word[nu] != words ||
+                           unit_outl[nu] != noutl))
+    atomicOr(flags, kFlagCorrupt);
+}
+
+template <int E>
+void launch_slab(const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_dec_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, d);
+}
+
+}  // namespace
+
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
+  const Geo& g = a.geo;
+  const int L = g.L;
+  const Grid g0 = box_grid(a.box[0], L);
+  const uint64_t n0 = uint64_t(g0.cnt[0]) * g0.cnt[1] * g0.cnt[2];
+  prof_begin(st, "dec_anchor", -1);
+  hipLaunchKernelGGL(k_dec_anchor, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
+                     a.anchor_off, g, a.rec[0], g0);
+  prof_end(st);
+  for (int k = 1; k <= a.level_out; ++k) {
+    const int logs = L - k;
+    const Grid gp = box_grid(a.box[k - 1], logs + 1);
+    const Grid gc = box_grid(a.box[k], logs);
+    DecSlabArgs d;
+    d.g = g;
+    d.level = k;
+    d.logs = logs;
+    for (int q = 0; q < 3; ++q) {
+      d.n[q] = ((g.n[q] - 1) >> logs) + 1;
+      // grids in level coordinates: level-k coordinate = full / 2^logs
+      d.in_first[q] = gp.first[q] >> (logs + 1);
+      d.in_cnt[q] = gp.cnt[q];
+      d.out_first[q] = gc.first[q] >> logs;
+      d.out_cnt[q] = gc.cnt[q];
+      d.bb_lo[q] = a.box[k].lo[q] >> g.logB;
+      d.bb_n[q] = ((a.box[k].hi[q] - 1) >> g.logB) - d.bb_lo[q] + 1;
+    }
+    bool full = true;
+    for (int q = 0; q < 3; ++q) full = full && a.box[k].lo[q] == 0 && a.box[k].hi[q] == g.n[q];
+    d.xcd_remap = full;
+    d.prev = a.rec[k - 1];
+    d.cur = a.rec[k];
+    d.unit_word = reinterpret_cast<const uint32_t*>(a.comp + a.sec[k]);
+    d.unit_outl = reinterpret_cast<const uint32_t*>(a.comp + a.off_outl[k]);
+    d.lane_len = reinterpret_cast<const uint16_t*>(a.comp + a.off_lane[k]);
+    d.pay = reinterpret_cast<const uint32_t*>(a.comp + a.off_pay[k]);
+    d.outv = reinterpret_cast<const float*>(a.comp + a.off_out[k]);
+    d.words = a.words[k];
+    d.noutl = a.outl[k];
+    d.nlanes = a.lc[k].nl;
+    d.nu = a.lc[k].nu;
+    d.E2 = a.E2[k];
+    d.lut = a.lut;
+    d.flags = a.flags;
+    prof_begin(st, "dec_check", k);
+    hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, d.unit_word, d.unit_outl, d.nu,
+                       d.words, d.noutl, d.flags);
+    prof_end(st);
+    const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
+    const int E = g.B >> logs;
+    prof_begin(st, "decode", k);
+    switch (E) {
+      case 2: launch_slab<2>(d, nblk, st); break;
+      case 4: launch_slab<4>(d, nblk, st); break;
+      case 8: launch_slab<8>(d, nblk, st); break;
+      case 16: launch_slab<16>(d, nblk, st); break;
+      case 32: launch_slab<32>(d, nblk, st); break;
+      default: launch_slab<64>(d, nblk, st); break;
+    }
+    prof_end(st);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace stz

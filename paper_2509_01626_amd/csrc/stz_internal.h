@@ -158,6 +158,7 @@ struct CompressArgs {
   unsigned long long* hist;   // 2R counters
   uint8_t* lens;              // 2R
   uint16_t* codes;            // 2R
+  void* cb_scratch;           // codebook_scratch_bytes(2R)
   uint16_t* lane_len;         // per level, at lane_base[l]
   uint64_t lane_base[kMaxLevels + 1];
   uint32_t* cnt;              // [2L segments][nu]: unit words, unit outliers
@@ -167,6 +168,11 @@ struct CompressArgs {
 };
 
 hipError_t launch_compress(const CompressArgs& a, hipStream_t st);
+
+// Code book from the histogram (lengths and canonical codes, 2R entries).
+size_t codebook_scratch_bytes(int nsym);
+void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, uint16_t* codes,
+                     void* scratch, hipStream_t st);
 
 struct DecodeArgs {
   const uint8_t* comp;
