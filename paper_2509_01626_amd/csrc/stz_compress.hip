@@ -25,7 +25,19 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
   float mn = INFINITY, mx = -INFINITY;
   bool bad = false;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+  const uint64_t t0 = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  uint64_t head = 0;  // elements handled by 16-byte loads
+  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+    head = N & ~uint64_t(3);
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    for (uint64_t i = t0; i < (head >> 2); i += stride) {
+      const float4 v = x4[i];
+      bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+      mn = fminf(fminf(mn, v.x), fminf(v.y, fminf(v.z, v.w)));
+      mx = fmaxf(fmaxf(mx, v.x), fmaxf(v.y, fmaxf(v.z, v.w)));
+    }
+  }
+  for (uint64_t i = head + t0; i < N; i += stride) {
     const float v = x[i];
     bad |= !isfinite(v);
     mn = fminf(mn, v);
@@ -143,6 +155,9 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
   const int R = a.g.R;
   const int64_t sf[3] = {0, 0, 0};
   const int ls = a.logs;
+  const int64_t org[3] = {oz, oy, ox};
+  const bool interior = block_interior(org, E, a.n);
+  uint32_t n_center = 0;  // the zero-residual symbol is counted in a register
   bool bad = false;
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;
@@ -171,7 +186,7 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
         const float xv =
             a.x[(((p[0] << ls) * a.g.n[1]) + (p[1] << ls)) * a.g.n[2] + (p[2] << ls)];
         bad |= !isfinite(xv);
-        const float pred = tile_predict<E>(tile, p, a.n, o, tz0, ty0, tx0);
+        const float pred = slab_predict<E>(tile, cc, lz - z0, ly, lx, p, a.n, interior);
         float rv;
         const int sy = quantize(xv, pred, E2, INV, e, R, &rv);
         // rank inside the unit: class sub-grid raster
@@ -179,11 +194,16 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
         const int My = oy_ ? Ey >> 1 : (Ey + 1) >> 1, Mx = ox_ ? Ex >> 1 : (Ex + 1) >> 1;
         a.sym[ubase[cc] + ((uint64_t(lz >> 1) * My + (ly >> 1)) * Mx + (lx >> 1))] = uint16_t(sy);
         if (a.cur) a.cur[gi] = rv;
-        atomicAdd(&h[sy], 1u);
+        if (sy == R)
+          ++n_center;
+        else
+          atomicAdd(&h[sy], 1u);
       }
     }
     __syncthreads();
   }
+  if (n_center) atomicAdd(&h[R], n_center);
+  __syncthreads();
   if (bad) atomicOr(&a.P->flags, kFlagNonfinite);
   for (int i = tid; i < a.nsym; i += blockDim.x)
     if (h[i]) atomicAdd(&a.hist[i], (unsigned long long)h[i]);
@@ -206,32 +226,44 @@ struct LaneLenArgs {
   uint32_t* cnt_outl;
 };
 
-// Bit length of every lane stream and per-unit totals.
+// Bit length of every lane stream and per-unit totals. One work-group per
+// block: thread t < 7m owns column j = t mod m of the block's class t/m + 1.
 __global__ __launch_bounds__(256) void k_lanelen(LaneLenArgs a) {
   __shared__ uint8_t L[2 * kMaxRadius];
+  __shared__ uint32_t bits_s[256], out_s[256];
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
+  const int m = (a.g.B >> a.logs) >> 1;
+  const int tid = threadIdx.x, c = tid / m + 1, j = tid % m;
+  const bool is_lane = tid < 7 * m;
+  const int64_t u = int64_t(blockIdx.x) * 7 + (c - 1);
+  uint32_t bits = 0, no = 0;
+  int Mx = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / kWave);
-  for (int64_t u = int64_t(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); u < int64_t(a.nu);
-       u += nwaves) {
+  if (is_lane) {
     const UnitGeo ug = unit_geo(a.g, u, a.logs);
-    const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1], Mx = ug.M[2];
-    const uint64_t base = unit_sym_off(a.g, a.logs, u);
-    uint32_t bits = 0, no = 0;
-    if (lane < int(Mx)) {
+    const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1];
+    Mx = ug.M[2];
+    if (j < Mx) {
+      const uint64_t base = uint64_t(unit_sym_off(a.g, a.logs, u));
       for (uint32_t t = 0; t < rows; ++t) {
-        const uint16_t s = a.sym[base + uint64_t(t) * Mx + lane];
+        const uint16_t s = a.sym[base + uint64_t(t) * Mx + j];
         bits += L[s];
         no += (s == 0);
       }
-      a.lane_len[unit_lane_off(a.g, a.logs, u) + lane] = uint16_t(bits);
+      a.lane_len[unit_lane_off(a.g, a.logs, u) + j] = uint16_t(bits);
     }
-    const uint32_t tb = wave_sum(bits), to = wave_sum(no);
-    if (lane == 0) {
-      a.cnt_words[u] = (tb + 31) >> 5;
-      a.cnt_outl[u] = to;
+  }
+  bits_s[tid] = bits;
+  out_s[tid] = no;
+  __syncthreads();
+  if (is_lane && j == 0) {
+    uint32_t tb = 0, to = 0;
+    for (int k = 0; k < Mx; ++k) {
+      tb += bits_s[tid + k];
+      to += out_s[tid + k];
     }
+    a.cnt_words[u] = (tb + 31) >> 5;
+    a.cnt_outl[u] = to;
   }
 }
 
@@ -435,82 +467,95 @@ __device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_
     atomicOr(&pay[wi], w);
 }
 
-// Bit-pack every lane stream, write the unit index and the outliers.
+// Bit-pack every lane stream, write the unit index and the outliers. Same
+// block mapping as k_lanelen; a unit's lanes sit inside one wave, so the
+// rank order of its outliers comes from a per-row ballot.
 __global__ __launch_bounds__(256) void k_pack(PackArgs a) {
   const DevParams* P = a.P;
   if (P->flags) return;
   __shared__ uint8_t Ls[2 * kMaxRadius];
   __shared__ uint16_t Cs[2 * kMaxRadius];
+  __shared__ uint32_t lb_s[256];
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) {
     Ls[i] = a.lens[i];
     Cs[i] = a.codes[i];
   }
-  __syncthreads();
   const int l = a.level;
   uint32_t* unit_word = reinterpret_cast<uint32_t*>(a.out + P->sec[l]);
   uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
   uint16_t* lane_arr = reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]);
   uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
   float* outv = reinterpret_cast<float*>(a.out + P->off_out[l]);
-  const int lane = threadIdx.x & 63;
-  const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-  const int64_t nwaves = int64_t(gridDim.x) * (blockDim.x / kWave);
-  for (int64_t u = int64_t(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); u < int64_t(a.nu);
-       u += nwaves) {
-    const UnitGeo ug = unit_geo(a.g, u, a.logs);
-    const uint32_t M1 = ug.M[1], Mx = ug.M[2], rows = uint32_t(ug.M[0]) * M1;
-    const bool act = lane < int(Mx);
-    const uint64_t lane0 = unit_lane_off(a.g, a.logs, u);
-    const uint32_t lb = act ? a.lane_len[lane0 + lane] : 0;
-    const uint32_t pre = wave_excl_scan(lb, lane);
-    const uint32_t uw = a.scan_words[u], uo = a.scan_outl[u];
-    if (lane == 0) {
-      unit_word[u] = uw;
-      unit_outl[u] = uo;
-      if (u == int64_t(a.nu) - 1) {
-        unit_word[a.nu] = a.scan_words[a.nu];
-        unit_outl[a.nu] = a.scan_outl[a.nu];
-      }
-    }
-    if (act) lane_arr[lane0 + lane] = uint16_t(lb);
-    const uint64_t start = uint64_t(uw) * 32 + pre, end = start + lb;
-    uint64_t pos = start;
-    uint32_t cur = 0;
-    uint32_t run = 0;
-    const uint64_t base = unit_sym_off(a.g, a.logs, u);
-    for (uint32_t t = 0; t < rows; ++t) {
-      const uint16_t s = act ? a.sym[base + uint64_t(t) * Mx + lane] : uint16_t(1);
-      if (act) {
-        const uint32_t len = Ls[s], c = Cs[s];
-        const uint32_t o = uint32_t(pos & 31);
-        if (o + len <= 32) {
-          cur |= c << (32 - o - len);
-          pos += len;
-          if ((pos & 31) == 0) {
-            emit_word(pay, (pos >> 5) - 1, cur, start, end);
-            cur = 0;
-          }
-        } else {
-          const uint32_t hi = len - (32 - o);
-          cur |= c >> hi;
-          emit_word(pay, pos >> 5, cur, start, end);
-          cur = c << (32 - hi);
-          pos += len;
-        }
-      }
-      const bool is_out = act && s == 0;
-      const uint64_t m = __ballot(is_out);
-      if (is_out) {
-        const uint32_t vy = t % M1, vz = t / M1;
-        const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
-        const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
-        const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * lane + ug.o[2]) << a.logs);
-        outv[uo + run + __popcll(m & lt_mask)] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
-      }
-      run += __popcll(m);
-    }
-    if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
+  const int m = (a.g.B >> a.logs) >> 1;
+  const int tid = threadIdx.x, lane = tid & 63, c = tid / m + 1, j = tid % m;
+  const bool is_lane = tid < 7 * m;
+  const int64_t u = int64_t(blockIdx.x) * 7 + (c - 1);
+  UnitGeo ug;
+  uint32_t lb = 0, rows = 0, M1 = 1;
+  int Mx = 0;
+  uint64_t lane0 = 0;
+  if (is_lane) {
+    ug = unit_geo(a.g, u, a.logs);
+    M1 = ug.M[1];
+    rows = uint32_t(ug.M[0]) * M1;
+    Mx = ug.M[2];
+    lane0 = uint64_t(unit_lane_off(a.g, a.logs, u));
+    if (j < Mx) lb = a.lane_len[lane0 + j];
   }
+  lb_s[tid] = lb;
+  __syncthreads();
+  if (!is_lane) return;
+  uint32_t pre = 0;
+  for (int k = 0; k < j; ++k) pre += lb_s[tid - j + k];
+  const uint32_t uw = a.scan_words[u], uo = a.scan_outl[u];
+  if (j == 0) {
+    unit_word[u] = uw;
+    unit_outl[u] = uo;
+    if (u == int64_t(a.nu) - 1) {
+      unit_word[a.nu] = a.scan_words[a.nu];
+      unit_outl[a.nu] = a.scan_outl[a.nu];
+    }
+  }
+  const bool act = j < Mx;
+  if (act) lane_arr[lane0 + j] = uint16_t(lb);
+  const uint64_t start = uint64_t(uw) * 32 + pre, end = start + lb;
+  uint64_t pos = start;
+  uint32_t cur = 0, run = 0;
+  const uint64_t base = uint64_t(unit_sym_off(a.g, a.logs, u));
+  const uint64_t segmask = (m >= 64 ? ~uint64_t(0) : ((uint64_t(1) << m) - 1)) << (lane - j);
+  const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+  for (uint32_t t = 0; t < rows; ++t) {
+    const uint16_t s = act ? a.sym[base + uint64_t(t) * Mx + j] : uint16_t(1);
+    if (act) {
+      const uint32_t len = Ls[s], cw = Cs[s];
+      const uint32_t o = uint32_t(pos & 31);
+      if (o + len <= 32) {
+        cur |= cw << (32 - o - len);
+        pos += len;
+        if ((pos & 31) == 0) {
+          emit_word(pay, (pos >> 5) - 1, cur, start, end);
+          cur = 0;
+        }
+      } else {
+        const uint32_t hi = len - (32 - o);
+        cur |= cw >> hi;
+        emit_word(pay, pos >> 5, cur, start, end);
+        cur = cw << (32 - hi);
+        pos += len;
+      }
+    }
+    const bool is_out = act && s == 0;
+    const uint64_t mk = __ballot(is_out) & segmask;
+    if (is_out) {
+      const uint32_t vy = t % M1, vz = t / M1;
+      const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
+      const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
+      const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * j + ug.o[2]) << a.logs);
+      outv[uo + run + __popcll(mk & lt_mask)] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
+    }
+    run += __popcll(mk);
+  }
+  if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
 }
 
 }  // namespace
@@ -583,7 +628,7 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     q.cnt_words = a.cnt + uint64_t(2 * (l - 1)) * nu;
     q.cnt_outl = a.cnt + uint64_t(2 * (l - 1) + 1) * nu;
     prof_begin(st, "lanelen", l);
-    hipLaunchKernelGGL(k_lanelen, dim3(grid_for(nu, 4, 2048)), dim3(256), 0, st, q);
+    hipLaunchKernelGGL(k_lanelen, dim3(unsigned(nu / 7)), dim3(256), 0, st, q);
     prof_end(st);
   }
   const int nblk = int((nu + kScanBlock - 1) / kScanBlock);
@@ -636,7 +681,7 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     p.out = a.out;
     p.P = a.params;
     prof_begin(st, "pack", l);
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(nu, 4, 4096)), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_pack, dim3(unsigned(nu / 7)), dim3(256), 0, st, p);
     prof_end(st);
   }
   return hipGetLastError();

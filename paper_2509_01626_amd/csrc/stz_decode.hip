@@ -133,6 +133,8 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
   const uint64_t ltmask = (uint64_t(1) << lane) - 1;
   const bool lane_active = is_lane && needed && j < Mx;
 
+  const int64_t org[3] = {oz, oy, ox};
+  const bool interior = block_interior(org, E, a.n);
   const int zlast = min(Ez, rz1);  // no output needed beyond this level plane
   bool complete = true;
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
             }
           } else {
             const int64_t p[3] = {oz + lz, oy + ly, ox + lx};
-            const float pred = tile_predict<E>(tile, p, a.n, o, tz0, ty0, tx0);
+            const float pred = slab_predict<E>(tile, cc, lz - z0, ly, lx, p, a.n, interior);
             const float prod = (float)(int(e) - a.g.R) * a.E2;
             val = pred + prod;
           }

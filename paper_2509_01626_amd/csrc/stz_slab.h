@@ -58,16 +58,167 @@ __device__ inline void load_tile(float* tile, const float* __restrict__ src, con
   }
 }
 
-// Prediction of the level point at global level coordinates p, class parity
-// o, from the slab's coarse tile whose origin (level coordinates, even) is
-// (tz0, ty0, tx0). n = level grid extents.
+// True when every odd level coordinate of the block has full cubic support
+// (offsets -3..+3 inside the level grid) on every axis: M3, P1 and P3 hold
+// for all its points, so each class uses its Eq. 6 / 7 / 8 form.
+__device__ inline bool block_interior(const int64_t o[3], int E, const int64_t n[3]) {
+  bool in = true;
+  for (int d = 0; d < 3; ++d) in = in && o[d] >= 2 && o[d] + E + 3 <= n[d];
+  return in;
+}
+
+// One-axis rule of the nested fallback (format 2.2); f(i) is the value at
+// offset index i along the axis: 0 = -3, 1 = -1, 2 = +1.
+template <class F>
+__device__ inline float nest_rule(bool p1, bool m3, F f) {
+  if (p1) {
+    const float lo = f(1);
+    const float hi = f(2);
+    return (lo + hi) * 0.5f;
+  }
+  if (m3) {
+    const float lo = f(1);
+    const float lo3 = f(0);
+    return ((3.0f * lo) - lo3) * 0.5f;
+  }
+  return f(1);
+}
+
+// Prediction of a class-C point from the slab's coarse tile (format 2.2), with
+// the class's odd axes fixed at compile time. w = tile-relative level
+// coordinates (level coordinate - tile origin - 2): an even coordinate sits at
+// tile index w/2 + 1; the neighbours of an odd one at offsets -3, -1, +1, +3
+// (offset index 0..3) at tile indices k..k+3, k = (w-1)/2. p = global level
+// coordinates and n = level grid extents give the availability flags; with
+// FULL every flag is known to hold (interior blocks).
+template <int E, int C, bool FULL>
+__device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, const int64_t p[3],
+                                  const int64_t n[3]) {
+  constexpr int T = SlabShape<E>::T;
+  constexpr bool OZ = (C >> 2) & 1, OY = (C >> 1) & 1, OX = C & 1;
+  constexpr int ND = int(OZ) + int(OY) + int(OX);
+  const int bz = OZ ? (wz - 1) >> 1 : (wz >> 1) + 1;
+  const int by = OY ? (wy - 1) >> 1 : (wy >> 1) + 1;
+  const int bx = OX ? (wx - 1) >> 1 : (wx >> 1) + 1;
+  // v(i, j, k): offset indices along the odd axes in order z, y, x.
+  auto v = [&](int i, int j, int k) {
+    int o[3] = {0, 0, 0};
+    int q = 0;
+    const int idx[3] = {i, j, k};
+    if constexpr (OZ) o[0] = idx[q++];
+    if constexpr (OY) o[1] = idx[q++];
+    if constexpr (OX) o[2] = idx[q++];
+    return tile[((bz + o[0]) * T + (by + o[1])) * T + (bx + o[2])];
+  };
+  // availability flags of the odd axes, in order
+  bool P1[3] = {true, true, true}, M3[3] = {true, true, true}, P3[3] = {true, true, true};
+  if constexpr (!FULL) {
+    int q = 0;
+    if constexpr (OZ) {
+      P1[q] = p[0] + 1 <= n[0] - 1;
+      M3[q] = p[0] >= 3;
+      P3[q] = p[0] + 3 <= n[0] - 1;
+      ++q;
+    }
+    if constexpr (OY) {
+      P1[q] = p[1] + 1 <= n[1] - 1;
+      M3[q] = p[1] >= 3;
+      P3[q] = p[1] + 3 <= n[1] - 1;
+      ++q;
+    }
+    if constexpr (OX) {
+      P1[q] = p[2] + 1 <= n[2] - 1;
+      M3[q] = p[2] >= 3;
+      P3[q] = p[2] + 3 <= n[2] - 1;
+      ++q;
+    }
+  }
+  if constexpr (ND == 1) {
+    if (P1[0]) {
+      const float B = v(1, 0, 0), Cv = v(2, 0, 0);
+      if (M3[0] && P3[0]) {
+        const float A = v(0, 0, 0), D = v(3, 0, 0);
+        return ((9.0f * (B + Cv)) - (A + D)) * 0.0625f;
+      }
+      if (P3[0]) {
+        const float D = v(3, 0, 0);
+        return ((3.0f * B + 6.0f * Cv) - D) * 0.125f;
+      }
+      if (M3[0]) {
+        const float A = v(0, 0, 0);
+        return ((6.0f * B + 3.0f * Cv) - A) * 0.125f;
+      }
+      return (B + Cv) * 0.5f;
+    }
+    const float B = v(1, 0, 0);
+    if (M3[0]) {
+      const float A = v(0, 0, 0);
+      return ((3.0f * B) - A) * 0.5f;
+    }
+    return B;
+  } else if constexpr (ND == 2) {
+    if (FULL || (P1[0] && M3[0] && P3[0] && P1[1] && M3[1] && P3[1])) {
+      float in = v(1, 1, 0);
+      in = in + v(1, 2, 0);
+      in = in + v(2, 1, 0);
+      in = in + v(2, 2, 0);
+      float out = v(0, 0, 0);
+      out = out + v(0, 3, 0);
+      out = out + v(3, 0, 0);
+      out = out + v(3, 3, 0);
+      return ((9.0f * in) - out) * 0.03125f;
+    }
+    return nest_rule(P1[0], M3[0], [&](int i) {
+      return nest_rule(P1[1], M3[1], [&](int j) { return v(i, j, 0); });
+    });
+  } else {
+    if (FULL || (P1[0] && M3[0] && P3[0] && P1[1] && M3[1] && P3[1] && P1[2] && M3[2] && P3[2])) {
+      float in = v(1, 1, 1);
+      in = in + v(1, 1, 2);
+      in = in + v(1, 2, 1);
+      in = in + v(1, 2, 2);
+      in = in + v(2, 1, 1);
+      in = in + v(2, 1, 2);
+      in = in + v(2, 2, 1);
+      in = in + v(2, 2, 2);
+      float out = v(0, 0, 0);
+      out = out + v(0, 0, 3);
+      out = out + v(0, 3, 0);
+      out = out + v(0, 3, 3);
+      out = out + v(3, 0, 0);
+      out = out + v(3, 0, 3);
+      out = out + v(3, 3, 0);
+      out = out + v(3, 3, 3);
+      return ((9.0f * in) - out) * 0.015625f;
+    }
+    return nest_rule(P1[0], M3[0], [&](int i) {
+      return nest_rule(P1[1], M3[1], [&](int j) {
+        return nest_rule(P1[2], M3[2], [&](int k) { return v(i, j, k); });
+      });
+    });
+  }
+}
+
+// Class dispatch (the class is uniform across a wave at each call site).
 template <int E>
-__device__ inline float tile_predict(const float* tile, const int64_t p[3], const int64_t n[3],
-                                     const int o[3], int64_t tz0, int64_t ty0, int64_t tx0) {
-  using S = SlabShape<E>;
-  return predict_point(p, 0, n, o, [&](int64_t z, int64_t y, int64_t x) {
-    return tile[((((z - tz0) >> 1) * S::T) + ((y - ty0) >> 1)) * S::T + ((x - tx0) >> 1)];
-  });
+__device__ inline float slab_predict(const float* tile, int cc, int wz, int wy, int wx,
+                                     const int64_t p[3], const int64_t n[3], bool interior) {
+#define STZ_CASE(C)                                                   \
+  case C:                                                             \
+    return interior ? tile_pred<E, C, true>(tile, wz, wy, wx, p, n)   \
+                    : tile_pred<E, C, false>(tile, wz, wy, wx, p, n);
+  switch (cc) {
+    STZ_CASE(1)
+    STZ_CASE(2)
+    STZ_CASE(3)
+    STZ_CASE(4)
+    STZ_CASE(5)
+    STZ_CASE(6)
+    default:
+      return interior ? tile_pred<E, 7, true>(tile, wz, wy, wx, p, n)
+                      : tile_pred<E, 7, false>(tile, wz, wy, wx, p, n);
+  }
+#undef STZ_CASE
 }
 
 }  // namespace
