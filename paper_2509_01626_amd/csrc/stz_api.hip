@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/stz.h: argument validation,
 // stream-header parsing, workspace management and kernel launch sequences.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -89,25 +90,47 @@ void pool_setup() {
   done[dev] = true;
 }
 
-// Stream-ordered scratch, released (to the pool) when the call ends.
+// Stream-ordered scratch: sub-buffers are laid out first (take), then one
+// allocation from the device pool backs all of them (commit); it returns to
+// the pool when the call ends.
 struct Workspace {
   hipStream_t st;
-  std::vector<void*> ptrs;
-  bool fail = false;
+  char* base = nullptr;
+  uint64_t size = 0;
   explicit Workspace(hipStream_t s) : st(s) { pool_setup(); }
   template <class T>
-  T* get(uint64_t n) {
+  uint64_t take(uint64_t n) {
+    const uint64_t off = size;
+    size += (std::max<uint64_t>(n, 1) * sizeof(T) + 255) & ~uint64_t(255);
+    return off;
+  }
+  bool commit() {
     void* p = nullptr;
-    if (n == 0) n = 1;
-    if (hipMallocAsync(&p, n * sizeof(T), st) != hipSuccess) {
-      fail = true;
-      return nullptr;
-    }
-    ptrs.push_back(p);
-    return static_cast<T*>(p);
+    if (hipMallocAsync(&p, std::max<uint64_t>(size, 256), st) != hipSuccess) return false;
+    base = static_cast<char*>(p);
+    return true;
+  }
+  template <class T>
+  T* at(uint64_t off) const {
+    return reinterpret_cast<T*>(base + off);
   }
   ~Workspace() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, st);
+    if (base) (void)hipFreeAsync(base, st);
+  }
+};
+
+// Per-thread pinned staging for the decoder table and the flag reset, so
+// both go to the device in one asynchronous copy. Each decode call ends with
+// a stream synchronization, after which the staging area may be reused.
+struct Staging {
+  uint16_t* lut = nullptr;  // 2^kLutBits entries, then a 32-bit zero word
+  Staging() {
+    if (hipHostMalloc(reinterpret_cast<void**>(&lut), (size_t(1) << kLutBits) * 2 + 16) !=
+        hipSuccess)
+      lut = nullptr;
+  }
+  ~Staging() {
+    if (lut) (void)hipHostFree(lut);
   }
 };
 
@@ -283,11 +306,14 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   a.box[level] = box;
   for (int k = level; k >= 1; --k) a.box[k - 1] = dilate(a.box[k], 3 * (int64_t(1) << (g.L - k)), g);
   Workspace ws(st);
-  for (int k = 0; k < level; ++k) a.rec[k] = ws.get<float>(box_points(a.box[k], g.L - k));
+  uint64_t o_rec[kMaxLevels + 1];
+  for (int k = 0; k < level; ++k) o_rec[k] = ws.take<float>(box_points(a.box[k], g.L - k));
+  const uint64_t o_lut = ws.take<uint8_t>(lut.size() * 2 + 16);
+  if (!ws.commit()) return STZ_ERR_NOMEM;
+  for (int k = 0; k < level; ++k) a.rec[k] = ws.at<float>(o_rec[k]);
   a.rec[level] = out;
-  uint16_t* dlut = ws.get<uint16_t>(lut.size());
-  uint32_t* dflags = ws.get<uint32_t>(1);
-  if (ws.fail) return STZ_ERR_NOMEM;
+  uint16_t* dlut = ws.at<uint16_t>(o_lut);
+  uint32_t* dflags = reinterpret_cast<uint32_t*>(dlut + lut.size());
   for (int l = 1; l <= g.L; ++l) {
     a.sec[l] = h.sec[l];
     a.off_outl[l] = h.off_outl[l];
@@ -311,9 +337,11 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   }
   a.lut = dlut;
   a.flags = dflags;
-  const uint32_t zero = 0;
-  if (hipMemcpyAsync(dlut, lut.data(), lut.size() * 2, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(dflags, &zero, 4, hipMemcpyHostToDevice, st) != hipSuccess)
+  thread_local Staging stage;
+  if (!stage.lut) return STZ_ERR_NOMEM;
+  std::memcpy(stage.lut, lut.data(), lut.size() * 2);
+  std::memset(stage.lut + lut.size(), 0, 16);
+  if (hipMemcpyAsync(dlut, stage.lut, lut.size() * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
     return STZ_ERR_DEVICE;
   if (launch_decode(a, st) != hipSuccess) return STZ_ERR_DEVICE;
   uint32_t flags = 0;
@@ -376,26 +404,39 @@ stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, dou
   if (nu > 0xFFFFFFF0ull) return STZ_ERR_ARG;
 
   Workspace ws(st);
-  a.params = ws.get<DevParams>(1);
+  const uint64_t o_params = ws.take<DevParams>(1);
   a.nparts = uint32_t(std::min<uint64_t>(1024, (N + 4095) / 4096));
-  a.part = ws.get<float2>(a.nparts);
-  for (int l = 0; l < L; ++l) a.rec[l] = ws.get<float>(grid_count(g, L - l));
+  const uint64_t o_part = ws.take<float2>(a.nparts);
+  uint64_t o_rec[kMaxLevels], o_sym[kMaxLevels + 1];
+  for (int l = 0; l < L; ++l) o_rec[l] = ws.take<float>(grid_count(g, L - l));
   uint64_t lanes = 0;
   for (int l = 1; l <= L; ++l) {
-    a.sym[l] = ws.get<uint16_t>(a.lc[l].nsym);
+    o_sym[l] = ws.take<uint16_t>(a.lc[l].nsym);
     a.lane_base[l] = lanes;
     lanes += a.lc[l].nl;
   }
-  a.lane_len = ws.get<uint16_t>(lanes);
-  a.hist = ws.get<unsigned long long>(nsym);
-  a.lens = ws.get<uint8_t>(nsym);
-  a.codes = ws.get<uint16_t>(nsym);
-  a.cb_scratch = ws.get<uint8_t>(codebook_scratch_bytes(nsym));
-  a.cnt = ws.get<uint32_t>(2 * L * nu);
-  a.scan = ws.get<uint32_t>(2 * L * (nu + 1));
+  const uint64_t o_lane = ws.take<uint16_t>(lanes);
+  const uint64_t o_hist = ws.take<unsigned long long>(nsym);
+  const uint64_t o_lens = ws.take<uint8_t>(nsym);
+  const uint64_t o_codes = ws.take<uint16_t>(nsym);
+  const uint64_t o_cb = ws.take<uint8_t>(codebook_scratch_bytes(nsym));
+  const uint64_t o_cnt = ws.take<uint32_t>(2 * L * nu);
+  const uint64_t o_scan = ws.take<uint32_t>(2 * L * (nu + 1));
   const uint64_t nblk = (nu + 2047) / 2048;
-  a.scan_part = ws.get<uint64_t>(2 * L * nblk);
-  if (ws.fail) return STZ_ERR_NOMEM;
+  const uint64_t o_spart = ws.take<uint64_t>(2 * L * nblk);
+  if (!ws.commit()) return STZ_ERR_NOMEM;
+  a.params = ws.at<DevParams>(o_params);
+  a.part = ws.at<float2>(o_part);
+  for (int l = 0; l < L; ++l) a.rec[l] = ws.at<float>(o_rec[l]);
+  for (int l = 1; l <= L; ++l) a.sym[l] = ws.at<uint16_t>(o_sym[l]);
+  a.lane_len = ws.at<uint16_t>(o_lane);
+  a.hist = ws.at<unsigned long long>(o_hist);
+  a.lens = ws.at<uint8_t>(o_lens);
+  a.codes = ws.at<uint16_t>(o_codes);
+  a.cb_scratch = ws.at<uint8_t>(o_cb);
+  a.cnt = ws.at<uint32_t>(o_cnt);
+  a.scan = ws.at<uint32_t>(o_scan);
+  a.scan_part = ws.at<uint64_t>(o_spart);
   if (launch_compress(a, st) != hipSuccess) return STZ_ERR_DEVICE;
   DevParams P;
   if (hipMemcpyAsync(&P, a.params, sizeof(P), hipMemcpyDeviceToHost, st) != hipSuccess ||

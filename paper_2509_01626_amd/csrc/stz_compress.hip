@@ -130,6 +130,65 @@ struct PredSlabArgs {
   int nsym;
 };
 
+// Per-slab state for predicting rows of one parity type.
+struct PredRows {
+  const float* x;
+  const float* tile;
+  uint16_t* ssym;
+  uint32_t* h;
+  float* cur;
+  int64_t oz, oy, ox;
+  int z0, Ex, ls;
+  int64_t n[3], fn[3];
+  float E2, INV;
+  double e;
+  int R;
+};
+
+// Predict and quantize one point of class C (0 = coarse copy only).
+template <int E, int C, bool INT>
+__device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int srow,
+                                  const float* xrow, float* grow, const int64_t p[3],
+                                  uint32_t* n_center, bool* bad) {
+  using S = SlabShape<E>;
+  constexpr int m = S::m;
+  if constexpr (C == 0) {
+    if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
+  } else {
+    const float xv = xrow[lx << c.ls];
+    *bad |= !isfinite(xv);
+    const float pred = tile_pred<E, C, INT>(c.tile, lz - c.z0, ly, lx, p, c.n);
+    float rv;
+    const int sy = quantize(xv, pred, c.E2, c.INV, c.e, c.R, &rv);
+    c.ssym[(C - 1) * (S::HZ * m * m) + srow] = uint16_t(sy);
+    if (grow) grow[lx] = rv;
+    if (sy == c.R)
+      ++*n_center;
+    else
+      atomicAdd(&c.h[sy], 1u);
+  }
+}
+
+// This wave's rows of parity type (ZP, YP); classes fixed at compile time.
+template <int E, int ZP, int YP, bool INT>
+__device__ inline void pred_type(const PredRows& c, int hs, int Ey, int wave, int lane,
+                                 uint32_t* n_center, bool* bad) {
+  using S = SlabShape<E>;
+  constexpr int m = S::m;
+  constexpr int C0 = 4 * ZP + 2 * YP;
+  for_type_rows<E, ZP, YP>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
+    float* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
+    const float* xrow =
+        c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);
+    const int srow = (((lz - c.z0) >> 1) * m + (ly >> 1)) * m + q;
+    const int l0 = 2 * q, l1 = 2 * q + 1;
+    const int64_t p0[3] = {c.oz + lz, c.oy + ly, c.ox + l0};
+    const int64_t p1[3] = {c.oz + lz, c.oy + ly, c.ox + l1};
+    if (l0 < c.Ex) pred_point<E, C0, INT>(c, lz, ly, l0, srow, xrow, grow, p0, n_center, bad);
+    if (l1 < c.Ex) pred_point<E, C0 + 1, INT>(c, lz, ly, l1, srow, xrow, grow, p1, n_center, bad);
+  });
+}
+
 // Predict and quantize every level-l point of one block (format 2.2, 2.3);
 // also writes the block's part of the level-l grid (coarse points copied,
 // level points reconstructed) for the next level's prediction.
@@ -139,6 +198,7 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
   constexpr int m = S::m;
   __shared__ uint32_t h[2 * kMaxRadius];
   __shared__ float tile[S::TILE];
+  __shared__ uint16_t ssym[7 * S::HZ * m * m];  // slab symbols, [class][v_z][v_y][v_x]
   __shared__ uint64_t ubase[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
@@ -164,40 +224,65 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
     load_tile<E>(tile, a.prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
     __syncthreads();
     const int hs = min(S::H, Ez - z0);
-    const int ntask = hs * S::TASKS_PER_Z;
-    for (int task = wave; task < ntask; task += 4) {
-      const int lz = z0 + task / S::TASKS_PER_Z;
-      const int rem = task % S::TASKS_PER_Z, par = rem / S::G, g = rem % S::G;
-      const int ly = par + 2 * (g * S::RW + lane / S::P);
-      const int q = lane % S::P;
-      if (lane / S::P >= S::RW || ly >= Ey) continue;
-      for (int hh = 0; hh < 2; ++hh) {
-        const int lx = 2 * q + hh;
-        if (lx >= Ex) continue;
-        const int o[3] = {lz & 1, ly & 1, hh};
-        const int cc = 4 * o[0] + 2 * o[1] + o[2];
-        const int64_t gi = ((oz + lz) * a.n[1] + (oy + ly)) * a.n[2] + (ox + lx);
-        if (cc == 0) {
-          if (a.cur)
-            a.cur[gi] = tile[((((lz - z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
-          continue;
+    PredRows ctx;
+    ctx.x = a.x;
+    ctx.tile = tile;
+    ctx.ssym = ssym;
+    ctx.h = h;
+    ctx.cur = a.cur;
+    ctx.oz = oz;
+    ctx.oy = oy;
+    ctx.ox = ox;
+    ctx.z0 = z0;
+    ctx.Ex = Ex;
+    ctx.ls = ls;
+    for (int d = 0; d < 3; ++d) {
+      ctx.n[d] = a.n[d];
+      ctx.fn[d] = a.g.n[d];
+    }
+    ctx.E2 = E2;
+    ctx.INV = INV;
+    ctx.e = e;
+    ctx.R = R;
+    if (interior) {
+      pred_type<E, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+    } else {
+      pred_type<E, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+    }
+    __syncthreads();
+    // The slab's rows of every unit, column-major inside the unit: column j of
+    // a unit with M_z*M_y rows starts at unit base + j*M_z*M_y, so this slab's
+    // part of each column is one contiguous run.
+    const int a0 = z0 >> 1;
+    for (int c = 1; c <= 7; ++c) {
+      const int oz_ = (c >> 2) & 1, oy_ = (c >> 1) & 1, ox_ = c & 1;
+      const int Mz = oz_ ? Ez >> 1 : (Ez + 1) >> 1, My = oy_ ? Ey >> 1 : (Ey + 1) >> 1,
+                Mx = ox_ ? Ex >> 1 : (Ex + 1) >> 1;
+      const int rz = min(a0 + S::HZ, Mz) - a0;
+      if (rz <= 0) continue;
+      const int run = rz * My;  // contiguous symbols per column in this slab
+      const int cnt = run * Mx;
+      uint16_t* dst = a.sym + ubase[c] + uint64_t(a0 * My);
+      const uint64_t cstride = uint64_t(Mz * My);
+      if (Ey == E && rz == S::HZ) {  // full extents: powers of two
+        constexpr int LMY = __builtin_ctz(m), LRUN = __builtin_ctz(S::HZ * m);
+        for (int i = tid; i < cnt; i += blockDim.x) {
+          const int j = i >> LRUN, t = i & ((1 << LRUN) - 1);
+          const int vz = t >> LMY, vy = t & (m - 1);
+          dst[uint64_t(j) * cstride + t] = ssym[((c - 1) * S::HZ + vz) * m * m + vy * m + j];
         }
-        const int64_t p[3] = {oz + lz, oy + ly, ox + lx};
-        const float xv =
-            a.x[(((p[0] << ls) * a.g.n[1]) + (p[1] << ls)) * a.g.n[2] + (p[2] << ls)];
-        bad |= !isfinite(xv);
-        const float pred = slab_predict<E>(tile, cc, lz - z0, ly, lx, p, a.n, interior);
-        float rv;
-        const int sy = quantize(xv, pred, E2, INV, e, R, &rv);
-        // rank inside the unit: class sub-grid raster
-        const int oy_ = o[1], ox_ = o[2];
-        const int My = oy_ ? Ey >> 1 : (Ey + 1) >> 1, Mx = ox_ ? Ex >> 1 : (Ex + 1) >> 1;
-        a.sym[ubase[cc] + ((uint64_t(lz >> 1) * My + (ly >> 1)) * Mx + (lx >> 1))] = uint16_t(sy);
-        if (a.cur) a.cur[gi] = rv;
-        if (sy == R)
-          ++n_center;
-        else
-          atomicAdd(&h[sy], 1u);
+      } else {
+        for (int i = tid; i < cnt; i += blockDim.x) {
+          const int j = i / run, t = i - j * run;
+          const int vz = t / My, vy = t - vz * My;
+          dst[uint64_t(j) * cstride + t] = ssym[((c - 1) * S::HZ + vz) * m * m + vy * m + j];
+        }
       }
     }
     __syncthreads();
@@ -244,9 +329,23 @@ __global__ __launch_bounds__(256) void k_lanelen(LaneLenArgs a) {
     const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1];
     Mx = ug.M[2];
     if (j < Mx) {
-      const uint64_t base = uint64_t(unit_sym_off(a.g, a.logs, u));
-      for (uint32_t t = 0; t < rows; ++t) {
-        const uint16_t s = a.sym[base + uint64_t(t) * Mx + j];
+      const uint16_t* col = a.sym + uint64_t(unit_sym_off(a.g, a.logs, u)) + uint64_t(j) * rows;
+      uint32_t t = 0;
+      if ((reinterpret_cast<uintptr_t>(col) & 15) == 0) {
+        const uint4* c4 = reinterpret_cast<const uint4*>(col);
+        for (; t + 8 <= rows; t += 8) {
+          const uint4 w = c4[t >> 3];
+          const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t s0 = v[k] & 0xFFFFu, s1 = v[k] >> 16;
+            bits += L[s0] + L[s1];
+            no += (s0 == 0) + (s1 == 0);
+          }
+        }
+      }
+      for (; t < rows; ++t) {
+        const uint16_t s = col[t];
         bits += L[s];
         no += (s == 0);
       }
@@ -524,8 +623,8 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs a) {
   const uint64_t base = uint64_t(unit_sym_off(a.g, a.logs, u));
   const uint64_t segmask = (m >= 64 ? ~uint64_t(0) : ((uint64_t(1) << m) - 1)) << (lane - j);
   const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-  for (uint32_t t = 0; t < rows; ++t) {
-    const uint16_t s = act ? a.sym[base + uint64_t(t) * Mx + j] : uint16_t(1);
+  const uint16_t* col = a.sym + base + uint64_t(j) * rows;
+  auto step = [&](uint32_t s, uint32_t t) {
     if (act) {
       const uint32_t len = Ls[s], cw = Cs[s];
       const uint32_t o = uint32_t(pos & 31);
@@ -554,7 +653,25 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs a) {
       outv[uo + run + __popcll(mk & lt_mask)] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
     }
     run += __popcll(mk);
+  };
+  // Rows in lockstep across the unit's lanes (the outlier ballot needs it);
+  // 8 symbols per 16-byte load when the column is aligned, which holds for
+  // every lane of a unit or for none.
+  uint32_t t = 0;
+  if ((reinterpret_cast<uintptr_t>(a.sym + base + uint64_t(0) * rows) & 15) == 0 && (rows & 7) == 0) {
+    const uint4* c4 = reinterpret_cast<const uint4*>(col);
+    for (; t < rows; t += 8) {
+      const uint4 w = act ? c4[t >> 3] : make_uint4(0x00010001u, 0x00010001u, 0x00010001u,
+                                                    0x00010001u);
+      const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        step(v[k] & 0xFFFFu, t + 2 * k);
+        step(v[k] >> 16, t + 2 * k + 1);
+      }
+    }
   }
+  for (; t < rows; ++t) step(act ? col[t] : uint16_t(1), t);
   if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
 }
 

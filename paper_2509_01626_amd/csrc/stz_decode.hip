@@ -36,6 +36,66 @@ struct DecSlabArgs {
   uint32_t* flags;
 };
 
+// Per-slab state for reconstructing rows of one parity type.
+struct DecRows {
+  const float* tile;
+  const uint16_t* symb;
+  const uint32_t* uo0;
+  const uint32_t* uo1;
+  const float* outv;
+  uint32_t* flags;
+  float* cur;
+  int64_t oz, oy, ox;
+  int z0, a0, Ex, rz0, rz1, ry0, ry1, rx0, rx1;
+  int64_t of[3], oc[3], n[3];
+  float E2;
+  int R;
+};
+
+// Value of one point of class C (0 = copy of a coarse point).
+template <int E, int C, bool INT>
+__device__ inline float dec_point(const DecRows& x, int lz, int ly, int lx, int srow,
+                                  const int64_t p[3]) {
+  using S = SlabShape<E>;
+  constexpr int m = S::m;
+  if constexpr (C == 0) {
+    return x.tile[((((lz - x.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
+  } else {
+    const uint16_t e = x.symb[(C - 1) * (S::HZ * m * m) + srow];
+    if (e & 0x8000u) {
+      const uint64_t oi = uint64_t(x.uo0[C]) + (e & 0x7FFFu);
+      if (oi < x.uo1[C]) return x.outv[oi];
+      atomicOr(x.flags, kFlagCorrupt);
+      return 0.0f;
+    }
+    const float pred = tile_pred<E, C, INT>(x.tile, lz - x.z0, ly, lx, p, x.n);
+    const float prod = (float)(int(e) - x.R) * x.E2;
+    return pred + prod;
+  }
+}
+
+// Reconstruct this wave's rows of parity type (ZP, YP): classes 4ZP+2YP (even
+// x) and 4ZP+2YP+1 (odd x), both fixed at compile time.
+template <int E, int ZP, int YP, bool INT>
+__device__ inline void dec_type(const DecRows& x, int hs, int Ey, int wave, int lane) {
+  using S = SlabShape<E>;
+  constexpr int m = S::m;
+  constexpr int C0 = 4 * ZP + 2 * YP;
+  for_type_rows<E, ZP, YP>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
+    if (lz < x.rz0 || lz >= x.rz1 || ly < x.ry0 || ly >= x.ry1) return;
+    float* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + ly - x.of[1])) * x.oc[2] +
+                  (x.ox - x.of[2]);
+    const int srow = (((lz >> 1) - x.a0) * m + (ly >> 1)) * m + q;
+    const int l0 = 2 * q, l1 = 2 * q + 1;
+    const int64_t p0[3] = {x.oz + lz, x.oy + ly, x.ox + l0};
+    const int64_t p1[3] = {x.oz + lz, x.oy + ly, x.ox + l1};
+    if (l0 < x.Ex && l0 >= x.rx0 && l0 < x.rx1)
+      orow[l0] = dec_point<E, C0, INT>(x, lz, ly, l0, srow, p0);
+    if (l1 < x.Ex && l1 >= x.rx0 && l1 < x.rx1)
+      orow[l1] = dec_point<E, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+  });
+}
+
 template <int E>
 __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
   using S = SlabShape<E>;
@@ -116,14 +176,17 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
     pos = uint64_t(w0) * 32 + pre;
   }
   // Bit window: `buf` holds `nb` valid bits, left aligned; `wi` = next word.
+  // `nxt` is the word after the window, loaded one refill ahead.
   uint64_t wi = pos >> 5, buf = 0;
   int nb = 0;
+  uint32_t nxt = 0;
   if (alive) {
     const uint32_t w = wi < a.words ? a.pay[wi] : 0;
     ++wi;
     const int sk = int(pos & 31);
     buf = (uint64_t(w) << 32) << sk;
     nb = 32 - sk;
+    nxt = wi < a.words ? a.pay[wi] : 0;
   }
   uint32_t used = 0, run = 0;
   bool bad = false;
@@ -146,34 +209,31 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
     // ---- decode this slab's rows into LDS -----------------------------------
     if (lane_active) {
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
+      int vz = a0, vy = 0;  // row r = vz*My + vy, advanced incrementally
       for (int r = r0; r < r1; ++r) {
-        int sy = 1;
-        if (alive) {
-          if (nb < kLmax) {
-            const uint32_t w = wi < a.words ? a.pay[wi] : 0;
-            ++wi;
-            buf |= uint64_t(w) << (32 - nb);
-            nb += 32;
-          }
-          const uint16_t e = lut[buf >> (64 - kLutBits)];
-          const int len = e >> 12;
-          if (len == 0 || used + len > lb) {
-            alive = false;
-            bad = true;
-          } else {
-            sy = e & 4095;
-            buf <<= len;
-            nb -= len;
-            used += len;
-          }
+        if (nb < kLmax) {
+          buf |= uint64_t(nxt) << (32 - nb);
+          nb += 32;
+          ++wi;
+          nxt = wi < a.words ? a.pay[wi] : 0;
         }
-        const bool is_out = alive && sy == 0;
+        const uint16_t e = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
+        const int len = e >> 12;
+        const int sy = e & 4095;
+        bad |= len == 0;  // not a code of the book; lane totals are checked at the end
+        buf <<= len;
+        nb -= len;
+        used += len;
+        const bool is_out = sy == 0 && len != 0;
         const uint64_t mk = __ballot(is_out) & segmask;
         uint16_t st = uint16_t(sy);
         if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
         run += __popcll(mk);
-        const int vz = r / My, vy = r - vz * My;
         symb[((c - 1) * S::HZ + (vz - a0)) * m * m + vy * m + j] = st;
+        if (++vy == My) {
+          vy = 0;
+          ++vz;
+        }
       }
     }
     // ---- coarse tile of the slab ----------------------------------------------
@@ -182,44 +242,43 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
     __syncthreads();
     // ---- reconstruct the slab ------------------------------------------------------
     const int hs = min(S::H, Ez - z0);
-    const int ntask = hs * S::TASKS_PER_Z;
-    for (int task = wave; task < ntask; task += 4) {
-      const int lz = z0 + task / S::TASKS_PER_Z;
-      const int rem = task % S::TASKS_PER_Z, par = rem / S::G, g = rem % S::G;
-      const int ly = par + 2 * (g * S::RW + lane / S::P);
-      const int q = lane % S::P;
-      if (lane / S::P >= S::RW || ly >= Ey || lz < rz0 || lz >= rz1 || ly < ry0 || ly >= ry1)
-        continue;
-      for (int h = 0; h < 2; ++h) {
-        const int lx = 2 * q + h;
-        if (lx >= Ex || lx < rx0 || lx >= rx1) continue;
-        const int o[3] = {lz & 1, ly & 1, h};
-        const int cc = 4 * o[0] + 2 * o[1] + o[2];
-        float val;
-        if (cc == 0) {
-          val = tile[((((lz - z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
-        } else {
-          const uint16_t e =
-              symb[((cc - 1) * S::HZ + (lz >> 1) - a0) * m * m + (ly >> 1) * m + (lx >> 1)];
-          if (e & 0x8000u) {
-            const uint64_t oi = uint64_t(uo0[cc]) + (e & 0x7FFFu);
-            if (oi < uo1[cc]) {
-              val = a.outv[oi];
-            } else {
-              val = 0.0f;
-              atomicOr(a.flags, kFlagCorrupt);
-            }
-          } else {
-            const int64_t p[3] = {oz + lz, oy + ly, ox + lx};
-            const float pred = slab_predict<E>(tile, cc, lz - z0, ly, lx, p, a.n, interior);
-            const float prod = (float)(int(e) - a.g.R) * a.E2;
-            val = pred + prod;
-          }
-        }
-        a.cur[((oz + lz - a.out_first[0]) * a.out_cnt[1] + (oy + ly - a.out_first[1])) *
-                  a.out_cnt[2] +
-              (ox + lx - a.out_first[2])] = val;
-      }
+    DecRows ctx;
+    ctx.tile = tile;
+    ctx.symb = symb;
+    ctx.uo0 = uo0;
+    ctx.uo1 = uo1;
+    ctx.outv = a.outv;
+    ctx.flags = a.flags;
+    ctx.cur = a.cur;
+    ctx.oz = oz;
+    ctx.oy = oy;
+    ctx.ox = ox;
+    ctx.z0 = z0;
+    ctx.a0 = a0;
+    ctx.Ex = Ex;
+    ctx.rz0 = rz0;
+    ctx.rz1 = rz1;
+    ctx.ry0 = ry0;
+    ctx.ry1 = ry1;
+    ctx.rx0 = rx0;
+    ctx.rx1 = rx1;
+    for (int d = 0; d < 3; ++d) {
+      ctx.of[d] = a.out_first[d];
+      ctx.oc[d] = a.out_cnt[d];
+      ctx.n[d] = a.n[d];
+    }
+    ctx.E2 = a.E2;
+    ctx.R = a.g.R;
+    if (interior) {
+      dec_type<E, 0, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, 0, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, 1, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, 1, 1, true>(ctx, hs, Ey, wave, lane);
+    } else {
+      dec_type<E, 0, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, 0, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, 1, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, 1, 1, false>(ctx, hs, Ey, wave, lane);
     }
     __syncthreads();
   }
@@ -227,7 +286,7 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
     if (used != lb) bad = true;
     if (j == 0 && uok[c] && run != uo1[c] - uo0[c]) bad = true;
   }
-  if (bad) atomicOr(a.flags, kFlagCorrupt);
+  if (bad && lane_active && alive) atomicOr(a.flags, kFlagCorrupt);
 }
 
 // Anchors of the box R_0 from the stream into the level-0 box grid.

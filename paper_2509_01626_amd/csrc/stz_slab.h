@@ -100,7 +100,9 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
   const int bz = OZ ? (wz - 1) >> 1 : (wz >> 1) + 1;
   const int by = OY ? (wy - 1) >> 1 : (wy >> 1) + 1;
   const int bx = OX ? (wx - 1) >> 1 : (wx >> 1) + 1;
-  // v(i, j, k): offset indices along the odd axes in order z, y, x.
+  // v(i, j, k): offset indices along the odd axes in order z, y, x; the tap
+  // offsets are compile-time constants relative to one base address.
+  const float* tb = tile + (bz * T + by) * T + bx;
   auto v = [&](int i, int j, int k) {
     int o[3] = {0, 0, 0};
     int q = 0;
@@ -108,7 +110,7 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
     if constexpr (OZ) o[0] = idx[q++];
     if constexpr (OY) o[1] = idx[q++];
     if constexpr (OX) o[2] = idx[q++];
-    return tile[((bz + o[0]) * T + (by + o[1])) * T + (bx + o[2])];
+    return tb[(o[0] * T + o[1]) * T + o[2]];
   };
   // availability flags of the odd axes, in order
   bool P1[3] = {true, true, true}, M3[3] = {true, true, true}, P3[3] = {true, true, true};
@@ -219,6 +221,32 @@ __device__ inline float slab_predict(const float* tile, int cc, int wz, int wy, 
                       : tile_pred<E, 7, false>(tile, wz, wy, wx, p, n);
   }
 #undef STZ_CASE
+}
+
+}  // namespace
+}  // namespace dev
+}  // namespace stz
+
+namespace stz {
+namespace dev {
+namespace {
+
+// Rows of parity type (ZP, YP) in the slab [z0, z0 + hs) assigned to this
+// wave: calls f(lz, ly, q) for the thread's (even, odd) x pair q of each row.
+// Every type has the same number of rows, so the four waves stay balanced.
+template <int E, int ZP, int YP, class F>
+__device__ inline void for_type_rows(int z0, int hs, int Ey, int wave, int lane, F f) {
+  using S = SlabShape<E>;
+  const int nz = (hs - ZP + 1) >> 1;  // planes of parity ZP in the slab
+  const int ntask = nz * S::G;
+  const int r = lane / S::P, q = lane % S::P;
+  if (r >= S::RW) return;
+  for (int t = wave; t < ntask; t += 4) {
+    const int iz = t / S::G, g = t - iz * S::G;
+    const int lz = z0 + ZP + 2 * iz;
+    const int ly = YP + 2 * (g * S::RW + r);
+    if (ly < Ey) f(lz, ly, q);
+  }
 }
 
 }  // namespace
