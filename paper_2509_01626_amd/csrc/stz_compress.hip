@@ -153,14 +153,14 @@ __device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int
   using S = SlabShape<E>;
   constexpr int m = S::m;
   if constexpr (C == 0) {
-    if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
+    if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
     const float xv = xrow[lx << c.ls];
     *bad |= !isfinite(xv);
     const float pred = tile_pred<E, C, INT>(c.tile, lz - c.z0, ly, lx, p, c.n);
     float rv;
     const int sy = quantize(xv, pred, c.E2, c.INV, c.e, c.R, &rv);
-    c.ssym[(C - 1) * (S::HZ * m * m) + srow] = uint16_t(sy);
+    c.ssym[(C - 1) * S::SCP + srow] = uint16_t(sy);
     if (grow) grow[lx] = rv;
     if (sy == c.R)
       ++*n_center;
@@ -180,7 +180,7 @@ __device__ inline void pred_type(const PredRows& c, int hs, int Ey, int wave, in
     float* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
     const float* xrow =
         c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);
-    const int srow = (((lz - c.z0) >> 1) * m + (ly >> 1)) * m + q;
+    const int srow = (((lz - c.z0) >> 1) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {c.oz + lz, c.oy + ly, c.ox + l0};
     const int64_t p1[3] = {c.oz + lz, c.oy + ly, c.ox + l1};
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
   constexpr int m = S::m;
   __shared__ uint32_t h[2 * kMaxRadius];
   __shared__ float tile[S::TILE];
-  __shared__ uint16_t ssym[7 * S::HZ * m * m];  // slab symbols, [class][v_z][v_y][v_x]
+  __shared__ uint16_t ssym[7 * S::SCP];  // slab symbols, [class][v_z][v_y][v_x] (padded)
   __shared__ uint64_t ubase[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
   bool bad = false;
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;
-    load_tile<E>(tile, a.prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    load_tile<S>(tile, a.prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
     __syncthreads();
     const int hs = min(S::H, Ez - z0);
     PredRows ctx;
@@ -275,13 +275,13 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
         for (int i = tid; i < cnt; i += blockDim.x) {
           const int j = i >> LRUN, t = i & ((1 << LRUN) - 1);
           const int vz = t >> LMY, vy = t & (m - 1);
-          dst[uint64_t(j) * cstride + t] = ssym[((c - 1) * S::HZ + vz) * m * m + vy * m + j];
+          dst[uint64_t(j) * cstride + t] = ssym[(c - 1) * S::SCP + (vz * m + vy) * S::SP + j];
         }
       } else {
         for (int i = tid; i < cnt; i += blockDim.x) {
           const int j = i / run, t = i - j * run;
           const int vz = t / My, vy = t - vz * My;
-          dst[uint64_t(j) * cstride + t] = ssym[((c - 1) * S::HZ + vz) * m * m + vy * m + j];
+          dst[uint64_t(j) * cstride + t] = ssym[(c - 1) * S::SCP + (vz * m + vy) * S::SP + j];
         }
       }
     }

@@ -52,16 +52,21 @@ struct DecRows {
   int R;
 };
 
+// Slab height of the decoder: for 32^3-point blocks, 4 planes keep the LDS
+// footprint (code table, slab symbols, coarse tile, stream ring) small enough
+// for four work-groups per CU.
+constexpr int dec_slab_h(int E) { return E == 32 ? 4 : default_slab_h(E); }
+
 // Value of one point of class C (0 = copy of a coarse point).
-template <int E, int C, bool INT>
+template <int E, int H, int C, bool INT>
 __device__ inline float dec_point(const DecRows& x, int lz, int ly, int lx, int srow,
                                   const int64_t p[3]) {
-  using S = SlabShape<E>;
+  using S = SlabShape<E, H>;
   constexpr int m = S::m;
   if constexpr (C == 0) {
-    return x.tile[((((lz - x.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::T + (lx >> 1) + 1];
+    return x.tile[((((lz - x.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
-    const uint16_t e = x.symb[(C - 1) * (S::HZ * m * m) + srow];
+    const uint16_t e = x.symb[(C - 1) * S::SCP + srow];
     if (e & 0x8000u) {
       const uint64_t oi = uint64_t(x.uo0[C]) + (e & 0x7FFFu);
       if (oi < x.uo1[C]) return x.outv[oi];
@@ -76,34 +81,43 @@ __device__ inline float dec_point(const DecRows& x, int lz, int ly, int lx, int 
 
 // Reconstruct this wave's rows of parity type (ZP, YP): classes 4ZP+2YP (even
 // x) and 4ZP+2YP+1 (odd x), both fixed at compile time.
-template <int E, int ZP, int YP, bool INT>
+template <int E, int H, int ZP, int YP, bool INT>
 __device__ inline void dec_type(const DecRows& x, int hs, int Ey, int wave, int lane) {
-  using S = SlabShape<E>;
+  using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
   for_type_rows<E, ZP, YP>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
     if (lz < x.rz0 || lz >= x.rz1 || ly < x.ry0 || ly >= x.ry1) return;
     float* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + ly - x.of[1])) * x.oc[2] +
                   (x.ox - x.of[2]);
-    const int srow = (((lz >> 1) - x.a0) * m + (ly >> 1)) * m + q;
+    const int srow = (((lz >> 1) - x.a0) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {x.oz + lz, x.oy + ly, x.ox + l0};
     const int64_t p1[3] = {x.oz + lz, x.oy + ly, x.ox + l1};
     if (l0 < x.Ex && l0 >= x.rx0 && l0 < x.rx1)
-      orow[l0] = dec_point<E, C0, INT>(x, lz, ly, l0, srow, p0);
+      orow[l0] = dec_point<E, H, C0, INT>(x, lz, ly, l0, srow, p0);
     if (l1 < x.Ex && l1 >= x.rx0 && l1 < x.rx1)
-      orow[l1] = dec_point<E, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+      orow[l1] = dec_point<E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
   });
 }
 
 template <int E>
 __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
-  using S = SlabShape<E>;
+  constexpr int H = dec_slab_h(E);
+  using S = SlabShape<E, H>;
   constexpr int m = S::m;
+  constexpr int NL = 7 * m;  // decoding lanes: one per (class, x column)
+  // Stream words a lane can touch while decoding one slab: at most HZ*m codes
+  // of <= kLmax bits, plus the bit window's lookahead (< 2 words).
+  constexpr int WPL = (S::HZ * m * kLmax + 31) / 32 + 2;
+  // Per-lane ring of 2*WPL stream words, [slot][lane]: the words of the
+  // current slab plus the prefetched words of the next one.
+  constexpr int RB = 2 * WPL;
   __shared__ uint16_t lut[1 << kLutBits];
-  __shared__ uint16_t symb[7 * S::HZ * m * m];
+  __shared__ uint16_t symb[7 * S::SCP];
   __shared__ float tile[S::TILE];
-  __shared__ uint32_t lanelen_s[7 * m];
+  __shared__ uint32_t ring[RB * NL];
+  __shared__ uint32_t lanelen_s[NL];
   __shared__ uint32_t uo0[8], uo1[8];
   __shared__ int uok[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -128,7 +142,7 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
 
   // ---- decode setup: lane t < 7m handles class c = t/m + 1, column j ------
   const int c = tid / m + 1, j = tid % m;
-  const bool is_lane = tid < 7 * m;
+  const bool is_lane = tid < NL;
   const int ocz = (c >> 2) & 1, ocy = (c >> 1) & 1, ocx = c & 1;
   const int Mz = ocz ? Ez >> 1 : (Ez + 1) >> 1;
   const int My = ocy ? Ey >> 1 : (Ey + 1) >> 1;
@@ -144,10 +158,11 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
       needed = needed && v0 < v1;
     }
   }
+  const bool lane_active = is_lane && needed && j < Mx;
   const int64_t u = blk * 7 + (c - 1);
   uint32_t lb = 0;
   uint64_t pos = 0;
-  if (is_lane && needed && j < Mx) {
+  if (lane_active) {
     const uint64_t lane0 = uint64_t(unit_lane_off(a.g, a.logs, u));
     lb = lane0 + j < a.nlanes ? a.lane_len[lane0 + j] : 0;
   }
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
   if (tid < 8) uok[tid] = 1;
   __syncthreads();
   bool alive = false;
-  if (is_lane && needed && j < Mx) {
+  if (lane_active) {
     uint32_t pre = 0, tot = 0;
     for (int k = 0; k < Mx; ++k) {
       const uint32_t v = lanelen_s[(c - 1) * m + k];
@@ -167,26 +182,32 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
     const bool ok = w0 <= w1 && w1 <= a.words && o0 <= o1 && o1 <= a.noutl &&
                     (uint64_t(tot) + 31) / 32 == uint64_t(w1 - w0);
     if (j == 0) {
-      uo0[c] = o0;
-      uo1[c] = o1;
+      // An inconsistent unit gets an empty outlier range, so no outlier
+      // index can leave the level's list.
+      uo0[c] = ok ? o0 : 0;
+      uo1[c] = ok ? o1 : 0;
       uok[c] = ok;
     }
     if (!ok) atomicOr(a.flags, kFlagCorrupt);
     alive = ok;
     pos = uint64_t(w0) * 32 + pre;
   }
-  // Bit window: `buf` holds `nb` valid bits, left aligned; `wi` = next word.
-  // `nxt` is the word after the window, loaded one refill ahead.
+  // Bit window: `buf` holds `nb` valid bits, left aligned; `wi` = next stream
+  // word, found in ring slot `rk`. Slot of word w = (w - first word) mod RB.
+  // Before each slab the ring holds the WPL words from `wi` on.
   uint64_t wi = pos >> 5, buf = 0;
-  int nb = 0;
-  uint32_t nxt = 0;
-  if (alive) {
-    const uint32_t w = wi < a.words ? a.pay[wi] : 0;
-    ++wi;
+  int nb = 0, rk = 0;
+  if (lane_active) {
+#pragma unroll
+    for (int k = 0; k <= WPL; ++k) {
+      const uint64_t idx = wi + k;
+      ring[k * NL + tid] = (alive && idx < a.words) ? a.pay[idx] : 0u;
+    }
     const int sk = int(pos & 31);
-    buf = (uint64_t(w) << 32) << sk;
+    buf = (uint64_t(ring[tid]) << 32) << sk;
     nb = 32 - sk;
-    nxt = wi < a.words ? a.pay[wi] : 0;
+    ++wi;
+    rk = 1;
   }
   uint32_t used = 0, run = 0;
   bool bad = false;
@@ -194,7 +215,6 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
   const int seg = lane - j;
   const uint64_t segmask = (m >= 64 ? ~uint64_t(0) : ((uint64_t(1) << m) - 1)) << seg;
   const uint64_t ltmask = (uint64_t(1) << lane) - 1;
-  const bool lane_active = is_lane && needed && j < Mx;
 
   const int64_t org[3] = {oz, oy, ox};
   const bool interior = block_interior(org, E, a.n);
@@ -206,16 +226,30 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
       break;
     }
     const int a0 = z0 >> 1;
+    // ---- coarse tile of the slab (global loads in flight during decoding) ----
+    const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;  // level coords, even
+    TileRegs<S> tr;
+    tile_fetch<S>(tr, a.prev, a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1, tx0 >> 1);
     // ---- decode this slab's rows into LDS -----------------------------------
     if (lane_active) {
+      // Prefetch the WPL words after this slab's window into registers; they
+      // land in the ring once the slab is decoded.
+      const uint64_t wb = wi;
+      const int rb = rk;
+      uint32_t pf[WPL];
+#pragma unroll
+      for (int k = 0; k < WPL; ++k) {
+        const uint64_t idx = wb + WPL + k;
+        pf[k] = (alive && idx < a.words) ? a.pay[idx] : 0u;
+      }
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
       int vz = a0, vy = 0;  // row r = vz*My + vy, advanced incrementally
       for (int r = r0; r < r1; ++r) {
         if (nb < kLmax) {
-          buf |= uint64_t(nxt) << (32 - nb);
+          buf |= uint64_t(ring[rk * NL + tid]) << (32 - nb);
           nb += 32;
           ++wi;
-          nxt = wi < a.words ? a.pay[wi] : 0;
+          if (++rk == RB) rk = 0;
         }
         const uint16_t e = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
         const int len = e >> 12;
@@ -229,16 +263,21 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
         uint16_t st = uint16_t(sy);
         if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
         run += __popcll(mk);
-        symb[((c - 1) * S::HZ + (vz - a0)) * m * m + vy * m + j] = st;
+        symb[(c - 1) * S::SCP + ((vz - a0) * m + vy) * S::SP + j] = st;
         if (++vy == My) {
           vy = 0;
           ++vz;
         }
       }
+      int sl = rb + WPL;
+      if (sl >= RB) sl -= RB;
+#pragma unroll
+      for (int k = 0; k < WPL; ++k) {
+        ring[sl * NL + tid] = pf[k];
+        if (++sl == RB) sl = 0;
+      }
     }
-    // ---- coarse tile of the slab ----------------------------------------------
-    const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;  // level coords, even
-    load_tile<E>(tile, a.prev, a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    tile_store<S>(tile, tr);
     __syncthreads();
     // ---- reconstruct the slab ------------------------------------------------------
     const int hs = min(S::H, Ez - z0);
@@ -270,15 +309,15 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
     ctx.E2 = a.E2;
     ctx.R = a.g.R;
     if (interior) {
-      dec_type<E, 0, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<E, 0, 1, true>(ctx, hs, Ey, wave, lane);
-      dec_type<E, 1, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<E, 1, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 0, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 0, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 1, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 1, 1, true>(ctx, hs, Ey, wave, lane);
     } else {
-      dec_type<E, 0, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<E, 0, 1, false>(ctx, hs, Ey, wave, lane);
-      dec_type<E, 1, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<E, 1, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 0, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 0, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 1, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<E, H, 1, 1, false>(ctx, hs, Ey, wave, lane);
     }
     __syncthreads();
   }
@@ -370,7 +409,7 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
     prof_end(st);
     const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
     const int E = g.B >> logs;
-    prof_begin(st, "decode", k);
+    prof_begin(st, full ? "decode" : "rdecode", k);
     switch (E) {
       case 2: launch_slab<2>(d, nblk, st); break;
       case 4: launch_slab<4>(d, nblk, st); break;

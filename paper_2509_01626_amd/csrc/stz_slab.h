@@ -19,14 +19,22 @@ namespace stz {
 namespace dev {
 namespace {
 
-template <int E>
+// Default slab height (level planes) for block edge E.
+constexpr int default_slab_h(int E) { return E >= 64 ? 2 : (E == 32 ? 8 : E); }
+
+template <int E, int HH = default_slab_h(E)>
 struct SlabShape {
   static constexpr int m = E / 2;                          // class sub-grid extent
-  static constexpr int H = E >= 64 ? 2 : (E == 32 ? 8 : E);  // level planes per slab
+  static constexpr int H = HH;                             // level planes per slab
   static constexpr int HZ = H / 2;                         // class rows (v_z) per slab
   static constexpr int T = m + 3;                          // coarse tile extent, x and y
   static constexpr int TZ = HZ + 3;                        // coarse tile planes
-  static constexpr int TILE = TZ * T * T;
+  static constexpr int TP = T;  // tile row pitch (floats)
+  static constexpr int TILE = TZ * T * TP;
+  // Symbol staging: row pitch m+2 u16 (an odd number of 32-bit words for
+  // m >= 4) and an 8-word skew between classes.
+  static constexpr int SP = m + 2;
+  static constexpr int SCP = HZ * m * SP + 16;
   static constexpr int P = m;                              // (even, odd) pairs per row
   static constexpr int RW = 64 / P < 1 ? 1 : 64 / P;       // rows per wave task
   static constexpr int G = (m + RW - 1) / RW;              // row groups per parity
@@ -44,17 +52,53 @@ __device__ inline int64_t wg_block(int64_t wg, int64_t nblocks, bool xcd_remap) 
 // Load the coarse tile of a slab: level-(l-1) points (coarse coordinates
 // cz0 + tz, cy0 + ty, cx0 + tx) inside the source grid box; others are zero
 // and never read by a stencil whose flags allow them.
-template <int E>
+template <class S>
 __device__ inline void load_tile(float* tile, const float* __restrict__ src, const int64_t sf[3],
                                  const int64_t sc[3], int64_t cz0, int64_t cy0, int64_t cx0) {
-  using S = SlabShape<E>;
-  for (int i = threadIdx.x; i < S::TILE; i += blockDim.x) {
+  for (int i = threadIdx.x; i < S::TZ * S::T * S::T; i += blockDim.x) {
     const int tx = i % S::T, r = i / S::T, ty = r % S::T, tz = r / S::T;
     const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
     float v = 0.0f;
     if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
       v = src[(cz * sc[1] + cy) * sc[2] + cx];
-    tile[i] = v;
+    tile[r * S::TP + tx] = v;
+  }
+}
+
+// The same tile in two halves: fetch this thread's share of the tile into
+// registers (256 threads), then store it, so that other work can run while
+// the loads are in flight.
+template <class S>
+struct TileRegs {
+  static constexpr int N = S::TZ * S::T * S::T;
+  static constexpr int K = (N + 255) / 256;
+  float v[K];
+};
+
+template <class S>
+__device__ inline void tile_fetch(TileRegs<S>& r, const float* __restrict__ src,
+                                  const int64_t sf[3], const int64_t sc[3], int64_t cz0,
+                                  int64_t cy0, int64_t cx0) {
+#pragma unroll
+  for (int k = 0; k < TileRegs<S>::K; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    float v = 0.0f;
+    if (i < TileRegs<S>::N) {
+      const int tx = i % S::T, t = i / S::T, ty = t % S::T, tz = t / S::T;
+      const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
+      if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
+        v = src[(cz * sc[1] + cy) * sc[2] + cx];
+    }
+    r.v[k] = v;
+  }
+}
+
+template <class S>
+__device__ inline void tile_store(float* tile, const TileRegs<S>& r) {
+#pragma unroll
+  for (int k = 0; k < TileRegs<S>::K; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < TileRegs<S>::N) tile[(i / S::T) * S::TP + i % S::T] = r.v[k];
   }
 }
 
@@ -94,7 +138,7 @@ __device__ inline float nest_rule(bool p1, bool m3, F f) {
 template <int E, int C, bool FULL>
 __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, const int64_t p[3],
                                   const int64_t n[3]) {
-  constexpr int T = SlabShape<E>::T;
+  constexpr int T = SlabShape<E>::T, TP = SlabShape<E>::TP;
   constexpr bool OZ = (C >> 2) & 1, OY = (C >> 1) & 1, OX = C & 1;
   constexpr int ND = int(OZ) + int(OY) + int(OX);
   const int bz = OZ ? (wz - 1) >> 1 : (wz >> 1) + 1;
@@ -102,7 +146,7 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
   const int bx = OX ? (wx - 1) >> 1 : (wx >> 1) + 1;
   // v(i, j, k): offset indices along the odd axes in order z, y, x; the tap
   // offsets are compile-time constants relative to one base address.
-  const float* tb = tile + (bz * T + by) * T + bx;
+  const float* tb = tile + (bz * T + by) * TP + bx;
   auto v = [&](int i, int j, int k) {
     int o[3] = {0, 0, 0};
     int q = 0;
@@ -110,7 +154,7 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
     if constexpr (OZ) o[0] = idx[q++];
     if constexpr (OY) o[1] = idx[q++];
     if constexpr (OX) o[2] = idx[q++];
-    return tb[(o[0] * T + o[1]) * T + o[2]];
+    return tb[(o[0] * T + o[1]) * TP + o[2]];
   };
   // availability flags of the odd axes, in order
   bool P1[3] = {true, true, true}, M3[3] = {true, true, true}, P3[3] = {true, true, true};
@@ -199,28 +243,6 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
       });
     });
   }
-}
-
-// Class dispatch (the class is uniform across a wave at each call site).
-template <int E>
-__device__ inline float slab_predict(const float* tile, int cc, int wz, int wy, int wx,
-                                     const int64_t p[3], const int64_t n[3], bool interior) {
-#define STZ_CASE(C)                                                   \
-  case C:                                                             \
-    return interior ? tile_pred<E, C, true>(tile, wz, wy, wx, p, n)   \
-                    : tile_pred<E, C, false>(tile, wz, wy, wx, p, n);
-  switch (cc) {
-    STZ_CASE(1)
-    STZ_CASE(2)
-    STZ_CASE(3)
-    STZ_CASE(4)
-    STZ_CASE(5)
-    STZ_CASE(6)
-    default:
-      return interior ? tile_pred<E, 7, true>(tile, wz, wy, wx, p, n)
-                      : tile_pred<E, 7, false>(tile, wz, wy, wx, p, n);
-  }
-#undef STZ_CASE
 }
 
 }  // namespace
