@@ -35,12 +35,64 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel events in the timed region")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
+COPY_PROBE_BYTES = 1 << 30
+
+
+def copy_probe():
+    """A plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE of
+    this kernel against its 1 GiB read and 1 GiB write give the factor that
+    turns those counters into HBM bytes."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES}), flush=True)
+
+
+def kernel_sources_digest():
+    """Digest of the sources of the device kernels (counters recorded for an
+    older digest no longer describe the built kernels)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2509_01626_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel_key):
+    """HBM bytes per launch of `kernel_key` from the committed counter summary
+    (profiles/traffic_512cube.txt), or None when it was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_512cube.txt")
+    try:
+        with open(path) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    digest = None
+    for ln in lines:
+        if ln.startswith("sources_digest:"):
+            digest = ln.split(":", 1)[1].strip()
+    if digest != kernel_sources_digest():
+        return None
+    for ln in lines:
+        if ln.startswith("traffic " + kernel_key + " "):
+            return int(ln.split()[2])
+    return None
+
+
 def kernel_bytes(name, level, info, lvl_tab, N):
-    """Algorithmic bytes one launch of a kernel must move (see the design
-    notes): inputs it has to read and outputs it has to write, counted once."""
+    """Algorithmic bytes one launch of a kernel must move: the inputs it has to
+    read and the outputs it has to write, each counted once."""
     L = info.levels
     dims = [int(v) for v in info.dims]
 
@@ -84,6 +136,9 @@ def level_table(comp_host):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
@@ -197,7 +252,7 @@ def main():
             ach = b / (ms / n * 1e-3) / 1e9
             roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "traffic": None, "bytes_per_launch": int(b),
+                        "traffic": recorded_traffic(dom), "bytes_per_launch": int(b),
                         "avg_us": round(ms / n * 1e3, 2), "device_ms_per_step": round(tot / K, 3)}
 
     cpu = None

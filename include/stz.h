@@ -112,6 +112,15 @@ stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t
                                  const uint64_t hi[3], uint32_t level, float* out,
                                  uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
 
+/* Device scratch (auxiliary): every call takes its scratch from a buffer the
+ * library keeps per (device, stream) and grows on demand, so repeated calls
+ * allocate nothing. Calls on one stream run in stream order and share that
+ * stream's buffer; calls on different streams use different buffers.
+ * stz_trim synchronizes the current device and releases its buffers (for a
+ * process that is done with the library, or before a stream is destroyed and
+ * its handle value reused by another stream would keep a large buffer alive). */
+stz_status stz_trim(void);
+
 /* Stage profiler (auxiliary; off by default, or on with STZ_PROFILE=1):
  * records HIP events on the call's stream around every kernel and
  * accumulates the elapsed time per kernel name and level ("predict@5") when

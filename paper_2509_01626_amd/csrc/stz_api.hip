@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "stz.h"
@@ -90,9 +91,29 @@ void pool_setup() {
   done[dev] = true;
 }
 
-// Stream-ordered scratch: sub-buffers are laid out first (take), then one
-// allocation from the device pool backs all of them (commit); it returns to
-// the pool when the call ends.
+// Device scratch cached per (device, stream): every call on a stream reuses
+// that stream's buffer, growing it when a call needs more. Calls on one stream
+// run in stream order, so they never use the buffer at the same time; the
+// allocation and release calls of the runtime (slow on the host) are paid
+// only when a buffer grows. stz_trim() returns the buffers.
+struct WsCache {
+  std::mutex mu;
+  std::unordered_map<uint64_t, std::pair<char*, uint64_t>> m;  // key -> (buffer, size)
+};
+
+WsCache& ws_cache() {
+  static WsCache* c = new WsCache;  // never destroyed: may be used during exit
+  return *c;
+}
+
+uint64_t ws_key(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  return (reinterpret_cast<uint64_t>(st) << 8) ^ uint64_t(dev & 255);
+}
+
+// Sub-buffers are laid out first (take), then the stream's cached buffer
+// backs all of them (commit).
 struct Workspace {
   hipStream_t st;
   char* base = nullptr;
@@ -105,34 +126,63 @@ struct Workspace {
     return off;
   }
   bool commit() {
-    void* p = nullptr;
-    if (hipMallocAsync(&p, std::max<uint64_t>(size, 256), st) != hipSuccess) return false;
-    base = static_cast<char*>(p);
+    WsCache& c = ws_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto& e = c.m[ws_key(st)];
+    if (e.second < size) {
+      if (e.first) (void)hipFreeAsync(e.first, st);
+      e.first = nullptr;
+      e.second = 0;
+      const uint64_t want = std::max<uint64_t>(size + size / 4, 1 << 20);
+      void* p = nullptr;
+      if (hipMallocAsync(&p, want, st) != hipSuccess) return false;
+      e.first = static_cast<char*>(p);
+      e.second = want;
+    }
+    base = e.first;
     return true;
   }
   template <class T>
   T* at(uint64_t off) const {
     return reinterpret_cast<T*>(base + off);
   }
-  ~Workspace() {
-    if (base) (void)hipFreeAsync(base, st);
+};
+
+// Per-thread pinned host staging for every small copy of a call: the decoder
+// table with the flag reset behind it (host to device), the stream header and
+// the status words (device to host). Pinned memory keeps these copies
+// asynchronous DMA transfers; each call ends with a stream synchronization,
+// after which the area may be reused.
+struct Staging {
+  static constexpr uint64_t kLutBytes = (uint64_t(1) << kLutBits) * 2 + 16;
+  static constexpr uint64_t kHdrBytes = kHeaderBytes + 2 * kMaxRadius;
+  uint8_t* base = nullptr;
+  uint16_t* lut = nullptr;    // 2^kLutBits entries, then 16 zero bytes
+  uint8_t* hdr = nullptr;     // stream header and code lengths
+  DevParams* params = nullptr;
+  uint32_t* flags = nullptr;
+  Staging() {
+    const uint64_t o_hdr = (kLutBytes + 255) & ~uint64_t(255);
+    const uint64_t o_par = (o_hdr + kHdrBytes + 255) & ~uint64_t(255);
+    const uint64_t o_flg = (o_par + sizeof(DevParams) + 255) & ~uint64_t(255);
+    if (hipHostMalloc(reinterpret_cast<void**>(&base), o_flg + 256) != hipSuccess) {
+      base = nullptr;
+      return;
+    }
+    lut = reinterpret_cast<uint16_t*>(base);
+    hdr = base + o_hdr;
+    params = reinterpret_cast<DevParams*>(base + o_par);
+    flags = reinterpret_cast<uint32_t*>(base + o_flg);
+  }
+  ~Staging() {
+    if (base) (void)hipHostFree(base);
   }
 };
 
-// Per-thread pinned staging for the decoder table and the flag reset, so
-// both go to the device in one asynchronous copy. Each decode call ends with
-// a stream synchronization, after which the staging area may be reused.
-struct Staging {
-  uint16_t* lut = nullptr;  // 2^kLutBits entries, then a 32-bit zero word
-  Staging() {
-    if (hipHostMalloc(reinterpret_cast<void**>(&lut), (size_t(1) << kLutBits) * 2 + 16) !=
-        hipSuccess)
-      lut = nullptr;
-  }
-  ~Staging() {
-    if (lut) (void)hipHostFree(lut);
-  }
-};
+Staging* staging() {
+  thread_local Staging stage;
+  return stage.base ? &stage : nullptr;
+}
 
 // Parsed stream header (format 2.5), validated against the geometry.
 struct Header {
@@ -157,12 +207,13 @@ T rd(const uint8_t* p) {
 
 stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* h) {
   if (!comp || size < kHeaderBytes) return STZ_ERR_CORRUPT;
-  const uint64_t want = std::min<uint64_t>(size, kHeaderBytes + 2 * kMaxRadius);
-  std::vector<uint8_t> b(want);
-  if (hipMemcpyAsync(b.data(), comp, want, hipMemcpyDeviceToHost, st) != hipSuccess)
+  const uint64_t want = std::min<uint64_t>(size, Staging::kHdrBytes);
+  Staging* stage = staging();
+  if (!stage) return STZ_ERR_NOMEM;
+  if (hipMemcpyAsync(stage->hdr, comp, want, hipMemcpyDeviceToHost, st) != hipSuccess)
     return STZ_ERR_DEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return STZ_ERR_DEVICE;
-  const uint8_t* p = b.data();
+  const uint8_t* p = stage->hdr;
   if (rd<uint32_t>(p) != kMagic || rd<uint32_t>(p + 4) != kVersion) return STZ_ERR_CORRUPT;
   uint64_t dims[3] = {rd<uint64_t>(p + 8), rd<uint64_t>(p + 16), rd<uint64_t>(p + 24)};
   stz_config cf;
@@ -337,19 +388,19 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   }
   a.lut = dlut;
   a.flags = dflags;
-  thread_local Staging stage;
-  if (!stage.lut) return STZ_ERR_NOMEM;
-  std::memcpy(stage.lut, lut.data(), lut.size() * 2);
-  std::memset(stage.lut + lut.size(), 0, 16);
-  if (hipMemcpyAsync(dlut, stage.lut, lut.size() * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
+  Staging* stage = staging();
+  if (!stage) return STZ_ERR_NOMEM;
+  std::memcpy(stage->lut, lut.data(), lut.size() * 2);
+  std::memset(stage->lut + lut.size(), 0, 16);
+  if (hipMemcpyAsync(dlut, stage->lut, lut.size() * 2 + 16, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
     return STZ_ERR_DEVICE;
   if (launch_decode(a, st) != hipSuccess) return STZ_ERR_DEVICE;
-  uint32_t flags = 0;
-  if (hipMemcpyAsync(&flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(stage->flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
   prof_flush();
-  return flags ? STZ_ERR_CORRUPT : STZ_OK;
+  return *stage->flags ? STZ_ERR_CORRUPT : STZ_OK;
 }
 
 }  // namespace
@@ -358,6 +409,23 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
 using namespace stz;
 
 extern "C" {
+
+stz_status stz_trim(void) {
+  WsCache& c = ws_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (hipDeviceSynchronize() != hipSuccess) return STZ_ERR_DEVICE;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return STZ_ERR_DEVICE;
+  for (auto it = c.m.begin(); it != c.m.end();) {
+    if (int(it->first & 255) == (cur & 255)) {
+      if (it->second.first) (void)hipFreeAsync(it->second.first, nullptr);
+      it = c.m.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return hipDeviceSynchronize() == hipSuccess ? STZ_OK : STZ_ERR_DEVICE;
+}
 
 uint64_t stz_compress_bound(const uint64_t dims[3], const stz_config* cfg) {
   Cfg c;
@@ -438,10 +506,13 @@ stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, dou
   a.scan = ws.at<uint32_t>(o_scan);
   a.scan_part = ws.at<uint64_t>(o_spart);
   if (launch_compress(a, st) != hipSuccess) return STZ_ERR_DEVICE;
-  DevParams P;
-  if (hipMemcpyAsync(&P, a.params, sizeof(P), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  Staging* stage = staging();
+  if (!stage) return STZ_ERR_NOMEM;
+  if (hipMemcpyAsync(stage->params, a.params, sizeof(DevParams), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
+  const DevParams& P = *stage->params;
   prof_flush();
   *out_size = P.total;
   if (P.flags & kFlagNonfinite) return STZ_ERR_NONFINITE;

@@ -151,7 +151,6 @@ __device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int
                                   const float* xrow, float* grow, const int64_t p[3],
                                   uint32_t* n_center, bool* bad) {
   using S = SlabShape<E>;
-  constexpr int m = S::m;
   if constexpr (C == 0) {
     if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {

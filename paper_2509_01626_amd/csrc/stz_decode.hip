@@ -62,7 +62,6 @@ template <int E, int H, int C, bool INT>
 __device__ inline float dec_point(const DecRows& x, int lz, int ly, int lx, int srow,
                                   const int64_t p[3]) {
   using S = SlabShape<E, H>;
-  constexpr int m = S::m;
   if constexpr (C == 0) {
     return x.tile[((((lz - x.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
@@ -243,14 +242,20 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
         pf[k] = (alive && idx < a.words) ? a.pay[idx] : 0u;
       }
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
-      int vz = a0, vy = 0;  // row r = vz*My + vy, advanced incrementally
+      int vy = 0;                        // row r = vz*My + vy, advanced incrementally
+      int so = (c - 1) * S::SCP + j;     // LDS slot of the row's symbol
+      uint32_t nw = ring[rk * NL + tid];  // next stream word (word wi)
       for (int r = r0; r < r1; ++r) {
-        if (nb < kLmax) {
-          buf |= uint64_t(ring[rk * NL + tid]) << (32 - nb);
-          nb += 32;
-          ++wi;
-          if (++rk == RB) rk = 0;
-        }
+        // Branch-free refill: merge the next word when fewer than kLmax
+        // bits are left, then read the following one from the ring.
+        const bool rf = nb < kLmax;
+        const int sh = rf ? 32 - nb : 0;
+        buf |= uint64_t(rf ? nw : 0u) << sh;
+        nb += rf ? 32 : 0;
+        wi += rf ? 1 : 0;
+        rk += rf ? 1 : 0;
+        rk = rk == RB ? 0 : rk;
+        nw = ring[rk * NL + tid];
         const uint16_t e = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
         const int len = e >> 12;
         const int sy = e & 4095;
@@ -259,14 +264,18 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
         nb -= len;
         used += len;
         const bool is_out = sy == 0 && len != 0;
-        const uint64_t mk = __ballot(is_out) & segmask;
+        const uint64_t wm = __ballot(is_out);
         uint16_t st = uint16_t(sy);
-        if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
-        run += __popcll(mk);
-        symb[(c - 1) * S::SCP + ((vz - a0) * m + vy) * S::SP + j] = st;
+        if (wm != 0) {  // wave-uniform: outliers are rare
+          const uint64_t mk = wm & segmask;
+          if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
+          run += __popcll(mk);
+        }
+        symb[so] = st;
+        so += S::SP;
         if (++vy == My) {
           vy = 0;
-          ++vz;
+          so += (m - My) * S::SP;
         }
       }
       int sl = rb + WPL;

@@ -61,6 +61,8 @@ def lib():
         L.stz_decompress_region.restype = C.c_int
         L.stz_decompress_region.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32,
                                             C.c_void_p, C.c_uint64, u64p, C.c_void_p]
+        L.stz_trim.restype = C.c_int
+        L.stz_trim.argtypes = []
         L.stz_status_string.restype = C.c_char_p
         L.stz_status_string.argtypes = [C.c_int]
         _lib = L
@@ -81,6 +83,13 @@ def _dims(shape):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def stz_trim():
+    """Release the library's cached device scratch on the current device."""
+    st = lib().stz_trim()
+    if st != OK:
+        raise StzError(st, "stz_trim")
 
 
 def config(block=32, levels=0, radius=0, eb_ratio=0.0):
