@@ -24,8 +24,9 @@
  *     return a host value (sizes, status of device-side checks) synchronize
  *     the stream once at their end.
  *   - Dims are {nz, ny, nx}, C order, x fastest.
- *   - Internal scratch memory is taken from a stream-ordered pool; the call
- *     returns STZ_ERR_NOMEM when it cannot be obtained.
+ *   - Internal scratch memory is a per-(device, stream) buffer that the
+ *     library grows on demand (see stz_trim); a call returns STZ_ERR_NOMEM
+ *     when it cannot be obtained.
  *   - Errors: STZ_ERR_ARG for invalid arguments, STZ_ERR_NONFINITE when the
  *     input holds NaN or Inf, STZ_ERR_BUFFER when an output capacity is too
  *     small (nothing meaningful is written), STZ_ERR_CORRUPT when a stream
@@ -111,6 +112,88 @@ stz_status stz_decompress_level(const void* comp, uint64_t size, uint32_t level,
 stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
                                  const uint64_t hi[3], uint32_t level, float* out,
                                  uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
+
+/* ---- Batched compression ------------------------------------------------
+ * Many independent fields of any sizes, each with its own bound and
+ * configuration, compressed by one sequence of persistent launches (every
+ * launch walks the blocks of all fields). Each job's stream is byte-identical
+ * to what stz_compress produces for the same arguments. Launch shapes
+ * (persistent grid sizes, slab heights) come from the batch tuning table,
+ * which stz_autotune_batch fills; they never change the output. */
+typedef struct {
+  const float* x;      /* device, dims[0]*dims[1]*dims[2] values              */
+  uint64_t dims[3];
+  int32_t eb_mode;     /* stz_eb_mode                                          */
+  uint32_t reserved;   /* must be 0                                            */
+  double eb;
+  stz_config cfg;
+  void* out;           /* device, out_cap bytes                                */
+  uint64_t out_cap;
+  uint64_t out_size;   /* written: stream size (or the size needed)            */
+  int32_t status;      /* written: the stz_status stz_compress would return    */
+  uint32_t reserved2;
+} stz_job;
+
+#define STZ_MAX_BATCH 65536
+
+/* Compress `njobs` (<= STZ_MAX_BATCH) fields described by `jobs` (host
+ * array). Invalid jobs get their status and are left out; the others run.
+ * Returns STZ_OK when every job succeeded, else the first failing job's
+ * status. Synchronizes `stream` once. */
+stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream);
+
+/* ---- Resident fields and batched decoding (serving) ---------------------
+ * stz_open validates the header of a compressed stream that stays in device
+ * memory (`comp`, `size` bytes, owned by the caller and kept alive and
+ * unchanged until stz_close) and uploads its decoder table once; later
+ * decodes need no host round trip. */
+typedef struct stz_field_s* stz_field;
+
+stz_status stz_open(const void* comp, uint64_t size, stz_field* field, void* stream);
+stz_status stz_field_info(stz_field field, stz_info_t* info);
+/* Synchronizes the device before releasing the field's table. */
+void stz_close(stz_field field);
+
+/* One decode request: the box [lo, hi) (full-resolution coordinates) of a
+ * resident field at progressive level `level` (levels of the field: the whole
+ * domain at level L is a full decompression), written in raster order into
+ * `out` (device, out_cap_elems floats), exactly as stz_decompress_region
+ * would write it. */
+typedef struct {
+  stz_field field;
+  uint64_t lo[3], hi[3];
+  uint32_t level;
+  uint32_t reserved;      /* must be 0                                          */
+  float* out;
+  uint64_t out_cap_elems;
+  uint64_t out_dims[3];   /* written: output shape                              */
+  int32_t status;         /* written: argument status; corruption found on the
+                             device is reported through the flags word          */
+  uint32_t reserved2;
+} stz_request;
+
+/* Decode `n` requests (host array) with one launch sequence: per level, one
+ * persistent launch per level block edge walks the blocks of every request's
+ * dependency cone. Asynchronous: when `dev_flags` (device, n words) is not
+ * NULL, the call does not synchronize; word i becomes nonzero when request i
+ * met a corrupt stream, and host-side argument errors are in status. With
+ * dev_flags NULL the call synchronizes and sets status to STZ_ERR_CORRUPT
+ * where needed. Returns STZ_OK when every request was accepted (and, when
+ * synchronous, decoded), else the first failing request's status. The
+ * library's host staging for a stream is reused by the next call on that
+ * stream only after the previous call's copies have run. */
+stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_flags,
+                                void* stream);
+
+/* ---- Autotuner -------------------------------------------------------------
+ * Times candidate launch shapes of the batched kernels (persistent grid sizes
+ * and slab heights, per level block edge) on the given jobs, keeps the
+ * fastest that reproduces the reference outputs exactly, and stores them in
+ * the process-wide batch tuning table. `jobs` are run several times (their
+ * outputs are overwritten); `report` (host, may be NULL) receives a text
+ * summary of at most report_cap bytes. Synchronizes `stream`. */
+stz_status stz_autotune_batch(stz_job* jobs, uint64_t njobs, char* report, uint64_t report_cap,
+                              void* stream);
 
 /* Device scratch (auxiliary): every call takes its scratch from a buffer the
  * library keeps per (device, stream) and grows on demand, so repeated calls

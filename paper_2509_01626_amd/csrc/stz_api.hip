@@ -1,9 +1,13 @@
 // Host side of the C ABI declared in include/stz.h: argument validation,
 // stream-header parsing, workspace management and kernel launch sequences.
 #include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <unordered_map>
 #include <vector>
 
@@ -74,6 +78,25 @@ void level_consts(const Geo& g, LevelConst* lc) {
     lc[l].nsym = uint64_t(level_nsym(g, g.L - l));
   }
 }
+
+}  // namespace
+
+BatchTuning& batch_tuning() {
+  static BatchTuning t = [] {
+    BatchTuning d;
+    d.grid = 2048;
+    for (int e = 0; e < kBatchEdges; ++e) {
+      d.grid_pred[e] = 1u << 20;
+      d.grid_dec[e] = 1u << 20;
+      d.pred_h[e] = 0;  // 0 = the plain launch's slab height
+      d.dec_h[e] = 0;
+    }
+    return d;
+  }();
+  return t;
+}
+
+namespace {
 
 // Keep freed stream-ordered allocations cached in the device pool.
 void pool_setup() {
@@ -313,81 +336,104 @@ uint64_t box_points(const Box& b, int logs) {
   return n;
 }
 
-// Decode the box (null = the whole domain) at `level` (negative = finest).
+// Validated arguments and scratch layout of one box decode (null box = the
+// whole domain, negative level = finest) against a parsed header; the same
+// plan serves a plain call and a request of a batch. A plan whose output is
+// empty (an axis without grid points) has cnt == 0 and launches nothing.
+struct DecodePlan {
+  DecodeArgs a;
+  uint64_t od[3] = {0, 0, 0}, cnt = 0;
+  uint64_t o_rec[kMaxLevels + 1] = {};
+
+  stz_status init(const Header& h, const void* comp, uint64_t size, const Box* boxp, int level,
+                  float* out, uint64_t out_cap) {
+    const Geo& g = h.g;
+    std::memset(&a, 0, sizeof(a));
+    if (level < 0) level = g.L;
+    if (level > g.L) return STZ_ERR_ARG;
+    Box box;
+    if (boxp) {
+      box = *boxp;
+    } else {
+      for (int d = 0; d < 3; ++d) {
+        box.lo[d] = 0;
+        box.hi[d] = g.n[d];
+      }
+    }
+    for (int d = 0; d < 3; ++d)
+      if (!(box.lo[d] < box.hi[d]) || box.hi[d] > g.n[d] || box.lo[d] < 0) return STZ_ERR_ARG;
+    const int logs_out = g.L - level;
+    const int64_t so = int64_t(1) << logs_out;
+    for (int d = 0; d < 3; ++d) {
+      const int64_t f = (box.lo[d] + so - 1) >> logs_out << logs_out;
+      od[d] = f < box.hi[d] ? uint64_t(((box.hi[d] - 1 - f) >> logs_out) + 1) : 0;
+    }
+    cnt = od[0] * od[1] * od[2];
+    if (cnt == 0) return STZ_OK;
+    if (!out || cnt > out_cap) return STZ_ERR_BUFFER;
+    a.comp = static_cast<const uint8_t*>(comp);
+    a.size = size;
+    a.geo = g;
+    a.level_out = level;
+    a.box[level] = box;
+    for (int k = level; k >= 1; --k)
+      a.box[k - 1] = dilate(a.box[k], 3 * (int64_t(1) << (g.L - k)), g);
+    a.rec[level] = out;
+    for (int l = 1; l <= g.L; ++l) {
+      a.sec[l] = h.sec[l];
+      a.off_outl[l] = h.off_outl[l];
+      a.off_lane[l] = h.off_lane[l];
+      a.off_pay[l] = h.off_pay[l];
+      a.off_out[l] = h.off_out[l];
+      a.words[l] = h.words[l];
+      a.outl[l] = h.outl[l];
+      a.lc[l] = h.lc[l];
+    }
+    a.anchor_off = h.anchor_off;
+    for (int l = 1; l <= g.L; ++l) {
+      double e;
+      if (l == g.L)
+        e = h.eb_abs;
+      else if (l == g.L - 1)
+        e = h.eb_abs / h.c.ratio;
+      else
+        e = (h.eb_abs / h.c.ratio) / h.c.ratio;
+      a.E2[l] = float(2.0 * e);
+    }
+    return STZ_OK;
+  }
+
+  void take(Workspace& ws) {
+    for (int k = 0; k < a.level_out; ++k)
+      o_rec[k] = ws.take<float>(box_points(a.box[k], a.geo.L - k));
+  }
+
+  void bind(const Workspace& ws, const uint16_t* lut, uint32_t* flags) {
+    for (int k = 0; k < a.level_out; ++k) a.rec[k] = ws.at<float>(o_rec[k]);
+    a.lut = lut;
+    a.flags = flags;
+  }
+};
+
 stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int level, float* out,
                       uint64_t out_cap, uint64_t out_dims[3], hipStream_t st) {
   Header h;
   stz_status s = read_header(comp, size, st, &h);
   if (s != STZ_OK) return s;
-  const Geo& g = h.g;
-  if (level < 0) level = g.L;
-  if (level > g.L) return STZ_ERR_ARG;
-  Box box;
-  if (boxp) {
-    box = *boxp;
-  } else {
-    for (int d = 0; d < 3; ++d) {
-      box.lo[d] = 0;
-      box.hi[d] = g.n[d];
-    }
-  }
-  for (int d = 0; d < 3; ++d)
-    if (!(box.lo[d] < box.hi[d]) || box.hi[d] > g.n[d] || box.lo[d] < 0) return STZ_ERR_ARG;
-  const int logs_out = g.L - level;
-  const int64_t so = int64_t(1) << logs_out;
-  uint64_t od[3];
-  for (int d = 0; d < 3; ++d) {
-    const int64_t f = (box.lo[d] + so - 1) >> logs_out << logs_out;
-    od[d] = f < box.hi[d] ? uint64_t(((box.hi[d] - 1 - f) >> logs_out) + 1) : 0;
-  }
+  DecodePlan pl;
+  s = pl.init(h, comp, size, boxp, level, out, out_cap);
   if (out_dims)
-    for (int d = 0; d < 3; ++d) out_dims[d] = od[d];
-  const uint64_t cnt = od[0] * od[1] * od[2];
-  if (cnt == 0) return STZ_OK;
-  if (!out || cnt > out_cap) return STZ_ERR_BUFFER;
+    for (int d = 0; d < 3; ++d) out_dims[d] = pl.od[d];
+  if (s != STZ_OK || pl.cnt == 0) return s;
   std::vector<uint16_t> lut;
   if (!build_lut(h.lens, &lut)) return STZ_ERR_CORRUPT;
-
-  DecodeArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.comp = static_cast<const uint8_t*>(comp);
-  a.size = size;
-  a.geo = g;
-  a.level_out = level;
-  a.box[level] = box;
-  for (int k = level; k >= 1; --k) a.box[k - 1] = dilate(a.box[k], 3 * (int64_t(1) << (g.L - k)), g);
   Workspace ws(st);
-  uint64_t o_rec[kMaxLevels + 1];
-  for (int k = 0; k < level; ++k) o_rec[k] = ws.take<float>(box_points(a.box[k], g.L - k));
+  pl.take(ws);
   const uint64_t o_lut = ws.take<uint8_t>(lut.size() * 2 + 16);
   if (!ws.commit()) return STZ_ERR_NOMEM;
-  for (int k = 0; k < level; ++k) a.rec[k] = ws.at<float>(o_rec[k]);
-  a.rec[level] = out;
   uint16_t* dlut = ws.at<uint16_t>(o_lut);
   uint32_t* dflags = reinterpret_cast<uint32_t*>(dlut + lut.size());
-  for (int l = 1; l <= g.L; ++l) {
-    a.sec[l] = h.sec[l];
-    a.off_outl[l] = h.off_outl[l];
-    a.off_lane[l] = h.off_lane[l];
-    a.off_pay[l] = h.off_pay[l];
-    a.off_out[l] = h.off_out[l];
-    a.words[l] = h.words[l];
-    a.outl[l] = h.outl[l];
-    a.lc[l] = h.lc[l];
-  }
-  a.anchor_off = h.anchor_off;
-  for (int l = 1; l <= g.L; ++l) {
-    double e;
-    if (l == g.L)
-      e = h.eb_abs;
-    else if (l == g.L - 1)
-      e = h.eb_abs / h.c.ratio;
-    else
-      e = (h.eb_abs / h.c.ratio) / h.c.ratio;
-    a.E2[l] = float(2.0 * e);
-  }
-  a.lut = dlut;
-  a.flags = dflags;
+  pl.bind(ws, dlut, dflags);
   Staging* stage = staging();
   if (!stage) return STZ_ERR_NOMEM;
   std::memcpy(stage->lut, lut.data(), lut.size() * 2);
@@ -395,12 +441,277 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   if (hipMemcpyAsync(dlut, stage->lut, lut.size() * 2 + 16, hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return STZ_ERR_DEVICE;
-  if (launch_decode(a, st) != hipSuccess) return STZ_ERR_DEVICE;
+  if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
   if (hipMemcpyAsync(stage->flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
   prof_flush();
   return *stage->flags ? STZ_ERR_CORRUPT : STZ_OK;
+}
+
+// ---- compression plan of one field ----------------------------------------
+stz_status params_status(const DevParams& P) {
+  if (P.flags & kFlagNonfinite) return STZ_ERR_NONFINITE;
+  if (P.flags & (kFlagBadBound | kFlagTooLarge)) return STZ_ERR_ARG;
+  if (P.flags & kFlagOverflow) return STZ_ERR_BUFFER;
+  return STZ_OK;
+}
+
+// Validated arguments, kernel argument block and scratch layout of one
+// compression; the same plan serves a plain call and a job of a batch.
+struct CompressPlan {
+  CompressArgs a;
+  uint64_t o_part = 0, o_rec[kMaxLevels] = {}, o_sym[kMaxLevels + 1] = {}, o_lane = 0,
+           o_hist = 0, o_lens = 0, o_codes = 0, o_cb = 0, o_cnt = 0, o_scan = 0, o_spart = 0;
+
+  stz_status init(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+                  const stz_config* cfg, void* out, uint64_t out_cap) {
+    Cfg c;
+    Geo g;
+    std::memset(&a, 0, sizeof(a));
+    if (!x || !dims) return STZ_ERR_ARG;
+    if (resolve_cfg(cfg, &c) != STZ_OK || !make_geo(dims, c, &g)) return STZ_ERR_ARG;
+    if (eb_mode != STZ_EB_ABS && eb_mode != STZ_EB_REL) return STZ_ERR_ARG;
+    if (!(eb > 0.0) || !std::isfinite(eb)) return STZ_ERR_ARG;
+    const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
+    a.x = x;
+    a.geo = g;
+    a.eb_mode = eb_mode;
+    a.eb = eb;
+    a.ratio = c.ratio;
+    a.out = static_cast<uint8_t*>(out);
+    a.out_cap = out ? out_cap : 0;
+    level_consts(g, a.lc);
+    a.n_anchor = grid_count(g, g.L);
+    if (a.lc[1].nu > 0xFFFFFFF0ull) return STZ_ERR_ARG;
+    a.nparts = uint32_t(std::min<uint64_t>(1024, (N + 4095) / 4096));
+    return STZ_OK;
+  }
+
+  void take(Workspace& ws) {
+    const Geo& g = a.geo;
+    const int L = g.L, nsym = 2 * g.R;
+    const uint64_t nu = a.lc[1].nu;
+    o_part = ws.take<float2>(a.nparts);
+    for (int l = 0; l < L; ++l) o_rec[l] = ws.take<float>(grid_count(g, L - l));
+    uint64_t lanes = 0;
+    for (int l = 1; l <= L; ++l) {
+      o_sym[l] = ws.take<uint16_t>(a.lc[l].nsym);
+      a.lane_base[l] = lanes;
+      lanes += a.lc[l].nl;
+    }
+    o_lane = ws.take<uint16_t>(lanes);
+    o_hist = ws.take<unsigned long long>(nsym);
+    o_lens = ws.take<uint8_t>(nsym);
+    o_codes = ws.take<uint16_t>(nsym);
+    o_cb = ws.take<uint8_t>(codebook_scratch_bytes(nsym));
+    o_cnt = ws.take<uint32_t>(2 * L * nu);
+    o_scan = ws.take<uint32_t>(2 * L * (nu + 1));
+    o_spart = ws.take<uint64_t>(2 * L * scan_blocks());
+  }
+
+  uint64_t scan_blocks() const { return (a.lc[1].nu + 2047) / 2048; }
+
+  void bind(const Workspace& ws, DevParams* params) {
+    const int L = a.geo.L;
+    a.params = params;
+    a.part = ws.at<float2>(o_part);
+    for (int l = 0; l < L; ++l) a.rec[l] = ws.at<float>(o_rec[l]);
+    for (int l = 1; l <= L; ++l) a.sym[l] = ws.at<uint16_t>(o_sym[l]);
+    a.lane_len = ws.at<uint16_t>(o_lane);
+    a.hist = ws.at<unsigned long long>(o_hist);
+    a.lens = ws.at<uint8_t>(o_lens);
+    a.codes = ws.at<uint16_t>(o_codes);
+    a.cb_scratch = ws.at<uint8_t>(o_cb);
+    a.cnt = ws.at<uint32_t>(o_cnt);
+    a.scan = ws.at<uint32_t>(o_scan);
+    a.scan_part = ws.at<uint64_t>(o_spart);
+  }
+};
+
+// Per-thread pinned host buffer for job tables and work maps (host to
+// device) and the per-job status blocks (device to host); grows on demand.
+// Every batch call ends with a stream synchronization.
+struct HostBuf {
+  uint8_t* p = nullptr;
+  uint64_t cap = 0;
+  hipEvent_t done = nullptr;  // recorded after the last copy out of the buffer
+  bool pending = false;
+  // Wait until the copies of an asynchronous call that read the buffer ran.
+  bool settle() {
+    if (pending && done && hipEventSynchronize(done) != hipSuccess) return false;
+    pending = false;
+    return true;
+  }
+  bool mark(hipStream_t st) {
+    if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+      done = nullptr;
+      return false;
+    }
+    pending = hipEventRecord(done, st) == hipSuccess;
+    return pending;
+  }
+  bool reserve(uint64_t n) {
+    if (!settle()) return false;
+    if (n <= cap) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    const uint64_t want = std::max<uint64_t>(n + n / 2, 1 << 16);
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), want) != hipSuccess) return false;
+    cap = want;
+    return true;
+  }
+  ~HostBuf() {
+    settle();
+    if (p) (void)hipHostFree(p);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+// One buffer per (thread, stream): a call waits only for the copies of the
+// previous call on the same stream.
+HostBuf& host_buf(hipStream_t st) {
+  thread_local std::unordered_map<uint64_t, HostBuf> m;
+  return m[ws_key(st)];
+}
+
+// Work maps of a batch, built on the host into one array of u32: every map is
+// first[n+1] followed by job[n]; bind() turns offsets into device pointers.
+struct BatchMaps {
+  std::vector<uint32_t> buf;
+  std::vector<std::pair<ItemMap*, uint64_t>> fix;  // map, offset of its first[]
+
+  // counts[k] items for table entry k; entries with no items are left out.
+  uint32_t add(ItemMap* m, const std::vector<uint32_t>& counts) {
+    std::vector<uint32_t> first, job;
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < counts.size(); ++k) {
+      if (!counts[k]) continue;
+      first.push_back(run);
+      job.push_back(k);
+      run += counts[k];
+    }
+    first.push_back(run);
+    m->n = uint32_t(job.size());
+    const uint64_t off = buf.size();
+    buf.insert(buf.end(), first.begin(), first.end());
+    buf.insert(buf.end(), job.begin(), job.end());
+    if (job.empty()) buf.push_back(0);
+    fix.push_back({m, off});
+    return run;
+  }
+
+  void bind(const uint32_t* dev) {
+    for (auto& f : fix) {
+      f.first->first = dev + f.second;
+      f.first->job = dev + f.second + f.first->n + 1;
+    }
+  }
+};
+
+uint32_t cap_items(uint64_t n, uint64_t per, uint64_t cap) {
+  return uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(cap, (n + per - 1) / per)));
+}
+
+int ilog2(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return k;
+}
+
+// Work maps of a batched compression over the live jobs (table order).
+void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<uint32_t>& live,
+                         BatchMaps* maps, CompressBatch* b) {
+  std::memset(b, 0, sizeof(*b));
+  const uint32_t n = uint32_t(live.size());
+  b->njobs = n;
+  const BatchTuning& tu = batch_tuning();
+  b->grid = tu.grid;
+  for (int e = 0; e < kBatchEdges; ++e) {
+    b->grid_pred[e] = tu.grid_pred[e];
+    b->pred_h[e] = tu.pred_h[e];
+  }
+  std::vector<uint32_t> c(n);
+  auto per_job = [&](auto f) {
+    for (uint32_t k = 0; k < n; ++k) c[k] = f(pl[live[k]].a);
+    return c;
+  };
+  b->n_jobs1 = maps->add(&b->jobs1, per_job([](const CompressArgs&) { return 1u; }));
+  b->n_minmax = maps->add(&b->minmax, per_job([](const CompressArgs& a) {
+    return a.eb_mode == STZ_EB_REL ? a.nparts : 0u;
+  }));
+  b->n_anchor = maps->add(&b->anchor, per_job([](const CompressArgs& a) {
+    return cap_items(a.n_anchor, 256, 4096);
+  }));
+  int maxL = 0;
+  for (uint32_t k = 0; k < n; ++k) maxL = std::max(maxL, pl[live[k]].a.geo.L);
+  b->max_levels = maxL;
+  for (int l = 1; l <= maxL; ++l) {
+    for (int e = 1; e < kBatchEdges; ++e) {
+      b->n_pred[l][e] = maps->add(&b->pred[l][e], per_job([&](const CompressArgs& a) {
+        const Geo& g = a.geo;
+        if (g.L < l || ilog2(g.B >> (g.L - l)) != e) return 0u;
+        return uint32_t(g.nb[0] * g.nb[1] * g.nb[2]);
+      }));
+    }
+    b->n_level[l] = maps->add(&b->level[l], per_job([&](const CompressArgs& a) {
+      const Geo& g = a.geo;
+      return g.L < l ? 0u : uint32_t(g.nb[0] * g.nb[1] * g.nb[2]);
+    }));
+  }
+  b->n_scan_ac = maps->add(&b->scan_ac, per_job([](const CompressArgs& a) {
+    return uint32_t((a.lc[1].nu + 2047) / 2048) * uint32_t(2 * a.geo.L);
+  }));
+  b->n_scan_b = maps->add(&b->scan_b, per_job([](const CompressArgs& a) {
+    return uint32_t(2 * a.geo.L);
+  }));
+  b->n_zero = maps->add(&b->zero, per_job([](const CompressArgs& a) {
+    return cap_items(a.out_cap, 16 * 256 * 8, 2048);
+  }));
+  b->n_head = maps->add(&b->head, per_job([](const CompressArgs& a) {
+    return cap_items(a.n_anchor + 2 * uint64_t(a.geo.R), 256, 4096);
+  }));
+}
+
+// Work maps of a batched decode over the live requests (table order).
+void build_decode_maps(const std::vector<DecodePlan>& pl, const std::vector<uint32_t>& live,
+                       BatchMaps* maps, DecodeBatch* b) {
+  std::memset(b, 0, sizeof(*b));
+  const uint32_t n = uint32_t(live.size());
+  b->nreq = n;
+  const BatchTuning& tu = batch_tuning();
+  b->grid = tu.grid;
+  for (int e = 0; e < kBatchEdges; ++e) {
+    b->grid_dec[e] = tu.grid_dec[e];
+    b->dec_h[e] = tu.dec_h[e];
+  }
+  std::vector<uint32_t> c(n);
+  auto per_req = [&](auto f) {
+    for (uint32_t k = 0; k < n; ++k) c[k] = f(pl[live[k]].a);
+    return c;
+  };
+  b->n_anchor = maps->add(&b->anchor, per_req([](const DecodeArgs& a) {
+    return cap_items(box_points(a.box[0], a.geo.L), 256, 4096);
+  }));
+  int maxk = 0;
+  for (uint32_t k = 0; k < n; ++k) maxk = std::max(maxk, pl[live[k]].a.level_out);
+  b->max_level = maxk;
+  for (int k = 1; k <= maxk; ++k) {
+    b->n_check[k] = maps->add(&b->check[k], per_req([&](const DecodeArgs& a) {
+      return a.level_out >= k ? 1u : 0u;
+    }));
+    for (int e = 1; e < kBatchEdges; ++e) {
+      b->n_dec[k][e] = maps->add(&b->dec[k][e], per_req([&](const DecodeArgs& a) {
+        const Geo& g = a.geo;
+        if (a.level_out < k || ilog2(g.B >> (g.L - k)) != e) return 0u;
+        uint64_t nb = 1;
+        for (int q = 0; q < 3; ++q)
+          nb *= uint64_t(((a.box[k].hi[q] - 1) >> g.logB) - (a.box[k].lo[q] >> g.logB) + 1);
+        return uint32_t(nb);
+      }));
+    }
+  }
 }
 
 }  // namespace
@@ -447,78 +758,508 @@ uint64_t stz_compress_bound(const uint64_t dims[3], const stz_config* cfg) {
 stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
                         const stz_config* cfg, void* out, uint64_t out_cap, uint64_t* out_size,
                         void* stream) {
-  Cfg c;
-  Geo g;
-  if (!x || !dims || !out_size) return STZ_ERR_ARG;
-  if (resolve_cfg(cfg, &c) != STZ_OK || !make_geo(dims, c, &g)) return STZ_ERR_ARG;
-  if (eb_mode != STZ_EB_ABS && eb_mode != STZ_EB_REL) return STZ_ERR_ARG;
-  if (!(eb > 0.0) || !std::isfinite(eb)) return STZ_ERR_ARG;
+  if (!out_size) return STZ_ERR_ARG;
+  CompressPlan pl;
+  const stz_status s0 = pl.init(x, dims, eb_mode, eb, cfg, out, out_cap);
+  if (s0 != STZ_OK) return s0;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
-  const int L = g.L, nsym = 2 * g.R;
-
-  CompressArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.x = x;
-  a.geo = g;
-  a.eb_mode = eb_mode;
-  a.eb = eb;
-  a.ratio = c.ratio;
-  a.out = static_cast<uint8_t*>(out);
-  a.out_cap = out ? out_cap : 0;
-  level_consts(g, a.lc);
-  a.n_anchor = grid_count(g, L);
-  const uint64_t nu = a.lc[1].nu;
-  if (nu > 0xFFFFFFF0ull) return STZ_ERR_ARG;
-
   Workspace ws(st);
   const uint64_t o_params = ws.take<DevParams>(1);
-  a.nparts = uint32_t(std::min<uint64_t>(1024, (N + 4095) / 4096));
-  const uint64_t o_part = ws.take<float2>(a.nparts);
-  uint64_t o_rec[kMaxLevels], o_sym[kMaxLevels + 1];
-  for (int l = 0; l < L; ++l) o_rec[l] = ws.take<float>(grid_count(g, L - l));
-  uint64_t lanes = 0;
-  for (int l = 1; l <= L; ++l) {
-    o_sym[l] = ws.take<uint16_t>(a.lc[l].nsym);
-    a.lane_base[l] = lanes;
-    lanes += a.lc[l].nl;
-  }
-  const uint64_t o_lane = ws.take<uint16_t>(lanes);
-  const uint64_t o_hist = ws.take<unsigned long long>(nsym);
-  const uint64_t o_lens = ws.take<uint8_t>(nsym);
-  const uint64_t o_codes = ws.take<uint16_t>(nsym);
-  const uint64_t o_cb = ws.take<uint8_t>(codebook_scratch_bytes(nsym));
-  const uint64_t o_cnt = ws.take<uint32_t>(2 * L * nu);
-  const uint64_t o_scan = ws.take<uint32_t>(2 * L * (nu + 1));
-  const uint64_t nblk = (nu + 2047) / 2048;
-  const uint64_t o_spart = ws.take<uint64_t>(2 * L * nblk);
+  pl.take(ws);
   if (!ws.commit()) return STZ_ERR_NOMEM;
-  a.params = ws.at<DevParams>(o_params);
-  a.part = ws.at<float2>(o_part);
-  for (int l = 0; l < L; ++l) a.rec[l] = ws.at<float>(o_rec[l]);
-  for (int l = 1; l <= L; ++l) a.sym[l] = ws.at<uint16_t>(o_sym[l]);
-  a.lane_len = ws.at<uint16_t>(o_lane);
-  a.hist = ws.at<unsigned long long>(o_hist);
-  a.lens = ws.at<uint8_t>(o_lens);
-  a.codes = ws.at<uint16_t>(o_codes);
-  a.cb_scratch = ws.at<uint8_t>(o_cb);
-  a.cnt = ws.at<uint32_t>(o_cnt);
-  a.scan = ws.at<uint32_t>(o_scan);
-  a.scan_part = ws.at<uint64_t>(o_spart);
-  if (launch_compress(a, st) != hipSuccess) return STZ_ERR_DEVICE;
+  pl.bind(ws, ws.at<DevParams>(o_params));
+  if (launch_compress(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
   Staging* stage = staging();
   if (!stage) return STZ_ERR_NOMEM;
-  if (hipMemcpyAsync(stage->params, a.params, sizeof(DevParams), hipMemcpyDeviceToHost, st) !=
+  if (hipMemcpyAsync(stage->params, pl.a.params, sizeof(DevParams), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
-  const DevParams& P = *stage->params;
   prof_flush();
-  *out_size = P.total;
-  if (P.flags & kFlagNonfinite) return STZ_ERR_NONFINITE;
-  if (P.flags & (kFlagBadBound | kFlagTooLarge)) return STZ_ERR_ARG;
-  if (P.flags & kFlagOverflow) return STZ_ERR_BUFFER;
+  *out_size = stage->params->total;
+  return params_status(*stage->params);
+}
+
+stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
+  if (!jobs && njobs) return STZ_ERR_ARG;
+  if (njobs == 0) return STZ_OK;
+  if (njobs > STZ_MAX_BATCH) return STZ_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<CompressPlan> pl(njobs);
+  std::vector<uint32_t> live;  // jobs that passed validation
+  for (uint64_t i = 0; i < njobs; ++i) {
+    jobs[i].out_size = 0;
+    jobs[i].status = jobs[i].reserved ? STZ_ERR_ARG
+                                      : pl[i].init(jobs[i].x, jobs[i].dims, jobs[i].eb_mode,
+                                                   jobs[i].eb, &jobs[i].cfg, jobs[i].out,
+                                                   jobs[i].out_cap);
+    if (jobs[i].status == STZ_OK) live.push_back(uint32_t(i));
+  }
+  const uint32_t nl = uint32_t(live.size());
+  if (nl) {
+    Workspace ws(st);
+    const uint64_t o_params = ws.take<DevParams>(nl);
+    for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
+    const uint64_t o_jobs = ws.take<CompressArgs>(nl);
+    BatchMaps maps;
+    CompressBatch b;
+    build_compress_maps(pl, live, &maps, &b);
+    const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
+    if (!ws.commit()) return STZ_ERR_NOMEM;
+    DevParams* dpar = ws.at<DevParams>(o_params);
+    for (uint32_t k = 0; k < nl; ++k) pl[live[k]].bind(ws, dpar + k);
+    HostBuf& hb = host_buf(st);
+    const uint64_t jb = uint64_t(nl) * sizeof(CompressArgs);
+    const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
+    const uint64_t pb = uint64_t(nl) * sizeof(DevParams);
+    if (!hb.reserve(std::max(jb + mb, pb))) return STZ_ERR_NOMEM;
+    for (uint32_t k = 0; k < nl; ++k)
+      std::memcpy(hb.p + uint64_t(k) * sizeof(CompressArgs), &pl[live[k]].a, sizeof(CompressArgs));
+    std::memcpy(hb.p + jb, maps.buf.data(), mb);
+    CompressArgs* dj = ws.at<CompressArgs>(o_jobs);
+    uint32_t* dm = ws.at<uint32_t>(o_maps);
+    if (hipMemcpyAsync(dj, hb.p, jb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dm, hb.p + jb, mb, hipMemcpyHostToDevice, st) != hipSuccess)
+      return STZ_ERR_DEVICE;
+    b.J = dj;
+    maps.bind(dm);
+    if (launch_compress_batch(b, st) != hipSuccess) return STZ_ERR_DEVICE;
+    if (hipMemcpyAsync(hb.p, dpar, pb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return STZ_ERR_DEVICE;
+    prof_flush();
+    const DevParams* hp = reinterpret_cast<const DevParams*>(hb.p);
+    for (uint32_t k = 0; k < nl; ++k) {
+      jobs[live[k]].out_size = hp[k].total;
+      jobs[live[k]].status = params_status(hp[k]);
+    }
+  }
+  for (uint64_t i = 0; i < njobs; ++i)
+    if (jobs[i].status != STZ_OK) return static_cast<stz_status>(jobs[i].status);
   return STZ_OK;
+}
+
+}  // extern "C"
+
+struct stz_field_s {
+  stz::Header h;
+  const uint8_t* comp = nullptr;
+  uint64_t size = 0;
+  uint16_t* lut = nullptr;  // device decoder table
+  uint64_t lut_entries = 0;
+  int device = 0;
+};
+
+extern "C" {
+
+stz_status stz_open(const void* comp, uint64_t size, stz_field* field, void* stream) {
+  if (!field) return STZ_ERR_ARG;
+  *field = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto* f = new (std::nothrow) stz_field_s;
+  if (!f) return STZ_ERR_NOMEM;
+  stz_status s = read_header(comp, size, st, &f->h);
+  std::vector<uint16_t> lut;
+  if (s == STZ_OK && !build_lut(f->h.lens, &lut)) s = STZ_ERR_CORRUPT;
+  if (s != STZ_OK) {
+    delete f;
+    return s;
+  }
+  f->comp = static_cast<const uint8_t*>(comp);
+  f->size = size;
+  f->lut_entries = lut.size();
+  Staging* stage = staging();
+  if (!stage || hipGetDevice(&f->device) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&f->lut), lut.size() * 2) != hipSuccess) {
+    delete f;
+    return STZ_ERR_NOMEM;
+  }
+  std::memcpy(stage->lut, lut.data(), lut.size() * 2);
+  if (hipMemcpyAsync(f->lut, stage->lut, lut.size() * 2, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipFree(f->lut);
+    delete f;
+    return STZ_ERR_DEVICE;
+  }
+  *field = f;
+  return STZ_OK;
+}
+
+stz_status stz_field_info(stz_field f, stz_info_t* info) {
+  if (!f || !info) return STZ_ERR_ARG;
+  const Header& h = f->h;
+  for (int d = 0; d < 3; ++d) info->dims[d] = uint64_t(h.g.n[d]);
+  info->block = uint32_t(h.c.B);
+  info->levels = uint32_t(h.c.L);
+  info->radius = uint32_t(h.c.R);
+  info->lmax = uint32_t(kLmax);
+  info->eb_mode = uint32_t(h.eb_mode);
+  info->reserved = 0;
+  info->eb = h.eb;
+  info->eb_abs = h.eb_abs;
+  info->eb_ratio = h.c.ratio;
+  info->total_bytes = h.total;
+  return STZ_OK;
+}
+
+void stz_close(stz_field f) {
+  if (!f) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != f->device) (void)hipSetDevice(f->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(f->lut);
+  if (cur != f->device) (void)hipSetDevice(cur);
+  delete f;
+}
+
+stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_flags,
+                                void* stream) {
+  if (!reqs && n) return STZ_ERR_ARG;
+  if (n == 0) return STZ_OK;
+  if (n > STZ_MAX_BATCH) return STZ_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<DecodePlan> pl(n);
+  std::vector<uint32_t> live;
+  for (uint64_t i = 0; i < n; ++i) {
+    stz_request& r = reqs[i];
+    for (int d = 0; d < 3; ++d) r.out_dims[d] = 0;
+    if (!r.field || r.reserved) {
+      r.status = STZ_ERR_ARG;
+      continue;
+    }
+    Box box;
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+      ok = ok && r.lo[d] < (uint64_t(1) << 40) && r.hi[d] < (uint64_t(1) << 40);
+      box.lo[d] = int64_t(r.lo[d]);
+      box.hi[d] = int64_t(r.hi[d]);
+    }
+    if (!ok || r.level > 64) {
+      r.status = STZ_ERR_ARG;
+      continue;
+    }
+    r.status = pl[i].init(r.field->h, r.field->comp, r.field->size, &box, int(r.level), r.out,
+                          r.out_cap_elems);
+    for (int d = 0; d < 3; ++d) r.out_dims[d] = pl[i].od[d];
+    if (r.status == STZ_OK && pl[i].cnt) live.push_back(uint32_t(i));
+  }
+  const uint32_t nl = uint32_t(live.size());
+  HostBuf& hb = host_buf(st);
+  Workspace ws(st);
+  BatchMaps maps;
+  DecodeBatch b;
+  uint64_t o_req = 0, o_flags = 0, o_maps = 0;
+  if (nl) {
+    for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
+    o_req = ws.take<DecodeArgs>(nl);
+    o_flags = ws.take<uint32_t>(nl);
+    build_decode_maps(pl, live, &maps, &b);
+    o_maps = ws.take<uint32_t>(maps.buf.size());
+    if (!ws.commit()) return STZ_ERR_NOMEM;
+  }
+  // Host staging: request table | work maps | zero flags | zero caller flags.
+  const uint64_t rb = uint64_t(nl) * sizeof(DecodeArgs);
+  const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
+  const uint64_t fb = uint64_t(nl) * 4;
+  const uint64_t cb = dev_flags ? n * 4 : 0;
+  if (!hb.reserve(rb + mb + fb + cb)) return STZ_ERR_NOMEM;
+  std::memset(hb.p + rb + mb, 0, fb + cb);
+  if (dev_flags &&
+      hipMemcpyAsync(dev_flags, hb.p + rb + mb + fb, cb, hipMemcpyHostToDevice, st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  if (nl) {
+    uint32_t* wflags = ws.at<uint32_t>(o_flags);
+    for (uint32_t k = 0; k < nl; ++k) {
+      const stz_request& r = reqs[live[k]];
+      pl[live[k]].bind(ws, r.field->lut, dev_flags ? dev_flags + live[k] : wflags + k);
+    }
+    for (uint32_t k = 0; k < nl; ++k)
+      std::memcpy(hb.p + uint64_t(k) * sizeof(DecodeArgs), &pl[live[k]].a, sizeof(DecodeArgs));
+    std::memcpy(hb.p + rb, maps.buf.data(), mb);
+    DecodeArgs* dr = ws.at<DecodeArgs>(o_req);
+    uint32_t* dm = ws.at<uint32_t>(o_maps);
+    if (hipMemcpyAsync(dr, hb.p, rb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dm, hb.p + rb, mb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(wflags, hb.p + rb + mb, fb, hipMemcpyHostToDevice, st) != hipSuccess)
+      return STZ_ERR_DEVICE;
+    if (!hb.mark(st)) return STZ_ERR_DEVICE;
+    b.R = dr;
+    maps.bind(dm);
+    if (launch_decode_batch(b, st) != hipSuccess) return STZ_ERR_DEVICE;
+    if (!dev_flags) {
+      // the flag words come back into the staging of the zero flags, which
+      // the stream has consumed before the kernels ran
+      if (hipMemcpyAsync(hb.p + rb + mb, wflags, fb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return STZ_ERR_DEVICE;
+      hb.pending = false;
+      prof_flush();
+      const uint32_t* hf = reinterpret_cast<const uint32_t*>(hb.p + rb + mb);
+      for (uint32_t k = 0; k < nl; ++k)
+        if (hf[k]) reqs[live[k]].status = STZ_ERR_CORRUPT;
+    }
+  } else if (dev_flags && !hb.mark(st)) {
+    return STZ_ERR_DEVICE;
+  }
+  for (uint64_t i = 0; i < n; ++i)
+    if (reqs[i].status != STZ_OK) return static_cast<stz_status>(reqs[i].status);
+  return STZ_OK;
+}
+
+}  // extern "C"
+
+namespace stz {
+namespace {
+
+// Candidate slab heights of the batched kernels per level block edge 2^e
+// (the heights the kernels are instantiated for).
+std::vector<int> pred_heights(int e) {
+  switch (e) {
+    case 3: return {8, 4};
+    case 4: return {16, 8, 4};
+    case 5: return {8, 4, 2};
+    case 6: return {2, 4};
+    default: return {0};
+  }
+}
+std::vector<int> dec_heights(int e) {
+  switch (e) {
+    case 4: return {16, 8, 4};
+    case 5: return {4, 8, 2};
+    default: return {0};
+  }
+}
+
+BatchTuning default_tuning() {
+  BatchTuning d;
+  d.grid = 2048;
+  for (int e = 0; e < kBatchEdges; ++e) {
+    d.grid_pred[e] = 1u << 20;
+    d.grid_dec[e] = 1u << 20;
+    d.pred_h[e] = 0;
+    d.dec_h[e] = 0;
+  }
+  return d;
+}
+
+struct Tuner {
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  unsigned long long* dh = nullptr;  // digests (device)
+  std::vector<unsigned long long> hh;
+  std::string rep;
+
+  bool setup(uint64_t n) {
+    hh.resize(n);
+    return hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void**>(&dh), std::max<uint64_t>(n, 1) * 8) == hipSuccess;
+  }
+  ~Tuner() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (dh) (void)hipFree(dh);
+  }
+  // Digests of n device ranges; false on a runtime error.
+  bool digest(const std::vector<const void*>& p, const std::vector<uint64_t>& b) {
+    if (launch_hash(p.data(), b.data(), p.size(), dh, st) != hipSuccess ||
+        hipMemcpy(hh.data(), dh, p.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return false;
+    return true;
+  }
+  // Mean milliseconds of `reps` runs of f (after one untimed run), or -1.
+  template <class F>
+  double time(F f, int reps) {
+    if (!f()) return -1.0;
+    if (hipEventRecord(e0, st) != hipSuccess) return -1.0;
+    for (int r = 0; r < reps; ++r)
+      if (!f()) return -1.0;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return -1.0;
+    return double(ms) / reps;
+  }
+  void note(const char* fmt, ...) {
+    char line[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(line, sizeof(line), fmt, ap);
+    va_end(ap);
+    rep += line;
+    rep += "\n";
+  }
+};
+
+}  // namespace
+}  // namespace stz
+
+extern "C" {
+
+stz_status stz_autotune_batch(stz_job* jobs, uint64_t njobs, char* report, uint64_t report_cap,
+                              void* stream) {
+  if (!jobs || njobs == 0 || njobs > STZ_MAX_BATCH) return STZ_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  BatchTuning& tu = batch_tuning();
+  tu = default_tuning();
+  Tuner t;
+  t.st = st;
+  if (!t.setup(njobs)) return STZ_ERR_NOMEM;
+  const int reps = 3;
+  // Reference outputs with the default shapes.
+  stz_status s = stz_compress_batch(jobs, njobs, stream);
+  if (s != STZ_OK) return s;
+  std::vector<const void*> ptr(njobs);
+  std::vector<uint64_t> len(njobs);
+  for (uint64_t i = 0; i < njobs; ++i) {
+    ptr[i] = jobs[i].out;
+    len[i] = jobs[i].out_size;
+  }
+  if (!t.digest(ptr, len)) return STZ_ERR_DEVICE;
+  const std::vector<unsigned long long> ref = t.hh;
+  // Level block edges present in the batch, with their total block counts.
+  uint64_t edge_blocks[kBatchEdges] = {};
+  for (uint64_t i = 0; i < njobs; ++i) {
+    Cfg c;
+    Geo g;
+    if (resolve_cfg(&jobs[i].cfg, &c) != STZ_OK || !make_geo(jobs[i].dims, c, &g)) continue;
+    for (int l = 1; l <= g.L; ++l)
+      edge_blocks[ilog2(g.B >> (g.L - l))] += uint64_t(g.nb[0] * g.nb[1] * g.nb[2]);
+  }
+  bool mismatch = false;
+  auto run_c = [&]() { return stz_compress_batch(jobs, njobs, stream) == STZ_OK; };
+  auto check_c = [&]() {
+    if (!t.digest(ptr, len)) return false;
+    const bool same = t.hh == ref;
+    mismatch = mismatch || !same;
+    return same;
+  };
+  double best = t.time(run_c, reps);
+  if (best < 0) return STZ_ERR_DEVICE;
+  t.note("compress default: %.3f ms", best);
+  const unsigned grids[] = {256, 512, 1024, 2048, 4096, 1u << 20};
+  // Coordinate descent, the edges with most blocks first.
+  std::vector<int> order;
+  for (int e = 1; e < kBatchEdges; ++e)
+    if (edge_blocks[e]) order.push_back(e);
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return edge_blocks[x] > edge_blocks[y]; });
+  for (int e : order) {
+    for (int h : pred_heights(e)) {
+      const int keep = tu.pred_h[e];
+      tu.pred_h[e] = h;
+      const double ms = t.time(run_c, reps);
+      if (ms >= 0 && check_c() && ms < best) {
+        best = ms;
+        t.note("  edge %d predict slab height %d: %.3f ms", 1 << e, h, ms);
+      } else {
+        tu.pred_h[e] = keep;
+      }
+    }
+    for (unsigned gsz : grids) {
+      const unsigned keep = tu.grid_pred[e];
+      tu.grid_pred[e] = gsz;
+      const double ms = t.time(run_c, reps);
+      if (ms >= 0 && check_c() && ms < best) {
+        best = ms;
+        t.note("  edge %d predict grid %u: %.3f ms", 1 << e, gsz, ms);
+      } else {
+        tu.grid_pred[e] = keep;
+      }
+    }
+  }
+  for (unsigned gsz : grids) {
+    const unsigned keep = tu.grid;
+    tu.grid = gsz;
+    const double ms = t.time(run_c, reps);
+    if (ms >= 0 && check_c() && ms < best) {
+      best = ms;
+      t.note("  grid %u: %.3f ms", gsz, ms);
+    } else {
+      tu.grid = keep;
+    }
+  }
+  t.note("compress tuned: %.3f ms", best);
+  if (!run_c()) return STZ_ERR_DEVICE;  // leave the jobs' outputs as produced
+
+  // Decoder shapes: full decodes of every job's stream.
+  std::vector<stz_field> fields(njobs, nullptr);
+  float* dout = nullptr;
+  uint64_t total = 0;
+  std::vector<uint64_t> off(njobs);
+  for (uint64_t i = 0; i < njobs; ++i) {
+    off[i] = total;
+    total += jobs[i].dims[0] * jobs[i].dims[1] * jobs[i].dims[2];
+  }
+  stz_status ds = STZ_OK;
+  if (hipMalloc(reinterpret_cast<void**>(&dout), std::max<uint64_t>(total, 1) * 4) != hipSuccess)
+    ds = STZ_ERR_NOMEM;
+  for (uint64_t i = 0; i < njobs && ds == STZ_OK; ++i)
+    ds = stz_open(jobs[i].out, jobs[i].out_size, &fields[i], stream);
+  std::vector<stz_request> rq(njobs);
+  std::vector<const void*> dptr(njobs);
+  std::vector<uint64_t> dlen(njobs);
+  if (ds == STZ_OK) {
+    for (uint64_t i = 0; i < njobs; ++i) {
+      stz_request& r = rq[i];
+      std::memset(&r, 0, sizeof(r));
+      r.field = fields[i];
+      for (int d = 0; d < 3; ++d) r.hi[d] = jobs[i].dims[d];
+      r.level = fields[i]->h.c.L;
+      r.out = dout + off[i];
+      r.out_cap_elems = total - off[i];
+      dptr[i] = r.out;
+      dlen[i] = 4 * jobs[i].dims[0] * jobs[i].dims[1] * jobs[i].dims[2];
+    }
+    auto run_d = [&]() { return stz_decompress_batch(rq.data(), njobs, nullptr, stream) == STZ_OK; };
+    std::vector<unsigned long long> dref;
+    if (!run_d() || !t.digest(dptr, dlen)) ds = STZ_ERR_DEVICE;
+    dref = t.hh;
+    auto check_d = [&]() {
+      if (!t.digest(dptr, dlen)) return false;
+      const bool same = t.hh == dref;
+      mismatch = mismatch || !same;
+      return same;
+    };
+    double dbest = ds == STZ_OK ? t.time(run_d, reps) : -1.0;
+    if (dbest < 0) ds = STZ_ERR_DEVICE;
+    if (ds == STZ_OK) {
+      t.note("decode default: %.3f ms", dbest);
+      for (int e : order) {
+        for (int h : dec_heights(e)) {
+          const int keep = tu.dec_h[e];
+          tu.dec_h[e] = h;
+          const double ms = t.time(run_d, reps);
+          if (ms >= 0 && check_d() && ms < dbest) {
+            dbest = ms;
+            t.note("  edge %d decode slab height %d: %.3f ms", 1 << e, h, ms);
+          } else {
+            tu.dec_h[e] = keep;
+          }
+        }
+        for (unsigned gsz : grids) {
+          const unsigned keep = tu.grid_dec[e];
+          tu.grid_dec[e] = gsz;
+          const double ms = t.time(run_d, reps);
+          if (ms >= 0 && check_d() && ms < dbest) {
+            dbest = ms;
+            t.note("  edge %d decode grid %u: %.3f ms", 1 << e, gsz, ms);
+          } else {
+            tu.grid_dec[e] = keep;
+          }
+        }
+      }
+      t.note("decode tuned: %.3f ms", dbest);
+    }
+  }
+  for (stz_field f : fields) stz_close(f);
+  if (dout) (void)hipFree(dout);
+  if (mismatch) t.note("some candidates changed the output and were rejected");
+  if (report && report_cap) {
+    const uint64_t k = std::min<uint64_t>(report_cap - 1, t.rep.size());
+    std::memcpy(report, t.rep.data(), k);
+    report[k] = 0;
+  }
+  return ds;
 }
 
 stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* stream) {

@@ -42,15 +42,14 @@ __device__ void bitonic_sort(uint64_t* key, int n) {
 // Code lengths for counts ceil(hist / 2^k), k = blockIdx.x: two queues over the
 // leaves sorted by (count, symbol), ties to the leaf queue, merged nodes in
 // creation order; depths by pointer jumping.
-__global__ __launch_bounds__(kCbThreads) void k_cb_build(const unsigned long long* hist, int nsym,
-                                                         uint8_t* lens_k, int* maxlen_k) {
+__device__ inline void cb_build_body(const unsigned long long* hist, int nsym, uint8_t* lens_k,
+                                     int* maxlen_k, int k) {
   __shared__ uint64_t W[2 * kCbMax];
   __shared__ uint16_t par[2 * kCbMax];
   __shared__ uint16_t dep[2 * kCbMax];
   __shared__ uint16_t leaf[kCbMax];
   __shared__ int s_m, s_max;
   const int t = threadIdx.x;
-  const int k = blockIdx.x;
   uint8_t* lens = lens_k + size_t(k) * nsym;
   int np2 = 1;
   while (np2 < nsym) np2 <<= 1;
@@ -158,10 +157,14 @@ __global__ __launch_bounds__(kCbThreads) void k_cb_build(const unsigned long lon
   if (t == 0) maxlen_k[k] = s_max;
 }
 
+__global__ __launch_bounds__(kCbThreads) void k_cb_build(const unsigned long long* hist, int nsym,
+                                                         uint8_t* lens_k, int* maxlen_k) {
+  cb_build_body(hist, nsym, lens_k, maxlen_k, blockIdx.x);
+}
+
 // Pick the first scale whose code fits in kLmax bits; canonical codes.
-__global__ __launch_bounds__(kCbThreads) void k_cb_final(const uint8_t* lens_k, const int* maxlen_k,
-                                                         int nsym, uint8_t* lens_out,
-                                                         uint16_t* codes_out) {
+__device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k, int nsym,
+                                     uint8_t* lens_out, uint16_t* codes_out) {
   __shared__ uint64_t key[kCbMax];
   __shared__ uint32_t bl[kLmax + 2], first[kLmax + 1], start[kLmax + 1];
   __shared__ int s_k;
@@ -208,14 +211,46 @@ __global__ __launch_bounds__(kCbThreads) void k_cb_final(const uint8_t* lens_k, 
   }
 }
 
+__global__ __launch_bounds__(kCbThreads) void k_cb_final(const uint8_t* lens_k, const int* maxlen_k,
+                                                         int nsym, uint8_t* lens_out,
+                                                         uint16_t* codes_out) {
+  cb_final_body(lens_k, maxlen_k, nsym, lens_out, codes_out);
+}
+
+// Scratch split: per-scale lengths, then per-scale longest code.
+__host__ __device__ inline uint8_t* cb_lens_k(void* scratch) {
+  return static_cast<uint8_t*>(scratch);
+}
+__host__ __device__ inline int* cb_maxlen_k(void* scratch, int nsym) {
+  return reinterpret_cast<int*>(static_cast<uint8_t*>(scratch) +
+                                ((size_t(kCbScales) * nsym + 15) & ~size_t(15)));
+}
+
+// Batched code books, one job per blockIdx.y. Scale k0 + blockIdx.x; scales
+// above 0 are skipped when scale 0 already fits (the common case), so a batch
+// pays for one tree per field unless a field needs the length limit.
+__global__ __launch_bounds__(kCbThreads) void kb_cb_build(const CompressArgs* J, int k0) {
+  const CompressArgs& a = J[blockIdx.y];
+  const int nsym = 2 * a.geo.R;
+  int* mk = cb_maxlen_k(a.cb_scratch, nsym);
+  if (k0 > 0 && mk[0] <= kLmax) return;
+  cb_build_body(a.hist, nsym, cb_lens_k(a.cb_scratch), mk, k0 + int(blockIdx.x));
+}
+
+__global__ __launch_bounds__(kCbThreads) void kb_cb_final(const CompressArgs* J) {
+  const CompressArgs& a = J[blockIdx.x];
+  const int nsym = 2 * a.geo.R;
+  cb_final_body(cb_lens_k(a.cb_scratch), cb_maxlen_k(a.cb_scratch, nsym), nsym, a.lens, a.codes);
+}
+
 }  // namespace
 
 size_t codebook_scratch_bytes(int nsym) { return size_t(kCbScales) * (size_t(nsym) + 4) + 64; }
 
 void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, uint16_t* codes,
                      void* scratch, hipStream_t st) {
-  uint8_t* lens_k = static_cast<uint8_t*>(scratch);
-  int* maxlen_k = reinterpret_cast<int*>(lens_k + ((size_t(kCbScales) * nsym + 15) & ~size_t(15)));
+  uint8_t* lens_k = cb_lens_k(scratch);
+  int* maxlen_k = cb_maxlen_k(scratch, nsym);
   prof_begin(st, "cb_build", -1);
   hipLaunchKernelGGL(k_cb_build, dim3(kCbScales), dim3(kCbThreads), 0, st, hist, nsym, lens_k,
                      maxlen_k);
@@ -223,6 +258,16 @@ void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, ui
   prof_begin(st, "cb_final", -1);
   hipLaunchKernelGGL(k_cb_final, dim3(1), dim3(kCbThreads), 0, st, lens_k, maxlen_k, nsym, lens,
                      codes);
+  prof_end(st);
+}
+
+void launch_codebook_batch(const CompressArgs* J, uint32_t njobs, hipStream_t st) {
+  prof_begin(st, "b_cb_build", -1);
+  hipLaunchKernelGGL(kb_cb_build, dim3(1, njobs), dim3(kCbThreads), 0, st, J, 0);
+  hipLaunchKernelGGL(kb_cb_build, dim3(kCbScales - 1, njobs), dim3(kCbThreads), 0, st, J, 1);
+  prof_end(st);
+  prof_begin(st, "b_cb_final", -1);
+  hipLaunchKernelGGL(kb_cb_final, dim3(njobs), dim3(kCbThreads), 0, st, J);
   prof_end(st);
 }
 

@@ -2,6 +2,8 @@
 // anchors, per-level predict+quantize (Sec. 3.1, Eqs. 3-8, Optimizations 3
 // and 5) with the code histogram, per-lane code lengths, segmented scans for
 // the stream layout, bit packing and outlier compaction.
+#include <algorithm>
+
 #include "stz_slab.h"
 
 namespace stz {
@@ -11,7 +13,10 @@ namespace {
 // ---------------------------------------------------------------------------
 // Compression kernels
 // ---------------------------------------------------------------------------
-__global__ void k_init(DevParams* P, unsigned long long* hist, int nsym) {
+// Every kernel is a device body run by one work-group (`wg` of `ngrid` for
+// grid-stride bodies) plus a plain launch; the batched launches run the same
+// bodies over a work map of many jobs.
+__device__ inline void init_body(DevParams* P, unsigned long long* hist, int nsym) {
   const int t = threadIdx.x;
   if (t == 0) {
     P->flags = 0;
@@ -20,12 +25,16 @@ __global__ void k_init(DevParams* P, unsigned long long* hist, int nsym) {
   for (int i = t; i < nsym; i += blockDim.x) hist[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N,
-                                                float2* part, DevParams* P) {
+__global__ void k_init(DevParams* P, unsigned long long* hist, int nsym) {
+  init_body(P, hist, nsym);
+}
+
+__device__ inline void minmax_body(const float* __restrict__ x, uint64_t N, float2* part,
+                                   DevParams* P, uint64_t wg, uint64_t ngrid) {
   float mn = INFINITY, mx = -INFINITY;
   bool bad = false;
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  const uint64_t t0 = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t stride = ngrid * blockDim.x;
+  const uint64_t t0 = wg * blockDim.x + threadIdx.x;
   uint64_t head = 0;  // elements handled by 16-byte loads
   if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
     head = N & ~uint64_t(3);
@@ -60,13 +69,18 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
       mn = fminf(mn, smn[i]);
       mx = fmaxf(mx, smx[i]);
     }
-    part[blockIdx.x] = make_float2(mn, mx);
+    part[wg] = make_float2(mn, mx);
   }
 }
 
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N,
+                                                float2* part, DevParams* P) {
+  minmax_body(x, N, part, P, blockIdx.x, gridDim.x);
+}
+
 // Resolve the absolute bound and the per-level constants (format 2.3).
-__global__ void k_resolve(DevParams* P, const float2* part, uint32_t nparts, int mode, double eb,
-                          double ratio, int L) {
+__device__ inline void resolve_body(DevParams* P, const float2* part, uint32_t nparts, int mode,
+                                    double eb, double ratio, int L) {
   if (threadIdx.x != 0) return;
   double eb_abs = eb;
   if (mode == 1) {
@@ -99,21 +113,31 @@ __global__ void k_resolve(DevParams* P, const float2* part, uint32_t nparts, int
   }
 }
 
+__global__ void k_resolve(DevParams* P, const float2* part, uint32_t nparts, int mode, double eb,
+                          double ratio, int L) {
+  resolve_body(P, part, nparts, mode, eb, ratio, L);
+}
+
 // Anchors: the stride-2^L grid, copied verbatim into the level-0 grid.
-__global__ void k_anchor(const float* __restrict__ x, Geo g, float* rec0, DevParams* P) {
+__device__ inline void anchor_body(const float* __restrict__ x, const Geo& g, float* rec0,
+                                   DevParams* P, uint64_t wg, uint64_t ngrid) {
   const int logs = g.L;
   const int64_t c0 = ((g.n[0] - 1) >> logs) + 1, c1 = ((g.n[1] - 1) >> logs) + 1,
                 c2 = ((g.n[2] - 1) >> logs) + 1;
   const int64_t na = c0 * c1 * c2;
   bool bad = false;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < na;
-       i += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t i = int64_t(wg) * blockDim.x + threadIdx.x; i < na;
+       i += int64_t(ngrid) * blockDim.x) {
     const int64_t ix = i % c2, t = i / c2, iy = t % c1, iz = t / c1;
     const float v = x[((iz << logs) * g.n[1] + (iy << logs)) * g.n[2] + (ix << logs)];
     bad |= !isfinite(v);
     rec0[i] = v;
   }
   if (bad) atomicOr(&P->flags, kFlagNonfinite);
+}
+
+__global__ void k_anchor(const float* __restrict__ x, Geo g, float* rec0, DevParams* P) {
+  anchor_body(x, g, rec0, P, blockIdx.x, gridDim.x);
 }
 
 struct PredSlabArgs {
@@ -146,11 +170,11 @@ struct PredRows {
 };
 
 // Predict and quantize one point of class C (0 = coarse copy only).
-template <int E, int C, bool INT>
+template <int E, int H, int C, bool INT>
 __device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int srow,
                                   const float* xrow, float* grow, const int64_t p[3],
                                   uint32_t* n_center, bool* bad) {
-  using S = SlabShape<E>;
+  using S = SlabShape<E, H>;
   if constexpr (C == 0) {
     if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
@@ -169,10 +193,10 @@ __device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int
 }
 
 // This wave's rows of parity type (ZP, YP); classes fixed at compile time.
-template <int E, int ZP, int YP, bool INT>
+template <int E, int H, int ZP, int YP, bool INT>
 __device__ inline void pred_type(const PredRows& c, int hs, int Ey, int wave, int lane,
                                  uint32_t* n_center, bool* bad) {
-  using S = SlabShape<E>;
+  using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
   for_type_rows<E, ZP, YP>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
@@ -183,17 +207,17 @@ __device__ inline void pred_type(const PredRows& c, int hs, int Ey, int wave, in
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {c.oz + lz, c.oy + ly, c.ox + l0};
     const int64_t p1[3] = {c.oz + lz, c.oy + ly, c.ox + l1};
-    if (l0 < c.Ex) pred_point<E, C0, INT>(c, lz, ly, l0, srow, xrow, grow, p0, n_center, bad);
-    if (l1 < c.Ex) pred_point<E, C0 + 1, INT>(c, lz, ly, l1, srow, xrow, grow, p1, n_center, bad);
+    if (l0 < c.Ex) pred_point<E, H, C0, INT>(c, lz, ly, l0, srow, xrow, grow, p0, n_center, bad);
+    if (l1 < c.Ex) pred_point<E, H, C0 + 1, INT>(c, lz, ly, l1, srow, xrow, grow, p1, n_center, bad);
   });
 }
 
 // Predict and quantize every level-l point of one block (format 2.2, 2.3);
 // also writes the block's part of the level-l grid (coarse points copied,
 // level points reconstructed) for the next level's prediction.
-template <int E>
-__global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
-  using S = SlabShape<E>;
+template <int E, int H>
+__device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_remap) {
+  using S = SlabShape<E, H>;
   constexpr int m = S::m;
   __shared__ uint32_t h[2 * kMaxRadius];
   __shared__ float tile[S::TILE];
@@ -202,7 +226,7 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
   const int64_t nblk = a.g.nb[0] * a.g.nb[1] * a.g.nb[2];
-  const int64_t blk = wg_block(blockIdx.x, nblk, true);
+  const int64_t blk = wg_block(wg, nblk, xcd_remap);
   const int64_t bx = blk % a.g.nb[2], by = (blk / a.g.nb[2]) % a.g.nb[1],
                 bz = blk / (a.g.nb[2] * a.g.nb[1]);
   const int64_t oz = bz * E, oy = by * E, ox = bx * E;
@@ -244,15 +268,15 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
     ctx.e = e;
     ctx.R = R;
     if (interior) {
-      pred_type<E, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     } else {
-      pred_type<E, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<E, H, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     }
     __syncthreads();
     // The slab's rows of every unit, column-major inside the unit: column j of
@@ -294,8 +318,8 @@ __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
 }
 
 template <int E>
-void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_pred_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, p);
+__global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
+  pred_body<E, default_slab_h(E)>(a, blockIdx.x, true);
 }
 
 struct LaneLenArgs {
@@ -312,14 +336,14 @@ struct LaneLenArgs {
 
 // Bit length of every lane stream and per-unit totals. One work-group per
 // block: thread t < 7m owns column j = t mod m of the block's class t/m + 1.
-__global__ __launch_bounds__(256) void k_lanelen(LaneLenArgs a) {
+__device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
   __shared__ uint8_t L[2 * kMaxRadius];
   __shared__ uint32_t bits_s[256], out_s[256];
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
   const int m = (a.g.B >> a.logs) >> 1;
   const int tid = threadIdx.x, c = tid / m + 1, j = tid % m;
   const bool is_lane = tid < 7 * m;
-  const int64_t u = int64_t(blockIdx.x) * 7 + (c - 1);
+  const int64_t u = wg * 7 + (c - 1);
   uint32_t bits = 0, no = 0;
   int Mx = 0;
   __syncthreads();
@@ -365,6 +389,8 @@ __global__ __launch_bounds__(256) void k_lanelen(LaneLenArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_lanelen(LaneLenArgs a) { lanelen_body(a, blockIdx.x); }
+
 // ---------------------------------------------------------------------------
 // Segmented exclusive scan: `nseg` segments of n u32 values, out[seg][n+1].
 // ---------------------------------------------------------------------------
@@ -391,21 +417,25 @@ __device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
   return pre + inc - v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_a(const uint32_t* in, uint64_t n, uint64_t* part,
-                                                int nblk) {
-  const int seg = blockIdx.y;
+__device__ inline void scan_a_body(const uint32_t* in, uint64_t n, uint64_t* part, int nblk,
+                                   int seg, int bx) {
   const uint32_t* src = in + uint64_t(seg) * n;
-  const uint64_t base = uint64_t(blockIdx.x) * kScanBlock + uint64_t(threadIdx.x) * kScanItems;
+  const uint64_t base = uint64_t(bx) * kScanBlock + uint64_t(threadIdx.x) * kScanItems;
   uint64_t s = 0;
   for (int i = 0; i < kScanItems; ++i)
     if (base + i < n) s += src[base + i];
   uint64_t tot;
   block_excl_scan(s, &tot);
-  if (threadIdx.x == 0) part[uint64_t(seg) * nblk + blockIdx.x] = tot;
+  if (threadIdx.x == 0) part[uint64_t(seg) * nblk + bx] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_b(uint64_t* part, int nblk) {
-  uint64_t* p = part + uint64_t(blockIdx.x) * nblk;
+__global__ __launch_bounds__(256) void k_scan_a(const uint32_t* in, uint64_t n, uint64_t* part,
+                                                int nblk) {
+  scan_a_body(in, n, part, nblk, blockIdx.y, blockIdx.x);
+}
+
+__device__ inline void scan_b_body(uint64_t* part, int nblk, int seg) {
+  uint64_t* p = part + uint64_t(seg) * nblk;
   uint64_t carry = 0;
   for (int b0 = 0; b0 < nblk; b0 += 256) {
     const int i = b0 + threadIdx.x;
@@ -417,12 +447,15 @@ __global__ __launch_bounds__(256) void k_scan_b(uint64_t* part, int nblk) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_scan_c(const uint32_t* in, uint64_t n, const uint64_t* part,
-                                                int nblk, uint32_t* out, DevParams* P) {
-  const int seg = blockIdx.y;
+__global__ __launch_bounds__(256) void k_scan_b(uint64_t* part, int nblk) {
+  scan_b_body(part, nblk, blockIdx.x);
+}
+
+__device__ inline void scan_c_body(const uint32_t* in, uint64_t n, const uint64_t* part, int nblk,
+                                   uint32_t* out, DevParams* P, int seg, int bx) {
   const uint32_t* src = in + uint64_t(seg) * n;
   uint32_t* dst = out + uint64_t(seg) * (n + 1);
-  const uint64_t base = uint64_t(blockIdx.x) * kScanBlock + uint64_t(threadIdx.x) * kScanItems;
+  const uint64_t base = uint64_t(bx) * kScanBlock + uint64_t(threadIdx.x) * kScanItems;
   uint32_t v[kScanItems];
   uint64_t s = 0;
   for (int i = 0; i < kScanItems; ++i) {
@@ -430,7 +463,7 @@ __global__ __launch_bounds__(256) void k_scan_c(const uint32_t* in, uint64_t n, 
     s += v[i];
   }
   uint64_t tot;
-  uint64_t run = part[uint64_t(seg) * nblk + blockIdx.x] + block_excl_scan(s, &tot);
+  uint64_t run = part[uint64_t(seg) * nblk + bx] + block_excl_scan(s, &tot);
   bool over = false;
   for (int i = 0; i < kScanItems; ++i) {
     if (base + i < n) {
@@ -444,6 +477,11 @@ __global__ __launch_bounds__(256) void k_scan_c(const uint32_t* in, uint64_t n, 
     }
   }
   if (over) atomicOr(&P->flags, kFlagTooLarge);
+}
+
+__global__ __launch_bounds__(256) void k_scan_c(const uint32_t* in, uint64_t n, const uint64_t* part,
+                                                int nblk, uint32_t* out, DevParams* P) {
+  scan_c_body(in, n, part, nblk, out, P, blockIdx.y, blockIdx.x);
 }
 
 struct LayoutArgs {
@@ -466,7 +504,7 @@ __device__ inline void st64(uint8_t* p, uint64_t v) {
 }
 
 // Stream layout (format 2.5) from the scanned totals; writes the header.
-__global__ void k_layout(LayoutArgs a) {
+__device__ inline void layout_body(const LayoutArgs& a) {
   if (threadIdx.x != 0) return;
   DevParams* P = a.P;
   const int L = a.g.L;
@@ -515,30 +553,43 @@ __global__ void k_layout(LayoutArgs a) {
   }
 }
 
+__global__ void k_layout(LayoutArgs a) { layout_body(a); }
+
 // Zero [from, total) of the stream (padding and the words packed with atomics).
-__global__ void k_zero(uint8_t* out, uint64_t from, const DevParams* P) {
+__device__ inline void zero_body(uint8_t* out, uint64_t from, const DevParams* P, uint64_t wg,
+                                 uint64_t ngrid) {
   if (P->flags) return;
   const uint64_t to = P->total;
   uint4* p = reinterpret_cast<uint4*>(out);
   const uint4 z = make_uint4(0, 0, 0, 0);
-  for (uint64_t i = from / 16 + uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < to / 16;
-       i += uint64_t(gridDim.x) * blockDim.x)
+  for (uint64_t i = from / 16 + wg * blockDim.x + threadIdx.x; i < to / 16;
+       i += ngrid * blockDim.x)
     p[i] = z;
 }
 
+__global__ void k_zero(uint8_t* out, uint64_t from, const DevParams* P) {
+  zero_body(out, from, P, blockIdx.x, gridDim.x);
+}
+
 // Code lengths and anchors into the stream.
-__global__ void k_fill_head(uint8_t* out, const uint8_t* lens, int nsym, const float* rec0,
-                            uint64_t na, const DevParams* P) {
+__device__ inline void fill_head_body(uint8_t* out, const uint8_t* lens, int nsym,
+                                      const float* rec0, uint64_t na, const DevParams* P,
+                                      uint64_t wg, uint64_t ngrid) {
   if (P->flags) return;
   const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(nsym));
   float* an = reinterpret_cast<float*>(out + anchor_off);
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < na + uint64_t(nsym);
-       i += uint64_t(gridDim.x) * blockDim.x) {
+  for (uint64_t i = wg * blockDim.x + threadIdx.x; i < na + uint64_t(nsym);
+       i += ngrid * blockDim.x) {
     if (i < uint64_t(nsym))
       out[kHeaderBytes + i] = lens[i];
     else
       an[i - nsym] = rec0[i - nsym];
   }
+}
+
+__global__ void k_fill_head(uint8_t* out, const uint8_t* lens, int nsym, const float* rec0,
+                            uint64_t na, const DevParams* P) {
+  fill_head_body(out, lens, nsym, rec0, na, P, blockIdx.x, gridDim.x);
 }
 
 struct PackArgs {
@@ -568,7 +619,7 @@ __device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_
 // Bit-pack every lane stream, write the unit index and the outliers. Same
 // block mapping as k_lanelen; a unit's lanes sit inside one wave, so the
 // rank order of its outliers comes from a per-row ballot.
-__global__ __launch_bounds__(256) void k_pack(PackArgs a) {
+__device__ inline void pack_body(const PackArgs& a, int64_t wg) {
   const DevParams* P = a.P;
   if (P->flags) return;
   __shared__ uint8_t Ls[2 * kMaxRadius];
@@ -587,7 +638,7 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs a) {
   const int m = (a.g.B >> a.logs) >> 1;
   const int tid = threadIdx.x, lane = tid & 63, c = tid / m + 1, j = tid % m;
   const bool is_lane = tid < 7 * m;
-  const int64_t u = int64_t(blockIdx.x) * 7 + (c - 1);
+  const int64_t u = wg * 7 + (c - 1);
   UnitGeo ug;
   uint32_t lb = 0, rows = 0, M1 = 1;
   int Mx = 0;
@@ -674,11 +725,261 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs a) {
   if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
 }
 
+__global__ __launch_bounds__(256) void k_pack(PackArgs a) { pack_body(a, blockIdx.x); }
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launch sequences
 // ---------------------------------------------------------------------------
+namespace {
+
+// Per-level argument blocks of one job, built the same way on the host (plain
+// launches) and on the device (batched launches, from the job table).
+__host__ __device__ inline PredSlabArgs pred_args(const CompressArgs& a, int l) {
+  const Geo& g = a.geo;
+  const int logs = g.L - l;
+  PredSlabArgs p;
+  p.x = a.x;
+  p.g = g;
+  p.level = l;
+  p.logs = logs;
+  for (int q = 0; q < 3; ++q) {
+    p.n[q] = ((g.n[q] - 1) >> logs) + 1;
+    p.nc[q] = ((g.n[q] - 1) >> (logs + 1)) + 1;
+  }
+  p.prev = a.rec[l - 1];
+  p.cur = l < g.L ? a.rec[l] : nullptr;
+  p.sym = a.sym[l];
+  p.P = a.params;
+  p.hist = a.hist;
+  p.nsym = 2 * g.R;
+  return p;
+}
+
+__host__ __device__ inline LaneLenArgs lanelen_args(const CompressArgs& a, int l) {
+  const uint64_t nu = a.lc[1].nu;
+  LaneLenArgs q;
+  q.g = a.geo;
+  q.logs = a.geo.L - l;
+  q.sym = a.sym[l];
+  q.nu = nu;
+  q.lens = a.lens;
+  q.nsym = 2 * a.geo.R;
+  q.lane_len = a.lane_len + a.lane_base[l];
+  q.cnt_words = a.cnt + uint64_t(2 * (l - 1)) * nu;
+  q.cnt_outl = a.cnt + uint64_t(2 * (l - 1) + 1) * nu;
+  return q;
+}
+
+__host__ __device__ inline LayoutArgs layout_args(const CompressArgs& a) {
+  LayoutArgs la;
+  la.g = a.geo;
+  la.eb_mode = a.eb_mode;
+  la.eb = a.eb;
+  la.ratio = a.ratio;
+  la.out_cap = a.out_cap;
+  la.out = a.out;
+  la.P = a.params;
+  la.scan = a.scan;
+  la.nu = a.lc[1].nu;
+  for (int l = 0; l <= kMaxLevels; ++l) la.lc[l] = a.lc[l];
+  la.n_anchor = a.n_anchor;
+  return la;
+}
+
+__host__ __device__ inline PackArgs pack_args(const CompressArgs& a, int l) {
+  const uint64_t nu = a.lc[1].nu;
+  PackArgs p;
+  p.x = a.x;
+  p.g = a.geo;
+  p.level = l;
+  p.logs = a.geo.L - l;
+  p.sym = a.sym[l];
+  p.nu = nu;
+  p.lens = a.lens;
+  p.codes = a.codes;
+  p.nsym = 2 * a.geo.R;
+  p.lane_len = a.lane_len + a.lane_base[l];
+  p.scan_words = a.scan + uint64_t(2 * (l - 1)) * (nu + 1);
+  p.scan_outl = a.scan + uint64_t(2 * (l - 1) + 1) * (nu + 1);
+  p.out = a.out;
+  p.P = a.params;
+  return p;
+}
+
+__host__ __device__ inline int scan_blocks(const CompressArgs& a) {
+  return int((a.lc[1].nu + kScanBlock - 1) / kScanBlock);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: a work map gives each job [first[i], first[i+1]) of the
+// launch's items (job[i] = index into the job table); persistent work-groups
+// walk the items with a grid stride, so any grid size covers any batch.
+// ---------------------------------------------------------------------------
+__device__ inline int map_find(const ItemMap& m, uint32_t item, uint32_t* loc, uint32_t* cnt) {
+  int lo = 0, hi = int(m.n);  // first[lo] <= item < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (m.first[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  *loc = item - m.first[lo];
+  *cnt = m.first[lo + 1] - m.first[lo];
+  return int(m.job[lo]);
+}
+
+#define STZ_FOR_ITEMS(m)                                                    \
+  for (uint32_t it_ = blockIdx.x, tot_ = (m).first[(m).n]; it_ < tot_;      \
+       it_ += gridDim.x, __syncthreads())
+
+__global__ void kb_init(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    init_body(a.params, a.hist, 2 * a.geo.R);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_minmax(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    const uint64_t N = uint64_t(a.geo.n[0]) * a.geo.n[1] * a.geo.n[2];
+    minmax_body(a.x, N, a.part, a.params, loc, cnt);
+  }
+}
+
+__global__ void kb_resolve(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    resolve_body(a.params, a.part, a.nparts, a.eb_mode, a.eb, a.ratio, a.geo.L);
+  }
+}
+
+__global__ void kb_anchor(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    anchor_body(a.x, a.geo, a.rec[0], a.params, loc, cnt);
+  }
+}
+
+template <int E, int H>
+__global__ __launch_bounds__(256) void kb_pred(const CompressArgs* J, ItemMap m, int l) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    pred_body<E, H>(pred_args(a, l), loc, false);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_lanelen(const CompressArgs* J, ItemMap m, int l) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    lanelen_body(lanelen_args(a, l), loc);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_scan_a(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    const int nb = scan_blocks(a);
+    scan_a_body(a.cnt, a.lc[1].nu, a.scan_part, nb, int(loc) / nb, int(loc) % nb);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_scan_b(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    scan_b_body(a.scan_part, scan_blocks(a), int(loc));
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_scan_c(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    const int nb = scan_blocks(a);
+    scan_c_body(a.cnt, a.lc[1].nu, a.scan_part, nb, a.scan, a.params, int(loc) / nb,
+                int(loc) % nb);
+  }
+}
+
+__global__ void kb_layout(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    layout_body(layout_args(a));
+  }
+}
+
+__global__ void kb_zero(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    zero_body(a.out, kHeaderBytes, a.params, loc, cnt);
+  }
+}
+
+__global__ void kb_fill_head(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    fill_head_body(a.out, a.lens, 2 * a.geo.R, a.rec[0], a.n_anchor, a.params, loc, cnt);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_pack(const CompressArgs* J, ItemMap m, int l) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    pack_body(pack_args(a, l), loc);
+  }
+}
+
+template <int E>
+void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, p);
+}
+
+template <int E, int H>
+void launch_pred_b(const CompressArgs* J, const ItemMap& m, int l, unsigned grid,
+                   hipStream_t st) {
+  hipLaunchKernelGGL((kb_pred<E, H>), dim3(grid), dim3(256), 0, st, J, m, l);
+}
+
+// Slab heights the batched predictor is built for, per level block edge.
+template <int E>
+bool launch_pred_bh(int h, const CompressArgs* J, const ItemMap& m, int l, unsigned grid,
+                    hipStream_t st) {
+  if constexpr (E <= 8) {
+    if (h == E) return launch_pred_b<E, E>(J, m, l, grid, st), true;
+    if constexpr (E == 8)
+      if (h == 4) return launch_pred_b<8, 4>(J, m, l, grid, st), true;
+  } else if constexpr (E == 16) {
+    if (h == 4) return launch_pred_b<16, 4>(J, m, l, grid, st), true;
+    if (h == 8) return launch_pred_b<16, 8>(J, m, l, grid, st), true;
+    if (h == 16) return launch_pred_b<16, 16>(J, m, l, grid, st), true;
+  } else if constexpr (E == 32) {
+    if (h == 2) return launch_pred_b<32, 2>(J, m, l, grid, st), true;
+    if (h == 4) return launch_pred_b<32, 4>(J, m, l, grid, st), true;
+    if (h == 8) return launch_pred_b<32, 8>(J, m, l, grid, st), true;
+  } else {
+    if (h == 2) return launch_pred_b<64, 2>(J, m, l, grid, st), true;
+    if (h == 4) return launch_pred_b<64, 4>(J, m, l, grid, st), true;
+  }
+  return launch_pred_b<E, default_slab_h(E)>(J, m, l, grid, st), true;
+}
+
+}  // namespace
+
 hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   const Geo& g = a.geo;
   const int L = g.L;
@@ -702,24 +1003,9 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
                      a.rec[0], a.params);
   prof_end(st);
   for (int l = 1; l <= L; ++l) {
-    const int logs = L - l;
-    PredSlabArgs p;
-    p.x = a.x;
-    p.g = g;
-    p.level = l;
-    p.logs = logs;
-    for (int q = 0; q < 3; ++q) {
-      p.n[q] = ((g.n[q] - 1) >> logs) + 1;
-      p.nc[q] = ((g.n[q] - 1) >> (logs + 1)) + 1;
-    }
-    p.prev = a.rec[l - 1];
-    p.cur = l < L ? a.rec[l] : nullptr;
-    p.sym = a.sym[l];
-    p.P = a.params;
-    p.hist = a.hist;
-    p.nsym = nsym;
+    const PredSlabArgs p = pred_args(a, l);
     const int64_t nblk = g.nb[0] * g.nb[1] * g.nb[2];
-    const int E = g.B >> logs;
+    const int E = g.B >> (L - l);
     prof_begin(st, "predict", l);
     switch (E) {
       case 2: launch_pred<2>(p, nblk, st); break;
@@ -733,21 +1019,11 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   }
   launch_codebook(a.hist, nsym, a.lens, a.codes, a.cb_scratch, st);
   for (int l = 1; l <= L; ++l) {
-    LaneLenArgs q;
-    q.g = g;
-    q.logs = L - l;
-    q.sym = a.sym[l];
-    q.nu = nu;
-    q.lens = a.lens;
-    q.nsym = nsym;
-    q.lane_len = a.lane_len + a.lane_base[l];
-    q.cnt_words = a.cnt + uint64_t(2 * (l - 1)) * nu;
-    q.cnt_outl = a.cnt + uint64_t(2 * (l - 1) + 1) * nu;
     prof_begin(st, "lanelen", l);
-    hipLaunchKernelGGL(k_lanelen, dim3(unsigned(nu / 7)), dim3(256), 0, st, q);
+    hipLaunchKernelGGL(k_lanelen, dim3(unsigned(nu / 7)), dim3(256), 0, st, lanelen_args(a, l));
     prof_end(st);
   }
-  const int nblk = int((nu + kScanBlock - 1) / kScanBlock);
+  const int nblk = scan_blocks(a);
   prof_begin(st, "scan_a", -1);
   hipLaunchKernelGGL(k_scan_a, dim3(nblk, 2 * L), dim3(256), 0, st, a.cnt, nu, a.scan_part, nblk);
   prof_end(st);
@@ -758,20 +1034,8 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_c, dim3(nblk, 2 * L), dim3(256), 0, st, a.cnt, nu, a.scan_part, nblk,
                      a.scan, a.params);
   prof_end(st);
-  LayoutArgs la;
-  la.g = g;
-  la.eb_mode = a.eb_mode;
-  la.eb = a.eb;
-  la.ratio = a.ratio;
-  la.out_cap = a.out_cap;
-  la.out = a.out;
-  la.P = a.params;
-  la.scan = a.scan;
-  la.nu = nu;
-  for (int l = 0; l <= kMaxLevels; ++l) la.lc[l] = a.lc[l];
-  la.n_anchor = a.n_anchor;
   prof_begin(st, "layout", -1);
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(64), 0, st, la);
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(64), 0, st, layout_args(a));
   prof_end(st);
   prof_begin(st, "zero", -1);
   hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, a.out, kHeaderBytes, a.params);
@@ -781,23 +1045,113 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
                      a.out, a.lens, nsym, a.rec[0], a.n_anchor, a.params);
   prof_end(st);
   for (int l = 1; l <= L; ++l) {
-    PackArgs p;
-    p.x = a.x;
-    p.g = g;
-    p.level = l;
-    p.logs = L - l;
-    p.sym = a.sym[l];
-    p.nu = nu;
-    p.lens = a.lens;
-    p.codes = a.codes;
-    p.nsym = nsym;
-    p.lane_len = a.lane_len + a.lane_base[l];
-    p.scan_words = a.scan + uint64_t(2 * (l - 1)) * (nu + 1);
-    p.scan_outl = a.scan + uint64_t(2 * (l - 1) + 1) * (nu + 1);
-    p.out = a.out;
-    p.P = a.params;
     prof_begin(st, "pack", l);
-    hipLaunchKernelGGL(k_pack, dim3(unsigned(nu / 7)), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_pack, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
+    prof_end(st);
+  }
+  return hipGetLastError();
+}
+
+namespace {
+
+// Order-independent digest of a byte range (whole 32-bit words; a partial
+// last word is zero-padded): the sum over words of a mix of (value, index).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_hash(const uint8_t* p, uint64_t bytes, unsigned long long* out) {
+  uint64_t acc = 0;
+  const uint64_t nw = (bytes + 3) / 4;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nw;
+       i += uint64_t(gridDim.x) * blockDim.x) {
+    uint32_t w = 0;
+    for (int k = 0; k < 4; ++k)
+      if (4 * i + k < bytes) w |= uint32_t(p[4 * i + k]) << (8 * k);
+    acc += mix64((uint64_t(w) << 32) ^ (i * 0x9e3779b97f4a7c15ull));
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)acc);
+}
+
+__global__ void k_clear64(unsigned long long* p, uint64_t n) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_hash(const void* const* ptrs, const uint64_t* bytes, uint64_t n,
+                       unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear64, dim3(grid_for(n, 256, 256)), dim3(256), 0, st, out, n);
+  for (uint64_t i = 0; i < n; ++i)
+    if (bytes[i])
+      hipLaunchKernelGGL(k_hash, dim3(grid_for((bytes[i] + 3) / 4, 256, 1024)), dim3(256), 0, st,
+                         static_cast<const uint8_t*>(ptrs[i]), bytes[i], out + i);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
+  const unsigned G = b.grid;
+  auto grid = [&](const ItemMap& m, uint32_t total) {
+    return dim3(std::max(1u, std::min<unsigned>(G, total)));
+  };
+  prof_begin(st, "b_init", -1);
+  hipLaunchKernelGGL(kb_init, grid(b.jobs1, b.n_jobs1), dim3(256), 0, st, b.J, b.jobs1);
+  prof_end(st);
+  if (b.n_minmax) {
+    prof_begin(st, "b_minmax", -1);
+    hipLaunchKernelGGL(kb_minmax, grid(b.minmax, b.n_minmax), dim3(256), 0, st, b.J, b.minmax);
+    prof_end(st);
+  }
+  prof_begin(st, "b_resolve", -1);
+  hipLaunchKernelGGL(kb_resolve, grid(b.jobs1, b.n_jobs1), dim3(64), 0, st, b.J, b.jobs1);
+  prof_end(st);
+  prof_begin(st, "b_anchor", -1);
+  hipLaunchKernelGGL(kb_anchor, grid(b.anchor, b.n_anchor), dim3(256), 0, st, b.J, b.anchor);
+  prof_end(st);
+  for (int l = 1; l <= b.max_levels; ++l) {
+    for (int e = 0; e < kBatchEdges; ++e) {
+      const ItemMap& m = b.pred[l][e];
+      if (!b.n_pred[l][e]) continue;
+      const unsigned gp = std::max(1u, std::min<unsigned>(b.grid_pred[e], b.n_pred[l][e]));
+      prof_begin(st, "b_predict", l);
+      const int h = b.pred_h[e];
+      switch (e) {
+        case 1: launch_pred_bh<2>(h, b.J, m, l, gp, st); break;
+        case 2: launch_pred_bh<4>(h, b.J, m, l, gp, st); break;
+        case 3: launch_pred_bh<8>(h, b.J, m, l, gp, st); break;
+        case 4: launch_pred_bh<16>(h, b.J, m, l, gp, st); break;
+        case 5: launch_pred_bh<32>(h, b.J, m, l, gp, st); break;
+        default: launch_pred_bh<64>(h, b.J, m, l, gp, st); break;
+      }
+      prof_end(st);
+    }
+  }
+  launch_codebook_batch(b.J, b.njobs, st);
+  for (int l = 1; l <= b.max_levels; ++l) {
+    prof_begin(st, "b_lanelen", l);
+    hipLaunchKernelGGL(kb_lanelen, grid(b.level[l], b.n_level[l]), dim3(256), 0, st, b.J,
+                       b.level[l], l);
+    prof_end(st);
+  }
+  prof_begin(st, "b_scan", -1);
+  hipLaunchKernelGGL(kb_scan_a, grid(b.scan_ac, b.n_scan_ac), dim3(256), 0, st, b.J, b.scan_ac);
+  hipLaunchKernelGGL(kb_scan_b, grid(b.scan_b, b.n_scan_b), dim3(256), 0, st, b.J, b.scan_b);
+  hipLaunchKernelGGL(kb_scan_c, grid(b.scan_ac, b.n_scan_ac), dim3(256), 0, st, b.J, b.scan_ac);
+  prof_end(st);
+  prof_begin(st, "b_layout", -1);
+  hipLaunchKernelGGL(kb_layout, grid(b.jobs1, b.n_jobs1), dim3(64), 0, st, b.J, b.jobs1);
+  hipLaunchKernelGGL(kb_zero, grid(b.zero, b.n_zero), dim3(256), 0, st, b.J, b.zero);
+  hipLaunchKernelGGL(kb_fill_head, grid(b.head, b.n_head), dim3(256), 0, st, b.J, b.head);
+  prof_end(st);
+  for (int l = 1; l <= b.max_levels; ++l) {
+    prof_begin(st, "b_pack", l);
+    hipLaunchKernelGGL(kb_pack, grid(b.level[l], b.n_level[l]), dim3(256), 0, st, b.J, b.level[l],
+                       l);
     prof_end(st);
   }
   return hipGetLastError();

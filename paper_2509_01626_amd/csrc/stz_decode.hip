@@ -8,6 +8,8 @@
 // ballot over the unit's lanes. The slab's coarse halo is staged in LDS, and
 // the whole slab of the level grid (coarse points copied, level points
 // predicted and dequantized) is written with coalesced rows.
+#include <algorithm>
+
 #include "stz_slab.h"
 
 namespace stz {
@@ -100,9 +102,8 @@ __device__ inline void dec_type(const DecRows& x, int hs, int Ey, int wave, int 
   });
 }
 
-template <int E>
-__global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
-  constexpr int H = dec_slab_h(E);
+template <int E, int H>
+__device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int NL = 7 * m;  // decoding lanes: one per (class, x column)
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
   for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut[i] = a.lut[i];
 
   const int64_t nblk = a.bb_n[0] * a.bb_n[1] * a.bb_n[2];
-  const int64_t bl = wg_block(blockIdx.x, nblk, a.xcd_remap);
+  const int64_t bl = wg_block(wg, nblk, a.xcd_remap);
   const int64_t bx = a.bb_lo[2] + bl % a.bb_n[2];
   const int64_t by = a.bb_lo[1] + (bl / a.bb_n[2]) % a.bb_n[1];
   const int64_t bz = a.bb_lo[0] + bl / (a.bb_n[2] * a.bb_n[1]);
@@ -337,15 +338,20 @@ __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
   if (bad && lane_active && alive) atomicOr(a.flags, kFlagCorrupt);
 }
 
+template <int E>
+__global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
+  dec_body<E, dec_slab_h(E)>(a, blockIdx.x);
+}
+
 // Anchors of the box R_0 from the stream into the level-0 box grid.
-__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, float* rec0,
-                             Grid g0) {
+__device__ inline void dec_anchor_body(const uint8_t* comp, uint64_t anchor_off, const Geo& g,
+                                       float* rec0, const Grid& g0, uint64_t wg, uint64_t ngrid) {
   const int logs = g.L;
   const int64_t c1 = ((g.n[1] - 1) >> logs) + 1, c2 = ((g.n[2] - 1) >> logs) + 1;
   const float* an = reinterpret_cast<const float*>(comp + anchor_off);
   const int64_t n = g0.cnt[0] * g0.cnt[1] * g0.cnt[2];
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t i = int64_t(wg) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(ngrid) * blockDim.x) {
     const int64_t ix = i % g0.cnt[2], t = i / g0.cnt[2], iy = t % g0.cnt[1], iz = t / g0.cnt[1];
     const int64_t z = g0.first[0] + (iz << logs), y = g0.first[1] + (iy << logs),
                   x = g0.first[2] + (ix << logs);
@@ -353,17 +359,130 @@ __global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, fl
   }
 }
 
-// Sentinel entries of a level's unit index (first offsets 0, last = totals).
-__global__ void k_dec_check(const uint32_t* unit_word, const uint32_t* unit_outl, uint64_t nu,
-                            uint64_t words, uint64_t noutl, uint32_t* flags) {
-  if (threadIdx.x == 0 && (unit_word[0] != 0 || unit_outl[0] != 0 || unit_word[nu] != words ||
-                           unit_outl[nu] != noutl))
-    atomicOr(flags, kFlagCorrupt);
+__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, float* rec0,
+                             Grid g0) {
+  dec_anchor_body(comp, anchor_off, g, rec0, g0, blockIdx.x, gridDim.x);
 }
+
+// Sentinel entries of a level's unit index (first offsets 0, last = totals).
+__device__ inline void dec_check_body(const DecSlabArgs& d) {
+  if (threadIdx.x == 0 && (d.unit_word[0] != 0 || d.unit_outl[0] != 0 ||
+                           d.unit_word[d.nu] != d.words || d.unit_outl[d.nu] != d.noutl))
+    atomicOr(d.flags, kFlagCorrupt);
+}
+
+// Level-k argument block of a decode, built the same way on the host (plain
+// launches) and on the device (batched launches, from the request table).
+__host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
+  const Geo& g = a.geo;
+  const int logs = g.L - k;
+  const Grid gp = box_grid(a.box[k - 1], logs + 1);
+  const Grid gc = box_grid(a.box[k], logs);
+  DecSlabArgs d;
+  d.g = g;
+  d.level = k;
+  d.logs = logs;
+  bool full = true;
+  for (int q = 0; q < 3; ++q) {
+    d.n[q] = ((g.n[q] - 1) >> logs) + 1;
+    // grids in level coordinates: level-k coordinate = full / 2^logs
+    d.in_first[q] = gp.first[q] >> (logs + 1);
+    d.in_cnt[q] = gp.cnt[q];
+    d.out_first[q] = gc.first[q] >> logs;
+    d.out_cnt[q] = gc.cnt[q];
+    d.bb_lo[q] = a.box[k].lo[q] >> g.logB;
+    d.bb_n[q] = ((a.box[k].hi[q] - 1) >> g.logB) - d.bb_lo[q] + 1;
+    full = full && a.box[k].lo[q] == 0 && a.box[k].hi[q] == g.n[q];
+  }
+  d.xcd_remap = full;
+  d.prev = a.rec[k - 1];
+  d.cur = a.rec[k];
+  d.unit_word = reinterpret_cast<const uint32_t*>(a.comp + a.sec[k]);
+  d.unit_outl = reinterpret_cast<const uint32_t*>(a.comp + a.off_outl[k]);
+  d.lane_len = reinterpret_cast<const uint16_t*>(a.comp + a.off_lane[k]);
+  d.pay = reinterpret_cast<const uint32_t*>(a.comp + a.off_pay[k]);
+  d.outv = reinterpret_cast<const float*>(a.comp + a.off_out[k]);
+  d.words = a.words[k];
+  d.noutl = a.outl[k];
+  d.nlanes = a.lc[k].nl;
+  d.nu = a.lc[k].nu;
+  d.E2 = a.E2[k];
+  d.lut = a.lut;
+  d.flags = a.flags;
+  return d;
+}
+
+__global__ void k_dec_check(DecSlabArgs d) { dec_check_body(d); }
 
 template <int E>
 void launch_slab(const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_dec_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, d);
+}
+
+// ---- batched decoding over a request table ----------------------------------
+__device__ inline int map_find_d(const ItemMap& m, uint32_t item, uint32_t* loc, uint32_t* cnt) {
+  int lo = 0, hi = int(m.n);  // first[lo] <= item < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (m.first[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  *loc = item - m.first[lo];
+  *cnt = m.first[lo + 1] - m.first[lo];
+  return int(m.job[lo]);
+}
+
+#define STZ_FOR_ITEMS(m)                                                    \
+  for (uint32_t it_ = blockIdx.x, tot_ = (m).first[(m).n]; it_ < tot_;      \
+       it_ += gridDim.x, __syncthreads())
+
+__global__ void kb_dec_anchor(const DecodeArgs* R, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const DecodeArgs& a = R[map_find_d(m, it_, &loc, &cnt)];
+    dec_anchor_body(a.comp, a.anchor_off, a.geo, a.rec[0], box_grid(a.box[0], a.geo.L), loc,
+                    cnt);
+  }
+}
+
+__global__ void kb_dec_check(const DecodeArgs* R, ItemMap m, int k) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const DecodeArgs& a = R[map_find_d(m, it_, &loc, &cnt)];
+    dec_check_body(dec_args(a, k));
+  }
+}
+
+template <int E, int H>
+__global__ __launch_bounds__(256) void kb_dec(const DecodeArgs* R, ItemMap m, int k) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const DecodeArgs& a = R[map_find_d(m, it_, &loc, &cnt)];
+    DecSlabArgs d = dec_args(a, k);
+    d.xcd_remap = false;
+    dec_body<E, H>(d, loc);
+  }
+}
+
+template <int E, int H>
+void launch_dec_b(const DecodeArgs* R, const ItemMap& m, int k, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((kb_dec<E, H>), dim3(grid), dim3(256), 0, st, R, m, k);
+}
+
+// Slab heights the batched decoder is built for, per level block edge.
+template <int E>
+void launch_dec_bh(int h, const DecodeArgs* R, const ItemMap& m, int k, unsigned grid,
+                   hipStream_t st) {
+  if constexpr (E == 16) {
+    if (h == 4) return launch_dec_b<16, 4>(R, m, k, grid, st);
+    if (h == 8) return launch_dec_b<16, 8>(R, m, k, grid, st);
+  } else if constexpr (E == 32) {
+    if (h == 2) return launch_dec_b<32, 2>(R, m, k, grid, st);
+    if (h == 8) return launch_dec_b<32, 8>(R, m, k, grid, st);
+  }
+  launch_dec_b<E, dec_slab_h(E)>(R, m, k, grid, st);
 }
 
 }  // namespace
@@ -378,47 +497,13 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
                      a.anchor_off, g, a.rec[0], g0);
   prof_end(st);
   for (int k = 1; k <= a.level_out; ++k) {
-    const int logs = L - k;
-    const Grid gp = box_grid(a.box[k - 1], logs + 1);
-    const Grid gc = box_grid(a.box[k], logs);
-    DecSlabArgs d;
-    d.g = g;
-    d.level = k;
-    d.logs = logs;
-    for (int q = 0; q < 3; ++q) {
-      d.n[q] = ((g.n[q] - 1) >> logs) + 1;
-      // grids in level coordinates: level-k coordinate = full / 2^logs
-      d.in_first[q] = gp.first[q] >> (logs + 1);
-      d.in_cnt[q] = gp.cnt[q];
-      d.out_first[q] = gc.first[q] >> logs;
-      d.out_cnt[q] = gc.cnt[q];
-      d.bb_lo[q] = a.box[k].lo[q] >> g.logB;
-      d.bb_n[q] = ((a.box[k].hi[q] - 1) >> g.logB) - d.bb_lo[q] + 1;
-    }
-    bool full = true;
-    for (int q = 0; q < 3; ++q) full = full && a.box[k].lo[q] == 0 && a.box[k].hi[q] == g.n[q];
-    d.xcd_remap = full;
-    d.prev = a.rec[k - 1];
-    d.cur = a.rec[k];
-    d.unit_word = reinterpret_cast<const uint32_t*>(a.comp + a.sec[k]);
-    d.unit_outl = reinterpret_cast<const uint32_t*>(a.comp + a.off_outl[k]);
-    d.lane_len = reinterpret_cast<const uint16_t*>(a.comp + a.off_lane[k]);
-    d.pay = reinterpret_cast<const uint32_t*>(a.comp + a.off_pay[k]);
-    d.outv = reinterpret_cast<const float*>(a.comp + a.off_out[k]);
-    d.words = a.words[k];
-    d.noutl = a.outl[k];
-    d.nlanes = a.lc[k].nl;
-    d.nu = a.lc[k].nu;
-    d.E2 = a.E2[k];
-    d.lut = a.lut;
-    d.flags = a.flags;
+    const DecSlabArgs d = dec_args(a, k);
     prof_begin(st, "dec_check", k);
-    hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, d.unit_word, d.unit_outl, d.nu,
-                       d.words, d.noutl, d.flags);
+    hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, d);
     prof_end(st);
     const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
-    const int E = g.B >> logs;
-    prof_begin(st, full ? "decode" : "rdecode", k);
+    const int E = g.B >> (L - k);
+    prof_begin(st, d.xcd_remap ? "decode" : "rdecode", k);
     switch (E) {
       case 2: launch_slab<2>(d, nblk, st); break;
       case 4: launch_slab<4>(d, nblk, st); break;
@@ -428,6 +513,37 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
       default: launch_slab<64>(d, nblk, st); break;
     }
     prof_end(st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
+  auto grid = [](unsigned cap, uint32_t total) {
+    return std::max(1u, std::min<unsigned>(cap, total));
+  };
+  prof_begin(st, "b_dec_anchor", -1);
+  hipLaunchKernelGGL(kb_dec_anchor, dim3(grid(b.grid, b.n_anchor)), dim3(256), 0, st, b.R,
+                     b.anchor);
+  prof_end(st);
+  for (int k = 1; k <= b.max_level; ++k) {
+    if (!b.n_check[k]) continue;
+    hipLaunchKernelGGL(kb_dec_check, dim3(grid(b.grid, b.n_check[k])), dim3(64), 0, st, b.R,
+                       b.check[k], k);
+    for (int e = 1; e < kBatchEdges; ++e) {
+      if (!b.n_dec[k][e]) continue;
+      const unsigned gd = grid(b.grid_dec[e], b.n_dec[k][e]);
+      const int h = b.dec_h[e];
+      prof_begin(st, "b_decode", k);
+      switch (e) {
+        case 1: launch_dec_bh<2>(h, b.R, b.dec[k][e], k, gd, st); break;
+        case 2: launch_dec_bh<4>(h, b.R, b.dec[k][e], k, gd, st); break;
+        case 3: launch_dec_bh<8>(h, b.R, b.dec[k][e], k, gd, st); break;
+        case 4: launch_dec_bh<16>(h, b.R, b.dec[k][e], k, gd, st); break;
+        case 5: launch_dec_bh<32>(h, b.R, b.dec[k][e], k, gd, st); break;
+        default: launch_dec_bh<64>(h, b.R, b.dec[k][e], k, gd, st); break;
+      }
+      prof_end(st);
+    }
   }
   return hipGetLastError();
 }

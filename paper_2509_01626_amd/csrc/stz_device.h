@@ -201,7 +201,7 @@ inline int grid_for(uint64_t n, int per_block, int cap) {
   return int(b);
 }
 
-inline Grid full_grid(const Geo& g, int logs) {
+__host__ __device__ inline Grid full_grid(const Geo& g, int logs) {
   Grid r;
   for (int d = 0; d < 3; ++d) {
     r.first[d] = 0;
@@ -211,7 +211,7 @@ inline Grid full_grid(const Geo& g, int logs) {
   return r;
 }
 
-inline Grid box_grid(const Box& b, int logs) {
+__host__ __device__ inline Grid box_grid(const Box& b, int logs) {
   Grid r;
   const int64_t s = int64_t(1) << logs;
   for (int d = 0; d < 3; ++d) {

@@ -169,6 +169,49 @@ struct CompressArgs {
 
 hipError_t launch_compress(const CompressArgs& a, hipStream_t st);
 
+// ---- batched launches -------------------------------------------------------
+// Work map of a batched launch: entry i covers items [first[i], first[i+1])
+// of job job[i]; first has n+1 entries. Device pointers.
+struct ItemMap {
+  const uint32_t* first;
+  const uint32_t* job;
+  uint32_t n;
+};
+
+constexpr int kBatchEdges = 7;  // level block edge E = 2^e, e = 1..6
+
+// One batched compression: the job table (device) and the work map of every
+// launch; n_* are the item totals (host copies of first[n]).
+struct CompressBatch {
+  const CompressArgs* J;
+  uint32_t njobs;
+  unsigned grid;                               // persistent work-groups per launch
+  unsigned grid_pred[kBatchEdges];             // per level block edge
+  int max_levels;
+  ItemMap jobs1, minmax, anchor, scan_ac, scan_b, zero, head;
+  uint32_t n_jobs1, n_minmax, n_anchor, n_scan_ac, n_scan_b, n_zero, n_head;
+  ItemMap pred[kMaxLevels + 1][kBatchEdges];   // blocks of level l with edge 2^e
+  uint32_t n_pred[kMaxLevels + 1][kBatchEdges];
+  ItemMap level[kMaxLevels + 1];               // blocks of every job with L >= l
+  uint32_t n_level[kMaxLevels + 1];
+  int pred_h[kBatchEdges];                     // predictor slab height per edge
+};
+
+// Launch shapes of the batched kernels (output-invariant), set by the
+// autotuner: persistent work-groups per launch and, per level block edge
+// 2^e, the predictor's and decoder's grids and slab heights.
+struct BatchTuning {
+  unsigned grid;
+  unsigned grid_pred[kBatchEdges];
+  int pred_h[kBatchEdges];
+  unsigned grid_dec[kBatchEdges];
+  int dec_h[kBatchEdges];
+};
+BatchTuning& batch_tuning();
+
+hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st);
+void launch_codebook_batch(const CompressArgs* J, uint32_t njobs, hipStream_t st);
+
 // Code book from the histogram (lengths and canonical codes, 2R entries).
 size_t codebook_scratch_bytes(int nsym);
 void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, uint16_t* codes,
@@ -193,5 +236,29 @@ struct DecodeArgs {
 };
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+
+// One batched decode: the request table (device) and the work maps of every
+// launch. Level k of request r has edge E = B_r >> (L_r - k).
+struct DecodeBatch {
+  const DecodeArgs* R;
+  uint32_t nreq;
+  unsigned grid;
+  unsigned grid_dec[kBatchEdges];
+  int dec_h[kBatchEdges];
+  int max_level;
+  ItemMap anchor;
+  uint32_t n_anchor;
+  ItemMap check[kMaxLevels + 1];
+  uint32_t n_check[kMaxLevels + 1];
+  ItemMap dec[kMaxLevels + 1][kBatchEdges];   // blocks of each request's box at level k
+  uint32_t n_dec[kMaxLevels + 1][kBatchEdges];
+};
+
+hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st);
+
+// Digest of each of n device byte ranges into out[i] (device), for checking
+// that two launch shapes give identical outputs.
+hipError_t launch_hash(const void* const* ptrs, const uint64_t* bytes, uint64_t n,
+                       unsigned long long* out, hipStream_t st);
 
 }  // namespace stz

@@ -28,6 +28,20 @@ class Info(C.Structure):
                 ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64)]
 
 
+class Job(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("dims", C.c_uint64 * 3), ("eb_mode", C.c_int32),
+                ("reserved", C.c_uint32), ("eb", C.c_double), ("cfg", Config),
+                ("out", C.c_void_p), ("out_cap", C.c_uint64), ("out_size", C.c_uint64),
+                ("status", C.c_int32), ("reserved2", C.c_uint32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("field", C.c_void_p), ("lo", C.c_uint64 * 3), ("hi", C.c_uint64 * 3),
+                ("level", C.c_uint32), ("reserved", C.c_uint32), ("out", C.c_void_p),
+                ("out_cap_elems", C.c_uint64), ("out_dims", C.c_uint64 * 3),
+                ("status", C.c_int32), ("reserved2", C.c_uint32)]
+
+
 class StzError(RuntimeError):
     def __init__(self, status, what):
         super().__init__(f"{what}: {_status_string(status)} ({status})")
@@ -61,6 +75,20 @@ def lib():
         L.stz_decompress_region.restype = C.c_int
         L.stz_decompress_region.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32,
                                             C.c_void_p, C.c_uint64, u64p, C.c_void_p]
+        L.stz_compress_batch.restype = C.c_int
+        L.stz_compress_batch.argtypes = [C.POINTER(Job), C.c_uint64, C.c_void_p]
+        L.stz_open.restype = C.c_int
+        L.stz_open.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p), C.c_void_p]
+        L.stz_field_info.restype = C.c_int
+        L.stz_field_info.argtypes = [C.c_void_p, C.POINTER(Info)]
+        L.stz_close.restype = None
+        L.stz_close.argtypes = [C.c_void_p]
+        L.stz_decompress_batch.restype = C.c_int
+        L.stz_decompress_batch.argtypes = [C.POINTER(Request), C.c_uint64, C.c_void_p,
+                                           C.c_void_p]
+        L.stz_autotune_batch.restype = C.c_int
+        L.stz_autotune_batch.argtypes = [C.POINTER(Job), C.c_uint64, C.c_char_p, C.c_uint64,
+                                         C.c_void_p]
         L.stz_trim.restype = C.c_int
         L.stz_trim.argtypes = []
         L.stz_status_string.restype = C.c_char_p
@@ -214,3 +242,104 @@ def decode_status(comp, fn="decompress", level=0, lo=None, hi=None, stream=None)
                                       _stream(stream))
     return L.stz_decompress_region(p, n, _dims(lo), _dims(hi), level, C.c_void_p(out.data_ptr()),
                                    out.numel(), od, _stream(stream))
+
+
+# ---- batched compression -------------------------------------------------------
+def make_jobs(xs, modes, ebs, cfgs, outs):
+    """ctypes job array for device tensors xs (float32) and byte buffers outs."""
+    n = len(xs)
+    jobs = (Job * n)()
+    for i in range(n):
+        x, out = xs[i], outs[i]
+        _check_dev(x, torch.float32)
+        _check_dev(out, torch.uint8)
+        j = jobs[i]
+        j.x = x.data_ptr()
+        for d in range(3):
+            j.dims[d] = int(x.shape[d])
+        j.eb_mode = int(modes[i])
+        j.eb = float(ebs[i])
+        j.cfg = cfgs[i]
+        j.out = out.data_ptr()
+        j.out_cap = out.numel()
+    return jobs
+
+
+def stz_compress_batch(xs, modes, ebs, cfgs, outs, stream=None, check=True):
+    """Compress many fields with one launch sequence; returns the compressed
+    views (outs[i][:size]) and the ctypes job array (per-job status/size)."""
+    jobs = make_jobs(xs, modes, ebs, cfgs, outs)
+    st = lib().stz_compress_batch(jobs, len(xs), _stream(stream))
+    if check and st != OK:
+        raise StzError(st, "stz_compress_batch")
+    return [outs[i][:jobs[i].out_size] for i in range(len(xs))], jobs
+
+
+def stz_autotune_batch(jobs, stream=None):
+    """Tune the batched launch shapes on `jobs` (a job array); returns the report."""
+    buf = C.create_string_buffer(8192)
+    st = lib().stz_autotune_batch(jobs, len(jobs), buf, 8192, _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_autotune_batch")
+    return buf.value.decode()
+
+
+# ---- resident fields and batched decoding ----------------------------------------
+class Field:
+    """A compressed stream kept in device memory with its decoder table
+    (stz_open); `comp` must stay alive and unchanged while the field is open."""
+
+    def __init__(self, comp, stream=None):
+        _check_dev(comp, torch.uint8)
+        self.comp = comp
+        h = C.c_void_p()
+        st = lib().stz_open(C.c_void_p(comp.data_ptr()), comp.numel(), C.byref(h),
+                            _stream(stream))
+        if st != OK:
+            raise StzError(st, "stz_open")
+        self.handle = h
+        self.info = Info()
+        lib().stz_field_info(h, C.byref(self.info))
+
+    def close(self):
+        if self.handle:
+            lib().stz_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def make_requests(items):
+    """items: (field, lo, hi, level, out tensor) tuples -> ctypes request array."""
+    n = len(items)
+    reqs = (Request * n)()
+    for i, (f, lo, hi, level, out) in enumerate(items):
+        _check_dev(out, torch.float32)
+        r = reqs[i]
+        r.field = f.handle
+        for d in range(3):
+            r.lo[d] = int(lo[d])
+            r.hi[d] = int(hi[d])
+        r.level = int(level)
+        r.out = out.data_ptr()
+        r.out_cap_elems = out.numel()
+    return reqs
+
+
+def stz_decompress_batch(reqs, flags=None, stream=None, check=True):
+    """Run a request array. With `flags` (device uint32 tensor, one word per
+    request) the call is asynchronous and corruption lands in the flags."""
+    fp = None
+    if flags is not None:
+        if not flags.is_cuda or flags.dtype != torch.int32 or flags.numel() < len(reqs):
+            raise ValueError("flags must be a device int32 tensor with one word per request")
+        fp = C.c_void_p(flags.data_ptr())
+    st = lib().stz_decompress_batch(reqs, len(reqs), fp, _stream(stream))
+    if check and st != OK:
+        raise StzError(st, "stz_decompress_batch")
+    return st
+
