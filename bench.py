@@ -37,6 +37,17 @@ def parse():
                     help="do not record per-kernel events in the timed region")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--batch-fields", type=int, default=256,
+                    help="fields in the many-field batch (0 = skip)")
+    ap.add_argument("--scale-n", type=int, default=1024,
+                    help="edge of the 4 co-located variables (0 = skip)")
+    ap.add_argument("--serve-fields", type=int, default=16, help="resident fields (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per offered load")
+    ap.add_argument("--serve-rates", default="1000,4000,16000",
+                    help="offered loads, requests per second")
+    ap.add_argument("--only", default="",
+                    help="comma list of sections to run: plain,batch,scale,serve")
     return ap.parse_args()
 
 
@@ -307,7 +318,290 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
     }
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(name):
+        return not only or name in only
+
+    if args.batch_fields > 0 and want("batch"):
+        res["batched"] = bench_batched(args, dev, oracle_check=not args.no_cpu_baseline)
+    if args.scale_n > 0 and want("scale"):
+        res["scale"] = bench_scale(args, dev)
+    if args.serve_fields > 0 and want("serve"):
+        res["serving"] = bench_serve(args, dev)
     print(json.dumps(res), flush=True)
+
+
+def _sync_time(f, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        f()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def bench_batched(args, dev, oracle_check=True):
+    """Many uneven fields: plain per-field calls vs one batched launch sequence
+    (launch shapes from the autotuner), same bounds, same outputs."""
+    import numpy as np
+    import torch
+
+    from paper_2509_01626_amd import fields, stz
+    desc = fields.batch_fields(args.batch_fields, 32, 256, seed=1000)
+    t0 = time.time()
+    xs = [fields.make_t(kind, dims, seed, dev) for kind, dims, seed, _ in desc]
+    torch.cuda.synchronize()
+    print(f"[bench] batch: {len(xs)} fields generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    ebs = [eb for _, _, _, eb in desc]
+    B = 32
+    cfgs = [stz.config(block=B) for _ in xs]
+    modes = [stz.EB_REL] * len(xs)
+    nvals = sum(x.numel() for x in xs)
+    fbytes = 4 * nvals
+    outs = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8, device=dev)
+            for x, c in zip(xs, cfgs)]
+    outs_p = [torch.empty_like(o) for o in outs]
+    # plain path: one call per field
+    plain_sizes = [0] * len(xs)
+
+    def plain_c():
+        for i, x in enumerate(xs):
+            c = stz.stz_compress(x, modes[i], ebs[i], cfgs[i], out=outs_p[i])
+            plain_sizes[i] = c.numel()
+
+    plain_c()
+    t_pc = _sync_time(plain_c, args.steps)
+    jobs = stz.make_jobs(xs, modes, ebs, cfgs, outs)
+    report = stz.stz_autotune_batch(jobs)
+    print("[bench] autotune:\n" + report, file=sys.stderr, flush=True)
+
+    def batch_c():
+        st = stz.lib().stz_compress_batch(jobs, len(xs), stz._stream())
+        if st != stz.OK:
+            raise stz.StzError(st, "stz_compress_batch")
+
+    batch_c()
+    t_bc = _sync_time(batch_c, args.steps)
+    sizes = [jobs[i].out_size for i in range(len(xs))]
+    same = sizes == plain_sizes and all(
+        torch.equal(outs[i][:sizes[i]], outs_p[i][:sizes[i]]) for i in range(len(xs)))
+    comps = [outs[i][:sizes[i]] for i in range(len(xs))]
+    # decompression: plain per-field calls vs one batch of full-domain requests
+    recon = [torch.empty_like(x) for x in xs]
+
+    def plain_d():
+        for c, r in zip(comps, recon):
+            stz.stz_decompress(c, out=r)
+
+    plain_d()
+    t_pd = _sync_time(plain_d, args.steps)
+    flds = [stz.Field(c) for c in comps]
+    recon_b = [torch.empty_like(x) for x in xs]
+    reqs = stz.make_requests([(f, [0, 0, 0], list(x.shape), f.info.levels, r)
+                              for f, x, r in zip(flds, xs, recon_b)])
+
+    def batch_d():
+        stz.stz_decompress_batch(reqs)
+
+    batch_d()
+    t_bd = _sync_time(batch_d, args.steps)
+    same_d = all(torch.equal(a.view(torch.int32), b.view(torch.int32))
+                 for a, b in zip(recon, recon_b))
+    ok_bound = all(float((r - x).abs().max()) <= f.info.eb_abs * (1 + 1e-6)
+                   for r, x, f in zip(recon_b, xs, flds))
+    oracle_ok = None
+    if oracle_check:
+        from oracle import oracle as O
+        order = sorted(range(len(xs)), key=lambda i: xs[i].numel())[:2]
+        oracle_ok = True
+        for i in order:
+            want = O.compress(xs[i].cpu().numpy(), O.EB_REL, ebs[i], O.config(block=B))
+            oracle_ok = oracle_ok and want == comps[i].cpu().numpy().tobytes()
+    for f in flds:
+        f.close()
+    cr = fbytes / sum(sizes)
+    res = {
+        "workload": f"{len(xs)} float32 fields, dims per axis U[32,256] (half Gaussian bumps, "
+                    f"half k^-5/3 spectral), rel eb log-uniform [1e-4,1e-2], B={B}",
+        "fields": len(xs), "values": nvals, "field_gb": round(fbytes / 1e9, 3),
+        "compression_ratio": round(cr, 3),
+        "compress_gbps": {"plain": round(fbytes / t_pc / 1e9, 2),
+                          "batched": round(fbytes / t_bc / 1e9, 2)},
+        "decompress_gbps": {"plain": round(fbytes / t_pd / 1e9, 2),
+                            "batched": round(fbytes / t_bd / 1e9, 2)},
+        "compress_ms": {"plain": round(t_pc * 1e3, 3), "batched": round(t_bc * 1e3, 3)},
+        "decompress_ms": {"plain": round(t_pd * 1e3, 3), "batched": round(t_bd * 1e3, 3)},
+        "batched_bytes_equal_plain": bool(same), "batched_decode_equal_plain": bool(same_d),
+        "within_bound": bool(ok_bound), "oracle_sample_equal": oracle_ok,
+        "autotune": [ln for ln in report.splitlines() if "tuned" in ln or "default" in ln],
+    }
+    del xs, outs, outs_p, recon, recon_b, comps
+    torch.cuda.empty_cache()
+    stz.stz_trim()
+    return res
+
+
+def bench_scale(args, dev):
+    """4 co-located variables (log-normal density, three velocity components):
+    plain per-variable calls vs one batch of 4 jobs, B = 64, rel eb 1e-3."""
+    import torch
+
+    from paper_2509_01626_amd import fields, stz
+    n = args.scale_n
+    dims = (n, n, n)
+    t0 = time.time()
+    xs = [fields.lognormal_t(dims, 2.0, 40, dev)] + \
+         [fields.grf_t(dims, 3.0, 41 + i, dev) for i in range(3)]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(f"[bench] scale: 4 x {n}^3 generated in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    cfg = stz.config(block=64)
+    fbytes = 4 * sum(x.numel() for x in xs)
+    outs = [torch.empty(stz.stz_compress_bound(dims, cfg), dtype=torch.uint8, device=dev)
+            for _ in xs]
+    sizes_p = [0] * 4
+
+    def plain_c():
+        for i, x in enumerate(xs):
+            sizes_p[i] = stz.stz_compress(x, stz.EB_REL, 1e-3, cfg, out=outs[i]).numel()
+
+    plain_c()
+    t_pc = _sync_time(plain_c, 2)
+    ref = [outs[i][:sizes_p[i]].clone() for i in range(4)]
+    jobs = stz.make_jobs(xs, [stz.EB_REL] * 4, [1e-3] * 4, [cfg] * 4, outs)
+    report = stz.stz_autotune_batch(jobs)
+    print("[bench] scale autotune:\n" + report, file=sys.stderr, flush=True)
+
+    def batch_c():
+        st = stz.lib().stz_compress_batch(jobs, 4, stz._stream())
+        if st != stz.OK:
+            raise stz.StzError(st, "stz_compress_batch")
+
+    batch_c()
+    t_bc = _sync_time(batch_c, 2)
+    sizes = [jobs[i].out_size for i in range(4)]
+    same = sizes == sizes_p and all(torch.equal(outs[i][:sizes[i]], ref[i]) for i in range(4))
+    del ref
+    comps = [outs[i][:sizes[i]] for i in range(4)]
+    recon = torch.empty(dims, dtype=torch.float32, device=dev)
+    err_ok = True
+
+    def plain_d():
+        for c in comps:
+            stz.stz_decompress(c, out=recon)
+
+    plain_d()
+    t_pd = _sync_time(plain_d, 2)
+    for c, x in zip(comps, xs):
+        stz.stz_decompress(c, out=recon)
+        e = float((recon - x).abs().max())
+        err_ok = err_ok and e <= stz.stz_info(c).eb_abs * (1 + 1e-6)
+    del xs
+    torch.cuda.empty_cache()
+    flds = [stz.Field(c) for c in comps]
+    outs_d = [torch.empty(dims, dtype=torch.float32, device=dev) for _ in range(4)]
+    reqs = stz.make_requests([(f, [0, 0, 0], list(dims), f.info.levels, o)
+                              for f, o in zip(flds, outs_d)])
+
+    def batch_d():
+        stz.stz_decompress_batch(reqs)
+
+    batch_d()
+    t_bd = _sync_time(batch_d, 2)
+    stz.stz_decompress(comps[3], out=recon)
+    same_d = torch.equal(recon.view(torch.int32), outs_d[3].view(torch.int32))
+    for f in flds:
+        f.close()
+    res = {
+        "workload": f"4 x {n}^3 float32: log-normal density exp(G), G with P(k)~k^-2; "
+                    "3 Gaussian random velocity fields with P(k)~k^-3; rel eb 1e-3, B=64",
+        "field_gb": round(fbytes / 1e9, 3),
+        "compression_ratio": round(fbytes / sum(sizes), 3),
+        "compress_gbps": {"plain": round(fbytes / t_pc / 1e9, 2),
+                          "batched": round(fbytes / t_bc / 1e9, 2)},
+        "decompress_gbps": {"plain": round(fbytes / t_pd / 1e9, 2),
+                            "batched": round(fbytes / t_bd / 1e9, 2)},
+        "batched_bytes_equal_plain": bool(same), "batched_decode_equal_plain": bool(same_d),
+        "within_bound": bool(err_ok),
+        "autotune": [ln for ln in report.splitlines() if "tuned" in ln or "default" in ln],
+    }
+    del outs, comps, recon, outs_d
+    torch.cuda.empty_cache()
+    stz.stz_trim()
+    return res
+
+
+def bench_serve(args, dev):
+    """Resident compressed 512^3 fields; Poisson decode requests for random
+    boxes at random progressive levels; continuous batching vs one request
+    per launch."""
+    import numpy as np
+    import torch
+
+    from paper_2509_01626_amd import fields, serve, stz
+    nf = args.serve_fields
+    dims = (512, 512, 512)
+    cfg = stz.config(block=32)
+    comps = []
+    buf = torch.empty(stz.stz_compress_bound(dims, cfg), dtype=torch.uint8, device=dev)
+    t0 = time.time()
+    for i in range(nf):
+        x = fields.spectral_t(dims, 5.0 / 3.0, 500 + i, dev)
+        c = stz.stz_compress(x, stz.EB_REL, 1e-3, cfg, out=buf)
+        comps.append(c.clone())
+        del x
+    del buf
+    torch.cuda.empty_cache()
+    print(f"[bench] serve: {nf} fields compressed in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    flds = [stz.Field(c) for c in comps]
+    infos = [f.info for f in flds]
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    points = []
+    for rate in rates:
+        pt = {"offered_rps": rate}
+        for mode, slots, mb in (("batched", 2, 64), ("plain", 1, 1)):
+            rng = np.random.default_rng(7)
+            arr = serve.poisson_arrivals(rng, args.serve_requests, rate, infos)
+            srv = serve.Server(flds, arena_bytes=8 << 30, slots=slots, max_batch=mb, device=dev)
+            # warm-up requests (not counted)
+            srv.run(serve.poisson_arrivals(np.random.default_rng(8), 50, rate, infos))
+            srv.done = []
+            srv.batch_sizes = []
+            srv.batches = 0
+            t = time.perf_counter()
+            done = srv.run(arr)
+            wall = time.perf_counter() - t
+            st = serve.latency_stats(done)
+            ok = sum(1 for r in done if r.status == stz.OK)
+            pt[mode] = {"completed_rps": round(ok / wall, 1), "p50_ms": st["p50_ms"],
+                        "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                        "launch_batches": srv.batches,
+                        "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)),
+                                            2)}
+            del srv
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            stz.stz_trim()  # the server's streams are gone: drop their scratch
+        print(f"[bench] serve rate {rate}: {pt}", file=sys.stderr, flush=True)
+        points.append(pt)
+    for f in flds:
+        f.close()
+    res = {
+        "workload": f"{nf} resident compressed 512^3 k^-5/3 spectral fields (rel eb 1e-3, B=32); "
+                    "Poisson requests: uniform field, level U{0..5}, box edge per axis U[16,256]",
+        "requests_per_load": args.serve_requests,
+        "resident_compressed_gb": round(sum(c.numel() for c in comps) / 1e9, 3),
+        "load_points": points,
+    }
+    del comps, flds
+    torch.cuda.empty_cache()
+    stz.stz_trim()
+    return res
 
 
 def _cpu_model():

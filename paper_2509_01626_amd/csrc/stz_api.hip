@@ -583,14 +583,17 @@ struct BatchMaps {
   std::vector<std::pair<ItemMap*, uint64_t>> fix;  // map, offset of its first[]
 
   // counts[k] items for table entry k; entries with no items are left out.
-  uint32_t add(ItemMap* m, const std::vector<uint32_t>& counts) {
+  // With pad8 every entry's range is rounded up to a multiple of 8 items, so
+  // that in a launch whose grid is a multiple of 8 the item's position within
+  // its job mod 8 is the XCD its work-group runs on (kernels skip the padding).
+  uint32_t add(ItemMap* m, const std::vector<uint32_t>& counts, bool pad8 = false) {
     std::vector<uint32_t> first, job;
     uint32_t run = 0;
     for (uint32_t k = 0; k < counts.size(); ++k) {
       if (!counts[k]) continue;
       first.push_back(run);
       job.push_back(k);
-      run += counts[k];
+      run += pad8 ? (counts[k] + 7) & ~7u : counts[k];
     }
     first.push_back(run);
     m->n = uint32_t(job.size());
@@ -653,7 +656,7 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
         const Geo& g = a.geo;
         if (g.L < l || ilog2(g.B >> (g.L - l)) != e) return 0u;
         return uint32_t(g.nb[0] * g.nb[1] * g.nb[2]);
-      }));
+      }), true);
     }
     b->n_level[l] = maps->add(&b->level[l], per_job([&](const CompressArgs& a) {
       const Geo& g = a.geo;
@@ -676,7 +679,7 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
 
 // Work maps of a batched decode over the live requests (table order).
 void build_decode_maps(const std::vector<DecodePlan>& pl, const std::vector<uint32_t>& live,
-                       BatchMaps* maps, DecodeBatch* b) {
+                       BatchMaps* maps, DecodeBatch* b, std::vector<DirectItem>* direct) {
   std::memset(b, 0, sizeof(*b));
   const uint32_t n = uint32_t(live.size());
   b->nreq = n;
@@ -701,6 +704,14 @@ void build_decode_maps(const std::vector<DecodePlan>& pl, const std::vector<uint
     b->n_check[k] = maps->add(&b->check[k], per_req([&](const DecodeArgs& a) {
       return a.level_out >= k ? 1u : 0u;
     }));
+    for (uint32_t r = 0; r < n; ++r) {
+      const DecodeArgs& a = pl[live[r]].a;
+      if (a.level_out < k) continue;
+      uint64_t nb = 1;
+      for (int q = 0; q < 3; ++q)
+        nb *= uint64_t(((a.box[k].hi[q] - 1) >> a.geo.logB) - (a.box[k].lo[q] >> a.geo.logB) + 1);
+      if (nb >= kDirectBlocks) direct->push_back({r, k});
+    }
     for (int e = 1; e < kBatchEdges; ++e) {
       b->n_dec[k][e] = maps->add(&b->dec[k][e], per_req([&](const DecodeArgs& a) {
         const Geo& g = a.geo;
@@ -708,8 +719,8 @@ void build_decode_maps(const std::vector<DecodePlan>& pl, const std::vector<uint
         uint64_t nb = 1;
         for (int q = 0; q < 3; ++q)
           nb *= uint64_t(((a.box[k].hi[q] - 1) >> g.logB) - (a.box[k].lo[q] >> g.logB) + 1);
-        return uint32_t(nb);
-      }));
+        return nb >= kDirectBlocks ? 0u : uint32_t(nb);
+      }), true);
     }
   }
 }
@@ -805,23 +816,32 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
     CompressBatch b;
     build_compress_maps(pl, live, &maps, &b);
     const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
+    const uint64_t ab = compress_batch_args_bytes(nl, b.max_levels);
+    const uint64_t o_args = ws.take<uint8_t>(ab);
     if (!ws.commit()) return STZ_ERR_NOMEM;
     DevParams* dpar = ws.at<DevParams>(o_params);
     for (uint32_t k = 0; k < nl; ++k) pl[live[k]].bind(ws, dpar + k);
     HostBuf& hb = host_buf(st);
+    // staging: job table | work maps | per-level argument blocks (256-aligned)
     const uint64_t jb = uint64_t(nl) * sizeof(CompressArgs);
     const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
+    const uint64_t ao = (jb + mb + 255) & ~uint64_t(255);
     const uint64_t pb = uint64_t(nl) * sizeof(DevParams);
-    if (!hb.reserve(std::max(jb + mb, pb))) return STZ_ERR_NOMEM;
+    if (!hb.reserve(std::max(ao + ab, pb))) return STZ_ERR_NOMEM;
     for (uint32_t k = 0; k < nl; ++k)
       std::memcpy(hb.p + uint64_t(k) * sizeof(CompressArgs), &pl[live[k]].a, sizeof(CompressArgs));
     std::memcpy(hb.p + jb, maps.buf.data(), mb);
+    build_compress_batch_args(reinterpret_cast<const CompressArgs*>(hb.p), nl, b.max_levels,
+                              hb.p + ao);
     CompressArgs* dj = ws.at<CompressArgs>(o_jobs);
     uint32_t* dm = ws.at<uint32_t>(o_maps);
+    uint8_t* da = ws.at<uint8_t>(o_args);
     if (hipMemcpyAsync(dj, hb.p, jb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(dm, hb.p + jb, mb, hipMemcpyHostToDevice, st) != hipSuccess)
+        hipMemcpyAsync(dm, hb.p + jb, mb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(da, hb.p + ao, ab, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
     b.J = dj;
+    b.args = da;
     maps.bind(dm);
     if (launch_compress_batch(b, st) != hipSuccess) return STZ_ERR_DEVICE;
     if (hipMemcpyAsync(hb.p, dpar, pb, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -949,21 +969,26 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
   Workspace ws(st);
   BatchMaps maps;
   DecodeBatch b;
-  uint64_t o_req = 0, o_flags = 0, o_maps = 0;
+  std::vector<DirectItem> direct;
+  uint64_t o_req = 0, o_flags = 0, o_maps = 0, o_args = 0;
   if (nl) {
     for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
     o_req = ws.take<DecodeArgs>(nl);
     o_flags = ws.take<uint32_t>(nl);
-    build_decode_maps(pl, live, &maps, &b);
+    build_decode_maps(pl, live, &maps, &b, &direct);
     o_maps = ws.take<uint32_t>(maps.buf.size());
+    o_args = ws.take<uint8_t>(decode_batch_args_bytes(nl, b.max_level));
     if (!ws.commit()) return STZ_ERR_NOMEM;
   }
-  // Host staging: request table | work maps | zero flags | zero caller flags.
+  // Host staging: request table | work maps | zero flags | zero caller flags |
+  // per-level argument blocks (256-aligned).
   const uint64_t rb = uint64_t(nl) * sizeof(DecodeArgs);
   const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
   const uint64_t fb = uint64_t(nl) * 4;
   const uint64_t cb = dev_flags ? n * 4 : 0;
-  if (!hb.reserve(rb + mb + fb + cb)) return STZ_ERR_NOMEM;
+  const uint64_t ao = (rb + mb + fb + cb + 255) & ~uint64_t(255);
+  const uint64_t ab = nl ? decode_batch_args_bytes(nl, b.max_level) : 0;
+  if (!hb.reserve(ao + ab)) return STZ_ERR_NOMEM;
   std::memset(hb.p + rb + mb, 0, fb + cb);
   if (dev_flags &&
       hipMemcpyAsync(dev_flags, hb.p + rb + mb + fb, cb, hipMemcpyHostToDevice, st) != hipSuccess)
@@ -977,14 +1002,22 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
     for (uint32_t k = 0; k < nl; ++k)
       std::memcpy(hb.p + uint64_t(k) * sizeof(DecodeArgs), &pl[live[k]].a, sizeof(DecodeArgs));
     std::memcpy(hb.p + rb, maps.buf.data(), mb);
+    build_decode_batch_args(reinterpret_cast<const DecodeArgs*>(hb.p), nl, b.max_level,
+                            hb.p + ao);
     DecodeArgs* dr = ws.at<DecodeArgs>(o_req);
     uint32_t* dm = ws.at<uint32_t>(o_maps);
+    uint8_t* da = ws.at<uint8_t>(o_args);
     if (hipMemcpyAsync(dr, hb.p, rb, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(dm, hb.p + rb, mb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(wflags, hb.p + rb + mb, fb, hipMemcpyHostToDevice, st) != hipSuccess)
+        hipMemcpyAsync(wflags, hb.p + rb + mb, fb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(da, hb.p + ao, ab, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
     if (!hb.mark(st)) return STZ_ERR_DEVICE;
     b.R = dr;
+    b.args = da;
+    b.host_R = reinterpret_cast<const DecodeArgs*>(hb.p);
+    b.direct = direct.data();
+    b.n_direct = uint32_t(direct.size());
     maps.bind(dm);
     if (launch_decode_batch(b, st) != hipSuccess) return STZ_ERR_DEVICE;
     if (!dev_flags) {

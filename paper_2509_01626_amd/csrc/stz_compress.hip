@@ -3,6 +3,7 @@
 // and 5) with the code histogram, per-lane code lengths, segmented scans for
 // the stream layout, bit packing and outlier compaction.
 #include <algorithm>
+#include <cstring>
 
 #include "stz_slab.h"
 
@@ -817,6 +818,9 @@ __host__ __device__ inline int scan_blocks(const CompressArgs& a) {
 // launch's items (job[i] = index into the job table); persistent work-groups
 // walk the items with a grid stride, so any grid size covers any batch.
 // ---------------------------------------------------------------------------
+// The item is the same for the whole work-group, so the results are moved to
+// scalar registers (readfirstlane): argument blocks indexed by them then come
+// through scalar loads.
 __device__ inline int map_find(const ItemMap& m, uint32_t item, uint32_t* loc, uint32_t* cnt) {
   int lo = 0, hi = int(m.n);  // first[lo] <= item < first[hi]
   while (hi - lo > 1) {
@@ -826,9 +830,10 @@ __device__ inline int map_find(const ItemMap& m, uint32_t item, uint32_t* loc, u
     else
       hi = mid;
   }
-  *loc = item - m.first[lo];
-  *cnt = m.first[lo + 1] - m.first[lo];
-  return int(m.job[lo]);
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  *loc = __builtin_amdgcn_readfirstlane(item - m.first[lo]);
+  *cnt = __builtin_amdgcn_readfirstlane(m.first[lo + 1] - m.first[lo]);
+  return __builtin_amdgcn_readfirstlane(int(m.job[lo]));
 }
 
 #define STZ_FOR_ITEMS(m)                                                    \
@@ -868,20 +873,24 @@ __global__ void kb_anchor(const CompressArgs* J, ItemMap m) {
   }
 }
 
+// Per-level argument blocks of a batch are built on the host (the same
+// builders as the plain launches) and read here through restrict pointers.
 template <int E, int H>
-__global__ __launch_bounds__(256) void kb_pred(const CompressArgs* J, ItemMap m, int l) {
+__global__ __launch_bounds__(256) void kb_pred(const PredSlabArgs* __restrict__ P, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
-    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    pred_body<E, H>(pred_args(a, l), loc, false);
+    const PredSlabArgs& a = P[map_find(m, it_, &loc, &cnt)];
+    const uint32_t nblk = uint32_t(a.g.nb[0] * a.g.nb[1] * a.g.nb[2]);
+    // padded range (multiple of 8): contiguous blocks per XCD, padding skipped
+    const uint32_t blk = uint32_t(wg_block(loc, cnt, true));
+    if (blk < nblk) pred_body<E, H>(a, blk, false);
   }
 }
 
-__global__ __launch_bounds__(256) void kb_lanelen(const CompressArgs* J, ItemMap m, int l) {
+__global__ __launch_bounds__(256) void kb_lanelen(const LaneLenArgs* __restrict__ Q, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
-    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    lanelen_body(lanelen_args(a, l), loc);
+    lanelen_body(Q[map_find(m, it_, &loc, &cnt)], loc);
   }
 }
 
@@ -936,11 +945,10 @@ __global__ void kb_fill_head(const CompressArgs* J, ItemMap m) {
   }
 }
 
-__global__ __launch_bounds__(256) void kb_pack(const CompressArgs* J, ItemMap m, int l) {
+__global__ __launch_bounds__(256) void kb_pack(const PackArgs* __restrict__ Q, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
-    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    pack_body(pack_args(a, l), loc);
+    pack_body(Q[map_find(m, it_, &loc, &cnt)], loc);
   }
 }
 
@@ -950,35 +958,66 @@ void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
 }
 
 template <int E, int H>
-void launch_pred_b(const CompressArgs* J, const ItemMap& m, int l, unsigned grid,
-                   hipStream_t st) {
-  hipLaunchKernelGGL((kb_pred<E, H>), dim3(grid), dim3(256), 0, st, J, m, l);
+void launch_pred_b(const PredSlabArgs* P, const ItemMap& m, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((kb_pred<E, H>), dim3(grid), dim3(256), 0, st, P, m);
 }
 
 // Slab heights the batched predictor is built for, per level block edge.
 template <int E>
-bool launch_pred_bh(int h, const CompressArgs* J, const ItemMap& m, int l, unsigned grid,
+void launch_pred_bh(int h, const PredSlabArgs* P, const ItemMap& m, unsigned grid,
                     hipStream_t st) {
-  if constexpr (E <= 8) {
-    if (h == E) return launch_pred_b<E, E>(J, m, l, grid, st), true;
-    if constexpr (E == 8)
-      if (h == 4) return launch_pred_b<8, 4>(J, m, l, grid, st), true;
+  if constexpr (E == 8) {
+    if (h == 4) return launch_pred_b<8, 4>(P, m, grid, st);
   } else if constexpr (E == 16) {
-    if (h == 4) return launch_pred_b<16, 4>(J, m, l, grid, st), true;
-    if (h == 8) return launch_pred_b<16, 8>(J, m, l, grid, st), true;
-    if (h == 16) return launch_pred_b<16, 16>(J, m, l, grid, st), true;
+    if (h == 4) return launch_pred_b<16, 4>(P, m, grid, st);
+    if (h == 8) return launch_pred_b<16, 8>(P, m, grid, st);
   } else if constexpr (E == 32) {
-    if (h == 2) return launch_pred_b<32, 2>(J, m, l, grid, st), true;
-    if (h == 4) return launch_pred_b<32, 4>(J, m, l, grid, st), true;
-    if (h == 8) return launch_pred_b<32, 8>(J, m, l, grid, st), true;
-  } else {
-    if (h == 2) return launch_pred_b<64, 2>(J, m, l, grid, st), true;
-    if (h == 4) return launch_pred_b<64, 4>(J, m, l, grid, st), true;
+    if (h == 2) return launch_pred_b<32, 2>(P, m, grid, st);
+    if (h == 4) return launch_pred_b<32, 4>(P, m, grid, st);
+  } else if constexpr (E == 64) {
+    if (h == 4) return launch_pred_b<64, 4>(P, m, grid, st);
   }
-  return launch_pred_b<E, default_slab_h(E)>(J, m, l, grid, st), true;
+  launch_pred_b<E, default_slab_h(E)>(P, m, grid, st);
 }
 
 }  // namespace
+
+// Per-level argument blocks of a batch: [level 1..max_levels][job] for the
+// predictor, the lane lengths and the packer, each array 256-byte aligned.
+namespace {
+struct BatchArgLayout {
+  uint64_t pred, lane, pack, total;
+  BatchArgLayout(uint32_t n, int levels) {
+    auto al = [](uint64_t v) { return (v + 255) & ~uint64_t(255); };
+    const uint64_t k = uint64_t(n) * uint64_t(levels);
+    pred = 0;
+    lane = al(pred + k * sizeof(PredSlabArgs));
+    pack = al(lane + k * sizeof(LaneLenArgs));
+    total = al(pack + k * sizeof(PackArgs));
+  }
+};
+}  // namespace
+
+uint64_t compress_batch_args_bytes(uint32_t n, int max_levels) {
+  return BatchArgLayout(n, max_levels).total;
+}
+
+void build_compress_batch_args(const CompressArgs* jobs, uint32_t n, int max_levels,
+                               uint8_t* dst) {
+  const BatchArgLayout lay(n, max_levels);
+  auto* P = reinterpret_cast<PredSlabArgs*>(dst + lay.pred);
+  auto* Q = reinterpret_cast<LaneLenArgs*>(dst + lay.lane);
+  auto* K = reinterpret_cast<PackArgs*>(dst + lay.pack);
+  std::memset(dst, 0, lay.total);
+  for (int l = 1; l <= max_levels; ++l)
+    for (uint32_t j = 0; j < n; ++j) {
+      if (jobs[j].geo.L < l) continue;
+      const uint64_t i = uint64_t(l - 1) * n + j;
+      P[i] = pred_args(jobs[j], l);
+      Q[i] = lanelen_args(jobs[j], l);
+      K[i] = pack_args(jobs[j], l);
+    }
+}
 
 hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   const Geo& g = a.geo;
@@ -1095,6 +1134,7 @@ hipError_t launch_hash(const void* const* ptrs, const uint64_t* bytes, uint64_t 
 }
 
 hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
+  const BatchArgLayout lay(b.njobs, b.max_levels);
   const unsigned G = b.grid;
   auto grid = [&](const ItemMap& m, uint32_t total) {
     return dim3(std::max(1u, std::min<unsigned>(G, total)));
@@ -1120,13 +1160,15 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
       const unsigned gp = std::max(1u, std::min<unsigned>(b.grid_pred[e], b.n_pred[l][e]));
       prof_begin(st, "b_predict", l);
       const int h = b.pred_h[e];
+      const PredSlabArgs* P = reinterpret_cast<const PredSlabArgs*>(b.args + lay.pred) +
+                              uint64_t(l - 1) * b.njobs;
       switch (e) {
-        case 1: launch_pred_bh<2>(h, b.J, m, l, gp, st); break;
-        case 2: launch_pred_bh<4>(h, b.J, m, l, gp, st); break;
-        case 3: launch_pred_bh<8>(h, b.J, m, l, gp, st); break;
-        case 4: launch_pred_bh<16>(h, b.J, m, l, gp, st); break;
-        case 5: launch_pred_bh<32>(h, b.J, m, l, gp, st); break;
-        default: launch_pred_bh<64>(h, b.J, m, l, gp, st); break;
+        case 1: launch_pred_bh<2>(h, P, m, gp, st); break;
+        case 2: launch_pred_bh<4>(h, P, m, gp, st); break;
+        case 3: launch_pred_bh<8>(h, P, m, gp, st); break;
+        case 4: launch_pred_bh<16>(h, P, m, gp, st); break;
+        case 5: launch_pred_bh<32>(h, P, m, gp, st); break;
+        default: launch_pred_bh<64>(h, P, m, gp, st); break;
       }
       prof_end(st);
     }
@@ -1134,8 +1176,10 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
   launch_codebook_batch(b.J, b.njobs, st);
   for (int l = 1; l <= b.max_levels; ++l) {
     prof_begin(st, "b_lanelen", l);
-    hipLaunchKernelGGL(kb_lanelen, grid(b.level[l], b.n_level[l]), dim3(256), 0, st, b.J,
-                       b.level[l], l);
+    hipLaunchKernelGGL(kb_lanelen, grid(b.level[l], b.n_level[l]), dim3(256), 0, st,
+                       reinterpret_cast<const LaneLenArgs*>(b.args + lay.lane) +
+                           uint64_t(l - 1) * b.njobs,
+                       b.level[l]);
     prof_end(st);
   }
   prof_begin(st, "b_scan", -1);
@@ -1150,8 +1194,10 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
   prof_end(st);
   for (int l = 1; l <= b.max_levels; ++l) {
     prof_begin(st, "b_pack", l);
-    hipLaunchKernelGGL(kb_pack, grid(b.level[l], b.n_level[l]), dim3(256), 0, st, b.J, b.level[l],
-                       l);
+    hipLaunchKernelGGL(kb_pack, grid(b.level[l], b.n_level[l]), dim3(256), 0, st,
+                       reinterpret_cast<const PackArgs*>(b.args + lay.pack) +
+                           uint64_t(l - 1) * b.njobs,
+                       b.level[l]);
     prof_end(st);
   }
   return hipGetLastError();

@@ -9,6 +9,7 @@
 // the whole slab of the level grid (coarse points copied, level points
 // predicted and dequantized) is written with coalesced rows.
 #include <algorithm>
+#include <cstring>
 
 #include "stz_slab.h"
 
@@ -429,9 +430,10 @@ __device__ inline int map_find_d(const ItemMap& m, uint32_t item, uint32_t* loc,
     else
       hi = mid;
   }
-  *loc = item - m.first[lo];
-  *cnt = m.first[lo + 1] - m.first[lo];
-  return int(m.job[lo]);
+  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: scalar registers
+  *loc = __builtin_amdgcn_readfirstlane(item - m.first[lo]);
+  *cnt = __builtin_amdgcn_readfirstlane(m.first[lo + 1] - m.first[lo]);
+  return __builtin_amdgcn_readfirstlane(int(m.job[lo]));
 }
 
 #define STZ_FOR_ITEMS(m)                                                    \
@@ -447,42 +449,43 @@ __global__ void kb_dec_anchor(const DecodeArgs* R, ItemMap m) {
   }
 }
 
-__global__ void kb_dec_check(const DecodeArgs* R, ItemMap m, int k) {
+// Per-level argument blocks of a batch are built on the host (the same
+// builder as the plain launches) and read here through restrict pointers.
+__global__ void kb_dec_check(const DecSlabArgs* __restrict__ D, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
-    const DecodeArgs& a = R[map_find_d(m, it_, &loc, &cnt)];
-    dec_check_body(dec_args(a, k));
+    dec_check_body(D[map_find_d(m, it_, &loc, &cnt)]);
   }
 }
 
 template <int E, int H>
-__global__ __launch_bounds__(256) void kb_dec(const DecodeArgs* R, ItemMap m, int k) {
+__global__ __launch_bounds__(256) void kb_dec(const DecSlabArgs* __restrict__ D, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
-    const DecodeArgs& a = R[map_find_d(m, it_, &loc, &cnt)];
-    DecSlabArgs d = dec_args(a, k);
-    d.xcd_remap = false;
-    dec_body<E, H>(d, loc);
+    const DecSlabArgs d = uniform_load(D + map_find_d(m, it_, &loc, &cnt));
+    // padded range (multiple of 8): contiguous blocks per XCD, padding skipped
+    const int64_t blk = wg_block(loc, cnt, true);
+    if (blk < d.bb_n[0] * d.bb_n[1] * d.bb_n[2]) dec_body<E, H>(d, blk);
   }
 }
 
 template <int E, int H>
-void launch_dec_b(const DecodeArgs* R, const ItemMap& m, int k, unsigned grid, hipStream_t st) {
-  hipLaunchKernelGGL((kb_dec<E, H>), dim3(grid), dim3(256), 0, st, R, m, k);
+void launch_dec_b(const DecSlabArgs* D, const ItemMap& m, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((kb_dec<E, H>), dim3(grid), dim3(256), 0, st, D, m);
 }
 
 // Slab heights the batched decoder is built for, per level block edge.
 template <int E>
-void launch_dec_bh(int h, const DecodeArgs* R, const ItemMap& m, int k, unsigned grid,
+void launch_dec_bh(int h, const DecSlabArgs* D, const ItemMap& m, unsigned grid,
                    hipStream_t st) {
   if constexpr (E == 16) {
-    if (h == 4) return launch_dec_b<16, 4>(R, m, k, grid, st);
-    if (h == 8) return launch_dec_b<16, 8>(R, m, k, grid, st);
+    if (h == 4) return launch_dec_b<16, 4>(D, m, grid, st);
+    if (h == 8) return launch_dec_b<16, 8>(D, m, grid, st);
   } else if constexpr (E == 32) {
-    if (h == 2) return launch_dec_b<32, 2>(R, m, k, grid, st);
-    if (h == 8) return launch_dec_b<32, 8>(R, m, k, grid, st);
+    if (h == 2) return launch_dec_b<32, 2>(D, m, grid, st);
+    if (h == 8) return launch_dec_b<32, 8>(D, m, grid, st);
   }
-  launch_dec_b<E, dec_slab_h(E)>(R, m, k, grid, st);
+  launch_dec_b<E, dec_slab_h(E)>(D, m, grid, st);
 }
 
 }  // namespace
@@ -517,6 +520,22 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+uint64_t decode_batch_args_bytes(uint32_t n, int max_level) {
+  return uint64_t(n) * uint64_t(max_level) * sizeof(DecSlabArgs);
+}
+
+void build_decode_batch_args(const DecodeArgs* reqs, uint32_t n, int max_level, uint8_t* dst) {
+  auto* D = reinterpret_cast<DecSlabArgs*>(dst);
+  std::memset(dst, 0, decode_batch_args_bytes(n, max_level));
+  for (int k = 1; k <= max_level; ++k)
+    for (uint32_t r = 0; r < n; ++r) {
+      if (reqs[r].level_out < k) continue;
+      DecSlabArgs d = dec_args(reqs[r], k);
+      d.xcd_remap = false;
+      D[uint64_t(k - 1) * n + r] = d;
+    }
+}
+
 hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
   auto grid = [](unsigned cap, uint32_t total) {
     return std::max(1u, std::min<unsigned>(cap, total));
@@ -526,21 +545,39 @@ hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
                      b.anchor);
   prof_end(st);
   for (int k = 1; k <= b.max_level; ++k) {
+    // Requests with many blocks at this level fill the device on their own:
+    // they get the plain launch (arguments by value, in scalar registers).
+    for (uint32_t i = 0; i < b.n_direct; ++i) {
+      if (b.direct[i].level != k) continue;
+      const DecSlabArgs d = dec_args(b.host_R[b.direct[i].req], k);
+      const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
+      prof_begin(st, "b_decode_direct", k);
+      switch (d.g.B >> (d.g.L - k)) {
+        case 2: launch_slab<2>(d, nblk, st); break;
+        case 4: launch_slab<4>(d, nblk, st); break;
+        case 8: launch_slab<8>(d, nblk, st); break;
+        case 16: launch_slab<16>(d, nblk, st); break;
+        case 32: launch_slab<32>(d, nblk, st); break;
+        default: launch_slab<64>(d, nblk, st); break;
+      }
+      prof_end(st);
+    }
     if (!b.n_check[k]) continue;
-    hipLaunchKernelGGL(kb_dec_check, dim3(grid(b.grid, b.n_check[k])), dim3(64), 0, st, b.R,
-                       b.check[k], k);
+    const DecSlabArgs* D = reinterpret_cast<const DecSlabArgs*>(b.args) + uint64_t(k - 1) * b.nreq;
+    hipLaunchKernelGGL(kb_dec_check, dim3(grid(b.grid, b.n_check[k])), dim3(64), 0, st, D,
+                       b.check[k]);
     for (int e = 1; e < kBatchEdges; ++e) {
       if (!b.n_dec[k][e]) continue;
       const unsigned gd = grid(b.grid_dec[e], b.n_dec[k][e]);
       const int h = b.dec_h[e];
       prof_begin(st, "b_decode", k);
       switch (e) {
-        case 1: launch_dec_bh<2>(h, b.R, b.dec[k][e], k, gd, st); break;
-        case 2: launch_dec_bh<4>(h, b.R, b.dec[k][e], k, gd, st); break;
-        case 3: launch_dec_bh<8>(h, b.R, b.dec[k][e], k, gd, st); break;
-        case 4: launch_dec_bh<16>(h, b.R, b.dec[k][e], k, gd, st); break;
-        case 5: launch_dec_bh<32>(h, b.R, b.dec[k][e], k, gd, st); break;
-        default: launch_dec_bh<64>(h, b.R, b.dec[k][e], k, gd, st); break;
+        case 1: launch_dec_bh<2>(h, D, b.dec[k][e], gd, st); break;
+        case 2: launch_dec_bh<4>(h, D, b.dec[k][e], gd, st); break;
+        case 3: launch_dec_bh<8>(h, D, b.dec[k][e], gd, st); break;
+        case 4: launch_dec_bh<16>(h, D, b.dec[k][e], gd, st); break;
+        case 5: launch_dec_bh<32>(h, D, b.dec[k][e], gd, st); break;
+        default: launch_dec_bh<64>(h, D, b.dec[k][e], gd, st); break;
       }
       prof_end(st);
     }

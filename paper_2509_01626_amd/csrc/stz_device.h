@@ -201,6 +201,20 @@ inline int grid_for(uint64_t n, int per_block, int cap) {
   return int(b);
 }
 
+// Copy of a work-group-uniform argument block into scalar registers: each
+// 32-bit word is loaded and broadcast from the first lane, so the compiler
+// keeps the fields in SGPRs as it does for kernel arguments.
+template <class T>
+__device__ inline T uniform_load(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "argument blocks are whole words");
+  T v;
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(p);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+  return v;
+}
+
 __host__ __device__ inline Grid full_grid(const Geo& g, int logs) {
   Grid r;
   for (int d = 0; d < 3; ++d) {

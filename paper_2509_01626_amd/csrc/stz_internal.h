@@ -184,6 +184,7 @@ constexpr int kBatchEdges = 7;  // level block edge E = 2^e, e = 1..6
 // launch; n_* are the item totals (host copies of first[n]).
 struct CompressBatch {
   const CompressArgs* J;
+  const uint8_t* args;                         // per-level argument blocks (device)
   uint32_t njobs;
   unsigned grid;                               // persistent work-groups per launch
   unsigned grid_pred[kBatchEdges];             // per level block edge
@@ -210,6 +211,11 @@ struct BatchTuning {
 BatchTuning& batch_tuning();
 
 hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st);
+// Per-level argument blocks of a batched compression, built on the host from
+// the bound job table (device pointers filled in) and uploaded with it.
+uint64_t compress_batch_args_bytes(uint32_t n, int max_levels);
+void build_compress_batch_args(const CompressArgs* jobs, uint32_t n, int max_levels,
+                               uint8_t* dst);
 void launch_codebook_batch(const CompressArgs* J, uint32_t njobs, hipStream_t st);
 
 // Code book from the histogram (lengths and canonical codes, 2R entries).
@@ -239,8 +245,19 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
 
 // One batched decode: the request table (device) and the work maps of every
 // launch. Level k of request r has edge E = B_r >> (L_r - k).
+// A (request, level) pair decoded by a plain launch of its own.
+struct DirectItem {
+  uint32_t req;
+  int level;
+};
+constexpr uint64_t kDirectBlocks = 1024;  // blocks at one level that fill the device
+
 struct DecodeBatch {
   const DecodeArgs* R;
+  const uint8_t* args;                        // per-level argument blocks (device)
+  const DecodeArgs* host_R;                   // host copy of the request table
+  const DirectItem* direct;                   // host array
+  uint32_t n_direct;
   uint32_t nreq;
   unsigned grid;
   unsigned grid_dec[kBatchEdges];
@@ -255,6 +272,10 @@ struct DecodeBatch {
 };
 
 hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st);
+// Per-level argument blocks of a batched decode, [level 1..max_level][request],
+// built on the host from the bound request table.
+uint64_t decode_batch_args_bytes(uint32_t n, int max_level);
+void build_decode_batch_args(const DecodeArgs* reqs, uint32_t n, int max_level, uint8_t* dst);
 
 // Digest of each of n device byte ranges into out[i] (device), for checking
 // that two launch shapes give identical outputs.

@@ -132,3 +132,117 @@ def make(kind, dims, seed):
     if kind == "spectral":
         return spectral(dims, 5.0 / 3.0, seed)
     raise ValueError(kind)
+
+
+# ---- device-side generators (large benchmark inputs) ------------------------------
+# The same recipes computed with torch on a GPU (float64, then float32), seeded
+# with torch's Philox generator: realizations differ from the numpy versions
+# above, statistics do not. Used where host generation of many or very large
+# fields would dominate a benchmark run; a field's values are copied to the host
+# whenever the CPU oracle has to check it.
+
+def _tgen(seed, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def bumps_t(dims, seed, device, n_bumps=32, sigma=(4.0, 16.0), noise=1e-3):
+    import torch
+    g = _tgen(seed, device)
+    f64 = torch.float64
+    ext = torch.tensor(dims, dtype=f64, device=device)
+    c = torch.rand(n_bumps, 3, generator=g, device=device, dtype=f64) * ext
+    sg = sigma[0] + (sigma[1] - sigma[0]) * torch.rand(n_bumps, generator=g, device=device,
+                                                       dtype=f64)
+    amp = torch.randn(n_bumps, generator=g, device=device, dtype=f64)
+    ax = [torch.arange(n, device=device, dtype=f64) for n in dims]
+    k = -0.5 / (sg * sg)
+    gz = torch.exp(k[:, None] * (ax[0][None, :] - c[:, 0:1]) ** 2) * amp[:, None]
+    gy = torch.exp(k[:, None] * (ax[1][None, :] - c[:, 1:2]) ** 2)
+    gx = torch.exp(k[:, None] * (ax[2][None, :] - c[:, 2:3]) ** 2)
+    # sum_i gz_i (x) gy_i (x) gx_i as one product over the bump index
+    gyx = (gy[:, :, None] * gx[:, None, :]).reshape(n_bumps, -1)
+    out = torch.matmul(gz.t().contiguous(), gyx).reshape(dims)
+    out += noise * torch.randn(dims, generator=g, device=device, dtype=f64)
+    return out.to(torch.float32).contiguous()
+
+
+def _kmag_t(dims, device):
+    import torch
+    nz, ny, nx = dims
+    f64 = torch.float64
+    kz = torch.fft.fftfreq(nz, d=1.0 / nz, device=device, dtype=f64)
+    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device=device, dtype=f64)
+    kx = torch.fft.rfftfreq(nx, d=1.0 / nx, device=device, dtype=f64)
+    return torch.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+
+
+def _filtered_t(dims, alpha, seed, device, random_phase, dtype):
+    import torch
+    g = _tgen(seed, device)
+    white = torch.randn(dims, generator=g, device=device, dtype=dtype)
+    W = torch.fft.rfftn(white)
+    del white
+    k = _kmag_t(dims, device).to(dtype)
+    amp = torch.where(k > 0, k.clamp_min(1e-30) ** (-alpha / 2.0), torch.zeros_like(k))
+    del k
+    if random_phase:
+        mag = W.abs()
+        W = torch.where(mag > 0, W / torch.where(mag > 0, mag, torch.ones_like(mag)),
+                        torch.zeros_like(W))
+        del mag
+    W = W * amp
+    del amp
+    W[0, 0, 0] = 0
+    f = torch.fft.irfftn(W, s=dims)
+    del W
+    f = f - f.mean()
+    sd = f.std()
+    if sd > 0:
+        f = f / sd
+    return f
+
+
+def spectral_t(dims, alpha, seed, device, dtype=None):
+    import torch
+    return _filtered_t(dims, alpha, seed, device, True,
+                       dtype or torch.float64).to(torch.float32).contiguous()
+
+
+def grf_t(dims, alpha, seed, device, dtype=None):
+    import torch
+    return _filtered_t(dims, alpha, seed, device, False,
+                       dtype or torch.float64).to(torch.float32).contiguous()
+
+
+def lognormal_t(dims, alpha, seed, device, dtype=None):
+    import torch
+    g = _filtered_t(dims, alpha, seed, device, False, dtype or torch.float64)
+    return torch.exp(g).to(torch.float32).contiguous()
+
+
+def spectral_crop_t(dims, alpha, seed, device):
+    """spectral_t synthesized on the power-of-two cube that holds `dims` and
+    cropped to `dims`, then normalized again: every field of a batch of uneven
+    shapes reuses one of a few FFT sizes."""
+    import torch
+    side = 1
+    while side < max(dims):
+        side *= 2
+    f = _filtered_t((side, side, side), alpha, seed, device, True, torch.float64)
+    f = f[:dims[0], :dims[1], :dims[2]]
+    f = f - f.mean()
+    sd = f.std()
+    if sd > 0:
+        f = f / sd
+    return f.to(torch.float32).contiguous()
+
+
+def make_t(kind, dims, seed, device):
+    if kind == "bumps":
+        return bumps_t(dims, seed, device)
+    if kind == "spectral":
+        return spectral_crop_t(dims, 5.0 / 3.0, seed, device)
+    raise ValueError(kind)

@@ -1,0 +1,223 @@
+"""Continuous-batching decode server over resident compressed fields.
+
+Compressed streams stay in device memory (``stz.Field``: header parsed and
+decoder table uploaded once). Requests for a box of a field at a progressive
+level (Sec. 3.3: progressive and random-access decompression) arrive at any
+time. The loop
+
+1. admits waiting requests in arrival order while their outputs fit in the
+   output arena (admission by memory; a request larger than the whole arena is
+   rejected);
+2. whenever one of its ``slots`` (HIP streams) is idle, launches every
+   admitted request (up to ``max_batch``) as one batched decode on that stream,
+   asynchronously, with one device status word per request;
+3. polls the in-flight batches' events; a finished batch hands each result to
+   ``on_done`` and frees its arena space, which lets more requests in.
+
+So requests arriving while others are on the GPU join the next batch as soon
+as a slot and memory free up, and batches on different slots overlap on the
+device. Latency = time the host sees the batch finished - arrival time.
+
+All decoding runs in the HIP library; this module only schedules.
+"""
+import collections
+import time
+
+import torch
+
+from . import stz
+
+
+class Arena:
+    """First-fit allocator over one device float32 buffer (offsets in floats,
+    rounded up to 64-float granules)."""
+
+    G = 64
+
+    def __init__(self, n_floats, device):
+        self.n = (int(n_floats) // self.G) * self.G
+        self.buf = torch.empty(self.n, dtype=torch.float32, device=device)
+        self.free = [(0, self.n)]  # sorted (offset, length)
+
+    def alloc(self, n):
+        n = max(self.G, -(-int(n) // self.G) * self.G)
+        for i, (o, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (o + n, ln - n)
+                return o, n
+        return None
+
+    def release(self, o, n):
+        self.free.append((o, n))
+        self.free.sort()
+        merged = []
+        for a, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((a, ln))
+        self.free = merged
+
+    def view(self, o, n):
+        return self.buf[o:o + n]
+
+
+class Request:
+    __slots__ = ("rid", "field", "lo", "hi", "level", "t_arrive", "t_done", "shape", "n",
+                 "off", "cap", "status")
+
+    def __init__(self, rid, field, lo, hi, level, t_arrive):
+        self.rid = rid
+        self.field = field
+        self.lo = list(lo)
+        self.hi = list(hi)
+        self.level = int(level)
+        self.t_arrive = t_arrive
+        self.t_done = None
+        self.shape = None
+        self.n = 0
+        self.off = None
+        self.cap = 0
+        self.status = None
+
+
+class Server:
+    def __init__(self, fields, arena_bytes, slots=2, max_batch=64, device="cuda:0",
+                 on_done=None):
+        self.fields = fields
+        self.arena = Arena(arena_bytes // 4, device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        self.busy = [None] * slots        # per slot: (event, batch, flags) or None
+        self.max_batch = max_batch
+        self.device = device
+        self.on_done = on_done
+        self.waiting = collections.deque()
+        self.admitted = []
+        self.done = []
+        self.batches = 0
+        self.batch_sizes = []
+
+    # -- request intake ---------------------------------------------------------------
+    def submit(self, req):
+        f = self.fields[req.field]
+        req.shape = stz.region_shape(f.info, req.lo, req.hi, req.level)
+        req.n = req.shape[0] * req.shape[1] * req.shape[2]
+        if req.n > self.arena.n:
+            req.status = stz.ERR_NOMEM
+            req.t_done = time.perf_counter()
+            self.done.append(req)
+            return
+        self.waiting.append(req)
+
+    def _admit(self):
+        while self.waiting:
+            r = self.waiting[0]
+            got = self.arena.alloc(max(r.n, 1))
+            if got is None:
+                return
+            r.off, r.cap = got
+            self.admitted.append(self.waiting.popleft())
+
+    def _launch(self):
+        for s in range(len(self.streams)):
+            if not self.admitted:
+                return
+            if self.busy[s] is not None:
+                continue
+            batch = self.admitted[:self.max_batch]
+            del self.admitted[:len(batch)]
+            items = [(self.fields[r.field], r.lo, r.hi, r.level,
+                      self.arena.view(r.off, r.cap)) for r in batch]
+            arr = stz.make_requests(items)
+            flags = torch.empty(len(batch), dtype=torch.int32, device=self.device)
+            st = self.streams[s]
+            with torch.cuda.stream(st):
+                stz.stz_decompress_batch(arr, flags=flags, stream=st, check=False)
+                ev = torch.cuda.Event()
+                ev.record(st)
+            for i, r in enumerate(batch):
+                r.status = arr[i].status
+            self.busy[s] = (ev, batch, flags)
+            self.batches += 1
+            self.batch_sizes.append(len(batch))
+
+    def _reap(self):
+        for s in range(len(self.streams)):
+            b = self.busy[s]
+            if b is None or not b[0].query():
+                continue
+            ev, batch, flags = b
+            t = time.perf_counter()
+            fl = flags.cpu().tolist()
+            for r, f in zip(batch, fl):
+                if r.status == stz.OK and f:
+                    r.status = stz.ERR_CORRUPT
+                r.t_done = t
+                if self.on_done is not None:
+                    self.on_done(r, self.arena.view(r.off, max(r.n, 1))[:r.n].view(r.shape))
+                self.arena.release(r.off, r.cap)
+                self.done.append(r)
+            self.busy[s] = None
+
+    def step(self):
+        self._reap()
+        self._admit()
+        self._launch()
+
+    def idle(self):
+        return not self.waiting and not self.admitted and all(b is None for b in self.busy)
+
+    # -- driver ---------------------------------------------------------------------
+    def run(self, arrivals):
+        """arrivals: list of (t_offset_seconds, field, lo, hi, level), sorted by time.
+        Submits each at its arrival time (relative to the start) and runs the loop
+        until every request is done. Returns the finished requests."""
+        t0 = time.perf_counter()
+        i = 0
+        n = len(arrivals)
+        while i < n or not self.idle():
+            now = time.perf_counter()
+            while i < n and arrivals[i][0] <= now - t0:
+                ta, f, lo, hi, lv = arrivals[i]
+                self.submit(Request(i, f, lo, hi, lv, t0 + ta))
+                i += 1
+            self.step()
+        return self.done
+
+
+def poisson_arrivals(rng, n, rate, fields_info, edge=(16, 256)):
+    """n requests with exponential inter-arrival times (rate per second): a
+    uniform field, a uniform progressive level 0..L and a box whose edge per
+    axis is uniform in `edge` (clipped to the field) at a uniform origin."""
+    t = 0.0
+    out = []
+    for _ in range(n):
+        t += rng.exponential(1.0 / rate)
+        k = int(rng.integers(0, len(fields_info)))
+        inf = fields_info[k]
+        dims = [int(v) for v in inf.dims]
+        lo, hi = [], []
+        for d in dims:
+            e = min(d, int(rng.integers(edge[0], edge[1] + 1)))
+            a = int(rng.integers(0, d - e + 1))
+            lo.append(a)
+            hi.append(a + e)
+        lv = int(rng.integers(0, inf.levels + 1))
+        out.append((t, k, lo, hi, lv))
+    return out
+
+
+def latency_stats(done):
+    lat = sorted((r.t_done - r.t_arrive) for r in done if r.status == stz.OK)
+    if not lat:
+        return {"p50_ms": None, "p99_ms": None, "mean_ms": None}
+
+    def pct(p):
+        i = min(len(lat) - 1, max(0, int(round(p / 100.0 * (len(lat) - 1)))))
+        return lat[i] * 1e3
+
+    return {"p50_ms": round(pct(50), 3), "p99_ms": round(pct(99), 3),
+            "mean_ms": round(sum(lat) / len(lat) * 1e3, 3)}

@@ -223,3 +223,31 @@ def test_autotuned_shapes_keep_outputs(gpu):
         assert torch.equal(o.view(torch.int32), stz.stz_decompress(c).reshape(-1).view(torch.int32))
     for f in flds:
         f.close()
+
+
+def test_batch_decode_large_request_direct_path(gpu):
+    """A request with many blocks per level takes the plain launch inside the
+    batch; results still equal the plain decoder's."""
+    import torch
+    stz = _stz()
+    xa = torch.from_numpy(fields.spectral((128, 96, 80), 5 / 3, seed=21)).to(gpu)  # 1920 blocks
+    xb = torch.from_numpy(fields.bumps((20, 30, 40), seed=22, n_bumps=4)).to(gpu)
+    ca = stz.stz_compress(xa, stz.EB_REL, 1e-3, stz.config(block=8))
+    cb = stz.stz_compress(xb, stz.EB_REL, 1e-3, stz.config(block=8))
+    fa, fb = stz.Field(ca), stz.Field(cb)
+    oa = torch.empty(xa.numel(), dtype=torch.float32, device=gpu)
+    ob = torch.empty(xb.numel(), dtype=torch.float32, device=gpu)
+    oc = torch.empty(xa.numel(), dtype=torch.float32, device=gpu)
+    lo, hi = [3, 5, 7], [120, 90, 77]
+    arr = stz.make_requests([(fa, [0, 0, 0], [128, 96, 80], 3, oa),
+                             (fb, [0, 0, 0], [20, 30, 40], 3, ob),
+                             (fa, lo, hi, 3, oc)])
+    print("[case] direct-path batch", flush=True)
+    stz.stz_decompress_batch(arr)
+    torch.cuda.synchronize()
+    assert torch.equal(oa.view(torch.int32), stz.stz_decompress(ca).reshape(-1).view(torch.int32))
+    assert torch.equal(ob.view(torch.int32), stz.stz_decompress(cb).reshape(-1).view(torch.int32))
+    want = stz.stz_decompress_region(ca, lo, hi, 3).reshape(-1)
+    assert torch.equal(oc[:want.numel()].view(torch.int32), want.view(torch.int32))
+    fa.close()
+    fb.close()
