@@ -617,10 +617,11 @@ __device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_
     atomicOr(&pay[wi], w);
 }
 
-// Bit-pack every lane stream, write the unit index and the outliers. Same
-// block mapping as k_lanelen; a unit's lanes sit inside one wave, so the
-// rank order of its outliers comes from a per-row ballot.
-__device__ inline void pack_body(const PackArgs& a, int64_t wg) {
+// Small units (block edge at this level below 32): one lane per column
+// stream packs its codes directly (same block mapping as k_lanelen); a unit's
+// lanes sit inside one wave, so the rank order of its outliers comes from a
+// per-row ballot.
+__device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   const DevParams* P = a.P;
   if (P->flags) return;
   __shared__ uint8_t Ls[2 * kMaxRadius];
@@ -724,6 +725,160 @@ __device__ inline void pack_body(const PackArgs& a, int64_t wg) {
   }
   for (; t < rows; ++t) step(act ? col[t] : uint16_t(1), t);
   if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
+}
+
+// Bit-pack the block's 7 units, write the unit index, the lane lengths and
+// the outliers. A unit's stream is the concatenation of its lanes, i.e. the
+// Huffman codes of the unit's symbols in their memory order (columns one after
+// the other), and starts on a word boundary; so a work-group encodes each unit
+// in chunks: coalesced symbol loads into LDS, a block scan of code lengths for
+// bit offsets, codes OR-ed into an LDS word buffer, complete words written out
+// with coalesced stores (the last partial word carries into the next chunk).
+constexpr int kPackChunk = 4096;                     // symbols per chunk
+constexpr int kPackPer = kPackChunk / 256;           // per thread
+constexpr int kPackWords = kPackChunk * kLmax / 32 + 2;
+
+__device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
+  const DevParams* P = a.P;
+  if (P->flags) return;
+  __shared__ uint8_t Ls[2 * kMaxRadius];
+  __shared__ uint16_t Cs[2 * kMaxRadius];
+  __shared__ uint16_t us[kPackChunk];
+  __shared__ uint32_t wb[kPackWords];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < a.nsym; i += blockDim.x) {
+    Ls[i] = a.lens[i];
+    Cs[i] = a.codes[i];
+  }
+  const int l = a.level;
+  uint32_t* unit_word = reinterpret_cast<uint32_t*>(a.out + P->sec[l]);
+  uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
+  uint16_t* lane_arr = reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]);
+  uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
+  float* outv = reinterpret_cast<float*>(a.out + P->off_out[l]);
+  const int m = (a.g.B >> a.logs) >> 1;
+  // unit index and lane lengths of the block's units
+  if (tid < 7) {
+    const int64_t u = wg * 7 + tid;
+    unit_word[u] = a.scan_words[u];
+    unit_outl[u] = a.scan_outl[u];
+    if (u == int64_t(a.nu) - 1) {
+      unit_word[a.nu] = a.scan_words[a.nu];
+      unit_outl[a.nu] = a.scan_outl[a.nu];
+    }
+  }
+  if (tid < 7 * m) {
+    const int64_t u = wg * 7 + tid / m;
+    const int j = tid % m;
+    const UnitGeo ug = unit_geo(a.g, u, a.logs);
+    if (j < ug.M[2]) {
+      const uint64_t li = uint64_t(unit_lane_off(a.g, a.logs, u)) + j;
+      lane_arr[li] = a.lane_len[li];
+    }
+  }
+  __syncthreads();
+  for (int c = 1; c <= 7; ++c) {
+    const int64_t u = wg * 7 + (c - 1);
+    const UnitGeo ug = unit_geo(a.g, u, a.logs);
+    const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1];
+    const uint32_t n_u = rows * uint32_t(ug.M[2]);
+    if (n_u == 0) continue;
+    const uint16_t* src = a.sym + uint64_t(unit_sym_off(a.g, a.logs, u));
+    uint32_t* dst = pay + a.scan_words[u];
+    uint64_t bits = 0;  // bits of the unit written or carried so far
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < n_u; c0 += kPackChunk) {
+      const int n = int(min<uint32_t>(kPackChunk, n_u - c0));
+      for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
+      __syncthreads();
+      // this thread's run of kPackPer symbols: lengths, then bit offsets
+      uint64_t mine = 0;
+      const int i0 = tid * kPackPer;
+#pragma unroll
+      for (int k = 0; k < kPackPer; ++k)
+        if (i0 + k < n) mine += Ls[us[i0 + k]];
+      uint64_t total;
+      const uint64_t off = block_excl_scan(mine, &total);
+      const int sk = int(bits & 31);  // bit position of the chunk inside word 0
+      const int nw = int((uint64_t(sk) + total + 31) >> 5);
+      for (int i = tid; i < nw; i += 256) wb[i] = 0;
+      __syncthreads();
+      if (tid == 0) wb[0] = carry;
+      __syncthreads();
+      uint64_t pos = uint64_t(sk) + off;
+      uint32_t cur = 0;
+      int64_t cw_i = int64_t(pos >> 5);
+#pragma unroll
+      for (int k = 0; k < kPackPer; ++k) {
+        if (i0 + k >= n) break;
+        const uint32_t s = us[i0 + k];
+        const uint32_t len = Ls[s], code = Cs[s];
+        const int o = int(pos & 31);
+        if (int64_t(pos >> 5) != cw_i) {
+          if (cur) atomicOr(&wb[cw_i], cur);
+          cur = 0;
+          cw_i = int64_t(pos >> 5);
+        }
+        if (o + int(len) <= 32) {
+          cur |= code << (32 - o - int(len));
+        } else {
+          const int hi = o + int(len) - 32;
+          cur |= code >> hi;
+          atomicOr(&wb[cw_i], cur);
+          cw_i += 1;
+          cur = code << (32 - hi);
+        }
+        pos += len;
+      }
+      if (cur) atomicOr(&wb[cw_i], cur);
+      __syncthreads();
+      // complete words out; the partial last word carries over
+      const uint64_t end = uint64_t(sk) + total;
+      const int full = int(end >> 5);
+      const uint64_t w0 = bits >> 5;
+      for (int i = tid; i < full; i += 256) dst[w0 + i] = wb[i];
+      carry = (end & 31) ? wb[full] : 0u;
+      bits += total;
+      __syncthreads();
+    }
+    if (bits & 31)
+      if (tid == 0) dst[bits >> 5] = carry;
+    // outliers in rank order (row-major: row t, then column j)
+    const uint32_t uo = a.scan_outl[u], n_out = a.scan_outl[u + 1] - uo;
+    if (n_out) {
+      const uint32_t Mx = uint32_t(ug.M[2]), M1 = uint32_t(ug.M[1]);
+      uint64_t run = 0;
+      for (uint32_t r0 = 0; r0 < n_u; r0 += 256) {
+        const uint32_t r = r0 + tid;
+        bool isz = false;
+        uint32_t t = 0, j = 0;
+        if (r < n_u) {
+          t = r / Mx;
+          j = r - t * Mx;
+          isz = src[uint64_t(j) * rows + t] == 0;
+        }
+        uint64_t cnt;
+        const uint64_t rank = run + block_excl_scan(isz ? 1 : 0, &cnt);
+        if (isz && rank < n_out) {
+          const uint32_t vy = t % M1, vz = t / M1;
+          const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
+          const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
+          const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * j + ug.o[2]) << a.logs);
+          outv[uo + rank] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
+        }
+        run += cnt;
+      }
+    }
+  }
+}
+
+// Units of 16^3 symbols and more take the chunked encoder, smaller ones the
+// lane encoder (both write the same bytes).
+__device__ inline void pack_body(const PackArgs& a, int64_t wg) {
+  if ((a.g.B >> a.logs) >= 32)
+    pack_units_body(a, wg);
+  else
+    pack_lanes_body(a, wg);
 }
 
 __global__ __launch_bounds__(256) void k_pack(PackArgs a) { pack_body(a, blockIdx.x); }
