@@ -151,8 +151,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the path has "
+              "no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

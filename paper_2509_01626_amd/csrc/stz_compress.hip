@@ -82,14 +82,20 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uin
 // Resolve the absolute bound and the per-level constants (format 2.3).
 __device__ inline void resolve_body(DevParams* P, const float2* part, uint32_t nparts, int mode,
                                     double eb, double ratio, int L) {
-  if (threadIdx.x != 0) return;
-  double eb_abs = eb;
-  if (mode == 1) {
-    float mn = part[0].x, mx = part[0].y;
-    for (uint32_t i = 1; i < nparts; ++i) {
+  // one wave of 64 threads: min and max of the partials (exact in any order)
+  float mn = INFINITY, mx = -INFINITY;
+  if (mode == 1)
+    for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
       mn = fminf(mn, part[i].x);
       mx = fmaxf(mx, part[i].y);
     }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, o, kWave));
+    mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+  }
+  if (threadIdx.x != 0) return;
+  double eb_abs = eb;
+  if (mode == 1) {
     P->mn = mn;
     P->mx = mx;
     const double range = (double)mx - (double)mn;
