@@ -185,6 +185,25 @@ typedef struct {
 stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_flags,
                                 void* stream);
 
+/* ---- ROI selection (Sec. 3.3, flexible scientific workflow) ---------------
+ * Decodes the resident field at progressive level `level` (cheap at coarse
+ * levels), computes for every unit the maximum (stat 0) or the value range
+ * max - min (stat 1, in double) over the level's grid points, and selects:
+ * rule 0 = units whose statistic exceeds `value`; rule 1 = the
+ * ceil(value * units) units with the largest statistic (0 < value <= 1; ties
+ * go to the smaller index). unit 0 = the blocks of B^3 full-resolution points
+ * (raster index; block b spans [b*B, (b+1)*B) per axis, so a selected block is
+ * a box for stz_decompress_region / stz_decompress_batch); unit 1/2/3 = the
+ * level grid's planes across axis z/y/x (index = plane number, full-resolution
+ * coordinate index * 2^(L-level)). Selected indices go to `sel` (host, cap
+ * entries, ascending), their number to *count (host; on STZ_ERR_BUFFER the
+ * number needed); `stats` (host, may be NULL) receives every unit's statistic.
+ * The statistics are computed on the device; the selection over the
+ * per-unit values runs on the host. Synchronizes `stream`. */
+stz_status stz_roi_select(stz_field field, uint32_t level, uint32_t unit, uint32_t stat,
+                          uint32_t rule, double value, uint32_t* sel, uint64_t cap,
+                          uint64_t* count, double* stats, void* stream);
+
 /* ---- Autotuner -------------------------------------------------------------
  * Times candidate launch shapes of the batched kernels (persistent grid sizes
  * and slab heights, per level block edge) on the given jobs, keeps the

@@ -67,6 +67,10 @@ def lib():
         L.stz_ref_canonical_codes.restype = None
         L.stz_ref_canonical_codes.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.stz_ref_level_bounds.restype = None
+        L.stz_ref_roi_select.restype = C.c_int
+        L.stz_ref_roi_select.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
+                                         C.c_uint32, C.c_uint32, C.c_double, C.c_void_p,
+                                         C.c_uint64, C.POINTER(C.c_uint64), C.c_void_p]
         L.stz_ref_level_bounds.argtypes = [C.c_double, C.c_double, C.c_int, C.c_void_p,
                                            C.c_void_p, C.c_void_p]
         _lib = L
@@ -229,3 +233,30 @@ def units_decoded():
     out = np.zeros(9 * 8, dtype=np.uint64)
     lib().stz_ref_units_decoded(out.ctypes.data)
     return out.reshape(9, 8)
+
+
+def roi_units(comp, level, unit):
+    """Number of ROI units: blocks (unit 0) or level-grid planes across an axis."""
+    inf = info(comp)
+    if unit == 0:
+        n = 1
+        for d in inf.dims:
+            n *= (int(d) + inf.block - 1) // inf.block
+        return n
+    s = 1 << (inf.levels - level)
+    return (int(inf.dims[unit - 1]) - 1) // s + 1
+
+
+def roi_select(comp, level, unit, stat, rule, value):
+    """ROI selection (Sec. 3.3): (selected unit indices, per-unit statistic)."""
+    n = roi_units(comp, level, unit)
+    sel = np.empty(max(n, 1), dtype=np.uint32)
+    stats = np.empty(max(n, 1), dtype=np.float64)
+    cnt = C.c_uint64(0)
+    buf = np.frombuffer(comp, dtype=np.uint8)
+    st = lib().stz_ref_roi_select(buf.ctypes.data, buf.size, level, unit, stat, rule, value,
+                                  sel.ctypes.data, sel.size, C.byref(cnt), stats.ctypes.data)
+    if st != OK:
+        raise OracleError(st, "roi_select")
+    return sel[:cnt.value].copy(), stats[:n].copy()
+

@@ -1202,6 +1202,73 @@ void stz_ref_canonical_codes(const uint8_t* lens, int nsym, uint32_t* codes) {
   canonical_codes(lens, nsym, codes);
 }
 
+// ROI selection (Sec. 3.3, "flexible scientific workflow"): the value range
+// or the maximum of every 3-D block or every 2-D slice of the field, taken over
+// the points of a progressive level's grid, then a threshold or the top
+// fraction. unit: 0 = blocks of B^3 full-resolution points (raster order),
+// 1/2/3 = planes of the level grid across axis z/y/x (index = plane number).
+// stat: 0 = max, 1 = range (max - min, in double). rule: 0 = stat > value,
+// 1 = the ceil(value * units) units with the largest stat (ties: smaller index
+// first). Selected indices ascending into blocks[], their number in *count;
+// stats[] (units entries) receives every unit's statistic when not null.
+int stz_ref_roi_select(const void* comp, uint64_t size, uint32_t level, uint32_t unit,
+                       uint32_t stat, uint32_t rule, double value, uint32_t* sel, uint64_t cap,
+                       uint64_t* count, double* stats) {
+  Parsed P;
+  int st = parse(comp, size, &P);
+  if (st != OK) return st;
+  if ((int)level > P.c.L || unit > 3 || stat > 1 || rule > 1) return ERR_ARG;
+  if (rule == 1 && !(value > 0.0 && value <= 1.0)) return ERR_ARG;
+  const Geo& g = P.g;
+  const size_t s = g.stride((int)level);
+  std::vector<float> rec;
+  st = decode_levels(comp, P, (int)level, false, nullptr, &rec);
+  if (st != OK) return st;
+  const size_t nb[3] = {(g.n[0] + g.B - 1) / g.B, (g.n[1] + g.B - 1) / g.B,
+                        (g.n[2] + g.B - 1) / g.B};
+  size_t nunits;
+  if (unit == 0)
+    nunits = nb[0] * nb[1] * nb[2];
+  else
+    nunits = g.grid_n(int(unit - 1), s);
+  std::vector<float> mx(nunits, -INFINITY), mn(nunits, INFINITY);
+  for (size_t z = 0; z < g.n[0]; z += s)
+    for (size_t y = 0; y < g.n[1]; y += s)
+      for (size_t x = 0; x < g.n[2]; x += s) {
+        size_t u;
+        if (unit == 0)
+          u = ((z / g.B) * nb[1] + y / g.B) * nb[2] + x / g.B;
+        else
+          u = (unit == 1 ? z : unit == 2 ? y : x) / s;
+        const float v = rec[g.idx(z, y, x)];
+        if (v > mx[u]) mx[u] = v;
+        if (v < mn[u]) mn[u] = v;
+      }
+  std::vector<double> st_all(nunits);
+  for (size_t u = 0; u < nunits; ++u)
+    st_all[u] = stat == 0 ? (double)mx[u] : (double)mx[u] - (double)mn[u];
+  if (stats)
+    for (size_t u = 0; u < nunits; ++u) stats[u] = st_all[u];
+  std::vector<uint32_t> pick;
+  if (rule == 0) {
+    for (size_t u = 0; u < nunits; ++u)
+      if (st_all[u] > value) pick.push_back(uint32_t(u));
+  } else {
+    const size_t k = std::min(nunits, (size_t)std::ceil(value * (double)nunits));
+    std::vector<uint32_t> order(nunits);
+    for (size_t u = 0; u < nunits; ++u) order[u] = uint32_t(u);
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      return st_all[a] > st_all[b] || (st_all[a] == st_all[b] && a < b);
+    });
+    pick.assign(order.begin(), order.begin() + k);
+    std::sort(pick.begin(), pick.end());
+  }
+  if (count) *count = pick.size();
+  if (pick.size() > cap) return ERR_BUFFER;
+  for (size_t i = 0; i < pick.size(); ++i) sel[i] = pick[i];
+  return OK;
+}
+
 // Per-level error bound constants: e (double), 2e and 1/(2e) as float.
 void stz_ref_level_bounds(double eb_abs, double ratio, int L, double* e, float* E2, float* INV) {
   Bounds bd;

@@ -1295,6 +1295,80 @@ stz_status stz_autotune_batch(stz_job* jobs, uint64_t njobs, char* report, uint6
   return ds;
 }
 
+stz_status stz_roi_select(stz_field f, uint32_t level, uint32_t unit, uint32_t stat,
+                          uint32_t rule, double value, uint32_t* sel, uint64_t cap,
+                          uint64_t* count, double* stats, void* stream) {
+  if (!f || !count || unit > 3 || stat > 1 || rule > 1) return STZ_ERR_ARG;
+  if (rule == 1 && !(value > 0.0 && value <= 1.0)) return STZ_ERR_ARG;
+  if (rule == 0 && std::isnan(value)) return STZ_ERR_ARG;
+  const Header& h = f->h;
+  const Geo& g = h.g;
+  if (int64_t(level) > g.L) return STZ_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int logs = g.L - int(level);
+  int64_t gn[3];
+  for (int d = 0; d < 3; ++d) gn[d] = ((g.n[d] - 1) >> logs) + 1;
+  const uint64_t ngrid = uint64_t(gn[0]) * gn[1] * gn[2];
+  const uint64_t nunits =
+      unit == 0 ? uint64_t(g.nb[0] * g.nb[1] * g.nb[2]) : uint64_t(gn[unit - 1]);
+  // decode the whole domain at `level` into scratch, then the statistics; the
+  // plan is made against a placeholder output and pointed at the scratch grid
+  DecodePlan pl;
+  stz_status s = pl.init(h, f->comp, f->size, nullptr, int(level),
+                         reinterpret_cast<float*>(uintptr_t(256)), ngrid);
+  if (s != STZ_OK) return s;
+  Workspace ws(st);
+  pl.take(ws);
+  const uint64_t o_grid = ws.take<float>(ngrid);
+  const uint64_t o_stats = ws.take<double>(nunits);
+  const uint64_t o_flags = ws.take<uint32_t>(1);
+  if (!ws.commit()) return STZ_ERR_NOMEM;
+  float* grid = ws.at<float>(o_grid);
+  uint32_t* dflags = ws.at<uint32_t>(o_flags);
+  pl.a.rec[pl.a.level_out] = grid;
+  pl.bind(ws, f->lut, dflags);
+  Staging* stage = staging();
+  if (!stage) return STZ_ERR_NOMEM;
+  *stage->flags = 0;
+  if (hipMemcpyAsync(dflags, stage->flags, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      launch_decode(pl.a, st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  double* dstats = ws.at<double>(o_stats);
+  const int64_t E = int64_t(g.B) >> logs;
+  const int64_t nb[3] = {g.nb[0], g.nb[1], g.nb[2]};
+  if (launch_roi_stats(grid, gn, E, int(unit), int(stat), nb, nunits, dstats, st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  HostBuf& hb = host_buf(st);
+  if (!hb.reserve(nunits * 8 + 8)) return STZ_ERR_NOMEM;
+  if (hipMemcpyAsync(hb.p, dstats, nunits * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hb.p + nunits * 8, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  prof_flush();
+  if (*reinterpret_cast<const uint32_t*>(hb.p + nunits * 8)) return STZ_ERR_CORRUPT;
+  const double* sv = reinterpret_cast<const double*>(hb.p);
+  if (stats) std::memcpy(stats, sv, nunits * 8);
+  std::vector<uint32_t> pick;
+  if (rule == 0) {
+    for (uint64_t u = 0; u < nunits; ++u)
+      if (sv[u] > value) pick.push_back(uint32_t(u));
+  } else {
+    const uint64_t k =
+        std::min<uint64_t>(nunits, uint64_t(std::ceil(value * double(nunits))));
+    std::vector<uint32_t> order(nunits);
+    for (uint64_t u = 0; u < nunits; ++u) order[u] = uint32_t(u);
+    std::partial_sort(order.begin(), order.begin() + k, order.end(), [&](uint32_t a, uint32_t b) {
+      return sv[a] > sv[b] || (sv[a] == sv[b] && a < b);
+    });
+    pick.assign(order.begin(), order.begin() + k);
+    std::sort(pick.begin(), pick.end());
+  }
+  *count = pick.size();
+  if (pick.size() > cap || (!sel && !pick.empty())) return STZ_ERR_BUFFER;
+  std::copy(pick.begin(), pick.end(), sel);
+  return STZ_OK;
+}
+
 stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* stream) {
   Header h;
   const stz_status s = read_header(comp, size, static_cast<hipStream_t>(stream), &h);

@@ -490,6 +490,64 @@ void launch_dec_bh(int h, const DecSlabArgs* D, const ItemMap& m, unsigned grid,
 
 }  // namespace
 
+// ROI statistics (Sec. 3.3): maximum and minimum of one unit of a level grid
+// (dims gn, stride s), unit = a block of B^3 full-resolution points (E = B/s
+// grid points per axis) or one plane across an axis; stat 0 = max, 1 = range.
+__global__ __launch_bounds__(256) void k_roi_stats(const float* __restrict__ grid, int64_t gn0,
+                                                   int64_t gn1, int64_t gn2, int64_t E, int unit,
+                                                   int stat, int64_t nb1, int64_t nb2,
+                                                   double* out) {
+  const int64_t u = blockIdx.x;
+  int64_t lo[3] = {0, 0, 0}, hi[3] = {gn0, gn1, gn2};
+  if (unit == 0) {
+    const int64_t b[3] = {u / (nb1 * nb2), (u / nb2) % nb1, u % nb2};
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = b[d] * E;
+      hi[d] = min(hi[d], lo[d] + E);
+    }
+  } else {
+    lo[unit - 1] = u;
+    hi[unit - 1] = u + 1;
+  }
+  const int64_t e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+  const int64_t cnt = (hi[0] - lo[0]) * e1 * e2;
+  float mx = -INFINITY, mn = INFINITY;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t x = i % e2, t = i / e2, y = t % e1, z = t / e1;
+    const float v = grid[((lo[0] + z) * gn1 + lo[1] + y) * gn2 + lo[2] + x];
+    mx = fmaxf(mx, v);
+    mn = fminf(mn, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+    mn = fminf(mn, __shfl_xor(mn, o, kWave));
+  }
+  __shared__ float smx[4], smn[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smx[w] = mx;
+    smn[w] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      mx = fmaxf(mx, smx[i]);
+      mn = fminf(mn, smn[i]);
+    }
+    out[u] = stat == 0 ? (double)mx : (double)mx - (double)mn;
+  }
+}
+
+hipError_t launch_roi_stats(const float* grid, const int64_t gn[3], int64_t E, int unit, int stat,
+                            const int64_t nb[3], uint64_t nunits, double* out, hipStream_t st) {
+  if (nunits == 0) return hipSuccess;
+  prof_begin(st, "roi_stats", -1);
+  hipLaunchKernelGGL(k_roi_stats, dim3(unsigned(nunits)), dim3(256), 0, st, grid, gn[0], gn[1],
+                     gn[2], E, unit, stat, nb[1], nb[2], out);
+  prof_end(st);
+  return hipGetLastError();
+}
+
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
   const Geo& g = a.geo;
   const int L = g.L;

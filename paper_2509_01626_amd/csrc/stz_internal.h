@@ -242,6 +242,9 @@ struct DecodeArgs {
 };
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+// Per-unit ROI statistics of a level grid (see stz_roi_select).
+hipError_t launch_roi_stats(const float* grid, const int64_t gn[3], int64_t E, int unit, int stat,
+                            const int64_t nb[3], uint64_t nunits, double* out, hipStream_t st);
 
 // One batched decode: the request table (device) and the work maps of every
 // launch. Level k of request r has edge E = B_r >> (L_r - k).

@@ -89,6 +89,10 @@ def lib():
         L.stz_autotune_batch.restype = C.c_int
         L.stz_autotune_batch.argtypes = [C.POINTER(Job), C.c_uint64, C.c_char_p, C.c_uint64,
                                          C.c_void_p]
+        L.stz_roi_select.restype = C.c_int
+        L.stz_roi_select.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                     C.c_double, C.c_void_p, C.c_uint64,
+                                     C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p]
         L.stz_trim.restype = C.c_int
         L.stz_trim.argtypes = []
         L.stz_status_string.restype = C.c_char_p
@@ -342,4 +346,51 @@ def stz_decompress_batch(reqs, flags=None, stream=None, check=True):
     if check and st != OK:
         raise StzError(st, "stz_decompress_batch")
     return st
+
+
+# ---- ROI selection ------------------------------------------------------------
+ROI_BLOCKS, ROI_SLICES_Z, ROI_SLICES_Y, ROI_SLICES_X = 0, 1, 2, 3
+ROI_MAX, ROI_RANGE = 0, 1
+ROI_THRESHOLD, ROI_TOP_FRACTION = 0, 1
+
+
+def roi_units(info, level, unit):
+    if unit == ROI_BLOCKS:
+        n = 1
+        for d in info.dims:
+            n *= (int(d) + info.block - 1) // info.block
+        return n
+    s = 1 << (info.levels - level)
+    return (int(info.dims[unit - 1]) - 1) // s + 1
+
+
+def stz_roi_select(field, level, unit=ROI_BLOCKS, stat=ROI_MAX, rule=ROI_THRESHOLD, value=0.0,
+                   stream=None):
+    """Select ROI units of a resident field from its level-`level` decode:
+    returns (selected unit indices, per-unit statistic) as numpy arrays."""
+    import numpy as np
+    n = roi_units(field.info, level, unit)
+    sel = np.empty(max(n, 1), dtype=np.uint32)
+    stats = np.empty(max(n, 1), dtype=np.float64)
+    cnt = C.c_uint64(0)
+    st = lib().stz_roi_select(field.handle, level, unit, stat, rule, float(value),
+                              sel.ctypes.data, sel.size, C.byref(cnt), stats.ctypes.data,
+                              _stream(stream))
+    if st != OK:
+        raise StzError(st, "stz_roi_select")
+    return sel[:cnt.value].copy(), stats[:n].copy()
+
+
+def roi_block_boxes(info, blocks):
+    """Full-resolution boxes [lo, hi) of ROI block indices (raster order)."""
+    B = info.block
+    nb = [(int(d) + B - 1) // B for d in info.dims]
+    out = []
+    for b in blocks:
+        b = int(b)
+        idx = (b // (nb[1] * nb[2]), (b // nb[2]) % nb[1], b % nb[2])
+        lo = [i * B for i in idx]
+        hi = [min(int(d), l + B) for d, l in zip(info.dims, lo)]
+        out.append((lo, hi))
+    return out
 
