@@ -744,18 +744,38 @@ constexpr int kPackChunk = 4096;                     // symbols per chunk
 constexpr int kPackPer = kPackChunk / 256;           // per thread
 constexpr int kPackWords = kPackChunk * kLmax / 32 + 2;
 
+// 32-bit exclusive scan over the work-group (256 threads).
+__device__ inline uint32_t block_excl_scan32(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t ws[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) pre += ws[i];
+    tot += ws[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - v;
+}
+
 __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   const DevParams* P = a.P;
   if (P->flags) return;
-  __shared__ uint8_t Ls[2 * kMaxRadius];
-  __shared__ uint16_t Cs[2 * kMaxRadius];
+  __shared__ uint32_t LC[2 * kMaxRadius];  // code | length << 16
   __shared__ uint16_t us[kPackChunk];
   __shared__ uint32_t wb[kPackWords];
+  __shared__ uint32_t u_rows[8], u_mx[8], u_my[8];
+  __shared__ uint64_t u_src[8];
   const int tid = threadIdx.x;
-  for (int i = tid; i < a.nsym; i += blockDim.x) {
-    Ls[i] = a.lens[i];
-    Cs[i] = a.codes[i];
-  }
+  for (int i = tid; i < a.nsym; i += blockDim.x)
+    LC[i] = uint32_t(a.codes[i]) | (uint32_t(a.lens[i]) << 16);
   const int l = a.level;
   uint32_t* unit_word = reinterpret_cast<uint32_t*>(a.out + P->sec[l]);
   uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
@@ -763,9 +783,14 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
   float* outv = reinterpret_cast<float*>(a.out + P->off_out[l]);
   const int m = (a.g.B >> a.logs) >> 1;
-  // unit index and lane lengths of the block's units
+  // per-unit geometry once per block (threads 0..6), unit index entries
   if (tid < 7) {
     const int64_t u = wg * 7 + tid;
+    const UnitGeo ug = unit_geo(a.g, u, a.logs);
+    u_rows[tid + 1] = uint32_t(ug.M[0]) * ug.M[1];
+    u_my[tid + 1] = uint32_t(ug.M[1]);
+    u_mx[tid + 1] = uint32_t(ug.M[2]);
+    u_src[tid + 1] = uint64_t(unit_sym_off(a.g, a.logs, u));
     unit_word[u] = a.scan_words[u];
     unit_outl[u] = a.scan_outl[u];
     if (u == int64_t(a.nu) - 1) {
@@ -773,62 +798,61 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       unit_outl[a.nu] = a.scan_outl[a.nu];
     }
   }
-  if (tid < 7 * m) {
-    const int64_t u = wg * 7 + tid / m;
-    const int j = tid % m;
-    const UnitGeo ug = unit_geo(a.g, u, a.logs);
-    if (j < ug.M[2]) {
-      const uint64_t li = uint64_t(unit_lane_off(a.g, a.logs, u)) + j;
+  __syncthreads();
+  if (tid < 7 * m) {  // lane lengths of the block's units
+    const int c = tid / m + 1, j = tid % m;
+    if (uint32_t(j) < u_mx[c]) {
+      const uint64_t li = uint64_t(unit_lane_off(a.g, a.logs, wg * 7 + c - 1)) + j;
       lane_arr[li] = a.lane_len[li];
     }
   }
-  __syncthreads();
   for (int c = 1; c <= 7; ++c) {
     const int64_t u = wg * 7 + (c - 1);
-    const UnitGeo ug = unit_geo(a.g, u, a.logs);
-    const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1];
-    const uint32_t n_u = rows * uint32_t(ug.M[2]);
+    const uint32_t rows = u_rows[c];
+    const uint32_t n_u = rows * u_mx[c];
     if (n_u == 0) continue;
-    const uint16_t* src = a.sym + uint64_t(unit_sym_off(a.g, a.logs, u));
+    const uint16_t* src = a.sym + u_src[c];
     uint32_t* dst = pay + a.scan_words[u];
-    uint64_t bits = 0;  // bits of the unit written or carried so far
+    uint32_t wdone = 0;  // whole words of the unit written so far
+    uint32_t sk = 0;     // bits carried in the partial word
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < n_u; c0 += kPackChunk) {
       const int n = int(min<uint32_t>(kPackChunk, n_u - c0));
       for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
       __syncthreads();
-      // this thread's run of kPackPer symbols: lengths, then bit offsets
-      uint64_t mine = 0;
+      // this thread's run of kPackPer symbols: (code, length) in registers
       const int i0 = tid * kPackPer;
+      uint32_t lc[kPackPer];
+      uint32_t mine = 0;
 #pragma unroll
-      for (int k = 0; k < kPackPer; ++k)
-        if (i0 + k < n) mine += Ls[us[i0 + k]];
-      uint64_t total;
-      const uint64_t off = block_excl_scan(mine, &total);
-      const int sk = int(bits & 31);  // bit position of the chunk inside word 0
-      const int nw = int((uint64_t(sk) + total + 31) >> 5);
-      for (int i = tid; i < nw; i += 256) wb[i] = 0;
+      for (int k = 0; k < kPackPer; ++k) {
+        lc[k] = i0 + k < n ? LC[us[i0 + k]] : 0u;
+        mine += lc[k] >> 16;
+      }
+      uint32_t total;
+      const uint32_t off = block_excl_scan32(mine, &total);
+      const uint32_t nw = (sk + total + 31) >> 5;
+      for (uint32_t i = tid; i < nw; i += 256) wb[i] = 0;
       __syncthreads();
       if (tid == 0) wb[0] = carry;
       __syncthreads();
-      uint64_t pos = uint64_t(sk) + off;
-      uint32_t cur = 0;
-      int64_t cw_i = int64_t(pos >> 5);
+      // codes of the run into the word buffer (chunk-relative bit positions)
+      uint32_t pos = sk + off;
+      uint32_t cw_i = pos >> 5, cur = 0;
 #pragma unroll
       for (int k = 0; k < kPackPer; ++k) {
-        if (i0 + k >= n) break;
-        const uint32_t s = us[i0 + k];
-        const uint32_t len = Ls[s], code = Cs[s];
-        const int o = int(pos & 31);
-        if (int64_t(pos >> 5) != cw_i) {
+        const uint32_t len = lc[k] >> 16, code = lc[k] & 0xFFFFu;
+        if (len == 0) continue;
+        if ((pos >> 5) != cw_i) {
           if (cur) atomicOr(&wb[cw_i], cur);
           cur = 0;
-          cw_i = int64_t(pos >> 5);
+          cw_i = pos >> 5;
         }
-        if (o + int(len) <= 32) {
-          cur |= code << (32 - o - int(len));
+        const uint32_t o = pos & 31;
+        if (o + len <= 32) {
+          cur |= code << (32 - o - len);
         } else {
-          const int hi = o + int(len) - 32;
+          const uint32_t hi = o + len - 32;
           cur |= code >> hi;
           atomicOr(&wb[cw_i], cur);
           cw_i += 1;
@@ -839,21 +863,21 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       if (cur) atomicOr(&wb[cw_i], cur);
       __syncthreads();
       // complete words out; the partial last word carries over
-      const uint64_t end = uint64_t(sk) + total;
-      const int full = int(end >> 5);
-      const uint64_t w0 = bits >> 5;
-      for (int i = tid; i < full; i += 256) dst[w0 + i] = wb[i];
+      const uint32_t end = sk + total;
+      const uint32_t full = end >> 5;
+      for (uint32_t i = tid; i < full; i += 256) dst[wdone + i] = wb[i];
       carry = (end & 31) ? wb[full] : 0u;
-      bits += total;
+      wdone += full;
+      sk = end & 31;
       __syncthreads();
     }
-    if (bits & 31)
-      if (tid == 0) dst[bits >> 5] = carry;
+    if (sk && tid == 0) dst[wdone] = carry;
     // outliers in rank order (row-major: row t, then column j)
     const uint32_t uo = a.scan_outl[u], n_out = a.scan_outl[u + 1] - uo;
     if (n_out) {
-      const uint32_t Mx = uint32_t(ug.M[2]), M1 = uint32_t(ug.M[1]);
-      uint64_t run = 0;
+      const UnitGeo ug = unit_geo(a.g, u, a.logs);
+      const uint32_t Mx = u_mx[c], M1 = u_my[c];
+      uint32_t run = 0;
       for (uint32_t r0 = 0; r0 < n_u; r0 += 256) {
         const uint32_t r = r0 + tid;
         bool isz = false;
@@ -863,8 +887,8 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
           j = r - t * Mx;
           isz = src[uint64_t(j) * rows + t] == 0;
         }
-        uint64_t cnt;
-        const uint64_t rank = run + block_excl_scan(isz ? 1 : 0, &cnt);
+        uint32_t cnt;
+        const uint32_t rank = run + block_excl_scan32(isz ? 1u : 0u, &cnt);
         if (isz && rank < n_out) {
           const uint32_t vy = t % M1, vz = t / M1;
           const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
