@@ -55,10 +55,12 @@ struct DecRows {
   int R;
 };
 
-// Slab height of the decoder: for 32^3-point blocks, 4 planes keep the LDS
-// footprint (code table, slab symbols, coarse tile, stream ring) small enough
-// for four work-groups per CU.
-constexpr int dec_slab_h(int E) { return E == 32 ? 4 : default_slab_h(E); }
+// Slab height of the decoder: for 32^3-point blocks, 2 planes keep the LDS
+// footprint (code table, slab symbols, coarse tile, stream ring) at 26 KB and
+// the registers under 100, for five work-groups per CU: the per-symbol decode
+// chains (one per lane stream) are latency-bound, so more blocks in flight win
+// over the extra slab passes.
+constexpr int dec_slab_h(int E) { return E == 32 ? 2 : default_slab_h(E); }
 
 // Value of one point of class C (0 = copy of a coarse point).
 template <int E, int H, int C, bool INT>
