@@ -22,7 +22,7 @@ class Config(C.Structure):
 class Info(C.Structure):
     _fields_ = [("dims", C.c_uint64 * 3), ("block", C.c_uint32), ("levels", C.c_uint32),
                 ("radius", C.c_uint32), ("lmax", C.c_uint32), ("eb_mode", C.c_uint32),
-                ("reserved", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
+                ("dtype", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
                 ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64)]
 
 
@@ -40,26 +40,34 @@ def lib():
             _build.build()
         L = C.CDLL(_build.LIB)
         u64p = C.POINTER(C.c_uint64)
-        L.stz_ref_compress_bound.restype = C.c_uint64
-        L.stz_ref_compress_bound.argtypes = [u64p, C.POINTER(Config)]
-        L.stz_ref_compress.restype = C.c_int
-        L.stz_ref_compress.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double,
-                                       C.POINTER(Config), C.c_void_p, C.c_uint64, u64p]
+        for sfx in ("", "_f64"):
+            f = getattr(L, "stz_ref_compress_bound" + sfx)
+            f.restype = C.c_uint64
+            f.argtypes = [u64p, C.POINTER(Config)]
+            f = getattr(L, "stz_ref_compress" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double, C.POINTER(Config), C.c_void_p,
+                          C.c_uint64, u64p]
+            f = getattr(L, "stz_ref_decompress" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64]
+            f = getattr(L, "stz_ref_decompress_level" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, u64p]
+            f = getattr(L, "stz_ref_decompress_region" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32, C.c_void_p,
+                          C.c_uint64, u64p]
         L.stz_ref_info.restype = C.c_int
         L.stz_ref_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Info)]
-        L.stz_ref_decompress.restype = C.c_int
-        L.stz_ref_decompress.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64]
-        L.stz_ref_decompress_level.restype = C.c_int
-        L.stz_ref_decompress_level.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p,
-                                               C.c_uint64, u64p]
-        L.stz_ref_decompress_region.restype = C.c_int
-        L.stz_ref_decompress_region.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32,
-                                                C.c_void_p, C.c_uint64, u64p]
-        L.stz_ref_symbols.restype = C.c_int
-        L.stz_ref_symbols.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double, C.POINTER(Config),
-                                      C.c_void_p, C.c_void_p, C.c_void_p]
+        for f in (L.stz_ref_symbols, L.stz_ref_symbols_f64):
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double, C.POINTER(Config),
+                          C.c_void_p, C.c_void_p, C.c_void_p]
         L.stz_ref_predict.restype = C.c_float
         L.stz_ref_predict.argtypes = [C.c_void_p, u64p, u64p, C.c_uint64]
+        L.stz_ref_predict_f64.restype = C.c_double
+        L.stz_ref_predict_f64.argtypes = [C.c_void_p, u64p, u64p, C.c_uint64]
         L.stz_ref_units_decoded.restype = None
         L.stz_ref_units_decoded.argtypes = [C.c_void_p]
         L.stz_ref_huffman_lengths.restype = None
@@ -91,32 +99,50 @@ class OracleError(RuntimeError):
         self.status = status
 
 
-def compress_bound(shape, cfg):
-    return int(lib().stz_ref_compress_bound(_dims(shape), C.byref(cfg)))
+def _sfx(dtype):
+    dt = np.dtype(dtype)
+    if dt == np.float32:
+        return ""
+    if dt == np.float64:
+        return "_f64"
+    raise TypeError(f"unsupported value type {dt}")
 
 
-def compress(x, eb_mode, eb, cfg):
-    """Compress a C-contiguous float32 array of shape (nz, ny, nx); returns bytes."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
+def compress_bound(shape, cfg, dtype=np.float32):
+    return int(getattr(lib(), "stz_ref_compress_bound" + _sfx(dtype))(_dims(shape),
+                                                                       C.byref(cfg)))
+
+
+def compress(x, eb_mode, eb, cfg, dtype=np.float32):
+    """Compress a C-contiguous array of shape (nz, ny, nx), converted to `dtype`
+    (float32 or float64); returns bytes."""
+    x = np.ascontiguousarray(x, dtype=dtype)
     assert x.ndim == 3
-    cap = compress_bound(x.shape, cfg)
+    cap = compress_bound(x.shape, cfg, dtype)
     out = np.zeros(cap, dtype=np.uint8)
     size = C.c_uint64(0)
-    st = lib().stz_ref_compress(x.ctypes.data, _dims(x.shape), eb_mode, eb, C.byref(cfg),
-                                out.ctypes.data, cap, C.byref(size))
+    st = getattr(lib(), "stz_ref_compress" + _sfx(dtype))(
+        x.ctypes.data, _dims(x.shape), eb_mode, eb, C.byref(cfg), out.ctypes.data, cap,
+        C.byref(size))
     if st != OK:
         raise OracleError(st, "compress")
     return out[: size.value].tobytes()
 
 
-def compress_status(x, eb_mode, eb, cfg, cap=None):
-    x = np.ascontiguousarray(x, dtype=np.float32)
+def compress_status(x, eb_mode, eb, cfg, cap=None, dtype=np.float32):
+    x = np.ascontiguousarray(x, dtype=dtype)
     if cap is None:
-        cap = max(compress_bound(x.shape, cfg), 1)
+        cap = max(compress_bound(x.shape, cfg, dtype), 1)
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     size = C.c_uint64(0)
-    return lib().stz_ref_compress(x.ctypes.data, _dims(x.shape), eb_mode, eb, C.byref(cfg),
-                                  out.ctypes.data, cap, C.byref(size))
+    return getattr(lib(), "stz_ref_compress" + _sfx(dtype))(
+        x.ctypes.data, _dims(x.shape), eb_mode, eb, C.byref(cfg), out.ctypes.data, cap,
+        C.byref(size))
+
+
+def value_type(inf):
+    """numpy value type of a stream from its info record."""
+    return np.float64 if inf.dtype == 1 else np.float32
 
 
 def info(comp):
@@ -131,9 +157,11 @@ def info(comp):
 def decompress(comp):
     inf = info(comp)
     shape = tuple(int(v) for v in inf.dims)
-    out = np.empty(shape, dtype=np.float32)
+    vt = value_type(inf)
+    out = np.empty(shape, dtype=vt)
     buf = np.frombuffer(comp, dtype=np.uint8)
-    st = lib().stz_ref_decompress(buf.ctypes.data, buf.size, out.ctypes.data, out.size)
+    st = getattr(lib(), "stz_ref_decompress" + _sfx(vt))(buf.ctypes.data, buf.size,
+                                                         out.ctypes.data, out.size)
     if st != OK:
         raise OracleError(st, "decompress")
     return out
@@ -143,11 +171,12 @@ def decompress_level(comp, level):
     inf = info(comp)
     s = 1 << (inf.levels - level)
     shape = tuple((int(n) - 1) // s + 1 for n in inf.dims)
-    out = np.empty(shape, dtype=np.float32)
+    vt = value_type(inf)
+    out = np.empty(shape, dtype=vt)
     od = (C.c_uint64 * 3)()
     buf = np.frombuffer(comp, dtype=np.uint8)
-    st = lib().stz_ref_decompress_level(buf.ctypes.data, buf.size, level, out.ctypes.data,
-                                        out.size, od)
+    st = getattr(lib(), "stz_ref_decompress_level" + _sfx(vt))(
+        buf.ctypes.data, buf.size, level, out.ctypes.data, out.size, od)
     if st != OK:
         raise OracleError(st, "decompress_level")
     assert tuple(od) == shape
@@ -162,48 +191,56 @@ def decompress_region(comp, lo, hi, level):
         first = -(-int(lo[d]) // s) * s
         shape.append((int(hi[d]) - 1 - first) // s + 1 if first < int(hi[d]) else 0)
     shape = tuple(shape)
-    out = np.empty(shape, dtype=np.float32)
+    vt = value_type(inf)
+    out = np.empty(shape, dtype=vt)
     od = (C.c_uint64 * 3)()
     buf = np.frombuffer(comp, dtype=np.uint8)
-    st = lib().stz_ref_decompress_region(buf.ctypes.data, buf.size, _dims(lo), _dims(hi), level,
-                                         out.ctypes.data, max(out.size, 0), od)
+    st = getattr(lib(), "stz_ref_decompress_region" + _sfx(vt))(
+        buf.ctypes.data, buf.size, _dims(lo), _dims(hi), level, out.ctypes.data,
+        max(out.size, 0), od)
     if st != OK:
         raise OracleError(st, "decompress_region")
     assert tuple(od) == shape, (tuple(od), shape)
     return out
 
 
-def decode_status(comp, fn="decompress", level=0, lo=None, hi=None):
-    """Status of a decode call on possibly corrupt bytes (never raises)."""
+def decode_status(comp, fn="decompress", level=0, lo=None, hi=None, dtype=np.float32):
+    """Status of a decode call (the `dtype` variant) on possibly corrupt bytes
+    (never raises)."""
     buf = np.frombuffer(comp, dtype=np.uint8)
-    out = np.empty(1 << 22, dtype=np.float32)
+    out = np.empty(1 << 22, dtype=dtype)
     od = (C.c_uint64 * 3)()
     L = lib()
+    x = _sfx(dtype)
     if fn == "decompress":
-        return L.stz_ref_decompress(buf.ctypes.data, buf.size, out.ctypes.data, out.size)
+        return getattr(L, "stz_ref_decompress" + x)(buf.ctypes.data, buf.size, out.ctypes.data,
+                                                    out.size)
     if fn == "level":
-        return L.stz_ref_decompress_level(buf.ctypes.data, buf.size, level, out.ctypes.data,
-                                          out.size, od)
-    return L.stz_ref_decompress_region(buf.ctypes.data, buf.size, _dims(lo), _dims(hi), level,
-                                       out.ctypes.data, out.size, od)
+        return getattr(L, "stz_ref_decompress_level" + x)(buf.ctypes.data, buf.size, level,
+                                                          out.ctypes.data, out.size, od)
+    return getattr(L, "stz_ref_decompress_region" + x)(buf.ctypes.data, buf.size, _dims(lo),
+                                                       _dims(hi), level, out.ctypes.data,
+                                                       out.size, od)
 
 
-def symbols(x, eb_mode, eb, cfg):
+def symbols(x, eb_mode, eb, cfg, dtype=np.float32):
     """Per-point symbol (-1 for anchors), reconstruction and level."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=dtype)
     sym = np.empty(x.shape, dtype=np.int32)
-    rec = np.empty(x.shape, dtype=np.float32)
+    rec = np.empty(x.shape, dtype=dtype)
     lvl = np.empty(x.shape, dtype=np.int32)
-    st = lib().stz_ref_symbols(x.ctypes.data, _dims(x.shape), eb_mode, eb, C.byref(cfg),
-                               sym.ctypes.data, rec.ctypes.data, lvl.ctypes.data)
+    st = getattr(lib(), "stz_ref_symbols" + _sfx(dtype))(
+        x.ctypes.data, _dims(x.shape), eb_mode, eb, C.byref(cfg), sym.ctypes.data,
+        rec.ctypes.data, lvl.ctypes.data)
     if st != OK:
         raise OracleError(st, "symbols")
     return sym, rec, lvl
 
 
-def predict(rec, p, s):
-    rec = np.ascontiguousarray(rec, dtype=np.float32)
-    return float(lib().stz_ref_predict(rec.ctypes.data, _dims(rec.shape), _dims(p), s))
+def predict(rec, p, s, dtype=np.float32):
+    rec = np.ascontiguousarray(rec, dtype=dtype)
+    f = getattr(lib(), "stz_ref_predict" + _sfx(dtype))
+    return float(f(rec.ctypes.data, _dims(rec.shape), _dims(p), s))
 
 
 def huffman_lengths(counts, lmax=12):

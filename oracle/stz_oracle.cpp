@@ -134,13 +134,16 @@ void unit_point(const Geo& g, const Unit& u, size_t s, size_t vz, size_t vy, siz
 // Prediction from the coarser level (Sec. 3.1, Optimizations 2 and 4).
 // `rec` is a full-resolution array; only stride-2s points are read.
 // ----------------------------------------------------------------------------
+// Values are float32 (the default) or float64 (dtype 1): the same formulas in
+// the same evaluation order, with T-typed constants.
+template <class T>
 struct Reader {
-  const float* rec;
+  const T* rec;
   const Geo* g;
   bool check;     // region decode: every value read must have been reconstructed
   bool* bad;
-  float at(long long z, long long y, long long x) const {
-    float v = rec[g->idx(size_t(z), size_t(y), size_t(x))];
+  T at(long long z, long long y, long long x) const {
+    T v = rec[g->idx(size_t(z), size_t(y), size_t(x))];
     if (check && std::isnan(v)) *bad = true;
     return v;
   }
@@ -163,23 +166,24 @@ AxisFlags axis_flags(const Geo& g, int d, size_t pd, size_t s) {
 // midpoint when both neighbours exist (Eq. 3), else linear extrapolation from
 // the two lower neighbours, else copy of the lower neighbour (Sec. 3.1 lets
 // boundary points fall back to whichever coarse neighbours exist).
-template <class F>
-float nested_rule(const AxisFlags& f, size_t s, F val) {
+template <class T, class F>
+T nested_rule(const AxisFlags& f, size_t s, F val) {
   const long long ss = (long long)s;
   if (f.P1) {
-    float lo = val(-ss);
-    float hi = val(ss);
-    return (lo + hi) * 0.5f;
+    T lo = val(-ss);
+    T hi = val(ss);
+    return (lo + hi) * T(0.5);
   }
   if (f.M3) {
-    float lo = val(-ss);
-    float lo3 = val(-3 * ss);
-    return ((3.0f * lo) - lo3) * 0.5f;
+    T lo = val(-ss);
+    T lo3 = val(-3 * ss);
+    return ((T(3) * lo) - lo3) * T(0.5);
   }
   return val(-ss);
 }
 
-float predict(const Reader& r, const Geo& g, const size_t p[3], size_t s) {
+template <class T>
+T predict(const Reader<T>& r, const Geo& g, const size_t p[3], size_t s) {
   int D[3];
   int nd = 0;
   for (int d = 0; d < 3; ++d)
@@ -205,42 +209,42 @@ float predict(const Reader& r, const Geo& g, const size_t p[3], size_t s) {
   if (nd == 1) {
     const AxisFlags& a = f[0];
     if (a.P1) {
-      float Bv = at_off(-ss, 0, 0);
-      float Cv = at_off(ss, 0, 0);
+      T Bv = at_off(-ss, 0, 0);
+      T Cv = at_off(ss, 0, 0);
       if (a.M3 && a.P3) {
         // Eq. 6: (-1, 9, 9, -1) / 16.
-        float A = at_off(-3 * ss, 0, 0);
-        float Dv = at_off(3 * ss, 0, 0);
-        return ((9.0f * (Bv + Cv)) - (A + Dv)) * 0.0625f;
+        T A = at_off(-3 * ss, 0, 0);
+        T Dv = at_off(3 * ss, 0, 0);
+        return ((T(9) * (Bv + Cv)) - (A + Dv)) * T(0.0625);
       }
       if (!a.M3 && a.P3) {
         // Quadratic through offsets -1, +1, +3: weights 3/8, 6/8, -1/8.
-        float Dv = at_off(3 * ss, 0, 0);
-        return ((3.0f * Bv + 6.0f * Cv) - Dv) * 0.125f;
+        T Dv = at_off(3 * ss, 0, 0);
+        return ((T(3) * Bv + T(6) * Cv) - Dv) * T(0.125);
       }
       if (a.M3 && !a.P3) {
         // Quadratic through offsets -3, -1, +1: weights -1/8, 6/8, 3/8.
-        float A = at_off(-3 * ss, 0, 0);
-        return ((6.0f * Bv + 3.0f * Cv) - A) * 0.125f;
+        T A = at_off(-3 * ss, 0, 0);
+        return ((T(6) * Bv + T(3) * Cv) - A) * T(0.125);
       }
-      return (Bv + Cv) * 0.5f;  // Eq. 3
+      return (Bv + Cv) * T(0.5);  // Eq. 3
     }
-    float Bv = at_off(-ss, 0, 0);
+    T Bv = at_off(-ss, 0, 0);
     if (a.M3) {
-      float A = at_off(-3 * ss, 0, 0);
-      return ((3.0f * Bv) - A) * 0.5f;
+      T A = at_off(-3 * ss, 0, 0);
+      return ((T(3) * Bv) - A) * T(0.5);
     }
     return Bv;
   }
 
   if (full && nd == 2) {
     // Eq. 7: mean of the two diagonal cubics: 9/32 * inner corners - 1/32 * outer.
-    float in = 0.0f, out = 0.0f;
+    T in = T(0), out = T(0);
     bool first = true;
     for (int s0 = -1; s0 <= 1; s0 += 2)
       for (int s1 = -1; s1 <= 1; s1 += 2) {
-        float vi = at_off(s0 * ss, s1 * ss, 0);
-        float vo = at_off(3 * s0 * ss, 3 * s1 * ss, 0);
+        T vi = at_off(s0 * ss, s1 * ss, 0);
+        T vo = at_off(3 * s0 * ss, 3 * s1 * ss, 0);
         if (first) {
           in = vi;
           out = vo;
@@ -250,17 +254,17 @@ float predict(const Reader& r, const Geo& g, const size_t p[3], size_t s) {
           out = out + vo;
         }
       }
-    return ((9.0f * in) - out) * 0.03125f;
+    return ((T(9) * in) - out) * T(0.03125);
   }
   if (full && nd == 3) {
     // Eq. 8: mean of the four body-diagonal cubics: 9/64 inner - 1/64 outer.
-    float in = 0.0f, out = 0.0f;
+    T in = T(0), out = T(0);
     bool first = true;
     for (int s0 = -1; s0 <= 1; s0 += 2)
       for (int s1 = -1; s1 <= 1; s1 += 2)
         for (int s2 = -1; s2 <= 1; s2 += 2) {
-          float vi = at_off(s0 * ss, s1 * ss, s2 * ss);
-          float vo = at_off(3 * s0 * ss, 3 * s1 * ss, 3 * s2 * ss);
+          T vi = at_off(s0 * ss, s1 * ss, s2 * ss);
+          T vo = at_off(3 * s0 * ss, 3 * s1 * ss, 3 * s2 * ss);
           if (first) {
             in = vi;
             out = vo;
@@ -270,7 +274,7 @@ float predict(const Reader& r, const Geo& g, const size_t p[3], size_t s) {
             out = out + vo;
           }
         }
-    return ((9.0f * in) - out) * 0.015625f;
+    return ((T(9) * in) - out) * T(0.015625);
   }
 
   // Multi-dimensional fallback (two or three odd axes, some cubic support
@@ -278,13 +282,13 @@ float predict(const Reader& r, const Geo& g, const size_t p[3], size_t s) {
   // both neighbours present on every axis this is Eq. 4 (two axes) or Eq. 5
   // (three axes) in real arithmetic.
   if (nd == 2) {
-    return nested_rule(f[0], s, [&](long long a) {
-      return nested_rule(f[1], s, [&](long long b) { return at_off(a, b, 0); });
+    return nested_rule<T>(f[0], s, [&](long long a) {
+      return nested_rule<T>(f[1], s, [&](long long b) { return at_off(a, b, 0); });
     });
   }
-  return nested_rule(f[0], s, [&](long long a) {
-    return nested_rule(f[1], s, [&](long long b) {
-      return nested_rule(f[2], s, [&](long long c) { return at_off(a, b, c); });
+  return nested_rule<T>(f[0], s, [&](long long a) {
+    return nested_rule<T>(f[1], s, [&](long long b) {
+      return nested_rule<T>(f[2], s, [&](long long c) { return at_off(a, b, c); });
     });
   });
 }
@@ -300,6 +304,9 @@ struct Bounds {
   double e[kMaxLevels + 1];
   float E2[kMaxLevels + 1];
   float INV[kMaxLevels + 1];
+  double E2d[kMaxLevels + 1];    // float64 data: 2e and 1/(2e) in double
+  double INVd[kMaxLevels + 1];
+  double echk[kMaxLevels + 1];   // float64 data: acceptance bound e*(1 - 2^-50)
 };
 
 void level_bounds(double eb_abs, double ratio, int L, Bounds* b) {
@@ -315,20 +322,42 @@ void level_bounds(double eb_abs, double ratio, int L, Bounds* b) {
     b->e[l] = e;
     b->E2[l] = (float)(2.0 * e);
     b->INV[l] = (float)(1.0 / (2.0 * e));
+    b->E2d[l] = 2.0 * e;
+    b->INVd[l] = 1.0 / (2.0 * e);
+    b->echk[l] = e * (1.0 - 0x1p-50);
   }
 }
 
 // Linear-scaling quantization of the prediction difference (Sec. 2.1 step 2,
 // Sec. 3.1 Optimization 3). Returns the symbol; 0 marks an outlier whose value
 // is stored verbatim.
-int quantize(float xv, float pred, float E2, float INV, double e, int R, float* rec) {
-  float diff = xv - pred;
-  float t = std::rint(diff * INV);
-  if (std::fabs(t) <= (float)(R - 1)) {
+//
+// float32 data: E2, INV are the float constants, the bound check |x - xr| <= e
+// is exact in double. float64 data: E2, INV in double; the check is evaluated
+// in double against e*(1 - 2^-50), which keeps the exact |x - xr| <= e despite
+// the rounding of the difference.
+template <class T>
+int quantize(T xv, T pred, const Bounds& bd, int l, int R, T* rec) {
+  T E2, INV;
+  if constexpr (sizeof(T) == 4) {
+    E2 = bd.E2[l];
+    INV = bd.INV[l];
+  } else {
+    E2 = bd.E2d[l];
+    INV = bd.INVd[l];
+  }
+  T diff = xv - pred;
+  T t = std::rint(diff * INV);
+  if (std::fabs(t) <= (T)(R - 1)) {
     int q = (int)t;
-    float prod = (float)q * E2;
-    float xr = pred + prod;
-    if (std::fabs((double)xv - (double)xr) <= e) {
+    T prod = (T)q * E2;
+    T xr = pred + prod;
+    bool ok;
+    if constexpr (sizeof(T) == 4)
+      ok = std::fabs((double)xv - (double)xr) <= bd.e[l];
+    else
+      ok = std::fabs(xv - xr) <= bd.echk[l];
+    if (ok) {
       *rec = xr;
       return q + R;
     }
@@ -493,7 +522,7 @@ struct stz_ref_config {
 
 struct stz_ref_info {
   uint64_t dims[3];
-  uint32_t block, levels, radius, lmax, eb_mode, reserved;
+  uint32_t block, levels, radius, lmax, eb_mode, dtype;  // dtype: 0 float32, 1 float64
   double eb, eb_abs, eb_ratio;
   uint64_t total_bytes;
 };
@@ -554,6 +583,7 @@ size_t n_anchor(const Geo& g) {
 struct LevelLayout {
   size_t nu, nl, nsym;
   size_t words, outl;
+  size_t vbytes = 4;  // bytes per stored value (outliers): 4 or 8
   size_t off_unit_word, off_unit_outl, off_lane, off_payload, off_outl, size;
 };
 
@@ -563,19 +593,23 @@ void layout_level(LevelLayout* ll) {
   ll->off_lane = ll->off_unit_outl + align16(4 * (ll->nu + 1));
   ll->off_payload = ll->off_lane + align16(2 * ll->nl);
   ll->off_outl = ll->off_payload + align16(4 * ll->words);
-  ll->size = ll->off_outl + align16(4 * ll->outl);
+  ll->size = ll->off_outl + align16(ll->vbytes * ll->outl);
 }
 
 }  // namespace
 
 extern "C" {
 
-uint64_t stz_ref_compress_bound(const uint64_t dims[3], const stz_ref_config* cfg) {
+}  // extern "C"
+
+namespace {
+
+uint64_t compress_bound_impl(const uint64_t dims[3], const stz_ref_config* cfg, size_t vb) {
   Cfg c;
   Geo g;
   if (resolve_cfg(cfg, &c) != OK || !make_geo(dims, c, &g)) return 0;
   size_t total = kHeaderBytes + align16(2 * size_t(c.R));
-  total += align16(4 * n_anchor(g));
+  total += align16(vb * n_anchor(g));
   for (int l = 1; l <= c.L; ++l) {
     std::vector<Unit> us = level_units(g, l);
     LevelLayout ll;
@@ -589,6 +623,7 @@ uint64_t stz_ref_compress_bound(const uint64_t dims[3], const stz_ref_config* cf
       ll.words += (u.nsym() * kLmax + 31) / 32;
     }
     ll.outl = ll.nsym;
+    ll.vbytes = vb;
     layout_level(&ll);
     total += ll.size;
   }
@@ -596,10 +631,12 @@ uint64_t stz_ref_compress_bound(const uint64_t dims[3], const stz_ref_config* cf
 }
 
 // Compression (Sec. 3.1-3.2 prediction and quantization, Huffman coding per
-// sub-block). Writes the stream to `out` (host memory).
-int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
-                     const stz_ref_config* cfg, void* out, uint64_t out_cap,
-                     uint64_t* out_size) {
+// sub-block). Writes the stream to `out` (host memory). T = float (value type
+// 0) or double (value type 1).
+template <class T>
+int compress_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
+                  const stz_ref_config* cfg, void* out, uint64_t out_cap, uint64_t* out_size) {
+  constexpr size_t VB = sizeof(T);
   Cfg c;
   Geo g;
   if (!x || !dims || !out_size) return ERR_ARG;
@@ -612,7 +649,7 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
   // Resolve the absolute bound: a value-range-relative bound scales by max-min.
   double eb_abs = eb;
   if (eb_mode == 1) {
-    float mn = x[0], mx = x[0];
+    T mn = x[0], mx = x[0];
     for (size_t i = 1; i < g.N; ++i) {
       mn = std::min(mn, x[i]);
       mx = std::max(mx, x[i]);
@@ -629,9 +666,9 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
 
   // Anchors: the stride-2^L grid, stored verbatim (replaces the paper's
   // separately coded coarsest level).
-  std::vector<float> rec(g.N, 0.0f);
+  std::vector<T> rec(g.N, T(0));
   const size_t s0 = g.stride(0);
-  std::vector<float> anchors;
+  std::vector<T> anchors;
   for (size_t z = 0; z < g.n[0]; z += s0)
     for (size_t y = 0; y < g.n[1]; y += s0)
       for (size_t xx = 0; xx < g.n[2]; xx += s0) {
@@ -644,9 +681,9 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
   const int nsym = 2 * c.R;
   std::vector<uint64_t> hist(nsym, 0);
   std::vector<std::vector<uint16_t>> syms(c.L + 1);
-  std::vector<std::vector<float>> outl(c.L + 1);
+  std::vector<std::vector<T>> outl(c.L + 1);
   std::vector<std::vector<Unit>> units(c.L + 1);
-  Reader rd{rec.data(), &g, false, nullptr};
+  Reader<T> rd{rec.data(), &g, false, nullptr};
   for (int l = 1; l <= c.L; ++l) {
     const size_t s = g.stride(l);
     units[l] = level_units(g, l);
@@ -657,9 +694,9 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
             size_t p[3];
             unit_point(g, u, s, vz, vy, vx, p);
             size_t i = g.idx(p[0], p[1], p[2]);
-            float pred = predict(rd, g, p, s);
-            float r;
-            int sym = quantize(x[i], pred, bd.E2[l], bd.INV[l], bd.e[l], c.R, &r);
+            T pred = predict(rd, g, p, s);
+            T r;
+            int sym = quantize(x[i], pred, bd, l, c.R, &r);
             rec[i] = r;
             if (sym == 0) outl[l].push_back(x[i]);
             syms[l].push_back((uint16_t)sym);
@@ -714,13 +751,14 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
     o.ll.nsym = syms[l].size();
     o.ll.words = o.payload.size();
     o.ll.outl = outl[l].size();
+    o.ll.vbytes = VB;
     layout_level(&o.ll);
   }
 
   // Assemble the stream.
   const size_t codelen_off = kHeaderBytes;
   const size_t anchor_off = codelen_off + align16(size_t(nsym));
-  size_t pos = anchor_off + align16(4 * anchors.size());
+  size_t pos = anchor_off + align16(VB * anchors.size());
   std::vector<size_t> sec(c.L + 1, 0);
   for (int l = 1; l <= c.L; ++l) {
     sec[l] = pos;
@@ -739,6 +777,7 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
   put32(o + 40, (uint32_t)c.R);
   put32(o + 44, (uint32_t)kLmax);
   put32(o + 48, (uint32_t)eb_mode);
+  put32(o + 52, VB == 8 ? 1u : 0u);  // value type: 0 float32, 1 float64
   putf64(o + 56, eb);
   putf64(o + 64, eb_abs);
   putf64(o + 72, c.ratio);
@@ -756,7 +795,7 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
     put64(e + 40, lv[l].ll.outl);
   }
   std::memcpy(o + codelen_off, lens.data(), size_t(nsym));
-  std::memcpy(o + anchor_off, anchors.data(), 4 * anchors.size());
+  std::memcpy(o + anchor_off, anchors.data(), VB * anchors.size());
   for (int l = 1; l <= c.L; ++l) {
     const LevelOut& L_ = lv[l];
     uint8_t* base = o + sec[l];
@@ -764,9 +803,33 @@ int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double
     std::memcpy(base + L_.ll.off_unit_outl, L_.unit_outl.data(), 4 * L_.unit_outl.size());
     std::memcpy(base + L_.ll.off_lane, L_.lane_len.data(), 2 * L_.lane_len.size());
     std::memcpy(base + L_.ll.off_payload, L_.payload.data(), 4 * L_.payload.size());
-    std::memcpy(base + L_.ll.off_outl, outl[l].data(), 4 * outl[l].size());
+    std::memcpy(base + L_.ll.off_outl, outl[l].data(), VB * outl[l].size());
   }
   return OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t stz_ref_compress_bound(const uint64_t dims[3], const stz_ref_config* cfg) {
+  return compress_bound_impl(dims, cfg, 4);
+}
+
+uint64_t stz_ref_compress_bound_f64(const uint64_t dims[3], const stz_ref_config* cfg) {
+  return compress_bound_impl(dims, cfg, 8);
+}
+
+int stz_ref_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+                     const stz_ref_config* cfg, void* out, uint64_t out_cap,
+                     uint64_t* out_size) {
+  return compress_impl<float>(x, dims, eb_mode, eb, cfg, out, out_cap, out_size);
+}
+
+int stz_ref_compress_f64(const double* x, const uint64_t dims[3], int eb_mode, double eb,
+                         const stz_ref_config* cfg, void* out, uint64_t out_cap,
+                         uint64_t* out_size) {
+  return compress_impl<double>(x, dims, eb_mode, eb, cfg, out, out_cap, out_size);
 }
 
 }  // extern "C"
@@ -779,6 +842,8 @@ namespace {
 struct Parsed {
   Geo g;
   Cfg c;
+  int dtype;      // 0 float32, 1 float64
+  size_t vb;      // bytes per stored value
   int eb_mode;
   double eb, eb_abs;
   uint64_t total;
@@ -804,6 +869,10 @@ int parse(const void* comp, uint64_t size, Parsed* P) {
   if (get32(b + 44) != (uint32_t)kLmax) return ERR_CORRUPT;
   if (resolve_cfg(&cf, &P->c) != OK || !make_geo(dims, P->c, &P->g)) return ERR_CORRUPT;
   P->eb_mode = (int)get32(b + 48);
+  const uint32_t dt = get32(b + 52);
+  if (dt > 1) return ERR_CORRUPT;
+  P->dtype = (int)dt;
+  P->vb = dt ? 8 : 4;
   P->eb = getf64(b + 56);
   P->eb_abs = getf64(b + 64);
   if (!(P->eb_abs > 0.0) || !std::isfinite(P->eb_abs)) return ERR_CORRUPT;
@@ -815,7 +884,7 @@ int parse(const void* comp, uint64_t size, Parsed* P) {
   if (P->codelen_off != kHeaderBytes) return ERR_CORRUPT;
   if (P->anchor_off != kHeaderBytes + align16(2 * size_t(P->c.R))) return ERR_CORRUPT;
   if (P->n_anch != n_anchor(P->g)) return ERR_CORRUPT;
-  uint64_t pos = P->anchor_off + align16(4 * P->n_anch);
+  uint64_t pos = P->anchor_off + align16(P->vb * P->n_anch);
   for (int l = 1; l <= P->c.L; ++l) {
     const uint8_t* e = b + kLevelTable + kLevelRec * size_t(l - 1);
     Parsed::Lv& v = P->lv[l];
@@ -838,6 +907,7 @@ int parse(const void* comp, uint64_t size, Parsed* P) {
     v.ll.nsym = v.nsym;
     v.ll.words = v.words;
     v.ll.outl = v.outl;
+    v.ll.vbytes = P->vb;
     layout_level(&v.ll);
     pos += v.ll.size;
     if (pos > P->total) return ERR_CORRUPT;
@@ -888,12 +958,14 @@ uint64_t g_units_decoded[kMaxLevels + 1][8];
 // Decode levels 1..level inside the boxes box[k] (half-open, per level k), or
 // the whole domain when region == false. `rec` is full resolution, NaN where
 // nothing was reconstructed.
+template <class T>
 int decode_levels(const void* comp, const Parsed& P, int level, bool region,
-                  const uint64_t (*box)[6], std::vector<float>* recp) {
+                  const uint64_t (*box)[6], std::vector<T>* recp) {
   const Geo& g = P.g;
   const uint8_t* b = static_cast<const uint8_t*>(comp);
-  std::vector<float>& rec = *recp;
-  rec.assign(g.N, std::numeric_limits<float>::quiet_NaN());
+  std::vector<T>& rec = *recp;
+  if (P.vb != sizeof(T)) return ERR_ARG;
+  rec.assign(g.N, std::numeric_limits<T>::quiet_NaN());
   const int nsym = 2 * P.c.R;
   const uint8_t* lens = b + P.codelen_off;
   Decoder dec;
@@ -922,21 +994,21 @@ int decode_levels(const void* comp, const Parsed& P, int level, bool region,
 
   // Anchors.
   const size_t s0 = g.stride(0);
-  const float* anch = reinterpret_cast<const float*>(b + P.anchor_off);
+  const uint8_t* anch = b + P.anchor_off;
   size_t ai = 0;
   for (size_t z = 0; z < g.n[0]; z += s0)
     for (size_t y = 0; y < g.n[1]; y += s0)
       for (size_t xx = 0; xx < g.n[2]; xx += s0, ++ai) {
         size_t p[3] = {z, y, xx};
         if (inside(0, p)) {
-          float v;
-          std::memcpy(&v, anch + ai, 4);
+          T v;
+          std::memcpy(&v, anch + sizeof(T) * ai, sizeof(T));
           rec[g.idx(z, y, xx)] = v;
         }
       }
 
   bool bad = false;
-  Reader rd{rec.data(), &g, region, &bad};
+  Reader<T> rd{rec.data(), &g, region, &bad};
   std::vector<int> sy;
   std::memset(g_units_decoded, 0, sizeof(g_units_decoded));
   for (int l = 1; l <= level; ++l) {
@@ -946,7 +1018,7 @@ int decode_levels(const void* comp, const Parsed& P, int level, bool region,
     const uint32_t* unit_outl = reinterpret_cast<const uint32_t*>(base + v.ll.off_unit_outl);
     const uint16_t* lane_len = reinterpret_cast<const uint16_t*>(base + v.ll.off_lane);
     const uint32_t* payload = reinterpret_cast<const uint32_t*>(base + v.ll.off_payload);
-    const float* outl = reinterpret_cast<const float*>(base + v.ll.off_outl);
+    const uint8_t* outl = base + v.ll.off_outl;
     if (unit_word[0] != 0 || unit_word[v.nu] != v.words) return ERR_CORRUPT;
     if (unit_outl[0] != 0 || unit_outl[v.nu] != v.outl) return ERR_CORRUPT;
     const size_t s = g.stride(l);
@@ -983,16 +1055,22 @@ int decode_levels(const void* comp, const Parsed& P, int level, bool region,
             size_t p[3];
             unit_point(g, u, s, vz, vy, vx, p);
             const int sym = sy[t];
-            float val = 0.0f;
+            T val = T(0);
             if (sym == 0) {
               if (oi >= oe) return ERR_CORRUPT;
-              std::memcpy(&val, outl + oi, 4);
+              std::memcpy(&val, outl + sizeof(T) * oi, sizeof(T));
               ++oi;
             }
             if (!inside(l, p)) continue;
             if (sym != 0) {
-              float pred = predict(rd, g, p, s);
-              float prod = (float)(sym - P.c.R) * bd.E2[l];
+              // The quantizer's reconstruction, same operands and order.
+              T pred = predict(rd, g, p, s);
+              T E2;
+              if constexpr (sizeof(T) == 4)
+                E2 = bd.E2[l];
+              else
+                E2 = bd.E2d[l];
+              T prod = (T)(sym - P.c.R) * E2;
               val = pred + prod;
             }
             rec[g.idx(p[0], p[1], p[2])] = val;
@@ -1019,7 +1097,7 @@ int stz_ref_info(const void* comp, uint64_t size, stz_ref_info* info) {
     info->radius = (uint32_t)P.c.R;
     info->lmax = (uint32_t)kLmax;
     info->eb_mode = (uint32_t)P.eb_mode;
-    info->reserved = 0;
+    info->dtype = (uint32_t)P.dtype;
     info->eb = P.eb;
     info->eb_abs = P.eb_abs;
     info->eb_ratio = P.c.ratio;
@@ -1028,14 +1106,20 @@ int stz_ref_info(const void* comp, uint64_t size, stz_ref_info* info) {
   return OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 // Progressive decompression: reconstruct levels 0..level and emit the stride
 // 2^(L-level) grid (Sec. 3.3, progressive decompression). level == L gives the
-// full field.
-int stz_ref_decompress_level(const void* comp, uint64_t size, uint32_t level, float* out,
-                             uint64_t out_cap, uint64_t out_dims[3]) {
+// full field. A stream of the other value type is rejected with ERR_ARG.
+template <class T>
+int decompress_level_impl(const void* comp, uint64_t size, uint32_t level, T* out,
+                          uint64_t out_cap, uint64_t out_dims[3]) {
   Parsed P;
   int st = parse(comp, size, &P);
   if (st != OK) return st;
+  if (P.vb != sizeof(T)) return ERR_ARG;
   if ((int)level > P.c.L) return ERR_ARG;
   const Geo& g = P.g;
   const size_t s = g.stride((int)level);
@@ -1044,8 +1128,8 @@ int stz_ref_decompress_level(const void* comp, uint64_t size, uint32_t level, fl
   if (out_dims)
     for (int d = 0; d < 3; ++d) out_dims[d] = od[d];
   if (!out || od[0] * od[1] * od[2] > out_cap) return ERR_BUFFER;
-  std::vector<float> rec;
-  st = decode_levels(comp, P, (int)level, false, nullptr, &rec);
+  std::vector<T> rec;
+  st = decode_levels<T>(comp, P, (int)level, false, nullptr, &rec);
   if (st != OK) return st;
   size_t o = 0;
   for (size_t z = 0; z < g.n[0]; z += s)
@@ -1054,24 +1138,27 @@ int stz_ref_decompress_level(const void* comp, uint64_t size, uint32_t level, fl
   return OK;
 }
 
-int stz_ref_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap) {
+template <class T>
+int decompress_impl(const void* comp, uint64_t size, T* out, uint64_t out_cap) {
   Parsed P;
   int st = parse(comp, size, &P);
   if (st != OK) return st;
   uint64_t od[3];
-  return stz_ref_decompress_level(comp, size, (uint32_t)P.c.L, out, out_cap, od);
+  return decompress_level_impl<T>(comp, size, (uint32_t)P.c.L, out, out_cap, od);
 }
 
 // Random-access decompression of the box [lo, hi) at a level (Sec. 3.3): the
 // box at the output level needs, at every coarser level k-1, the box widened by
 // the stencil reach 3*s_k; only units with a point inside their level's box are
 // decoded, and only points inside are predicted.
-int stz_ref_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
-                              const uint64_t hi[3], uint32_t level, float* out,
-                              uint64_t out_cap, uint64_t out_dims[3]) {
+template <class T>
+int decompress_region_impl(const void* comp, uint64_t size, const uint64_t lo[3],
+                           const uint64_t hi[3], uint32_t level, T* out, uint64_t out_cap,
+                           uint64_t out_dims[3]) {
   Parsed P;
   int st = parse(comp, size, &P);
   if (st != OK) return st;
+  if (P.vb != sizeof(T)) return ERR_ARG;
   const Geo& g = P.g;
   if ((int)level > P.c.L || !lo || !hi) return ERR_ARG;
   for (int d = 0; d < 3; ++d)
@@ -1100,18 +1187,52 @@ int stz_ref_decompress_region(const void* comp, uint64_t size, const uint64_t lo
   const size_t cnt = od[0] * od[1] * od[2];
   if (cnt == 0) return OK;
   if (!out || cnt > out_cap) return ERR_BUFFER;
-  std::vector<float> rec;
-  st = decode_levels(comp, P, (int)level, true, box, &rec);
+  std::vector<T> rec;
+  st = decode_levels<T>(comp, P, (int)level, true, box, &rec);
   if (st != OK) return st;
   size_t o = 0;
   for (size_t z = first[0]; z < hi[0]; z += s)
     for (size_t y = first[1]; y < hi[1]; y += s)
       for (size_t x = first[2]; x < hi[2]; x += s) {
-        float v = rec[g.idx(z, y, x)];
+        T v = rec[g.idx(z, y, x)];
         if (std::isnan(v)) return ERR_CORRUPT;
         out[o++] = v;
       }
   return OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stz_ref_decompress_level(const void* comp, uint64_t size, uint32_t level, float* out,
+                             uint64_t out_cap, uint64_t out_dims[3]) {
+  return decompress_level_impl<float>(comp, size, level, out, out_cap, out_dims);
+}
+
+int stz_ref_decompress_level_f64(const void* comp, uint64_t size, uint32_t level, double* out,
+                                 uint64_t out_cap, uint64_t out_dims[3]) {
+  return decompress_level_impl<double>(comp, size, level, out, out_cap, out_dims);
+}
+
+int stz_ref_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap) {
+  return decompress_impl<float>(comp, size, out, out_cap);
+}
+
+int stz_ref_decompress_f64(const void* comp, uint64_t size, double* out, uint64_t out_cap) {
+  return decompress_impl<double>(comp, size, out, out_cap);
+}
+
+int stz_ref_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
+                              const uint64_t hi[3], uint32_t level, float* out,
+                              uint64_t out_cap, uint64_t out_dims[3]) {
+  return decompress_region_impl<float>(comp, size, lo, hi, level, out, out_cap, out_dims);
+}
+
+int stz_ref_decompress_region_f64(const void* comp, uint64_t size, const uint64_t lo[3],
+                                  const uint64_t hi[3], uint32_t level, double* out,
+                                  uint64_t out_cap, uint64_t out_dims[3]) {
+  return decompress_region_impl<double>(comp, size, lo, hi, level, out, out_cap, out_dims);
 }
 
 // ---------------------------------------------------------------------------
@@ -1121,8 +1242,13 @@ int stz_ref_decompress_region(const void* comp, uint64_t size, const uint64_t lo
 // Per-point symbols and reconstruction of the compressor, in full-resolution
 // order: sym[i] = -1 for anchors, else the symbol of point i; rec[i] = the value
 // the decoder reproduces. Also returns the level of each point.
-int stz_ref_symbols(const float* x, const uint64_t dims[3], int eb_mode, double eb,
-                    const stz_ref_config* cfg, int32_t* sym, float* rec_out, int32_t* level_of) {
+}  // extern "C"
+
+namespace {
+
+template <class T>
+int symbols_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
+                 const stz_ref_config* cfg, int32_t* sym, T* rec_out, int32_t* level_of) {
   Cfg c;
   Geo g;
   if (resolve_cfg(cfg, &c) != OK || !make_geo(dims, c, &g)) return ERR_ARG;
@@ -1131,7 +1257,7 @@ int stz_ref_symbols(const float* x, const uint64_t dims[3], int eb_mode, double 
     if (!std::isfinite(x[i])) return ERR_NONFINITE;
   double eb_abs = eb;
   if (eb_mode == 1) {
-    float mn = x[0], mx = x[0];
+    T mn = x[0], mx = x[0];
     for (size_t i = 1; i < g.N; ++i) {
       mn = std::min(mn, x[i]);
       mx = std::max(mx, x[i]);
@@ -1142,7 +1268,7 @@ int stz_ref_symbols(const float* x, const uint64_t dims[3], int eb_mode, double 
   }
   Bounds bd;
   level_bounds(eb_abs, c.ratio, c.L, &bd);
-  std::vector<float> rec(g.N, 0.0f);
+  std::vector<T> rec(g.N, T(0));
   const size_t s0 = g.stride(0);
   for (size_t i = 0; i < g.N; ++i) {
     sym[i] = -2;
@@ -1156,7 +1282,7 @@ int stz_ref_symbols(const float* x, const uint64_t dims[3], int eb_mode, double 
         sym[i] = -1;
         level_of[i] = 0;
       }
-  Reader rd{rec.data(), &g, false, nullptr};
+  Reader<T> rd{rec.data(), &g, false, nullptr};
   for (int l = 1; l <= c.L; ++l) {
     const size_t s = g.stride(l);
     for (const Unit& u : level_units(g, l))
@@ -1166,15 +1292,30 @@ int stz_ref_symbols(const float* x, const uint64_t dims[3], int eb_mode, double 
             size_t p[3];
             unit_point(g, u, s, vz, vy, vx, p);
             size_t i = g.idx(p[0], p[1], p[2]);
-            float pred = predict(rd, g, p, s);
-            float r;
-            sym[i] = quantize(x[i], pred, bd.E2[l], bd.INV[l], bd.e[l], c.R, &r);
+            T pred = predict(rd, g, p, s);
+            T r;
+            sym[i] = quantize<T>(x[i], pred, bd, l, c.R, &r);
             rec[i] = r;
             level_of[i] = l;
           }
   }
-  std::memcpy(rec_out, rec.data(), 4 * g.N);
+  std::memcpy(rec_out, rec.data(), sizeof(T) * g.N);
   return OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stz_ref_symbols(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+                    const stz_ref_config* cfg, int32_t* sym, float* rec_out, int32_t* level_of) {
+  return symbols_impl<float>(x, dims, eb_mode, eb, cfg, sym, rec_out, level_of);
+}
+
+int stz_ref_symbols_f64(const double* x, const uint64_t dims[3], int eb_mode, double eb,
+                        const stz_ref_config* cfg, int32_t* sym, double* rec_out,
+                        int32_t* level_of) {
+  return symbols_impl<double>(x, dims, eb_mode, eb, cfg, sym, rec_out, level_of);
 }
 
 // The prediction of point p at stride s from a full-resolution array `rec`.
@@ -1183,7 +1324,17 @@ float stz_ref_predict(const float* rec, const uint64_t dims[3], const uint64_t p
   Geo g;
   for (int d = 0; d < 3; ++d) g.n[d] = dims[d];
   g.N = dims[0] * dims[1] * dims[2];
-  Reader rd{rec, &g, false, nullptr};
+  Reader<float> rd{rec, &g, false, nullptr};
+  size_t pp[3] = {p[0], p[1], p[2]};
+  return predict(rd, g, pp, s);
+}
+
+double stz_ref_predict_f64(const double* rec, const uint64_t dims[3], const uint64_t p[3],
+                           uint64_t s) {
+  Geo g;
+  for (int d = 0; d < 3; ++d) g.n[d] = dims[d];
+  g.N = dims[0] * dims[1] * dims[2];
+  Reader<double> rd{rec, &g, false, nullptr};
   size_t pp[3] = {p[0], p[1], p[2]};
   return predict(rd, g, pp, s);
 }
@@ -1202,6 +1353,50 @@ void stz_ref_canonical_codes(const uint8_t* lens, int nsym, uint32_t* codes) {
   canonical_codes(lens, nsym, codes);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Per-unit statistic of the ROI selection below over the decoded level grid.
+template <class T>
+int roi_stats(const void* comp, const Parsed& P, uint32_t level, uint32_t unit, uint32_t stat,
+              std::vector<double>* out) {
+  const Geo& g = P.g;
+  const size_t s = g.stride((int)level);
+  std::vector<T> rec;
+  int st = decode_levels<T>(comp, P, (int)level, false, nullptr, &rec);
+  if (st != OK) return st;
+  const size_t nb[3] = {(g.n[0] + g.B - 1) / g.B, (g.n[1] + g.B - 1) / g.B,
+                        (g.n[2] + g.B - 1) / g.B};
+  size_t nunits;
+  if (unit == 0)
+    nunits = nb[0] * nb[1] * nb[2];
+  else
+    nunits = g.grid_n(int(unit - 1), s);
+  std::vector<T> mx(nunits, -std::numeric_limits<T>::infinity());
+  std::vector<T> mn(nunits, std::numeric_limits<T>::infinity());
+  for (size_t z = 0; z < g.n[0]; z += s)
+    for (size_t y = 0; y < g.n[1]; y += s)
+      for (size_t x = 0; x < g.n[2]; x += s) {
+        size_t u;
+        if (unit == 0)
+          u = ((z / g.B) * nb[1] + y / g.B) * nb[2] + x / g.B;
+        else
+          u = (unit == 1 ? z : unit == 2 ? y : x) / s;
+        const T v = rec[g.idx(z, y, x)];
+        if (v > mx[u]) mx[u] = v;
+        if (v < mn[u]) mn[u] = v;
+      }
+  out->assign(nunits, 0.0);
+  for (size_t u = 0; u < nunits; ++u)
+    (*out)[u] = stat == 0 ? (double)mx[u] : (double)mx[u] - (double)mn[u];
+  return OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 // ROI selection (Sec. 3.3, "flexible scientific workflow"): the value range
 // or the maximum of every 3-D block or every 2-D slice of the field, taken over
 // the points of a progressive level's grid, then a threshold or the top
@@ -1211,6 +1406,7 @@ void stz_ref_canonical_codes(const uint8_t* lens, int nsym, uint32_t* codes) {
 // 1 = the ceil(value * units) units with the largest stat (ties: smaller index
 // first). Selected indices ascending into blocks[], their number in *count;
 // stats[] (units entries) receives every unit's statistic when not null.
+// Either value type.
 int stz_ref_roi_select(const void* comp, uint64_t size, uint32_t level, uint32_t unit,
                        uint32_t stat, uint32_t rule, double value, uint32_t* sel, uint64_t cap,
                        uint64_t* count, double* stats) {
@@ -1219,34 +1415,11 @@ int stz_ref_roi_select(const void* comp, uint64_t size, uint32_t level, uint32_t
   if (st != OK) return st;
   if ((int)level > P.c.L || unit > 3 || stat > 1 || rule > 1) return ERR_ARG;
   if (rule == 1 && !(value > 0.0 && value <= 1.0)) return ERR_ARG;
-  const Geo& g = P.g;
-  const size_t s = g.stride((int)level);
-  std::vector<float> rec;
-  st = decode_levels(comp, P, (int)level, false, nullptr, &rec);
+  std::vector<double> st_all;
+  st = P.dtype == 0 ? roi_stats<float>(comp, P, level, unit, stat, &st_all)
+                    : roi_stats<double>(comp, P, level, unit, stat, &st_all);
   if (st != OK) return st;
-  const size_t nb[3] = {(g.n[0] + g.B - 1) / g.B, (g.n[1] + g.B - 1) / g.B,
-                        (g.n[2] + g.B - 1) / g.B};
-  size_t nunits;
-  if (unit == 0)
-    nunits = nb[0] * nb[1] * nb[2];
-  else
-    nunits = g.grid_n(int(unit - 1), s);
-  std::vector<float> mx(nunits, -INFINITY), mn(nunits, INFINITY);
-  for (size_t z = 0; z < g.n[0]; z += s)
-    for (size_t y = 0; y < g.n[1]; y += s)
-      for (size_t x = 0; x < g.n[2]; x += s) {
-        size_t u;
-        if (unit == 0)
-          u = ((z / g.B) * nb[1] + y / g.B) * nb[2] + x / g.B;
-        else
-          u = (unit == 1 ? z : unit == 2 ? y : x) / s;
-        const float v = rec[g.idx(z, y, x)];
-        if (v > mx[u]) mx[u] = v;
-        if (v < mn[u]) mn[u] = v;
-      }
-  std::vector<double> st_all(nunits);
-  for (size_t u = 0; u < nunits; ++u)
-    st_all[u] = stat == 0 ? (double)mx[u] : (double)mx[u] - (double)mn[u];
+  const size_t nunits = st_all.size();
   if (stats)
     for (size_t u = 0; u < nunits; ++u) stats[u] = st_all[u];
   std::vector<uint32_t> pick;

@@ -4,9 +4,10 @@ Written separately from the C++ oracle, in a different shape: instead of level
 loops over blocks and classes, every point's reconstruction is defined
 recursively from the reconstructions of the coarser points its stencil reads
 (Sec. 3.1-3.2 of the paper: a point depends only on the previous, coarser
-level). Float32 evaluation order follows the format (it is part of the
-format), using numpy float32 scalars, which round every operation to nearest
-even and never fuse a multiply with an add.
+level). The evaluation order follows the format (it is part of the format),
+using numpy float32 (or float64) scalars, which round every operation to
+nearest even and never fuse a multiply with an add. For float64 data the
+error-bound test is done in exact rational arithmetic.
 
 Also holds:
   * an independent 1-D hierarchical subdivision (Deslauriers-Dubuc 4-point
@@ -16,6 +17,7 @@ Also holds:
     weights) for pinning the Huffman code lengths.
 """
 import heapq
+from fractions import Fraction
 from functools import lru_cache
 
 import numpy as np
@@ -40,7 +42,7 @@ def flags(n, c, s):
     return (c + s <= n - 1, c - 3 * s >= 0, c + 3 * s <= n - 1)
 
 
-def one_axis(flag, s, f):
+def one_axis(flag, s, f, F=F):
     """Nested fallback rule along one axis (linear / extrapolate / copy)."""
     p1, m3, _ = flag
     if p1:
@@ -50,8 +52,9 @@ def one_axis(flag, s, f):
     return f(-s)
 
 
-def stencil(val, dims, p, s):
-    """Prediction of point p at stride s; val(q) returns the coarse value at q."""
+def stencil(val, dims, p, s, F=F):
+    """Prediction of point p at stride s; val(q) returns the coarse value at q.
+    F is the value type (numpy float32 or float64 scalar)."""
     odd = [d for d in range(3) if (p[d] // s) % 2 == 1]
     fl = [flags(dims[d], p[d], s) for d in odd]
 
@@ -92,7 +95,7 @@ def stencil(val, dims, p, s):
     def nest(i, offs):
         if i == len(odd):
             return at(offs)
-        return one_axis(fl[i], s, lambda o: nest(i + 1, offs + [o]))
+        return one_axis(fl[i], s, lambda o: nest(i + 1, offs + [o]), F)
 
     return nest(0, [])
 
@@ -122,12 +125,16 @@ def resolve_eb(x, mode, eb):
     return eb * (abs(mn) if abs(mn) > 0 else 1.0)
 
 
-def brute_symbols(x, mode, eb, B, L, R=512, ratio=2.5):
+def brute_symbols(x, mode, eb, B, L, R=512, ratio=2.5, dtype=np.float32):
     """Per-point (symbol, reconstruction, level); symbol -1 marks anchors."""
-    x = np.asarray(x, dtype=np.float32)
+    F = np.dtype(dtype).type
+    x = np.asarray(x, dtype=dtype)
     dims = x.shape
     eb_abs = resolve_eb(x, mode, eb)
     e, E2, INV = level_bounds(eb_abs, ratio, L)
+    if F is np.float64:
+        E2 = {l: F(2.0 * e[l]) for l in e}
+        INV = {l: F(1.0 / (2.0 * e[l])) for l in e}
     assert 1 <= L and (1 << L) <= B
 
     @lru_cache(maxsize=None)
@@ -141,18 +148,18 @@ def brute_symbols(x, mode, eb, B, L, R=512, ratio=2.5):
         if lv == 0:
             return -1, xv
         s = 1 << (L - lv)
-        pred = F(stencil(rec, dims, p, s))
+        pred = F(stencil(rec, dims, p, s, F))
         diff = xv - pred
         t = np.rint(diff * INV[lv])
         if abs(t) <= F(R - 1):
             q = int(t)
             xr = pred + F(q) * E2[lv]
-            if abs(float(xv) - float(xr)) <= e[lv]:
+            if abs(Fraction(float(xv)) - Fraction(float(xr))) <= Fraction(e[lv]):
                 return q + R, F(xr)
         return 0, xv
 
     sym = np.empty(dims, dtype=np.int32)
-    out = np.empty(dims, dtype=np.float32)
+    out = np.empty(dims, dtype=dtype)
     lvl = np.empty(dims, dtype=np.int32)
     for p in np.ndindex(*dims):
         a, b = solve(p)
