@@ -66,10 +66,11 @@ typedef struct {
                         Optimization 5), >= 1; 0 -> 2.5                      */
 } stz_config;
 
-/* Stream description (parsed header). */
+/* Stream description (parsed header). dtype is the value type of the field
+ * (header byte offset 52): 0 = float32, 1 = float64. */
 typedef struct {
   uint64_t dims[3];
-  uint32_t block, levels, radius, lmax, eb_mode, reserved;
+  uint32_t block, levels, radius, lmax, eb_mode, dtype;
   double eb, eb_abs, eb_ratio;
   uint64_t total_bytes;
 } stz_info_t;
@@ -113,6 +114,30 @@ stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t
                                  const uint64_t hi[3], uint32_t level, float* out,
                                  uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
 
+/* ---- float64 fields -------------------------------------------------------
+ * Double-precision fields (the paper's WarpX data are float64, Sec. 4.1,
+ * Table 2) use the same format with value type 1 in the header: prediction
+ * (Eqs. 3-8) and quantization evaluated in double in the same order, and the
+ * anchors and outliers stored as 8-byte values. The acceptance test of a
+ * quantized value is |x - x'| <= e*(1 - 2^-50) on the rounded double
+ * difference, which guarantees the exact |x - x'| <= e. Arguments, layouts
+ * and errors are those of the float32 calls above, with double in place of
+ * float; each decoder accepts only streams of its own value type and returns
+ * STZ_ERR_ARG for the other. The batched calls, fields opened for batches and
+ * ROI selection: see their own comments. */
+uint64_t stz_compress_bound_f64(const uint64_t dims[3], const stz_config* cfg);
+stz_status stz_compress_f64(const double* x, const uint64_t dims[3], int eb_mode, double eb,
+                            const stz_config* cfg, void* out, uint64_t out_cap,
+                            uint64_t* out_size, void* stream);
+stz_status stz_decompress_f64(const void* comp, uint64_t size, double* out,
+                              uint64_t out_cap_elems, void* stream);
+stz_status stz_decompress_level_f64(const void* comp, uint64_t size, uint32_t level, double* out,
+                                    uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
+stz_status stz_decompress_region_f64(const void* comp, uint64_t size, const uint64_t lo[3],
+                                     const uint64_t hi[3], uint32_t level, double* out,
+                                     uint64_t out_cap_elems, uint64_t out_dims[3],
+                                     void* stream);
+
 /* ---- Batched compression ------------------------------------------------
  * Many independent fields of any sizes, each with its own bound and
  * configuration, compressed by one sequence of persistent launches (every
@@ -136,8 +161,8 @@ typedef struct {
 
 #define STZ_MAX_BATCH 65536
 
-/* Compress `njobs` (<= STZ_MAX_BATCH) fields described by `jobs` (host
- * array). Invalid jobs get their status and are left out; the others run.
+/* Compress `njobs` (<= STZ_MAX_BATCH) float32 fields described by `jobs`
+ * (host array). Invalid jobs get their status and are left out; the others run.
  * Returns STZ_OK when every job succeeded, else the first failing job's
  * status. Synchronizes `stream` once. */
 stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream);
@@ -174,7 +199,9 @@ typedef struct {
 
 /* Decode `n` requests (host array) with one launch sequence: per level, one
  * persistent launch per level block edge walks the blocks of every request's
- * dependency cone. Asynchronous: when `dev_flags` (device, n words) is not
+ * dependency cone. Requests take float32 fields; a request on a float64 field
+ * gets STZ_ERR_ARG (decode those with stz_decompress_region_f64).
+ * Asynchronous: when `dev_flags` (device, n words) is not
  * NULL, the call does not synchronize; word i becomes nonzero when request i
  * met a corrupt stream, and host-side argument errors are in status. With
  * dev_flags NULL the call synchronizes and sets status to STZ_ERR_CORRUPT
@@ -199,7 +226,8 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
  * entries, ascending), their number to *count (host; on STZ_ERR_BUFFER the
  * number needed); `stats` (host, may be NULL) receives every unit's statistic.
  * The statistics are computed on the device; the selection over the
- * per-unit values runs on the host. Synchronizes `stream`. */
+ * per-unit values runs on the host. Fields of either value type. Synchronizes
+ * `stream`. */
 stz_status stz_roi_select(stz_field field, uint32_t level, uint32_t unit, uint32_t stat,
                           uint32_t rule, double value, uint32_t* sel, uint64_t cap,
                           uint64_t* count, double* stats, void* stream);

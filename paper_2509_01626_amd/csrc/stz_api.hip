@@ -211,6 +211,7 @@ Staging* staging() {
 struct Header {
   Geo g;
   Cfg c;
+  int vb;  // bytes per stored value: 4 (value type 0, float32) or 8 (1, float64)
   int eb_mode;
   double eb, eb_abs;
   uint64_t total, anchor_off, n_anchor;
@@ -249,6 +250,9 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
   if (rd<uint32_t>(p + 44) != uint32_t(kLmax)) return STZ_ERR_CORRUPT;
   if (resolve_cfg(&cf, &h->c) != STZ_OK || !make_geo(dims, h->c, &h->g)) return STZ_ERR_CORRUPT;
   h->eb_mode = int(rd<uint32_t>(p + 48));
+  const uint32_t vt = rd<uint32_t>(p + 52);
+  if (vt > 1) return STZ_ERR_CORRUPT;
+  h->vb = vt ? 8 : 4;
   h->eb = rd<double>(p + 56);
   h->eb_abs = rd<double>(p + 64);
   if (!(h->eb_abs > 0.0) || !std::isfinite(h->eb_abs)) return STZ_ERR_CORRUPT;
@@ -263,7 +267,8 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
   if (kHeaderBytes + nsym > want) return STZ_ERR_CORRUPT;
   h->lens.assign(p + kHeaderBytes, p + kHeaderBytes + nsym);
   level_consts(h->g, h->lc);
-  uint64_t pos = h->anchor_off + align16(4 * h->n_anchor);
+  const uint64_t vb = uint64_t(h->vb);
+  uint64_t pos = h->anchor_off + align16(vb * h->n_anchor);
   for (int l = 1; l <= h->g.L; ++l) {
     const uint8_t* e = p + kLevelTable + kLevelRec * uint64_t(l - 1);
     const uint64_t sec = rd<uint64_t>(e), nu = rd<uint64_t>(e + 8), nl = rd<uint64_t>(e + 16),
@@ -278,7 +283,7 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
     h->off_lane[l] = h->off_outl[l] + align16(4 * (nu + 1));
     h->off_pay[l] = h->off_lane[l] + align16(2 * nl);
     h->off_out[l] = h->off_pay[l] + align16(4 * W);
-    pos = h->off_out[l] + align16(4 * O);
+    pos = h->off_out[l] + align16(vb * O);
     if (pos > h->total) return STZ_ERR_CORRUPT;
   }
   if (pos != h->total) return STZ_ERR_CORRUPT;
@@ -346,7 +351,7 @@ struct DecodePlan {
   uint64_t o_rec[kMaxLevels + 1] = {};
 
   stz_status init(const Header& h, const void* comp, uint64_t size, const Box* boxp, int level,
-                  float* out, uint64_t out_cap) {
+                  void* out, uint64_t out_cap) {
     const Geo& g = h.g;
     std::memset(&a, 0, sizeof(a));
     if (level < 0) level = g.L;
@@ -374,6 +379,7 @@ struct DecodePlan {
     a.comp = static_cast<const uint8_t*>(comp);
     a.size = size;
     a.geo = g;
+    a.vb = h.vb;
     a.level_out = level;
     a.box[level] = box;
     for (int k = level; k >= 1; --k)
@@ -399,27 +405,30 @@ struct DecodePlan {
       else
         e = (h.eb_abs / h.c.ratio) / h.c.ratio;
       a.E2[l] = float(2.0 * e);
+      a.E2d[l] = 2.0 * e;
     }
     return STZ_OK;
   }
 
   void take(Workspace& ws) {
     for (int k = 0; k < a.level_out; ++k)
-      o_rec[k] = ws.take<float>(box_points(a.box[k], a.geo.L - k));
+      o_rec[k] = ws.take<uint8_t>(uint64_t(a.vb) * box_points(a.box[k], a.geo.L - k));
   }
 
   void bind(const Workspace& ws, const uint16_t* lut, uint32_t* flags) {
-    for (int k = 0; k < a.level_out; ++k) a.rec[k] = ws.at<float>(o_rec[k]);
+    for (int k = 0; k < a.level_out; ++k) a.rec[k] = ws.at<uint8_t>(o_rec[k]);
     a.lut = lut;
     a.flags = flags;
   }
 };
 
-stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int level, float* out,
-                      uint64_t out_cap, uint64_t out_dims[3], hipStream_t st) {
+// vb = the caller's value type; a stream of the other type is rejected.
+stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int level, void* out,
+                      uint64_t out_cap, uint64_t out_dims[3], int vb, hipStream_t st) {
   Header h;
   stz_status s = read_header(comp, size, st, &h);
   if (s != STZ_OK) return s;
+  if (h.vb != vb) return STZ_ERR_ARG;
   DecodePlan pl;
   s = pl.init(h, comp, size, boxp, level, out, out_cap);
   if (out_dims)
@@ -464,7 +473,7 @@ struct CompressPlan {
   uint64_t o_part = 0, o_rec[kMaxLevels] = {}, o_sym[kMaxLevels + 1] = {}, o_lane = 0,
            o_hist = 0, o_lens = 0, o_codes = 0, o_cb = 0, o_cnt = 0, o_scan = 0, o_spart = 0;
 
-  stz_status init(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+  stz_status init(const void* x, int vb, const uint64_t dims[3], int eb_mode, double eb,
                   const stz_config* cfg, void* out, uint64_t out_cap) {
     Cfg c;
     Geo g;
@@ -475,6 +484,7 @@ struct CompressPlan {
     if (!(eb > 0.0) || !std::isfinite(eb)) return STZ_ERR_ARG;
     const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
     a.x = x;
+    a.vb = vb;
     a.geo = g;
     a.eb_mode = eb_mode;
     a.eb = eb;
@@ -492,8 +502,8 @@ struct CompressPlan {
     const Geo& g = a.geo;
     const int L = g.L, nsym = 2 * g.R;
     const uint64_t nu = a.lc[1].nu;
-    o_part = ws.take<float2>(a.nparts);
-    for (int l = 0; l < L; ++l) o_rec[l] = ws.take<float>(grid_count(g, L - l));
+    o_part = ws.take<uint8_t>(2 * uint64_t(a.vb) * a.nparts);
+    for (int l = 0; l < L; ++l) o_rec[l] = ws.take<uint8_t>(uint64_t(a.vb) * grid_count(g, L - l));
     uint64_t lanes = 0;
     for (int l = 1; l <= L; ++l) {
       o_sym[l] = ws.take<uint16_t>(a.lc[l].nsym);
@@ -515,8 +525,8 @@ struct CompressPlan {
   void bind(const Workspace& ws, DevParams* params) {
     const int L = a.geo.L;
     a.params = params;
-    a.part = ws.at<float2>(o_part);
-    for (int l = 0; l < L; ++l) a.rec[l] = ws.at<float>(o_rec[l]);
+    a.part = ws.at<uint8_t>(o_part);
+    for (int l = 0; l < L; ++l) a.rec[l] = ws.at<uint8_t>(o_rec[l]);
     for (int l = 1; l <= L; ++l) a.sym[l] = ws.at<uint16_t>(o_sym[l]);
     a.lane_len = ws.at<uint16_t>(o_lane);
     a.hist = ws.at<unsigned long long>(o_hist);
@@ -749,29 +759,34 @@ stz_status stz_trim(void) {
   return hipDeviceSynchronize() == hipSuccess ? STZ_OK : STZ_ERR_DEVICE;
 }
 
-uint64_t stz_compress_bound(const uint64_t dims[3], const stz_config* cfg) {
+}  // extern "C"
+
+namespace stz {
+namespace {
+
+uint64_t compress_bound(const uint64_t dims[3], const stz_config* cfg, uint64_t vb) {
   Cfg c;
   Geo g;
   if (!dims || resolve_cfg(cfg, &c) != STZ_OK || !make_geo(dims, c, &g)) return 0;
   LevelConst lc[kMaxLevels + 1];
   level_consts(g, lc);
-  uint64_t total = kHeaderBytes + align16(2 * uint64_t(c.R)) + align16(4 * grid_count(g, g.L));
+  uint64_t total = kHeaderBytes + align16(2 * uint64_t(c.R)) + align16(vb * grid_count(g, g.L));
   for (int l = 1; l <= g.L; ++l) {
     const uint64_t nu = lc[l].nu;
     // every unit: at most kLmax bits per symbol plus one padding word
     const uint64_t words = (lc[l].nsym * kLmax + 31) / 32 + nu;
     total += 2 * align16(4 * (nu + 1)) + align16(2 * lc[l].nl) + align16(4 * words) +
-             align16(4 * lc[l].nsym);
+             align16(vb * lc[l].nsym);
   }
   return total;
 }
 
-stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+stz_status compress_one(const void* x, int vb, const uint64_t dims[3], int eb_mode, double eb,
                         const stz_config* cfg, void* out, uint64_t out_cap, uint64_t* out_size,
                         void* stream) {
   if (!out_size) return STZ_ERR_ARG;
   CompressPlan pl;
-  const stz_status s0 = pl.init(x, dims, eb_mode, eb, cfg, out, out_cap);
+  const stz_status s0 = pl.init(x, vb, dims, eb_mode, eb, cfg, out, out_cap);
   if (s0 != STZ_OK) return s0;
   hipStream_t st = static_cast<hipStream_t>(stream);
   Workspace ws(st);
@@ -791,6 +806,31 @@ stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, dou
   return params_status(*stage->params);
 }
 
+}  // namespace
+}  // namespace stz
+
+extern "C" {
+
+uint64_t stz_compress_bound(const uint64_t dims[3], const stz_config* cfg) {
+  return compress_bound(dims, cfg, 4);
+}
+
+uint64_t stz_compress_bound_f64(const uint64_t dims[3], const stz_config* cfg) {
+  return compress_bound(dims, cfg, 8);
+}
+
+stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
+                        const stz_config* cfg, void* out, uint64_t out_cap, uint64_t* out_size,
+                        void* stream) {
+  return compress_one(x, 4, dims, eb_mode, eb, cfg, out, out_cap, out_size, stream);
+}
+
+stz_status stz_compress_f64(const double* x, const uint64_t dims[3], int eb_mode, double eb,
+                            const stz_config* cfg, void* out, uint64_t out_cap,
+                            uint64_t* out_size, void* stream) {
+  return compress_one(x, 8, dims, eb_mode, eb, cfg, out, out_cap, out_size, stream);
+}
+
 stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
   if (!jobs && njobs) return STZ_ERR_ARG;
   if (njobs == 0) return STZ_OK;
@@ -801,7 +841,7 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
   for (uint64_t i = 0; i < njobs; ++i) {
     jobs[i].out_size = 0;
     jobs[i].status = jobs[i].reserved ? STZ_ERR_ARG
-                                      : pl[i].init(jobs[i].x, jobs[i].dims, jobs[i].eb_mode,
+                                      : pl[i].init(jobs[i].x, 4, jobs[i].dims, jobs[i].eb_mode,
                                                    jobs[i].eb, &jobs[i].cfg, jobs[i].out,
                                                    jobs[i].out_cap);
     if (jobs[i].status == STZ_OK) live.push_back(uint32_t(i));
@@ -915,7 +955,7 @@ stz_status stz_field_info(stz_field f, stz_info_t* info) {
   info->radius = uint32_t(h.c.R);
   info->lmax = uint32_t(kLmax);
   info->eb_mode = uint32_t(h.eb_mode);
-  info->reserved = 0;
+  info->dtype = h.vb == 8 ? 1u : 0u;
   info->eb = h.eb;
   info->eb_abs = h.eb_abs;
   info->eb_ratio = h.c.ratio;
@@ -955,7 +995,7 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
       box.lo[d] = int64_t(r.lo[d]);
       box.hi[d] = int64_t(r.hi[d]);
     }
-    if (!ok || r.level > 64) {
+    if (!ok || r.level > 64 || r.field->h.vb != 4) {  // batches decode float32 fields
       r.status = STZ_ERR_ARG;
       continue;
     }
@@ -1315,15 +1355,15 @@ stz_status stz_roi_select(stz_field f, uint32_t level, uint32_t unit, uint32_t s
   // plan is made against a placeholder output and pointed at the scratch grid
   DecodePlan pl;
   stz_status s = pl.init(h, f->comp, f->size, nullptr, int(level),
-                         reinterpret_cast<float*>(uintptr_t(256)), ngrid);
+                         reinterpret_cast<void*>(uintptr_t(256)), ngrid);
   if (s != STZ_OK) return s;
   Workspace ws(st);
   pl.take(ws);
-  const uint64_t o_grid = ws.take<float>(ngrid);
+  const uint64_t o_grid = ws.take<uint8_t>(uint64_t(h.vb) * ngrid);
   const uint64_t o_stats = ws.take<double>(nunits);
   const uint64_t o_flags = ws.take<uint32_t>(1);
   if (!ws.commit()) return STZ_ERR_NOMEM;
-  float* grid = ws.at<float>(o_grid);
+  void* grid = ws.at<uint8_t>(o_grid);
   uint32_t* dflags = ws.at<uint32_t>(o_flags);
   pl.a.rec[pl.a.level_out] = grid;
   pl.bind(ws, f->lut, dflags);
@@ -1336,7 +1376,8 @@ stz_status stz_roi_select(stz_field f, uint32_t level, uint32_t unit, uint32_t s
   double* dstats = ws.at<double>(o_stats);
   const int64_t E = int64_t(g.B) >> logs;
   const int64_t nb[3] = {g.nb[0], g.nb[1], g.nb[2]};
-  if (launch_roi_stats(grid, gn, E, int(unit), int(stat), nb, nunits, dstats, st) != hipSuccess)
+  if (launch_roi_stats(grid, h.vb, gn, E, int(unit), int(stat), nb, nunits, dstats, st) !=
+      hipSuccess)
     return STZ_ERR_DEVICE;
   HostBuf& hb = host_buf(st);
   if (!hb.reserve(nunits * 8 + 8)) return STZ_ERR_NOMEM;
@@ -1380,7 +1421,7 @@ stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* str
     info->radius = uint32_t(h.c.R);
     info->lmax = uint32_t(kLmax);
     info->eb_mode = uint32_t(h.eb_mode);
-    info->reserved = 0;
+    info->dtype = h.vb == 8 ? 1u : 0u;
     info->eb = h.eb;
     info->eb_abs = h.eb_abs;
     info->eb_ratio = h.c.ratio;
@@ -1389,9 +1430,14 @@ stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* str
   return STZ_OK;
 }
 
-stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
-                                 const uint64_t hi[3], uint32_t level, float* out,
-                                 uint64_t out_cap_elems, uint64_t out_dims[3], void* stream) {
+}  // extern "C"
+
+namespace stz {
+namespace {
+
+stz_status region_one(const void* comp, uint64_t size, const uint64_t lo[3], const uint64_t hi[3],
+                      uint32_t level, void* out, uint64_t out_cap_elems, uint64_t out_dims[3],
+                      int vb, void* stream) {
   if (!lo || !hi) return STZ_ERR_ARG;
   Box b;
   for (int d = 0; d < 3; ++d) {
@@ -1400,21 +1446,56 @@ stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t
     b.hi[d] = int64_t(hi[d]);
   }
   if (level > uint32_t(kMaxLevels)) return STZ_ERR_ARG;
-  return decode_box(comp, size, &b, int(level), out, out_cap_elems, out_dims,
+  return decode_box(comp, size, &b, int(level), out, out_cap_elems, out_dims, vb,
                     static_cast<hipStream_t>(stream));
+}
+
+stz_status level_one(const void* comp, uint64_t size, uint32_t level, void* out,
+                     uint64_t out_cap_elems, uint64_t out_dims[3], int vb, void* stream) {
+  if (level > uint32_t(kMaxLevels)) return STZ_ERR_ARG;
+  return decode_box(comp, size, nullptr, int(level), out, out_cap_elems, out_dims, vb,
+                    static_cast<hipStream_t>(stream));
+}
+
+}  // namespace
+}  // namespace stz
+
+extern "C" {
+
+stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
+                                 const uint64_t hi[3], uint32_t level, float* out,
+                                 uint64_t out_cap_elems, uint64_t out_dims[3], void* stream) {
+  return region_one(comp, size, lo, hi, level, out, out_cap_elems, out_dims, 4, stream);
+}
+
+stz_status stz_decompress_region_f64(const void* comp, uint64_t size, const uint64_t lo[3],
+                                     const uint64_t hi[3], uint32_t level, double* out,
+                                     uint64_t out_cap_elems, uint64_t out_dims[3],
+                                     void* stream) {
+  return region_one(comp, size, lo, hi, level, out, out_cap_elems, out_dims, 8, stream);
 }
 
 stz_status stz_decompress_level(const void* comp, uint64_t size, uint32_t level, float* out,
                                 uint64_t out_cap_elems, uint64_t out_dims[3], void* stream) {
-  if (level > uint32_t(kMaxLevels)) return STZ_ERR_ARG;
-  return decode_box(comp, size, nullptr, int(level), out, out_cap_elems, out_dims,
-                    static_cast<hipStream_t>(stream));
+  return level_one(comp, size, level, out, out_cap_elems, out_dims, 4, stream);
+}
+
+stz_status stz_decompress_level_f64(const void* comp, uint64_t size, uint32_t level, double* out,
+                                    uint64_t out_cap_elems, uint64_t out_dims[3], void* stream) {
+  return level_one(comp, size, level, out, out_cap_elems, out_dims, 8, stream);
 }
 
 stz_status stz_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap_elems,
                           void* stream) {
   uint64_t od[3];
-  return decode_box(comp, size, nullptr, -1, out, out_cap_elems, od,
+  return decode_box(comp, size, nullptr, -1, out, out_cap_elems, od, 4,
+                    static_cast<hipStream_t>(stream));
+}
+
+stz_status stz_decompress_f64(const void* comp, uint64_t size, double* out,
+                              uint64_t out_cap_elems, void* stream) {
+  uint64_t od[3];
+  return decode_box(comp, size, nullptr, -1, out, out_cap_elems, od, 8,
                     static_cast<hipStream_t>(stream));
 }
 

@@ -30,34 +30,63 @@ __global__ void k_init(DevParams* P, unsigned long long* hist, int nsym) {
   init_body(P, hist, nsym);
 }
 
-__device__ inline void minmax_body(const float* __restrict__ x, uint64_t N, float2* part,
+template <class T>
+__device__ inline T vmin(T a, T b) {
+  if constexpr (sizeof(T) == 4)
+    return fminf(a, b);
+  else
+    return fmin(a, b);
+}
+template <class T>
+__device__ inline T vmax(T a, T b) {
+  if constexpr (sizeof(T) == 4)
+    return fmaxf(a, b);
+  else
+    return fmax(a, b);
+}
+
+// Min, max and finiteness of the field: 16-byte loads (4 floats or 2
+// doubles) over the aligned part, scalar loads for the rest.
+template <class T>
+__device__ inline void minmax_body(const T* __restrict__ x, uint64_t N, MinMax<T>* part,
                                    DevParams* P, uint64_t wg, uint64_t ngrid) {
-  float mn = INFINITY, mx = -INFINITY;
+  T mn = T(INFINITY), mx = T(-INFINITY);
   bool bad = false;
   const uint64_t stride = ngrid * blockDim.x;
   const uint64_t t0 = wg * blockDim.x + threadIdx.x;
   uint64_t head = 0;  // elements handled by 16-byte loads
   if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
-    head = N & ~uint64_t(3);
-    const float4* x4 = reinterpret_cast<const float4*>(x);
-    for (uint64_t i = t0; i < (head >> 2); i += stride) {
-      const float4 v = x4[i];
-      bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
-      mn = fminf(fminf(mn, v.x), fminf(v.y, fminf(v.z, v.w)));
-      mx = fmaxf(fmaxf(mx, v.x), fmaxf(v.y, fmaxf(v.z, v.w)));
+    if constexpr (sizeof(T) == 4) {
+      head = N & ~uint64_t(3);
+      const float4* x4 = reinterpret_cast<const float4*>(x);
+      for (uint64_t i = t0; i < (head >> 2); i += stride) {
+        const float4 v = x4[i];
+        bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+        mn = fminf(fminf(mn, v.x), fminf(v.y, fminf(v.z, v.w)));
+        mx = fmaxf(fmaxf(mx, v.x), fmaxf(v.y, fmaxf(v.z, v.w)));
+      }
+    } else {
+      head = N & ~uint64_t(1);
+      const double2* x2 = reinterpret_cast<const double2*>(x);
+      for (uint64_t i = t0; i < (head >> 1); i += stride) {
+        const double2 v = x2[i];
+        bad |= !isfinite(v.x) || !isfinite(v.y);
+        mn = fmin(mn, fmin(v.x, v.y));
+        mx = fmax(mx, fmax(v.x, v.y));
+      }
     }
   }
   for (uint64_t i = head + t0; i < N; i += stride) {
-    const float v = x[i];
+    const T v = x[i];
     bad |= !isfinite(v);
-    mn = fminf(mn, v);
-    mx = fmaxf(mx, v);
+    mn = vmin(mn, v);
+    mx = vmax(mx, v);
   }
   for (int o = 32; o > 0; o >>= 1) {
-    mn = fminf(mn, __shfl_xor(mn, o, kWave));
-    mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+    mn = vmin(mn, __shfl_xor(mn, o, kWave));
+    mx = vmax(mx, __shfl_xor(mx, o, kWave));
   }
-  __shared__ float smn[4], smx[4];
+  __shared__ T smn[4], smx[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
     smn[w] = mn;
@@ -67,31 +96,34 @@ __device__ inline void minmax_body(const float* __restrict__ x, uint64_t N, floa
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < 4; ++i) {
-      mn = fminf(mn, smn[i]);
-      mx = fmaxf(mx, smx[i]);
+      mn = vmin(mn, smn[i]);
+      mx = vmax(mx, smx[i]);
     }
-    part[wg] = make_float2(mn, mx);
+    part[wg].mn = mn;
+    part[wg].mx = mx;
   }
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, uint64_t N,
-                                                float2* part, DevParams* P) {
-  minmax_body(x, N, part, P, blockIdx.x, gridDim.x);
+template <class T>
+__global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ x, uint64_t N,
+                                                MinMax<T>* part, DevParams* P) {
+  minmax_body<T>(x, N, part, P, blockIdx.x, gridDim.x);
 }
 
 // Resolve the absolute bound and the per-level constants (format 2.3).
-__device__ inline void resolve_body(DevParams* P, const float2* part, uint32_t nparts, int mode,
+template <class T>
+__device__ inline void resolve_body(DevParams* P, const MinMax<T>* part, uint32_t nparts, int mode,
                                     double eb, double ratio, int L) {
   // one wave of 64 threads: min and max of the partials (exact in any order)
-  float mn = INFINITY, mx = -INFINITY;
+  T mn = T(INFINITY), mx = T(-INFINITY);
   if (mode == 1)
     for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
-      mn = fminf(mn, part[i].x);
-      mx = fmaxf(mx, part[i].y);
+      mn = vmin(mn, part[i].mn);
+      mx = vmax(mx, part[i].mx);
     }
   for (int o = 32; o > 0; o >>= 1) {
-    mn = fminf(mn, __shfl_xor(mn, o, kWave));
-    mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
+    mn = vmin(mn, __shfl_xor(mn, o, kWave));
+    mx = vmax(mx, __shfl_xor(mx, o, kWave));
   }
   if (threadIdx.x != 0) return;
   double eb_abs = eb;
@@ -117,16 +149,21 @@ __device__ inline void resolve_body(DevParams* P, const float2* part, uint32_t n
     P->e[l] = e;
     P->E2[l] = (float)(2.0 * e);
     P->INV[l] = (float)(1.0 / (2.0 * e));
+    P->E2d[l] = 2.0 * e;
+    P->INVd[l] = 1.0 / (2.0 * e);
+    P->echk[l] = e * (1.0 - 0x1p-50);
   }
 }
 
-__global__ void k_resolve(DevParams* P, const float2* part, uint32_t nparts, int mode, double eb,
-                          double ratio, int L) {
-  resolve_body(P, part, nparts, mode, eb, ratio, L);
+template <class T>
+__global__ void k_resolve(DevParams* P, const MinMax<T>* part, uint32_t nparts, int mode,
+                          double eb, double ratio, int L) {
+  resolve_body<T>(P, part, nparts, mode, eb, ratio, L);
 }
 
 // Anchors: the stride-2^L grid, copied verbatim into the level-0 grid.
-__device__ inline void anchor_body(const float* __restrict__ x, const Geo& g, float* rec0,
+template <class T>
+__device__ inline void anchor_body(const T* __restrict__ x, const Geo& g, T* rec0,
                                    DevParams* P, uint64_t wg, uint64_t ngrid) {
   const int logs = g.L;
   const int64_t c0 = ((g.n[0] - 1) >> logs) + 1, c1 = ((g.n[1] - 1) >> logs) + 1,
@@ -136,60 +173,62 @@ __device__ inline void anchor_body(const float* __restrict__ x, const Geo& g, fl
   for (int64_t i = int64_t(wg) * blockDim.x + threadIdx.x; i < na;
        i += int64_t(ngrid) * blockDim.x) {
     const int64_t ix = i % c2, t = i / c2, iy = t % c1, iz = t / c1;
-    const float v = x[((iz << logs) * g.n[1] + (iy << logs)) * g.n[2] + (ix << logs)];
+    const T v = x[((iz << logs) * g.n[1] + (iy << logs)) * g.n[2] + (ix << logs)];
     bad |= !isfinite(v);
     rec0[i] = v;
   }
   if (bad) atomicOr(&P->flags, kFlagNonfinite);
 }
 
-__global__ void k_anchor(const float* __restrict__ x, Geo g, float* rec0, DevParams* P) {
-  anchor_body(x, g, rec0, P, blockIdx.x, gridDim.x);
+template <class T>
+__global__ void k_anchor(const T* __restrict__ x, Geo g, T* rec0, DevParams* P) {
+  anchor_body<T>(x, g, rec0, P, blockIdx.x, gridDim.x);
 }
 
 struct PredSlabArgs {
-  const float* x;
+  const void* x;     // field values (value type of the kernel)
   Geo g;
   int level, logs;
   int64_t n[3];      // level grid extents
   int64_t nc[3];     // previous level's grid extents
-  const float* prev; // level-(l-1) grid, complete
-  float* cur;        // level-l grid; null at the finest level
+  const void* prev;  // level-(l-1) grid, complete
+  void* cur;         // level-l grid; null at the finest level
   uint16_t* sym;
   DevParams* P;
   unsigned long long* hist;
   int nsym;
 };
 
-// Per-slab state for predicting rows of one parity type.
+// Per-slab state for predicting rows of one parity type (T = value type).
+template <class T>
 struct PredRows {
-  const float* x;
-  const float* tile;
+  const T* x;
+  const T* tile;
   uint16_t* ssym;
   uint32_t* h;
-  float* cur;
+  T* cur;
   int64_t oz, oy, ox;
   int z0, Ex, ls;
   int64_t n[3], fn[3];
-  float E2, INV;
-  double e;
+  T E2, INV;
+  double chk;  // acceptance bound of the quantizer
   int R;
 };
 
 // Predict and quantize one point of class C (0 = coarse copy only).
-template <int E, int H, int C, bool INT>
-__device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int srow,
-                                  const float* xrow, float* grow, const int64_t p[3],
+template <class T, int E, int H, int C, bool INT>
+__device__ inline void pred_point(const PredRows<T>& c, int lz, int ly, int lx, int srow,
+                                  const T* xrow, T* grow, const int64_t p[3],
                                   uint32_t* n_center, bool* bad) {
   using S = SlabShape<E, H>;
   if constexpr (C == 0) {
     if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
-    const float xv = xrow[lx << c.ls];
+    const T xv = xrow[lx << c.ls];
     *bad |= !isfinite(xv);
-    const float pred = tile_pred<E, C, INT>(c.tile, lz - c.z0, ly, lx, p, c.n);
-    float rv;
-    const int sy = quantize(xv, pred, c.E2, c.INV, c.e, c.R, &rv);
+    const T pred = tile_pred<T, E, C, INT>(c.tile, lz - c.z0, ly, lx, p, c.n);
+    T rv;
+    const int sy = quantize<T>(xv, pred, c.E2, c.INV, c.chk, c.R, &rv);
     c.ssym[(C - 1) * S::SCP + srow] = uint16_t(sy);
     if (grow) grow[lx] = rv;
     if (sy == c.R)
@@ -200,34 +239,36 @@ __device__ inline void pred_point(const PredRows& c, int lz, int ly, int lx, int
 }
 
 // This wave's rows of parity type (ZP, YP); classes fixed at compile time.
-template <int E, int H, int ZP, int YP, bool INT>
-__device__ inline void pred_type(const PredRows& c, int hs, int Ey, int wave, int lane,
+template <class T, int E, int H, int ZP, int YP, bool INT>
+__device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave, int lane,
                                  uint32_t* n_center, bool* bad) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
   for_type_rows<E, ZP, YP>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
-    float* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
-    const float* xrow =
+    T* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
+    const T* xrow =
         c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);
     const int srow = (((lz - c.z0) >> 1) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {c.oz + lz, c.oy + ly, c.ox + l0};
     const int64_t p1[3] = {c.oz + lz, c.oy + ly, c.ox + l1};
-    if (l0 < c.Ex) pred_point<E, H, C0, INT>(c, lz, ly, l0, srow, xrow, grow, p0, n_center, bad);
-    if (l1 < c.Ex) pred_point<E, H, C0 + 1, INT>(c, lz, ly, l1, srow, xrow, grow, p1, n_center, bad);
+    if (l0 < c.Ex)
+      pred_point<T, E, H, C0, INT>(c, lz, ly, l0, srow, xrow, grow, p0, n_center, bad);
+    if (l1 < c.Ex)
+      pred_point<T, E, H, C0 + 1, INT>(c, lz, ly, l1, srow, xrow, grow, p1, n_center, bad);
   });
 }
 
 // Predict and quantize every level-l point of one block (format 2.2, 2.3);
 // also writes the block's part of the level-l grid (coarse points copied,
 // level points reconstructed) for the next level's prediction.
-template <int E, int H>
+template <class T, int E, int H>
 __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_remap) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   __shared__ uint32_t h[2 * kMaxRadius];
-  __shared__ float tile[S::TILE];
+  __shared__ T tile[S::TILE];
   __shared__ uint16_t ssym[7 * S::SCP];  // slab symbols, [class][v_z][v_y][v_x] (padded)
   __shared__ uint64_t ubase[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -240,8 +281,20 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   const int Ez = int(min<int64_t>(E, a.n[0] - oz)), Ey = int(min<int64_t>(E, a.n[1] - oy)),
             Ex = int(min<int64_t>(E, a.n[2] - ox));
   if (tid >= 1 && tid <= 7) ubase[tid] = uint64_t(unit_sym_off(a.g, a.logs, blk * 7 + tid - 1));
-  const float E2 = a.P->E2[a.level], INV = a.P->INV[a.level];
-  const double e = a.P->e[a.level];
+  T E2, INV;
+  double chk;
+  if constexpr (sizeof(T) == 4) {
+    E2 = a.P->E2[a.level];
+    INV = a.P->INV[a.level];
+    chk = a.P->e[a.level];
+  } else {
+    E2 = a.P->E2d[a.level];
+    INV = a.P->INVd[a.level];
+    chk = a.P->echk[a.level];
+  }
+  const T* xv = static_cast<const T*>(a.x);
+  const T* prev = static_cast<const T*>(a.prev);
+  T* cur = static_cast<T*>(a.cur);
   const int R = a.g.R;
   const int64_t sf[3] = {0, 0, 0};
   const int ls = a.logs;
@@ -251,15 +304,15 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   bool bad = false;
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;
-    load_tile<S>(tile, a.prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    load_tile<S, T>(tile, prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
     __syncthreads();
     const int hs = min(S::H, Ez - z0);
-    PredRows ctx;
-    ctx.x = a.x;
+    PredRows<T> ctx;
+    ctx.x = xv;
     ctx.tile = tile;
     ctx.ssym = ssym;
     ctx.h = h;
-    ctx.cur = a.cur;
+    ctx.cur = cur;
     ctx.oz = oz;
     ctx.oy = oy;
     ctx.ox = ox;
@@ -272,18 +325,18 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     }
     ctx.E2 = E2;
     ctx.INV = INV;
-    ctx.e = e;
+    ctx.chk = chk;
     ctx.R = R;
     if (interior) {
-      pred_type<E, H, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, H, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, H, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, H, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     } else {
-      pred_type<E, H, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, H, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, H, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<E, H, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     }
     __syncthreads();
     // The slab's rows of every unit, column-major inside the unit: column j of
@@ -324,9 +377,9 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     if (h[i]) atomicAdd(&a.hist[i], (unsigned long long)h[i]);
 }
 
-template <int E>
+template <class T, int E>
 __global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
-  pred_body<E, default_slab_h(E)>(a, blockIdx.x, true);
+  pred_body<T, E, default_slab_h(E)>(a, blockIdx.x, true);
 }
 
 struct LaneLenArgs {
@@ -493,6 +546,7 @@ __global__ __launch_bounds__(256) void k_scan_c(const uint32_t* in, uint64_t n, 
 
 struct LayoutArgs {
   Geo g;
+  int vb;        // bytes per stored value (anchors, outliers): 4 or 8
   int eb_mode;
   double eb, ratio;
   uint64_t out_cap;
@@ -516,7 +570,8 @@ __device__ inline void layout_body(const LayoutArgs& a) {
   DevParams* P = a.P;
   const int L = a.g.L;
   const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(2 * a.g.R));
-  uint64_t pos = anchor_off + align16(4 * a.n_anchor);
+  const uint64_t vb = uint64_t(a.vb);
+  uint64_t pos = anchor_off + align16(vb * a.n_anchor);
   for (int l = 1; l <= L; ++l) {
     const uint64_t W = a.scan[uint64_t(2 * (l - 1)) * (a.nu + 1) + a.nu];
     const uint64_t O = a.scan[uint64_t(2 * (l - 1) + 1) * (a.nu + 1) + a.nu];
@@ -527,7 +582,7 @@ __device__ inline void layout_body(const LayoutArgs& a) {
     P->off_lane[l] = P->off_outl[l] + align16(4 * (a.nu + 1));
     P->off_pay[l] = P->off_lane[l] + align16(2 * a.lc[l].nl);
     P->off_out[l] = P->off_pay[l] + align16(4 * W);
-    pos = P->off_out[l] + align16(4 * O);
+    pos = P->off_out[l] + align16(vb * O);
   }
   P->total = pos;
   if (pos > a.out_cap) P->flags |= kFlagOverflow;
@@ -542,6 +597,7 @@ __device__ inline void layout_body(const LayoutArgs& a) {
   st32(o + 40, uint32_t(a.g.R));
   st32(o + 44, uint32_t(kLmax));
   st32(o + 48, uint32_t(a.eb_mode));
+  st32(o + 52, a.vb == 8 ? 1u : 0u);  // value type: 0 float32, 1 float64
   st64(o + 56, __double_as_longlong(a.eb));
   st64(o + 64, __double_as_longlong(P->eb_abs));
   st64(o + 72, __double_as_longlong(a.ratio));
@@ -580,27 +636,31 @@ __global__ void k_zero(uint8_t* out, uint64_t from, const DevParams* P) {
 
 // Code lengths and anchors into the stream.
 __device__ inline void fill_head_body(uint8_t* out, const uint8_t* lens, int nsym,
-                                      const float* rec0, uint64_t na, const DevParams* P,
+                                      const void* rec0, int vb, uint64_t na, const DevParams* P,
                                       uint64_t wg, uint64_t ngrid) {
   if (P->flags) return;
   const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(nsym));
-  float* an = reinterpret_cast<float*>(out + anchor_off);
   for (uint64_t i = wg * blockDim.x + threadIdx.x; i < na + uint64_t(nsym);
        i += ngrid * blockDim.x) {
     if (i < uint64_t(nsym))
       out[kHeaderBytes + i] = lens[i];
+    else if (vb == 8)
+      reinterpret_cast<double*>(out + anchor_off)[i - nsym] =
+          static_cast<const double*>(rec0)[i - nsym];
     else
-      an[i - nsym] = rec0[i - nsym];
+      reinterpret_cast<float*>(out + anchor_off)[i - nsym] =
+          static_cast<const float*>(rec0)[i - nsym];
   }
 }
 
-__global__ void k_fill_head(uint8_t* out, const uint8_t* lens, int nsym, const float* rec0,
-                            uint64_t na, const DevParams* P) {
-  fill_head_body(out, lens, nsym, rec0, na, P, blockIdx.x, gridDim.x);
+__global__ void k_fill_head(uint8_t* out, const uint8_t* lens, int nsym, const void* rec0,
+                            int vb, uint64_t na, const DevParams* P) {
+  fill_head_body(out, lens, nsym, rec0, vb, na, P, blockIdx.x, gridDim.x);
 }
 
 struct PackArgs {
-  const float* x;
+  const void* x;  // field values, vb bytes each
+  int vb;
   Geo g;
   int level, logs;
   const uint16_t* sym;
@@ -614,6 +674,14 @@ struct PackArgs {
   uint8_t* out;
   const DevParams* P;
 };
+
+// Outlier k of a level: the input value at full-resolution index i, verbatim.
+__device__ inline void put_outlier(uint8_t* outv, int vb, uint64_t k, const void* x, int64_t i) {
+  if (vb == 8)
+    reinterpret_cast<double*>(outv)[k] = static_cast<const double*>(x)[i];
+  else
+    reinterpret_cast<float*>(outv)[k] = static_cast<const float*>(x)[i];
+}
 
 __device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_t start,
                                  uint64_t end) {
@@ -642,7 +710,7 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
   uint16_t* lane_arr = reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]);
   uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
-  float* outv = reinterpret_cast<float*>(a.out + P->off_out[l]);
+  uint8_t* outv = a.out + P->off_out[l];
   const int m = (a.g.B >> a.logs) >> 1;
   const int tid = threadIdx.x, lane = tid & 63, c = tid / m + 1, j = tid % m;
   const bool is_lane = tid < 7 * m;
@@ -708,7 +776,8 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
       const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
       const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
       const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * j + ug.o[2]) << a.logs);
-      outv[uo + run + __popcll(mk & lt_mask)] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
+      put_outlier(outv, a.vb, uo + run + __popcll(mk & lt_mask), a.x,
+                  (pz * a.g.n[1] + py) * a.g.n[2] + px);
     }
     run += __popcll(mk);
   };
@@ -781,7 +850,7 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
   uint16_t* lane_arr = reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]);
   uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
-  float* outv = reinterpret_cast<float*>(a.out + P->off_out[l]);
+  uint8_t* outv = a.out + P->off_out[l];
   const int m = (a.g.B >> a.logs) >> 1;
   // per-unit geometry once per block (threads 0..6), unit index entries
   if (tid < 7) {
@@ -894,7 +963,7 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
           const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
           const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
           const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * j + ug.o[2]) << a.logs);
-          outv[uo + rank] = a.x[(pz * a.g.n[1] + py) * a.g.n[2] + px];
+          put_outlier(outv, a.vb, uo + rank, a.x, (pz * a.g.n[1] + py) * a.g.n[2] + px);
         }
         run += cnt;
       }
@@ -961,6 +1030,7 @@ __host__ __device__ inline LaneLenArgs lanelen_args(const CompressArgs& a, int l
 __host__ __device__ inline LayoutArgs layout_args(const CompressArgs& a) {
   LayoutArgs la;
   la.g = a.geo;
+  la.vb = a.vb;
   la.eb_mode = a.eb_mode;
   la.eb = a.eb;
   la.ratio = a.ratio;
@@ -978,6 +1048,7 @@ __host__ __device__ inline PackArgs pack_args(const CompressArgs& a, int l) {
   const uint64_t nu = a.lc[1].nu;
   PackArgs p;
   p.x = a.x;
+  p.vb = a.vb;
   p.g = a.geo;
   p.level = l;
   p.logs = a.geo.L - l;
@@ -1038,7 +1109,8 @@ __global__ __launch_bounds__(256) void kb_minmax(const CompressArgs* J, ItemMap 
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
     const uint64_t N = uint64_t(a.geo.n[0]) * a.geo.n[1] * a.geo.n[2];
-    minmax_body(a.x, N, a.part, a.params, loc, cnt);
+    minmax_body<float>(static_cast<const float*>(a.x), N, static_cast<MinMax<float>*>(a.part),
+                       a.params, loc, cnt);
   }
 }
 
@@ -1046,7 +1118,8 @@ __global__ void kb_resolve(const CompressArgs* J, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    resolve_body(a.params, a.part, a.nparts, a.eb_mode, a.eb, a.ratio, a.geo.L);
+    resolve_body<float>(a.params, static_cast<const MinMax<float>*>(a.part), a.nparts, a.eb_mode,
+                        a.eb, a.ratio, a.geo.L);
   }
 }
 
@@ -1054,7 +1127,8 @@ __global__ void kb_anchor(const CompressArgs* J, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    anchor_body(a.x, a.geo, a.rec[0], a.params, loc, cnt);
+    anchor_body<float>(static_cast<const float*>(a.x), a.geo, static_cast<float*>(a.rec[0]),
+                       a.params, loc, cnt);
   }
 }
 
@@ -1068,7 +1142,7 @@ __global__ __launch_bounds__(256) void kb_pred(const PredSlabArgs* __restrict__ 
     const uint32_t nblk = uint32_t(a.g.nb[0] * a.g.nb[1] * a.g.nb[2]);
     // padded range (multiple of 8): contiguous blocks per XCD, padding skipped
     const uint32_t blk = uint32_t(wg_block(loc, cnt, true));
-    if (blk < nblk) pred_body<E, H>(a, blk, false);
+    if (blk < nblk) pred_body<float, E, H>(a, blk, false);
   }
 }
 
@@ -1126,7 +1200,7 @@ __global__ void kb_fill_head(const CompressArgs* J, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    fill_head_body(a.out, a.lens, 2 * a.geo.R, a.rec[0], a.n_anchor, a.params, loc, cnt);
+    fill_head_body(a.out, a.lens, 2 * a.geo.R, a.rec[0], a.vb, a.n_anchor, a.params, loc, cnt);
   }
 }
 
@@ -1137,9 +1211,9 @@ __global__ __launch_bounds__(256) void kb_pack(const PackArgs* __restrict__ Q, I
   }
 }
 
-template <int E>
+template <class T, int E>
 void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_pred_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, p);
+  hipLaunchKernelGGL((k_pred_slab<T, E>), dim3(unsigned(nblk)), dim3(256), 0, st, p);
 }
 
 template <int E, int H>
@@ -1204,7 +1278,10 @@ void build_compress_batch_args(const CompressArgs* jobs, uint32_t n, int max_lev
     }
 }
 
-hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
+namespace {
+
+template <class T>
+hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   const Geo& g = a.geo;
   const int L = g.L;
   const int nsym = 2 * g.R;
@@ -1215,16 +1292,17 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   prof_end(st);
   if (a.eb_mode == 1) {
     prof_begin(st, "minmax", -1);
-    hipLaunchKernelGGL(k_minmax, dim3(a.nparts), dim3(256), 0, st, a.x, N, a.part, a.params);
+    hipLaunchKernelGGL(k_minmax<T>, dim3(a.nparts), dim3(256), 0, st, static_cast<const T*>(a.x),
+                       N, static_cast<MinMax<T>*>(a.part), a.params);
     prof_end(st);
   }
   prof_begin(st, "resolve", -1);
-  hipLaunchKernelGGL(k_resolve, dim3(1), dim3(64), 0, st, a.params, a.part, a.nparts, a.eb_mode,
-                     a.eb, a.ratio, L);
+  hipLaunchKernelGGL(k_resolve<T>, dim3(1), dim3(64), 0, st, a.params,
+                     static_cast<const MinMax<T>*>(a.part), a.nparts, a.eb_mode, a.eb, a.ratio, L);
   prof_end(st);
   prof_begin(st, "anchor", -1);
-  hipLaunchKernelGGL(k_anchor, dim3(grid_for(a.n_anchor, 256, 4096)), dim3(256), 0, st, a.x, g,
-                     a.rec[0], a.params);
+  hipLaunchKernelGGL(k_anchor<T>, dim3(grid_for(a.n_anchor, 256, 4096)), dim3(256), 0, st,
+                     static_cast<const T*>(a.x), g, static_cast<T*>(a.rec[0]), a.params);
   prof_end(st);
   for (int l = 1; l <= L; ++l) {
     const PredSlabArgs p = pred_args(a, l);
@@ -1232,12 +1310,12 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     const int E = g.B >> (L - l);
     prof_begin(st, "predict", l);
     switch (E) {
-      case 2: launch_pred<2>(p, nblk, st); break;
-      case 4: launch_pred<4>(p, nblk, st); break;
-      case 8: launch_pred<8>(p, nblk, st); break;
-      case 16: launch_pred<16>(p, nblk, st); break;
-      case 32: launch_pred<32>(p, nblk, st); break;
-      default: launch_pred<64>(p, nblk, st); break;
+      case 2: launch_pred<T, 2>(p, nblk, st); break;
+      case 4: launch_pred<T, 4>(p, nblk, st); break;
+      case 8: launch_pred<T, 8>(p, nblk, st); break;
+      case 16: launch_pred<T, 16>(p, nblk, st); break;
+      case 32: launch_pred<T, 32>(p, nblk, st); break;
+      default: launch_pred<T, 64>(p, nblk, st); break;
     }
     prof_end(st);
   }
@@ -1266,7 +1344,7 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
   prof_end(st);
   prof_begin(st, "fill_head", -1);
   hipLaunchKernelGGL(k_fill_head, dim3(grid_for(a.n_anchor + nsym, 256, 4096)), dim3(256), 0, st,
-                     a.out, a.lens, nsym, a.rec[0], a.n_anchor, a.params);
+                     a.out, a.lens, nsym, a.rec[0], a.vb, a.n_anchor, a.params);
   prof_end(st);
   for (int l = 1; l <= L; ++l) {
     prof_begin(st, "pack", l);
@@ -1274,6 +1352,12 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
     prof_end(st);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_compress(const CompressArgs& a, hipStream_t st) {
+  return a.vb == 8 ? launch_compress_t<double>(a, st) : launch_compress_t<float>(a, st);
 }
 
 namespace {

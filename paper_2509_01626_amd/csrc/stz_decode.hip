@@ -24,34 +24,36 @@ struct DecSlabArgs {
   int64_t n[3];                 // level grid extents
   int64_t bb_lo[3], bb_n[3];    // blocks to process
   bool xcd_remap;
-  const float* prev;            // level-(l-1) box grid
+  const void* prev;             // level-(l-1) box grid (value type of the kernel)
   int64_t in_first[3], in_cnt[3];  // (coarse coordinates)
-  float* cur;                   // level-l box grid (output)
+  void* cur;                    // level-l box grid (output)
   int64_t out_first[3], out_cnt[3];
   const uint32_t* unit_word;
   const uint32_t* unit_outl;
   const uint16_t* lane_len;
   const uint32_t* pay;
-  const float* outv;
+  const void* outv;             // outlier values
   uint64_t words, noutl, nlanes, nu;
-  float E2;
+  float E2;                     // 2e for float32 fields
+  double E2d;                   // 2e for float64 fields
   const uint16_t* lut;
   uint32_t* flags;
 };
 
-// Per-slab state for reconstructing rows of one parity type.
+// Per-slab state for reconstructing rows of one parity type (T = value type).
+template <class T>
 struct DecRows {
-  const float* tile;
+  const T* tile;
   const uint16_t* symb;
   const uint32_t* uo0;
   const uint32_t* uo1;
-  const float* outv;
+  const T* outv;
   uint32_t* flags;
-  float* cur;
+  T* cur;
   int64_t oz, oy, ox;
   int z0, a0, Ex, rz0, rz1, ry0, ry1, rx0, rx1;
   int64_t of[3], oc[3], n[3];
-  float E2;
+  T E2;
   int R;
 };
 
@@ -63,9 +65,9 @@ struct DecRows {
 constexpr int dec_slab_h(int E) { return E == 32 ? 2 : default_slab_h(E); }
 
 // Value of one point of class C (0 = copy of a coarse point).
-template <int E, int H, int C, bool INT>
-__device__ inline float dec_point(const DecRows& x, int lz, int ly, int lx, int srow,
-                                  const int64_t p[3]) {
+template <class T, int E, int H, int C, bool INT>
+__device__ inline T dec_point(const DecRows<T>& x, int lz, int ly, int lx, int srow,
+                              const int64_t p[3]) {
   using S = SlabShape<E, H>;
   if constexpr (C == 0) {
     return x.tile[((((lz - x.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
@@ -75,37 +77,38 @@ __device__ inline float dec_point(const DecRows& x, int lz, int ly, int lx, int 
       const uint64_t oi = uint64_t(x.uo0[C]) + (e & 0x7FFFu);
       if (oi < x.uo1[C]) return x.outv[oi];
       atomicOr(x.flags, kFlagCorrupt);
-      return 0.0f;
+      return T(0);
     }
-    const float pred = tile_pred<E, C, INT>(x.tile, lz - x.z0, ly, lx, p, x.n);
-    const float prod = (float)(int(e) - x.R) * x.E2;
+    // the quantizer's reconstruction: same operands, same order
+    const T pred = tile_pred<T, E, C, INT>(x.tile, lz - x.z0, ly, lx, p, x.n);
+    const T prod = (T)(int(e) - x.R) * x.E2;
     return pred + prod;
   }
 }
 
 // Reconstruct this wave's rows of parity type (ZP, YP): classes 4ZP+2YP (even
 // x) and 4ZP+2YP+1 (odd x), both fixed at compile time.
-template <int E, int H, int ZP, int YP, bool INT>
-__device__ inline void dec_type(const DecRows& x, int hs, int Ey, int wave, int lane) {
+template <class T, int E, int H, int ZP, int YP, bool INT>
+__device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, int lane) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
   for_type_rows<E, ZP, YP>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
     if (lz < x.rz0 || lz >= x.rz1 || ly < x.ry0 || ly >= x.ry1) return;
-    float* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + ly - x.of[1])) * x.oc[2] +
+    T* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + ly - x.of[1])) * x.oc[2] +
                   (x.ox - x.of[2]);
     const int srow = (((lz >> 1) - x.a0) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {x.oz + lz, x.oy + ly, x.ox + l0};
     const int64_t p1[3] = {x.oz + lz, x.oy + ly, x.ox + l1};
     if (l0 < x.Ex && l0 >= x.rx0 && l0 < x.rx1)
-      orow[l0] = dec_point<E, H, C0, INT>(x, lz, ly, l0, srow, p0);
+      orow[l0] = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
     if (l1 < x.Ex && l1 >= x.rx0 && l1 < x.rx1)
-      orow[l1] = dec_point<E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+      orow[l1] = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
   });
 }
 
-template <int E, int H>
+template <class T, int E, int H>
 __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
@@ -118,7 +121,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   constexpr int RB = 2 * WPL;
   __shared__ uint16_t lut[1 << kLutBits];
   __shared__ uint16_t symb[7 * S::SCP];
-  __shared__ float tile[S::TILE];
+  __shared__ T tile[S::TILE];
   __shared__ uint32_t ring[RB * NL];
   __shared__ uint32_t lanelen_s[NL];
   __shared__ uint32_t uo0[8], uo1[8];
@@ -231,8 +234,9 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     const int a0 = z0 >> 1;
     // ---- coarse tile of the slab (global loads in flight during decoding) ----
     const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;  // level coords, even
-    TileRegs<S> tr;
-    tile_fetch<S>(tr, a.prev, a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    TileRegs<S, T> tr;
+    tile_fetch<S, T>(tr, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1,
+                     tx0 >> 1);
     // ---- decode this slab's rows into LDS -----------------------------------
     if (lane_active) {
       // Prefetch the WPL words after this slab's window into registers; they
@@ -290,18 +294,18 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
         if (++sl == RB) sl = 0;
       }
     }
-    tile_store<S>(tile, tr);
+    tile_store<S, T>(tile, tr);
     __syncthreads();
     // ---- reconstruct the slab ------------------------------------------------------
     const int hs = min(S::H, Ez - z0);
-    DecRows ctx;
+    DecRows<T> ctx;
     ctx.tile = tile;
     ctx.symb = symb;
     ctx.uo0 = uo0;
     ctx.uo1 = uo1;
-    ctx.outv = a.outv;
+    ctx.outv = static_cast<const T*>(a.outv);
     ctx.flags = a.flags;
-    ctx.cur = a.cur;
+    ctx.cur = static_cast<T*>(a.cur);
     ctx.oz = oz;
     ctx.oy = oy;
     ctx.ox = ox;
@@ -319,18 +323,21 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
       ctx.oc[d] = a.out_cnt[d];
       ctx.n[d] = a.n[d];
     }
-    ctx.E2 = a.E2;
+    if constexpr (sizeof(T) == 4)
+      ctx.E2 = a.E2;
+    else
+      ctx.E2 = a.E2d;
     ctx.R = a.g.R;
     if (interior) {
-      dec_type<E, H, 0, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<E, H, 0, 1, true>(ctx, hs, Ey, wave, lane);
-      dec_type<E, H, 1, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<E, H, 1, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 0, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 0, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 1, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 1, 1, true>(ctx, hs, Ey, wave, lane);
     } else {
-      dec_type<E, H, 0, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<E, H, 0, 1, false>(ctx, hs, Ey, wave, lane);
-      dec_type<E, H, 1, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<E, H, 1, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 0, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 0, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 1, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, 1, 1, false>(ctx, hs, Ey, wave, lane);
     }
     __syncthreads();
   }
@@ -341,17 +348,18 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   if (bad && lane_active && alive) atomicOr(a.flags, kFlagCorrupt);
 }
 
-template <int E>
+template <class T, int E>
 __global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
-  dec_body<E, dec_slab_h(E)>(a, blockIdx.x);
+  dec_body<T, E, dec_slab_h(E)>(a, blockIdx.x);
 }
 
 // Anchors of the box R_0 from the stream into the level-0 box grid.
+template <class T>
 __device__ inline void dec_anchor_body(const uint8_t* comp, uint64_t anchor_off, const Geo& g,
-                                       float* rec0, const Grid& g0, uint64_t wg, uint64_t ngrid) {
+                                       T* rec0, const Grid& g0, uint64_t wg, uint64_t ngrid) {
   const int logs = g.L;
   const int64_t c1 = ((g.n[1] - 1) >> logs) + 1, c2 = ((g.n[2] - 1) >> logs) + 1;
-  const float* an = reinterpret_cast<const float*>(comp + anchor_off);
+  const T* an = reinterpret_cast<const T*>(comp + anchor_off);
   const int64_t n = g0.cnt[0] * g0.cnt[1] * g0.cnt[2];
   for (int64_t i = int64_t(wg) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(ngrid) * blockDim.x) {
@@ -362,9 +370,9 @@ __device__ inline void dec_anchor_body(const uint8_t* comp, uint64_t anchor_off,
   }
 }
 
-__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, float* rec0,
-                             Grid g0) {
-  dec_anchor_body(comp, anchor_off, g, rec0, g0, blockIdx.x, gridDim.x);
+template <class T>
+__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, T* rec0, Grid g0) {
+  dec_anchor_body<T>(comp, anchor_off, g, rec0, g0, blockIdx.x, gridDim.x);
 }
 
 // Sentinel entries of a level's unit index (first offsets 0, last = totals).
@@ -404,12 +412,13 @@ __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
   d.unit_outl = reinterpret_cast<const uint32_t*>(a.comp + a.off_outl[k]);
   d.lane_len = reinterpret_cast<const uint16_t*>(a.comp + a.off_lane[k]);
   d.pay = reinterpret_cast<const uint32_t*>(a.comp + a.off_pay[k]);
-  d.outv = reinterpret_cast<const float*>(a.comp + a.off_out[k]);
+  d.outv = a.comp + a.off_out[k];
   d.words = a.words[k];
   d.noutl = a.outl[k];
   d.nlanes = a.lc[k].nl;
   d.nu = a.lc[k].nu;
   d.E2 = a.E2[k];
+  d.E2d = a.E2d[k];
   d.lut = a.lut;
   d.flags = a.flags;
   return d;
@@ -417,9 +426,22 @@ __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
 
 __global__ void k_dec_check(DecSlabArgs d) { dec_check_body(d); }
 
-template <int E>
+template <class T, int E>
 void launch_slab(const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_dec_slab<E>, dim3(unsigned(nblk)), dim3(256), 0, st, d);
+  hipLaunchKernelGGL((k_dec_slab<T, E>), dim3(unsigned(nblk)), dim3(256), 0, st, d);
+}
+
+// Plain launch of one level of a decode, by level block edge.
+template <class T>
+void launch_slab_e(int E, const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
+  switch (E) {
+    case 2: launch_slab<T, 2>(d, nblk, st); break;
+    case 4: launch_slab<T, 4>(d, nblk, st); break;
+    case 8: launch_slab<T, 8>(d, nblk, st); break;
+    case 16: launch_slab<T, 16>(d, nblk, st); break;
+    case 32: launch_slab<T, 32>(d, nblk, st); break;
+    default: launch_slab<T, 64>(d, nblk, st); break;
+  }
 }
 
 // ---- batched decoding over a request table ----------------------------------
@@ -446,8 +468,8 @@ __global__ void kb_dec_anchor(const DecodeArgs* R, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const DecodeArgs& a = R[map_find_d(m, it_, &loc, &cnt)];
-    dec_anchor_body(a.comp, a.anchor_off, a.geo, a.rec[0], box_grid(a.box[0], a.geo.L), loc,
-                    cnt);
+    dec_anchor_body<float>(a.comp, a.anchor_off, a.geo, static_cast<float*>(a.rec[0]),
+                           box_grid(a.box[0], a.geo.L), loc, cnt);
   }
 }
 
@@ -467,7 +489,7 @@ __global__ __launch_bounds__(256) void kb_dec(const DecSlabArgs* __restrict__ D,
     const DecSlabArgs d = uniform_load(D + map_find_d(m, it_, &loc, &cnt));
     // padded range (multiple of 8): contiguous blocks per XCD, padding skipped
     const int64_t blk = wg_block(loc, cnt, true);
-    if (blk < d.bb_n[0] * d.bb_n[1] * d.bb_n[2]) dec_body<E, H>(d, blk);
+    if (blk < d.bb_n[0] * d.bb_n[1] * d.bb_n[2]) dec_body<float, E, H>(d, blk);
   }
 }
 
@@ -495,7 +517,8 @@ void launch_dec_bh(int h, const DecSlabArgs* D, const ItemMap& m, unsigned grid,
 // ROI statistics (Sec. 3.3): maximum and minimum of one unit of a level grid
 // (dims gn, stride s), unit = a block of B^3 full-resolution points (E = B/s
 // grid points per axis) or one plane across an axis; stat 0 = max, 1 = range.
-__global__ __launch_bounds__(256) void k_roi_stats(const float* __restrict__ grid, int64_t gn0,
+template <class T>
+__global__ __launch_bounds__(256) void k_roi_stats(const T* __restrict__ grid, int64_t gn0,
                                                    int64_t gn1, int64_t gn2, int64_t E, int unit,
                                                    int stat, int64_t nb1, int64_t nb2,
                                                    double* out) {
@@ -513,18 +536,20 @@ __global__ __launch_bounds__(256) void k_roi_stats(const float* __restrict__ gri
   }
   const int64_t e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
   const int64_t cnt = (hi[0] - lo[0]) * e1 * e2;
-  float mx = -INFINITY, mn = INFINITY;
+  // max/min are exact in any order, in either value type
+  T mx = T(-INFINITY), mn = T(INFINITY);
   for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
     const int64_t x = i % e2, t = i / e2, y = t % e1, z = t / e1;
-    const float v = grid[((lo[0] + z) * gn1 + lo[1] + y) * gn2 + lo[2] + x];
-    mx = fmaxf(mx, v);
-    mn = fminf(mn, v);
+    const T v = grid[((lo[0] + z) * gn1 + lo[1] + y) * gn2 + lo[2] + x];
+    mx = v > mx ? v : mx;
+    mn = v < mn ? v : mn;
   }
   for (int o = 32; o > 0; o >>= 1) {
-    mx = fmaxf(mx, __shfl_xor(mx, o, kWave));
-    mn = fminf(mn, __shfl_xor(mn, o, kWave));
+    const T a = __shfl_xor(mx, o, kWave), b = __shfl_xor(mn, o, kWave);
+    mx = a > mx ? a : mx;
+    mn = b < mn ? b : mn;
   }
-  __shared__ float smx[4], smn[4];
+  __shared__ T smx[4], smn[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
     smx[w] = mx;
@@ -533,31 +558,41 @@ __global__ __launch_bounds__(256) void k_roi_stats(const float* __restrict__ gri
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < 4; ++i) {
-      mx = fmaxf(mx, smx[i]);
-      mn = fminf(mn, smn[i]);
+      mx = smx[i] > mx ? smx[i] : mx;
+      mn = smn[i] < mn ? smn[i] : mn;
     }
     out[u] = stat == 0 ? (double)mx : (double)mx - (double)mn;
   }
 }
 
-hipError_t launch_roi_stats(const float* grid, const int64_t gn[3], int64_t E, int unit, int stat,
-                            const int64_t nb[3], uint64_t nunits, double* out, hipStream_t st) {
+hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
+                            int stat, const int64_t nb[3], uint64_t nunits, double* out,
+                            hipStream_t st) {
   if (nunits == 0) return hipSuccess;
   prof_begin(st, "roi_stats", -1);
-  hipLaunchKernelGGL(k_roi_stats, dim3(unsigned(nunits)), dim3(256), 0, st, grid, gn[0], gn[1],
-                     gn[2], E, unit, stat, nb[1], nb[2], out);
+  if (vb == 8)
+    hipLaunchKernelGGL(k_roi_stats<double>, dim3(unsigned(nunits)), dim3(256), 0, st,
+                       static_cast<const double*>(grid), gn[0], gn[1], gn[2], E, unit, stat,
+                       nb[1], nb[2], out);
+  else
+    hipLaunchKernelGGL(k_roi_stats<float>, dim3(unsigned(nunits)), dim3(256), 0, st,
+                       static_cast<const float*>(grid), gn[0], gn[1], gn[2], E, unit, stat,
+                       nb[1], nb[2], out);
   prof_end(st);
   return hipGetLastError();
 }
 
-hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
+namespace {
+
+template <class T>
+hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
   const Geo& g = a.geo;
   const int L = g.L;
   const Grid g0 = box_grid(a.box[0], L);
   const uint64_t n0 = uint64_t(g0.cnt[0]) * g0.cnt[1] * g0.cnt[2];
   prof_begin(st, "dec_anchor", -1);
-  hipLaunchKernelGGL(k_dec_anchor, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
-                     a.anchor_off, g, a.rec[0], g0);
+  hipLaunchKernelGGL(k_dec_anchor<T>, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
+                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0);
   prof_end(st);
   for (int k = 1; k <= a.level_out; ++k) {
     const DecSlabArgs d = dec_args(a, k);
@@ -567,17 +602,16 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
     const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
     const int E = g.B >> (L - k);
     prof_begin(st, d.xcd_remap ? "decode" : "rdecode", k);
-    switch (E) {
-      case 2: launch_slab<2>(d, nblk, st); break;
-      case 4: launch_slab<4>(d, nblk, st); break;
-      case 8: launch_slab<8>(d, nblk, st); break;
-      case 16: launch_slab<16>(d, nblk, st); break;
-      case 32: launch_slab<32>(d, nblk, st); break;
-      default: launch_slab<64>(d, nblk, st); break;
-    }
+    launch_slab_e<T>(E, d, nblk, st);
     prof_end(st);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
+  return a.vb == 8 ? launch_decode_t<double>(a, st) : launch_decode_t<float>(a, st);
 }
 
 uint64_t decode_batch_args_bytes(uint32_t n, int max_level) {
@@ -612,14 +646,7 @@ hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
       const DecSlabArgs d = dec_args(b.host_R[b.direct[i].req], k);
       const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
       prof_begin(st, "b_decode_direct", k);
-      switch (d.g.B >> (d.g.L - k)) {
-        case 2: launch_slab<2>(d, nblk, st); break;
-        case 4: launch_slab<4>(d, nblk, st); break;
-        case 8: launch_slab<8>(d, nblk, st); break;
-        case 16: launch_slab<16>(d, nblk, st); break;
-        case 32: launch_slab<32>(d, nblk, st); break;
-        default: launch_slab<64>(d, nblk, st); break;
-      }
+      launch_slab_e<float>(d.g.B >> (d.g.L - k), d, nblk, st);
       prof_end(st);
     }
     if (!b.n_check[k]) continue;

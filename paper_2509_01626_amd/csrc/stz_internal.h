@@ -115,12 +115,17 @@ struct Box {
 };
 
 // Parameters resolved on the device (error bounds) and the stream layout.
+// Quantizer constants for both value types: float32 fields use E2/INV and the
+// exact bound e; float64 fields use E2d/INVd and the acceptance bound echk.
 struct DevParams {
   double eb_abs;
   double e[kMaxLevels + 1];
   float E2[kMaxLevels + 1];
   float INV[kMaxLevels + 1];
-  float mn, mx;
+  double E2d[kMaxLevels + 1];
+  double INVd[kMaxLevels + 1];
+  double echk[kMaxLevels + 1];
+  double mn, mx;
   uint32_t flags;
   uint32_t pad;
   uint64_t total;                          // stream bytes
@@ -140,9 +145,17 @@ struct LevelConst {
   uint64_t nsym;   // symbols
 };
 
+// Value type of a field: 4 = float32 (stream value type 0), 8 = float64 (1).
+// Min/max partials of the range reduction, in the field's value type.
+template <class T>
+struct MinMax {
+  T mn, mx;
+};
+
 // ---- launchers (defined with the kernels) ----------------------------------
 struct CompressArgs {
-  const float* x;
+  const void* x;           // field values (float or double, see vb)
+  int vb;                  // bytes per value: 4 or 8
   Geo geo;
   int eb_mode;
   double eb, ratio;
@@ -150,9 +163,9 @@ struct CompressArgs {
   uint64_t out_cap;
   DevParams* params;
   // scratch
-  float2* part;            // min/max partials
+  void* part;              // MinMax<value type> partials
   uint32_t nparts;
-  float* rec[kMaxLevels];  // compact grids of levels 0..L-1
+  void* rec[kMaxLevels];   // compact grids of levels 0..L-1 (value type)
   uint16_t* sym[kMaxLevels + 1];
   LevelConst lc[kMaxLevels + 1];
   unsigned long long* hist;   // 2R counters
@@ -227,9 +240,10 @@ struct DecodeArgs {
   const uint8_t* comp;
   uint64_t size;
   Geo geo;
+  int vb;                     // bytes per value: 4 or 8
   int level_out;
   Box box[kMaxLevels + 1];    // R_k per level
-  float* rec[kMaxLevels + 1]; // box grids of levels 0..level_out (last = output)
+  void* rec[kMaxLevels + 1];  // box grids of levels 0..level_out (last = output)
   uint64_t sec[kMaxLevels + 1];
   uint64_t off_outl[kMaxLevels + 1], off_lane[kMaxLevels + 1], off_pay[kMaxLevels + 1],
       off_out[kMaxLevels + 1];
@@ -237,14 +251,16 @@ struct DecodeArgs {
   LevelConst lc[kMaxLevels + 1];
   uint64_t anchor_off;
   float E2[kMaxLevels + 1];
+  double E2d[kMaxLevels + 1];
   const uint16_t* lut;   // 2^kLutBits entries: symbol | length << 12
   uint32_t* flags;       // device word
 };
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
 // Per-unit ROI statistics of a level grid (see stz_roi_select).
-hipError_t launch_roi_stats(const float* grid, const int64_t gn[3], int64_t E, int unit, int stat,
-                            const int64_t nb[3], uint64_t nunits, double* out, hipStream_t st);
+hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
+                            int stat, const int64_t nb[3], uint64_t nunits, double* out,
+                            hipStream_t st);
 
 // One batched decode: the request table (device) and the work maps of every
 // launch. Level k of request r has edge E = B_r >> (L_r - k).

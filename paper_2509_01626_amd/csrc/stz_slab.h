@@ -29,7 +29,7 @@ struct SlabShape {
   static constexpr int HZ = H / 2;                         // class rows (v_z) per slab
   static constexpr int T = m + 3;                          // coarse tile extent, x and y
   static constexpr int TZ = HZ + 3;                        // coarse tile planes
-  static constexpr int TP = T;  // tile row pitch (floats)
+  static constexpr int TP = T;  // tile row pitch (values)
   static constexpr int TILE = TZ * T * TP;
   // Symbol staging: row pitch m+2 u16 (an odd number of 32-bit words for
   // m >= 4) and an 8-word skew between classes.
@@ -52,13 +52,13 @@ __device__ inline int64_t wg_block(int64_t wg, int64_t nblocks, bool xcd_remap) 
 // Load the coarse tile of a slab: level-(l-1) points (coarse coordinates
 // cz0 + tz, cy0 + ty, cx0 + tx) inside the source grid box; others are zero
 // and never read by a stencil whose flags allow them.
-template <class S>
-__device__ inline void load_tile(float* tile, const float* __restrict__ src, const int64_t sf[3],
+template <class S, class V>
+__device__ inline void load_tile(V* tile, const V* __restrict__ src, const int64_t sf[3],
                                  const int64_t sc[3], int64_t cz0, int64_t cy0, int64_t cx0) {
   for (int i = threadIdx.x; i < S::TZ * S::T * S::T; i += blockDim.x) {
     const int tx = i % S::T, r = i / S::T, ty = r % S::T, tz = r / S::T;
     const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
-    float v = 0.0f;
+    V v = V(0);
     if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
       v = src[(cz * sc[1] + cy) * sc[2] + cx];
     tile[r * S::TP + tx] = v;
@@ -68,22 +68,22 @@ __device__ inline void load_tile(float* tile, const float* __restrict__ src, con
 // The same tile in two halves: fetch this thread's share of the tile into
 // registers (256 threads), then store it, so that other work can run while
 // the loads are in flight.
-template <class S>
+template <class S, class V>
 struct TileRegs {
   static constexpr int N = S::TZ * S::T * S::T;
   static constexpr int K = (N + 255) / 256;
-  float v[K];
+  V v[K];
 };
 
-template <class S>
-__device__ inline void tile_fetch(TileRegs<S>& r, const float* __restrict__ src,
+template <class S, class V>
+__device__ inline void tile_fetch(TileRegs<S, V>& r, const V* __restrict__ src,
                                   const int64_t sf[3], const int64_t sc[3], int64_t cz0,
                                   int64_t cy0, int64_t cx0) {
 #pragma unroll
-  for (int k = 0; k < TileRegs<S>::K; ++k) {
+  for (int k = 0; k < TileRegs<S, V>::K; ++k) {
     const int i = threadIdx.x + 256 * k;
-    float v = 0.0f;
-    if (i < TileRegs<S>::N) {
+    V v = V(0);
+    if (i < TileRegs<S, V>::N) {
       const int tx = i % S::T, t = i / S::T, ty = t % S::T, tz = t / S::T;
       const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
       if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
@@ -93,12 +93,12 @@ __device__ inline void tile_fetch(TileRegs<S>& r, const float* __restrict__ src,
   }
 }
 
-template <class S>
-__device__ inline void tile_store(float* tile, const TileRegs<S>& r) {
+template <class S, class V>
+__device__ inline void tile_store(V* tile, const TileRegs<S, V>& r) {
 #pragma unroll
-  for (int k = 0; k < TileRegs<S>::K; ++k) {
+  for (int k = 0; k < TileRegs<S, V>::K; ++k) {
     const int i = threadIdx.x + 256 * k;
-    if (i < TileRegs<S>::N) tile[(i / S::T) * S::TP + i % S::T] = r.v[k];
+    if (i < TileRegs<S, V>::N) tile[(i / S::T) * S::TP + i % S::T] = r.v[k];
   }
 }
 
@@ -112,18 +112,18 @@ __device__ inline bool block_interior(const int64_t o[3], int E, const int64_t n
 }
 
 // One-axis rule of the nested fallback (format 2.2); f(i) is the value at
-// offset index i along the axis: 0 = -3, 1 = -1, 2 = +1.
-template <class F>
-__device__ inline float nest_rule(bool p1, bool m3, F f) {
+// offset index i along the axis: 0 = -3, 1 = -1, 2 = +1. V = value type.
+template <class V, class F>
+__device__ inline V nest_rule(bool p1, bool m3, F f) {
   if (p1) {
-    const float lo = f(1);
-    const float hi = f(2);
-    return (lo + hi) * 0.5f;
+    const V lo = f(1);
+    const V hi = f(2);
+    return (lo + hi) * V(0.5);
   }
   if (m3) {
-    const float lo = f(1);
-    const float lo3 = f(0);
-    return ((3.0f * lo) - lo3) * 0.5f;
+    const V lo = f(1);
+    const V lo3 = f(0);
+    return ((V(3) * lo) - lo3) * V(0.5);
   }
   return f(1);
 }
@@ -134,10 +134,11 @@ __device__ inline float nest_rule(bool p1, bool m3, F f) {
 // tile index w/2 + 1; the neighbours of an odd one at offsets -3, -1, +1, +3
 // (offset index 0..3) at tile indices k..k+3, k = (w-1)/2. p = global level
 // coordinates and n = level grid extents give the availability flags; with
-// FULL every flag is known to hold (interior blocks).
-template <int E, int C, bool FULL>
-__device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, const int64_t p[3],
-                                  const int64_t n[3]) {
+// FULL every flag is known to hold (interior blocks). V = value type: the
+// same formulas and order in float32 or float64.
+template <class V, int E, int C, bool FULL>
+__device__ inline V tile_pred(const V* tile, int wz, int wy, int wx, const int64_t p[3],
+                              const int64_t n[3]) {
   constexpr int T = SlabShape<E>::T, TP = SlabShape<E>::TP;
   constexpr bool OZ = (C >> 2) & 1, OY = (C >> 1) & 1, OX = C & 1;
   constexpr int ND = int(OZ) + int(OY) + int(OX);
@@ -146,7 +147,7 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
   const int bx = OX ? (wx - 1) >> 1 : (wx >> 1) + 1;
   // v(i, j, k): offset indices along the odd axes in order z, y, x; the tap
   // offsets are compile-time constants relative to one base address.
-  const float* tb = tile + (bz * T + by) * TP + bx;
+  const V* tb = tile + (bz * T + by) * TP + bx;
   auto v = [&](int i, int j, int k) {
     int o[3] = {0, 0, 0};
     int q = 0;
@@ -181,45 +182,45 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
   }
   if constexpr (ND == 1) {
     if (P1[0]) {
-      const float B = v(1, 0, 0), Cv = v(2, 0, 0);
+      const V B = v(1, 0, 0), Cv = v(2, 0, 0);
       if (M3[0] && P3[0]) {
-        const float A = v(0, 0, 0), D = v(3, 0, 0);
-        return ((9.0f * (B + Cv)) - (A + D)) * 0.0625f;
+        const V A = v(0, 0, 0), D = v(3, 0, 0);
+        return ((V(9) * (B + Cv)) - (A + D)) * V(0.0625);
       }
       if (P3[0]) {
-        const float D = v(3, 0, 0);
-        return ((3.0f * B + 6.0f * Cv) - D) * 0.125f;
+        const V D = v(3, 0, 0);
+        return ((V(3) * B + V(6) * Cv) - D) * V(0.125);
       }
       if (M3[0]) {
-        const float A = v(0, 0, 0);
-        return ((6.0f * B + 3.0f * Cv) - A) * 0.125f;
+        const V A = v(0, 0, 0);
+        return ((V(6) * B + V(3) * Cv) - A) * V(0.125);
       }
-      return (B + Cv) * 0.5f;
+      return (B + Cv) * V(0.5);
     }
-    const float B = v(1, 0, 0);
+    const V B = v(1, 0, 0);
     if (M3[0]) {
-      const float A = v(0, 0, 0);
-      return ((3.0f * B) - A) * 0.5f;
+      const V A = v(0, 0, 0);
+      return ((V(3) * B) - A) * V(0.5);
     }
     return B;
   } else if constexpr (ND == 2) {
     if (FULL || (P1[0] && M3[0] && P3[0] && P1[1] && M3[1] && P3[1])) {
-      float in = v(1, 1, 0);
+      V in = v(1, 1, 0);
       in = in + v(1, 2, 0);
       in = in + v(2, 1, 0);
       in = in + v(2, 2, 0);
-      float out = v(0, 0, 0);
+      V out = v(0, 0, 0);
       out = out + v(0, 3, 0);
       out = out + v(3, 0, 0);
       out = out + v(3, 3, 0);
-      return ((9.0f * in) - out) * 0.03125f;
+      return ((V(9) * in) - out) * V(0.03125);
     }
-    return nest_rule(P1[0], M3[0], [&](int i) {
-      return nest_rule(P1[1], M3[1], [&](int j) { return v(i, j, 0); });
+    return nest_rule<V>(P1[0], M3[0], [&](int i) {
+      return nest_rule<V>(P1[1], M3[1], [&](int j) { return v(i, j, 0); });
     });
   } else {
     if (FULL || (P1[0] && M3[0] && P3[0] && P1[1] && M3[1] && P3[1] && P1[2] && M3[2] && P3[2])) {
-      float in = v(1, 1, 1);
+      V in = v(1, 1, 1);
       in = in + v(1, 1, 2);
       in = in + v(1, 2, 1);
       in = in + v(1, 2, 2);
@@ -227,7 +228,7 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
       in = in + v(2, 1, 2);
       in = in + v(2, 2, 1);
       in = in + v(2, 2, 2);
-      float out = v(0, 0, 0);
+      V out = v(0, 0, 0);
       out = out + v(0, 0, 3);
       out = out + v(0, 3, 0);
       out = out + v(0, 3, 3);
@@ -235,11 +236,11 @@ __device__ inline float tile_pred(const float* tile, int wz, int wy, int wx, con
       out = out + v(3, 0, 3);
       out = out + v(3, 3, 0);
       out = out + v(3, 3, 3);
-      return ((9.0f * in) - out) * 0.015625f;
+      return ((V(9) * in) - out) * V(0.015625);
     }
-    return nest_rule(P1[0], M3[0], [&](int i) {
-      return nest_rule(P1[1], M3[1], [&](int j) {
-        return nest_rule(P1[2], M3[2], [&](int k) { return v(i, j, k); });
+    return nest_rule<V>(P1[0], M3[0], [&](int i) {
+      return nest_rule<V>(P1[1], M3[1], [&](int j) {
+        return nest_rule<V>(P1[2], M3[2], [&](int k) { return v(i, j, k); });
       });
     });
   }

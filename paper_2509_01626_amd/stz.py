@@ -24,7 +24,7 @@ class Config(C.Structure):
 class Info(C.Structure):
     _fields_ = [("dims", C.c_uint64 * 3), ("block", C.c_uint32), ("levels", C.c_uint32),
                 ("radius", C.c_uint32), ("lmax", C.c_uint32), ("eb_mode", C.c_uint32),
-                ("reserved", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
+                ("dtype", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
                 ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64)]
 
 
@@ -60,21 +60,27 @@ def lib():
                                "(run __graft_entry__.build())")
         L = C.CDLL(_build.LIB)
         u64p = C.POINTER(C.c_uint64)
-        L.stz_compress_bound.restype = C.c_uint64
-        L.stz_compress_bound.argtypes = [u64p, C.POINTER(Config)]
-        L.stz_compress.restype = C.c_int
-        L.stz_compress.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double, C.POINTER(Config),
-                                   C.c_void_p, C.c_uint64, u64p, C.c_void_p]
+        for sfx in ("", "_f64"):  # float32 and float64 variants, same signatures
+            f = getattr(L, "stz_compress_bound" + sfx)
+            f.restype = C.c_uint64
+            f.argtypes = [u64p, C.POINTER(Config)]
+            f = getattr(L, "stz_compress" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, u64p, C.c_int, C.c_double, C.POINTER(Config), C.c_void_p,
+                          C.c_uint64, u64p, C.c_void_p]
+            f = getattr(L, "stz_decompress" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p]
+            f = getattr(L, "stz_decompress_level" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, u64p,
+                          C.c_void_p]
+            f = getattr(L, "stz_decompress_region" + sfx)
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32, C.c_void_p,
+                          C.c_uint64, u64p, C.c_void_p]
         L.stz_info.restype = C.c_int
         L.stz_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Info), C.c_void_p]
-        L.stz_decompress.restype = C.c_int
-        L.stz_decompress.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p]
-        L.stz_decompress_level.restype = C.c_int
-        L.stz_decompress_level.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p,
-                                           C.c_uint64, u64p, C.c_void_p]
-        L.stz_decompress_region.restype = C.c_int
-        L.stz_decompress_region.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32,
-                                            C.c_void_p, C.c_uint64, u64p, C.c_void_p]
         L.stz_compress_batch.restype = C.c_int
         L.stz_compress_batch.argtypes = [C.POINTER(Job), C.c_uint64, C.c_void_p]
         L.stz_open.restype = C.c_int
@@ -133,34 +139,53 @@ def _check_dev(t, dtype):
         raise ValueError(f"expected a contiguous {dtype} tensor on a GPU")
 
 
-def stz_compress_bound(shape, cfg):
-    return int(lib().stz_compress_bound(_dims(shape), C.byref(cfg)))
+def _sfx(dtype):
+    """Entry-point suffix of a value type: float32 -> "", float64 -> "_f64"."""
+    if dtype == torch.float32:
+        return ""
+    if dtype == torch.float64:
+        return "_f64"
+    raise ValueError(f"unsupported value type {dtype} (float32 or float64)")
+
+
+def value_type(inf):
+    """torch value type of a stream, from its info record."""
+    return torch.float64 if inf.dtype == 1 else torch.float32
+
+
+def stz_compress_bound(shape, cfg, dtype=torch.float32):
+    return int(getattr(lib(), "stz_compress_bound" + _sfx(dtype))(_dims(shape), C.byref(cfg)))
 
 
 def stz_compress(x, eb_mode, eb, cfg, out=None, stream=None):
-    """Compress device tensor x (float32, shape (nz, ny, nx)). Returns a uint8
-    device tensor holding the stream (a view of `out` when given)."""
-    _check_dev(x, torch.float32)
+    """Compress device tensor x (float32 or float64, shape (nz, ny, nx)).
+    Returns a uint8 device tensor holding the stream (a view of `out` when
+    given)."""
+    sfx = _sfx(x.dtype)
+    _check_dev(x, x.dtype)
     assert x.dim() == 3
     if out is None:
-        out = torch.empty(stz_compress_bound(x.shape, cfg), dtype=torch.uint8, device=x.device)
+        out = torch.empty(stz_compress_bound(x.shape, cfg, x.dtype), dtype=torch.uint8,
+                          device=x.device)
     _check_dev(out, torch.uint8)
     size = C.c_uint64(0)
-    st = lib().stz_compress(C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
-                            C.c_void_p(out.data_ptr()), out.numel(), C.byref(size),
-                            _stream(stream))
+    st = getattr(lib(), "stz_compress" + sfx)(
+        C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
+        C.c_void_p(out.data_ptr()), out.numel(), C.byref(size), _stream(stream))
     if st != OK:
-        raise StzError(st, "stz_compress")
+        raise StzError(st, "stz_compress" + sfx)
     return out[: size.value]
 
 
 def stz_compress_status(x, eb_mode, eb, cfg, out_cap=None, stream=None):
     """Status code and reported size of a compress call (never raises)."""
-    cap = stz_compress_bound(x.shape, cfg) if out_cap is None else out_cap
+    sfx = _sfx(x.dtype)
+    cap = stz_compress_bound(x.shape, cfg, x.dtype) if out_cap is None else out_cap
     out = torch.empty(max(cap, 1), dtype=torch.uint8, device=x.device)
     size = C.c_uint64(0)
-    st = lib().stz_compress(C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
-                            C.c_void_p(out.data_ptr()), cap, C.byref(size), _stream(stream))
+    st = getattr(lib(), "stz_compress" + sfx)(
+        C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
+        C.c_void_p(out.data_ptr()), cap, C.byref(size), _stream(stream))
     return st, size.value
 
 
@@ -173,16 +198,20 @@ def stz_info(comp, stream=None):
     return inf
 
 
+# The decoders take the variant of the output's value type: by default the
+# stream's own; a given `out` of the other type gets STZ_ERR_ARG back.
 def stz_decompress(comp, out=None, stream=None, info=None):
     inf = info if info is not None else stz_info(comp, stream)
     shape = tuple(int(v) for v in inf.dims)
     if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=comp.device)
-    _check_dev(out, torch.float32)
-    st = lib().stz_decompress(C.c_void_p(comp.data_ptr()), comp.numel(),
-                              C.c_void_p(out.data_ptr()), out.numel(), _stream(stream))
+        out = torch.empty(shape, dtype=value_type(inf), device=comp.device)
+    sfx = _sfx(out.dtype)
+    _check_dev(out, out.dtype)
+    st = getattr(lib(), "stz_decompress" + sfx)(C.c_void_p(comp.data_ptr()), comp.numel(),
+                                                C.c_void_p(out.data_ptr()), out.numel(),
+                                                _stream(stream))
     if st != OK:
-        raise StzError(st, "stz_decompress")
+        raise StzError(st, "stz_decompress" + sfx)
     return out.view(shape)
 
 
@@ -205,13 +234,15 @@ def stz_decompress_level(comp, level, out=None, stream=None, info=None):
     shape = level_shape(inf, level)
     n = shape[0] * shape[1] * shape[2]
     if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=comp.device)
-    _check_dev(out, torch.float32)
+        out = torch.empty(shape, dtype=value_type(inf), device=comp.device)
+    sfx = _sfx(out.dtype)
+    _check_dev(out, out.dtype)
     od = (C.c_uint64 * 3)()
-    st = lib().stz_decompress_level(C.c_void_p(comp.data_ptr()), comp.numel(), level,
-                                    C.c_void_p(out.data_ptr()), out.numel(), od, _stream(stream))
+    st = getattr(lib(), "stz_decompress_level" + sfx)(
+        C.c_void_p(comp.data_ptr()), comp.numel(), level, C.c_void_p(out.data_ptr()),
+        out.numel(), od, _stream(stream))
     if st != OK:
-        raise StzError(st, "stz_decompress_level")
+        raise StzError(st, "stz_decompress_level" + sfx)
     assert tuple(od) == shape
     return out.reshape(-1)[:n].view(shape)
 
@@ -221,31 +252,37 @@ def stz_decompress_region(comp, lo, hi, level, out=None, stream=None, info=None)
     shape = region_shape(inf, lo, hi, level)
     n = shape[0] * shape[1] * shape[2]
     if out is None:
-        out = torch.empty(max(n, 1), dtype=torch.float32, device=comp.device)
-    _check_dev(out, torch.float32)
+        out = torch.empty(max(n, 1), dtype=value_type(inf), device=comp.device)
+    sfx = _sfx(out.dtype)
+    _check_dev(out, out.dtype)
     od = (C.c_uint64 * 3)()
-    st = lib().stz_decompress_region(C.c_void_p(comp.data_ptr()), comp.numel(), _dims(lo),
-                                     _dims(hi), level, C.c_void_p(out.data_ptr()), out.numel(),
-                                     od, _stream(stream))
+    st = getattr(lib(), "stz_decompress_region" + sfx)(
+        C.c_void_p(comp.data_ptr()), comp.numel(), _dims(lo), _dims(hi), level,
+        C.c_void_p(out.data_ptr()), out.numel(), od, _stream(stream))
     if st != OK:
-        raise StzError(st, "stz_decompress_region")
+        raise StzError(st, "stz_decompress_region" + sfx)
     assert tuple(od) == shape, (tuple(od), shape)
     return out.reshape(-1)[:n].view(shape)
 
 
-def decode_status(comp, fn="decompress", level=0, lo=None, hi=None, stream=None):
-    """Status of a decode call on possibly corrupt bytes (never raises)."""
-    out = torch.empty(1 << 22, dtype=torch.float32, device=comp.device)
+def decode_status(comp, fn="decompress", level=0, lo=None, hi=None, stream=None,
+                  dtype=torch.float32):
+    """Status of a decode call (the `dtype` variant) on possibly corrupt bytes
+    (never raises)."""
+    out = torch.empty(1 << 22, dtype=dtype, device=comp.device)
     od = (C.c_uint64 * 3)()
     L = lib()
+    x = _sfx(dtype)
     p, n = C.c_void_p(comp.data_ptr()), comp.numel()
     if fn == "decompress":
-        return L.stz_decompress(p, n, C.c_void_p(out.data_ptr()), out.numel(), _stream(stream))
+        return getattr(L, "stz_decompress" + x)(p, n, C.c_void_p(out.data_ptr()), out.numel(),
+                                                _stream(stream))
     if fn == "level":
-        return L.stz_decompress_level(p, n, level, C.c_void_p(out.data_ptr()), out.numel(), od,
-                                      _stream(stream))
-    return L.stz_decompress_region(p, n, _dims(lo), _dims(hi), level, C.c_void_p(out.data_ptr()),
-                                   out.numel(), od, _stream(stream))
+        return getattr(L, "stz_decompress_level" + x)(p, n, level, C.c_void_p(out.data_ptr()),
+                                                      out.numel(), od, _stream(stream))
+    return getattr(L, "stz_decompress_region" + x)(p, n, _dims(lo), _dims(hi), level,
+                                                   C.c_void_p(out.data_ptr()), out.numel(), od,
+                                                   _stream(stream))
 
 
 # ---- batched compression -------------------------------------------------------
