@@ -211,6 +211,13 @@ def spectral_t(dims, alpha, seed, device, dtype=None):
                        dtype or torch.float64).to(torch.float32).contiguous()
 
 
+def spectral64_t(dims, alpha, seed, device):
+    """spectral_t kept in float64 (a double-precision field, for the float64
+    path)."""
+    import torch
+    return _filtered_t(dims, alpha, seed, device, True, torch.float64).contiguous()
+
+
 def grf_t(dims, alpha, seed, device, dtype=None):
     import torch
     return _filtered_t(dims, alpha, seed, device, False,
