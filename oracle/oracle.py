@@ -12,18 +12,20 @@ from . import build as _build
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_BUFFER, ERR_CORRUPT = 0, -1, -2, -3, -4
 EB_ABS, EB_REL = 0, 1
+CODING_DEFAULT, CODING_HUFFMAN, CODING_ZERO_CHUNKS = 0, 1, 2
 
 
 class Config(C.Structure):
     _fields_ = [("block", C.c_uint32), ("levels", C.c_uint32), ("radius", C.c_uint32),
-                ("reserved", C.c_uint32), ("eb_ratio", C.c_double)]
+                ("coding", C.c_uint32), ("eb_ratio", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("dims", C.c_uint64 * 3), ("block", C.c_uint32), ("levels", C.c_uint32),
                 ("radius", C.c_uint32), ("lmax", C.c_uint32), ("eb_mode", C.c_uint32),
                 ("dtype", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
-                ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64)]
+                ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64),
+                ("coding", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 _lib = None
@@ -89,8 +91,8 @@ def _dims(shape):
     return (C.c_uint64 * 3)(*[int(v) for v in shape])
 
 
-def config(block=32, levels=0, radius=0, eb_ratio=0.0):
-    return Config(block, levels, radius, 0, eb_ratio)
+def config(block=32, levels=0, radius=0, eb_ratio=0.0, coding=CODING_DEFAULT):
+    return Config(block, levels, radius, coding, eb_ratio)
 
 
 class OracleError(RuntimeError):

@@ -19,7 +19,11 @@
 //     level (Sec. 3.1, Optimization 5);
 //   * Huffman coding of the quantization codes, one coding unit per sub-block
 //     (Sec. 2.3 and Sec. 3.3), decodable per level (progressive, Sec. 3.3) and
-//     per block (random access, Sec. 3.3).
+//     per block (random access, Sec. 3.3);
+//   * optionally (the default) a lossless zero-chunk stage ahead of the
+//     Huffman coder: a run of centre codes (zero residual) covering one
+//     chunk of a lane stream is coded as one extra token. The paper's
+//     ratios need a stage beyond Huffman coding; this is the format's own.
 // Readings where the paper is silent (boundary stencils, float evaluation order,
 // quantizer parameters, the coarsest level, Huffman tie-breaks, byte layout) are
 // the format's, listed with the design notes of this repository.
@@ -516,7 +520,7 @@ struct stz_ref_config {
   uint32_t block;   // B: power of two in [2, 64]; 0 selects 32
   uint32_t levels;  // L: 1..log2(B); 0 selects log2(B)
   uint32_t radius;  // R: 1..1024; 0 selects 512
-  uint32_t reserved;
+  uint32_t coding;  // 1 = Huffman only, 2 = zero chunks + Huffman; 0 selects 2
   double eb_ratio;  // >= 1; 0 selects 2.5
 };
 
@@ -525,6 +529,7 @@ struct stz_ref_info {
   uint32_t block, levels, radius, lmax, eb_mode, dtype;  // dtype: 0 float32, 1 float64
   double eb, eb_abs, eb_ratio;
   uint64_t total_bytes;
+  uint32_t coding, reserved;  // coding: 1 Huffman only, 2 zero chunks
 };
 
 }  // extern "C"
@@ -533,8 +538,13 @@ namespace {
 
 struct Cfg {
   int B, L, R;
+  int coding;  // 1 Huffman only, 2 zero chunks + Huffman
   double ratio;
 };
+
+// Code alphabet: the 2R quantization symbols, plus the zero-chunk token 2R
+// when that stage is on.
+int alphabet(const Cfg& c) { return 2 * c.R + (c.coding == 2 ? 1 : 0); }
 
 int resolve_cfg(const stz_ref_config* c, Cfg* out) {
   stz_ref_config d = {0, 0, 0, 0, 0.0};
@@ -549,6 +559,8 @@ int resolve_cfg(const stz_ref_config* c, Cfg* out) {
   if (R < 1 || R > 1024) return ERR_ARG;
   double ratio = d.eb_ratio != 0.0 ? d.eb_ratio : 2.5;
   if (!(ratio >= 1.0) || !std::isfinite(ratio)) return ERR_ARG;
+  if (d.coding > 2) return ERR_ARG;
+  out->coding = d.coding ? (int)d.coding : 2;
   out->B = B;
   out->L = L;
   out->R = R;
@@ -608,7 +620,7 @@ uint64_t compress_bound_impl(const uint64_t dims[3], const stz_ref_config* cfg, 
   Cfg c;
   Geo g;
   if (resolve_cfg(cfg, &c) != OK || !make_geo(dims, c, &g)) return 0;
-  size_t total = kHeaderBytes + align16(2 * size_t(c.R));
+  size_t total = kHeaderBytes + align16(size_t(alphabet(c)));
   total += align16(vb * n_anchor(g));
   for (int l = 1; l <= c.L; ++l) {
     std::vector<Unit> us = level_units(g, l);
@@ -678,7 +690,8 @@ int compress_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
       }
 
   // Predict and quantize level by level, coarse to fine (Sec. 3.2).
-  const int nsym = 2 * c.R;
+  const int nsym = alphabet(c);
+  const int Z = 2 * c.R;  // zero-chunk token (when coding == 2)
   std::vector<uint64_t> hist(nsym, 0);
   std::vector<std::vector<uint16_t>> syms(c.L + 1);
   std::vector<std::vector<T>> outl(c.L + 1);
@@ -700,11 +713,36 @@ int compress_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
             rec[i] = r;
             if (sym == 0) outl[l].push_back(x[i]);
             syms[l].push_back((uint16_t)sym);
-            hist[sym]++;
           }
   }
 
-  // Huffman codebook over all symbols of all levels.
+  // Tokens: lane j of a unit lists its symbols in (v_z, v_y) order; a chunk
+  // is the M_y symbols of one v_z. With zero chunks on, a nonempty chunk whose
+  // symbols are all the centre symbol R is one token Z; every other symbol is
+  // its own token. The histogram counts tokens.
+  auto chunk_is_zero = [&](int l, size_t base, const Unit& u, size_t j, size_t vz) {
+    if (c.coding != 2 || u.M[1] == 0) return false;  // empty chunks have no token
+    for (size_t vy = 0; vy < u.M[1]; ++vy)
+      if (syms[l][base + (vz * u.M[1] + vy) * u.M[2] + j] != (uint16_t)c.R) return false;
+    return true;
+  };
+  for (int l = 1; l <= c.L; ++l) {
+    size_t base = 0;
+    for (const Unit& u : units[l]) {
+      for (size_t j = 0; j < u.M[2]; ++j)
+        for (size_t vz = 0; vz < u.M[0]; ++vz) {
+          if (chunk_is_zero(l, base, u, j, vz)) {
+            hist[Z]++;
+          } else {
+            for (size_t vy = 0; vy < u.M[1]; ++vy)
+              hist[syms[l][base + (vz * u.M[1] + vy) * u.M[2] + j]]++;
+          }
+        }
+      base += u.nsym();
+    }
+  }
+
+  // Huffman codebook over all tokens of all levels.
   std::vector<uint8_t> lens(nsym);
   std::vector<uint32_t> codes(nsym);
   huffman_lengths(hist.data(), nsym, kLmax, lens.data());
@@ -727,12 +765,17 @@ int compress_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
       o.unit_outl.push_back((uint32_t)outl_base);
       std::vector<uint32_t> words;
       BitWriter bw{&words, 0};
-      const size_t rows = u.M[0] * u.M[1];
       for (size_t j = 0; j < u.M[2]; ++j) {
         uint64_t start = bw.pos;
-        for (size_t t = 0; t < rows; ++t) {
-          uint16_t sy = syms[l][sym_base + t * u.M[2] + j];
-          bw.put(codes[sy], lens[sy]);
+        for (size_t vz = 0; vz < u.M[0]; ++vz) {
+          if (chunk_is_zero(l, sym_base, u, j, vz)) {
+            bw.put(codes[Z], lens[Z]);
+            continue;
+          }
+          for (size_t vy = 0; vy < u.M[1]; ++vy) {
+            uint16_t sy = syms[l][sym_base + (vz * u.M[1] + vy) * u.M[2] + j];
+            bw.put(codes[sy], lens[sy]);
+          }
         }
         uint64_t bits = bw.pos - start;
         if (bits > 0xFFFFu) return ERR_ARG;  // cannot happen for B <= 64
@@ -785,6 +828,7 @@ int compress_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
   put64(o + 88, codelen_off);
   put64(o + 96, anchor_off);
   put64(o + 104, anchors.size());
+  put32(o + 112, (uint32_t)c.coding);
   for (int l = 1; l <= c.L; ++l) {
     uint8_t* e = o + kLevelTable + kLevelRec * size_t(l - 1);
     put64(e + 0, sec[l]);
@@ -863,9 +907,10 @@ int parse(const void* comp, uint64_t size, Parsed* P) {
   cf.block = get32(b + 32);
   cf.levels = get32(b + 36);
   cf.radius = get32(b + 40);
-  cf.reserved = 0;
+  cf.coding = get32(b + 112);
   cf.eb_ratio = getf64(b + 72);
   if (cf.block == 0 || cf.levels == 0 || cf.radius == 0) return ERR_CORRUPT;
+  if (cf.coding != 1 && cf.coding != 2) return ERR_CORRUPT;
   if (get32(b + 44) != (uint32_t)kLmax) return ERR_CORRUPT;
   if (resolve_cfg(&cf, &P->c) != OK || !make_geo(dims, P->c, &P->g)) return ERR_CORRUPT;
   P->eb_mode = (int)get32(b + 48);
@@ -882,7 +927,7 @@ int parse(const void* comp, uint64_t size, Parsed* P) {
   P->anchor_off = get64(b + 96);
   P->n_anch = get64(b + 104);
   if (P->codelen_off != kHeaderBytes) return ERR_CORRUPT;
-  if (P->anchor_off != kHeaderBytes + align16(2 * size_t(P->c.R))) return ERR_CORRUPT;
+  if (P->anchor_off != kHeaderBytes + align16(size_t(alphabet(P->c)))) return ERR_CORRUPT;
   if (P->n_anch != n_anchor(P->g)) return ERR_CORRUPT;
   uint64_t pos = P->anchor_off + align16(P->vb * P->n_anch);
   for (int l = 1; l <= P->c.L; ++l) {
@@ -918,9 +963,10 @@ int parse(const void* comp, uint64_t size, Parsed* P) {
 
 // Decode every lane of one unit into `sy` (rank order). Returns false on any
 // inconsistency (code not in the book, lane length or unit size mismatch).
+// Z = zero-chunk token (-1 when that stage is off), R = centre symbol.
 bool decode_unit(const Decoder& dec, const uint32_t* payload, uint64_t nwords, uint64_t w0,
-                 uint64_t w1, const uint16_t* lane_len, const Unit& u, std::vector<int>* sy) {
-  const size_t rows = u.M[0] * u.M[1];
+                 uint64_t w1, const uint16_t* lane_len, const Unit& u, int Z, int R,
+                 std::vector<int>* sy) {
   sy->assign(u.nsym(), 0);
   uint64_t pos = w0 * 32;
   const uint64_t end = w1 * 32;
@@ -928,22 +974,29 @@ bool decode_unit(const Decoder& dec, const uint32_t* payload, uint64_t nwords, u
   for (size_t j = 0; j < u.M[2]; ++j) {
     const uint64_t lane_end = pos + lane_len[j];
     if (lane_end > end) return false;
-    for (size_t t = 0; t < rows; ++t) {
-      uint32_t code = 0;
-      int sym = -1;
-      for (int l = 1; l <= kLmax; ++l) {
-        if (pos >= lane_end) return false;
-        int bit = get_bit(payload, nwords, pos++);
-        if (bit < 0) return false;
-        code = (code << 1) | uint32_t(bit);
-        if (dec.count[l] && code >= dec.first[l] && code - dec.first[l] < dec.count[l]) {
-          sym = dec.by_len[l][code - dec.first[l]];
+    for (size_t vz = 0; vz < u.M[0]; ++vz)
+      for (size_t vy = 0; vy < u.M[1]; ++vy) {
+        uint32_t code = 0;
+        int sym = -1;
+        for (int l = 1; l <= kLmax; ++l) {
+          if (pos >= lane_end) return false;
+          int bit = get_bit(payload, nwords, pos++);
+          if (bit < 0) return false;
+          code = (code << 1) | uint32_t(bit);
+          if (dec.count[l] && code >= dec.first[l] && code - dec.first[l] < dec.count[l]) {
+            sym = dec.by_len[l][code - dec.first[l]];
+            break;
+          }
+        }
+        if (sym < 0) return false;
+        if (sym == Z) {
+          // a zero-chunk token starts a chunk and stands for all of it
+          if (vy != 0) return false;
+          for (size_t k = 0; k < u.M[1]; ++k) (*sy)[(vz * u.M[1] + k) * u.M[2] + j] = R;
           break;
         }
+        (*sy)[(vz * u.M[1] + vy) * u.M[2] + j] = sym;
       }
-      if (sym < 0) return false;
-      (*sy)[t * u.M[2] + j] = sym;
-    }
     if (pos != lane_end) return false;
   }
   // The unit occupies whole words: at most 31 padding bits.
@@ -966,7 +1019,8 @@ int decode_levels(const void* comp, const Parsed& P, int level, bool region,
   std::vector<T>& rec = *recp;
   if (P.vb != sizeof(T)) return ERR_ARG;
   rec.assign(g.N, std::numeric_limits<T>::quiet_NaN());
-  const int nsym = 2 * P.c.R;
+  const int nsym = alphabet(P.c);
+  const int Z = P.c.coding == 2 ? 2 * P.c.R : -1;
   const uint8_t* lens = b + P.codelen_off;
   Decoder dec;
   if (!dec.build(lens, nsym)) return ERR_CORRUPT;
@@ -1042,7 +1096,7 @@ int decode_levels(const void* comp, const Parsed& P, int level, bool region,
         if (!any) continue;
       }
       if (!decode_unit(dec, payload, v.words, unit_word[ui], unit_word[ui + 1], lane_len + lb, u,
-                       &sy))
+                       Z, P.c.R, &sy))
         return ERR_CORRUPT;
       g_units_decoded[l][4 * u.o[0] + 2 * u.o[1] + u.o[2]]++;
       uint32_t oi = unit_outl[ui];
@@ -1102,6 +1156,8 @@ int stz_ref_info(const void* comp, uint64_t size, stz_ref_info* info) {
     info->eb_abs = P.eb_abs;
     info->eb_ratio = P.c.ratio;
     info->total_bytes = P.total;
+    info->coding = (uint32_t)P.c.coding;
+    info->reserved = 0;
   }
   return OK;
 }

@@ -235,11 +235,17 @@ def read_stream(comp):
     magic, version = struct.unpack_from("<II", b, 0)
     assert magic == 0x315A5453 and version == 1
     nz, ny, nx = struct.unpack_from("<QQQ", b, 8)
-    B, L, R, lmax, mode = struct.unpack_from("<IIIII", b, 32)
+    B, L, R, lmax, mode, vtype = struct.unpack_from("<IIIIII", b, 32)
     eb, eb_abs, ratio = struct.unpack_from("<ddd", b, 56)
     total, clo, ao, na = struct.unpack_from("<QQQQ", b, 80)
+    (coding,) = struct.unpack_from("<I", b, 112)
     assert total == len(b) and clo == 512 and lmax == 12
-    lens = list(b[clo:clo + 2 * R])
+    assert vtype in (0, 1) and coding in (1, 2)
+    vf, vw = ("<f8", 8) if vtype == 1 else ("<f4", 4)
+    # code alphabet: symbols 0..2R-1, and token 2R (a chunk of centre symbols)
+    # when the zero-chunk stage is on
+    Z = 2 * R if coding == 2 else None
+    lens = list(b[clo:clo + 2 * R + (coding == 2)])
     # canonical codes: (length, symbol) order, consecutive integers per length
     book = {}
     code = 0
@@ -250,10 +256,12 @@ def read_stream(comp):
         code += 1
         prev = ln
     dims = (nz, ny, nx)
-    anchors = np.frombuffer(b, dtype="<f4", count=na, offset=ao)
+    anchors = np.frombuffer(b, dtype=vf, count=na, offset=ao)
     sym = np.full(dims, -1, dtype=np.int32)
     outv = {}
-    pos = _a16(ao + 4 * na)
+    nz_tokens = 0
+    lane_bits = 0
+    pos = _a16(ao + vw * na)
     for l in range(1, L + 1):
         off, nu, nl, nsym, words, nout = struct.unpack_from("<6Q", b, 128 + 48 * (l - 1))
         assert off == pos
@@ -262,11 +270,12 @@ def read_stream(comp):
         uo = np.frombuffer(b, "<u4", nu + 1, o2)
         o3 = o2 + _a16(4 * (nu + 1))
         lane = np.frombuffer(b, "<u2", nl, o3)
+        lane_bits += int(lane.astype(np.int64).sum())
         o4 = o3 + _a16(2 * nl)
         pay = np.frombuffer(b, "<u4", words, o4)
         o5 = o4 + _a16(4 * words)
-        outl = np.frombuffer(b, "<f4", nout, o5)
-        pos = o5 + _a16(4 * nout)
+        outl = np.frombuffer(b, vf, nout, o5)
+        pos = o5 + _a16(vw * nout)
         bits = "".join(format(int(w), "032b") for w in pay)
         s = 1 << (L - l)
         ui = 0
@@ -290,6 +299,12 @@ def read_stream(comp):
                                         cur += bits[p]
                                         p += 1
                                         assert len(cur) <= 12
+                                    if book[cur] == Z:
+                                        assert vy == 0
+                                        nz_tokens += 1
+                                        for k in range(M[1]):
+                                            vals[(vz, k, j)] = R
+                                        break
                                     vals[(vz, vy, j)] = book[cur]
                             assert p == end
                         assert -(-p // 32) == int(uw[ui + 1]) or M[0] * M[1] * M[2] == 0
@@ -308,4 +323,5 @@ def read_stream(comp):
                         ui += 1
         assert ui == nu and li == nl
     assert pos == total
-    return dict(dims=dims, B=B, L=L, R=R, eb_abs=eb_abs, anchors=anchors, sym=sym, outliers=outv)
+    return dict(dims=dims, B=B, L=L, R=R, eb_abs=eb_abs, anchors=anchors, sym=sym, outliers=outv,
+                coding=coding, zero_tokens=nz_tokens, lens=lens, lane_bits=lane_bits)
