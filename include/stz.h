@@ -56,23 +56,36 @@ typedef enum {
  * (max - min), as in the paper's problem statement (Sec. 2.1). */
 typedef enum { STZ_EB_ABS = 0, STZ_EB_REL = 1 } stz_eb_mode;
 
+/* Entropy-coding stage. Huffman only codes every quantization symbol; the
+ * zero-chunk stage first replaces each chunk of a lane stream (the symbols of
+ * one sub-block row along y inside a block) whose symbols all have zero
+ * residual by one extra token, then Huffman-codes the tokens. It is lossless:
+ * both modes reconstruct the same values. */
+typedef enum {
+  STZ_CODING_DEFAULT = 0,     /* zero chunks + Huffman                         */
+  STZ_CODING_HUFFMAN = 1,
+  STZ_CODING_ZERO_CHUNKS = 2
+} stz_coding;
+
 /* Block and level configuration. Zero fields select the defaults. */
 typedef struct {
   uint32_t block;    /* B: block edge, power of two in [2, 64]; 0 -> 32      */
   uint32_t levels;   /* L: levels above the anchors, 1..log2(B); 0 -> log2 B */
   uint32_t radius;   /* R: quantization radius, 1..1024, alphabet 2R; 0->512 */
-  uint32_t reserved; /* must be 0                                            */
+  uint32_t coding;   /* stz_coding                                           */
   double eb_ratio;   /* bound ratio between adjacent paper levels (Sec. 3.1,
                         Optimization 5), >= 1; 0 -> 2.5                      */
 } stz_config;
 
 /* Stream description (parsed header). dtype is the value type of the field
- * (header byte offset 52): 0 = float32, 1 = float64. */
+ * (header byte offset 52): 0 = float32, 1 = float64. coding is the resolved
+ * stz_coding (1 or 2). */
 typedef struct {
   uint64_t dims[3];
   uint32_t block, levels, radius, lmax, eb_mode, dtype;
   double eb, eb_abs, eb_ratio;
   uint64_t total_bytes;
+  uint32_t coding, reserved;
 } stz_info_t;
 
 /* Upper bound of the compressed size in bytes for `dims` and `cfg` (host

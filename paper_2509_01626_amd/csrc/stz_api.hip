@@ -22,13 +22,15 @@ namespace {
 
 struct Cfg {
   int B, logB, L, R;
+  int coding;  // STZ_CODING_HUFFMAN or STZ_CODING_ZERO_CHUNKS
   double ratio;
 };
 
 stz_status resolve_cfg(const stz_config* c, Cfg* o) {
   stz_config d = {0, 0, 0, 0, 0.0};
   if (c) d = *c;
-  if (d.reserved != 0) return STZ_ERR_ARG;
+  if (d.coding > STZ_CODING_ZERO_CHUNKS) return STZ_ERR_ARG;
+  o->coding = d.coding == STZ_CODING_DEFAULT ? int(STZ_CODING_ZERO_CHUNKS) : int(d.coding);
   const int B = d.block ? int(d.block) : 32;
   if (B < 2 || B > 64 || (B & (B - 1))) return STZ_ERR_ARG;
   int k = 0;
@@ -60,6 +62,8 @@ bool make_geo(const uint64_t dims[3], const Cfg& c, Geo* g) {
   g->logB = c.logB;
   g->L = c.L;
   g->R = c.R;
+  g->Z = c.coding == STZ_CODING_ZERO_CHUNKS ? 2 * c.R : -1;
+  g->pad = 0;
   return true;
 }
 
@@ -178,7 +182,7 @@ struct Workspace {
 // after which the area may be reused.
 struct Staging {
   static constexpr uint64_t kLutBytes = (uint64_t(1) << kLutBits) * 2 + 16;
-  static constexpr uint64_t kHdrBytes = kHeaderBytes + 2 * kMaxRadius;
+  static constexpr uint64_t kHdrBytes = kHeaderBytes + kMaxAlphabet;
   uint8_t* base = nullptr;
   uint16_t* lut = nullptr;    // 2^kLutBits entries, then 16 zero bytes
   uint8_t* hdr = nullptr;     // stream header and code lengths
@@ -244,9 +248,11 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
   cf.block = rd<uint32_t>(p + 32);
   cf.levels = rd<uint32_t>(p + 36);
   cf.radius = rd<uint32_t>(p + 40);
-  cf.reserved = 0;
+  cf.coding = rd<uint32_t>(p + 112);
   cf.eb_ratio = rd<double>(p + 72);
   if (!cf.block || !cf.levels || !cf.radius) return STZ_ERR_CORRUPT;
+  if (cf.coding != STZ_CODING_HUFFMAN && cf.coding != STZ_CODING_ZERO_CHUNKS)
+    return STZ_ERR_CORRUPT;
   if (rd<uint32_t>(p + 44) != uint32_t(kLmax)) return STZ_ERR_CORRUPT;
   if (resolve_cfg(&cf, &h->c) != STZ_OK || !make_geo(dims, h->c, &h->g)) return STZ_ERR_CORRUPT;
   h->eb_mode = int(rd<uint32_t>(p + 48));
@@ -258,7 +264,7 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
   if (!(h->eb_abs > 0.0) || !std::isfinite(h->eb_abs)) return STZ_ERR_CORRUPT;
   h->total = rd<uint64_t>(p + 80);
   if (h->total > size) return STZ_ERR_CORRUPT;
-  const uint64_t nsym = 2 * uint64_t(h->c.R);
+  const uint64_t nsym = uint64_t(alphabet(h->g));
   if (rd<uint64_t>(p + 88) != kHeaderBytes) return STZ_ERR_CORRUPT;
   h->anchor_off = rd<uint64_t>(p + 96);
   h->n_anchor = rd<uint64_t>(p + 104);
@@ -500,7 +506,7 @@ struct CompressPlan {
 
   void take(Workspace& ws) {
     const Geo& g = a.geo;
-    const int L = g.L, nsym = 2 * g.R;
+    const int L = g.L, nsym = alphabet(g);
     const uint64_t nu = a.lc[1].nu;
     o_part = ws.take<uint8_t>(2 * uint64_t(a.vb) * a.nparts);
     for (int l = 0; l < L; ++l) o_rec[l] = ws.take<uint8_t>(uint64_t(a.vb) * grid_count(g, L - l));
@@ -683,7 +689,7 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
     return cap_items(a.out_cap, 16 * 256 * 8, 2048);
   }));
   b->n_head = maps->add(&b->head, per_job([](const CompressArgs& a) {
-    return cap_items(a.n_anchor + 2 * uint64_t(a.geo.R), 256, 4096);
+    return cap_items(a.n_anchor + uint64_t(alphabet(a.geo)), 256, 4096);
   }));
 }
 
@@ -770,7 +776,8 @@ uint64_t compress_bound(const uint64_t dims[3], const stz_config* cfg, uint64_t 
   if (!dims || resolve_cfg(cfg, &c) != STZ_OK || !make_geo(dims, c, &g)) return 0;
   LevelConst lc[kMaxLevels + 1];
   level_consts(g, lc);
-  uint64_t total = kHeaderBytes + align16(2 * uint64_t(c.R)) + align16(vb * grid_count(g, g.L));
+  uint64_t total =
+      kHeaderBytes + align16(uint64_t(alphabet(g))) + align16(vb * grid_count(g, g.L));
   for (int l = 1; l <= g.L; ++l) {
     const uint64_t nu = lc[l].nu;
     // every unit: at most kLmax bits per symbol plus one padding word
@@ -960,6 +967,8 @@ stz_status stz_field_info(stz_field f, stz_info_t* info) {
   info->eb_abs = h.eb_abs;
   info->eb_ratio = h.c.ratio;
   info->total_bytes = h.total;
+  info->coding = uint32_t(h.c.coding);
+  info->reserved = 0;
   return STZ_OK;
 }
 
@@ -1426,6 +1435,8 @@ stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* str
     info->eb_abs = h.eb_abs;
     info->eb_ratio = h.c.ratio;
     info->total_bytes = h.total;
+    info->coding = uint32_t(h.c.coding);
+    info->reserved = 0;
   }
   return STZ_OK;
 }

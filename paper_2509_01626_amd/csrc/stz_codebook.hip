@@ -4,7 +4,7 @@
 // nonzero count c with (c+1)>>1 and rebuilding. Applying that k times gives
 // ceil(c / 2^k), so the rule is: the smallest k >= 0 whose Huffman code for
 // the counts ceil(c / 2^k) has no code longer than kLmax. Counts never exceed
-// 2^40, so k <= 40 always succeeds (all counts 1, at most 2048 symbols). The
+// 2^40, so k <= 40 always succeeds (all counts 1, at most 2049 tokens). The
 // device builds the trees for every k in parallel, one work-group per k, and a
 // second kernel picks the first k that fits: the latency of one build instead
 // of one build per halving.
@@ -15,7 +15,10 @@ using namespace dev;
 namespace {
 
 constexpr int kCbThreads = 1024;
-constexpr int kCbMax = 2 * kMaxRadius;  // largest alphabet
+constexpr int kCbMax = 4096;            // power of two >= the largest alphabet
+constexpr int kSymBits = 12;            // symbol field of the sort keys
+constexpr uint64_t kSymMask = (uint64_t(1) << kSymBits) - 1;
+static_assert(kMaxAlphabet <= kCbMax && kCbMax <= (1 << kSymBits), "alphabet too large");
 constexpr int kCbScales = 42;           // k = 0..41
 constexpr uint64_t kInf = ~uint64_t(0);
 
@@ -62,7 +65,7 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   for (int i = t; i < np2; i += blockDim.x) {
     const uint64_t c = i < nsym ? uint64_t(hist[i]) : 0;
     if (c) {
-      W[i] = (((c + add) >> k) << 11) | uint64_t(i);
+      W[i] = (((c + add) >> k) << kSymBits) | uint64_t(i);
       atomicAdd(&s_m, 1);
     } else {
       W[i] = kInf;
@@ -72,13 +75,13 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   bitonic_sort(W, np2);
   const int m = s_m;
   if (m <= 1) {
-    if (m == 1 && t == 0) lens[W[0] & 2047] = 1;
+    if (m == 1 && t == 0) lens[W[0] & kSymMask] = 1;
     if (t == 0) maxlen_k[k] = m;
     return;
   }
   for (int i = t; i < m; i += blockDim.x) {
-    leaf[i] = uint16_t(W[i] & 2047);
-    W[i] = W[i] >> 11;
+    leaf[i] = uint16_t(W[i] & kSymMask);
+    W[i] = W[i] >> kSymBits;
   }
   __syncthreads();
   if (t == 0) {
@@ -185,7 +188,7 @@ __device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k,
   while (np2 < nsym) np2 <<= 1;
   for (int i = t; i < np2; i += blockDim.x) {
     const int l = i < nsym ? lens[i] : 0;
-    key[i] = l ? ((uint64_t(l) << 11) | uint64_t(i)) : kInf;
+    key[i] = l ? ((uint64_t(l) << kSymBits) | uint64_t(i)) : kInf;
     if (l) atomicAdd(&bl[l], 1u);
     if (i < nsym) {
       lens_out[i] = uint8_t(l);
@@ -206,7 +209,7 @@ __device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k,
   for (int i = t; i < np2; i += blockDim.x) {
     const uint64_t k = key[i];
     if (k == kInf) continue;
-    const int l = int(k >> 11), sy = int(k & 2047);
+    const int l = int(k >> kSymBits), sy = int(k & kSymMask);
     codes_out[sy] = uint16_t(first[l] + (uint32_t(i) - start[l]));
   }
 }
@@ -231,7 +234,7 @@ __host__ __device__ inline int* cb_maxlen_k(void* scratch, int nsym) {
 // pays for one tree per field unless a field needs the length limit.
 __global__ __launch_bounds__(kCbThreads) void kb_cb_build(const CompressArgs* J, int k0) {
   const CompressArgs& a = J[blockIdx.y];
-  const int nsym = 2 * a.geo.R;
+  const int nsym = alphabet(a.geo);
   int* mk = cb_maxlen_k(a.cb_scratch, nsym);
   if (k0 > 0 && mk[0] <= kLmax) return;
   cb_build_body(a.hist, nsym, cb_lens_k(a.cb_scratch), mk, k0 + int(blockIdx.x));
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kCbThreads) void kb_cb_build(const CompressArgs* J,
 
 __global__ __launch_bounds__(kCbThreads) void kb_cb_final(const CompressArgs* J) {
   const CompressArgs& a = J[blockIdx.x];
-  const int nsym = 2 * a.geo.R;
+  const int nsym = alphabet(a.geo);
   cb_final_body(cb_lens_k(a.cb_scratch), cb_maxlen_k(a.cb_scratch, nsym), nsym, a.lens, a.codes);
 }
 

@@ -267,7 +267,7 @@ template <class T, int E, int H>
 __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_remap) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
-  __shared__ uint32_t h[2 * kMaxRadius];
+  __shared__ uint32_t h[kMaxAlphabet];
   __shared__ T tile[S::TILE];
   __shared__ uint16_t ssym[7 * S::SCP];  // slab symbols, [class][v_z][v_y][v_x] (padded)
   __shared__ uint64_t ubase[8];
@@ -301,6 +301,7 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   const int64_t org[3] = {oz, oy, ox};
   const bool interior = block_interior(org, E, a.n);
   uint32_t n_center = 0;  // the zero-residual symbol is counted in a register
+  uint32_t n_zero = 0, n_cover = 0;  // zero chunks found, centre symbols they cover
   bool bad = false;
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;
@@ -339,10 +340,31 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
       pred_type<T, E, H, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     }
     __syncthreads();
+    const int a0 = z0 >> 1;
+    // Zero chunks (format 2.4): a chunk is the M_y symbols of one (class,
+    // v_z, v_x); one whose symbols are all R becomes one token Z, so the
+    // histogram counts Z once and those symbols not at all. Slabs hold whole
+    // v_z rows, so every chunk lies in one slab.
+    if (a.g.Z >= 0) {
+      for (int i = tid; i < 7 * S::HZ * m; i += blockDim.x) {
+        const int c = i / (S::HZ * m) + 1, rr = i - (c - 1) * (S::HZ * m);
+        const int vzl = rr / m, j = rr - vzl * m;
+        const int Mz = (c >> 2) & 1 ? Ez >> 1 : (Ez + 1) >> 1;
+        const int My = (c >> 1) & 1 ? Ey >> 1 : (Ey + 1) >> 1;
+        const int Mx = c & 1 ? Ex >> 1 : (Ex + 1) >> 1;
+        if (a0 + vzl >= Mz || j >= Mx || My == 0) continue;
+        const uint16_t* q = ssym + (c - 1) * S::SCP + (vzl * m) * S::SP + j;
+        bool all = true;
+        for (int vy = 0; vy < My; ++vy) all = all && q[vy * S::SP] == uint16_t(R);
+        if (all) {
+          ++n_zero;
+          n_cover += uint32_t(My);
+        }
+      }
+    }
     // The slab's rows of every unit, column-major inside the unit: column j of
     // a unit with M_z*M_y rows starts at unit base + j*M_z*M_y, so this slab's
     // part of each column is one contiguous run.
-    const int a0 = z0 >> 1;
     for (int c = 1; c <= 7; ++c) {
       const int oz_ = (c >> 2) & 1, oy_ = (c >> 1) & 1, ox_ = c & 1;
       const int Mz = oz_ ? Ez >> 1 : (Ez + 1) >> 1, My = oy_ ? Ey >> 1 : (Ey + 1) >> 1,
@@ -370,7 +392,8 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     }
     __syncthreads();
   }
-  if (n_center) atomicAdd(&h[R], n_center);
+  if (n_center != n_cover) atomicAdd(&h[R], n_center - n_cover);  // mod 2^32, sums >= 0
+  if (n_zero) atomicAdd(&h[a.g.Z], n_zero);
   __syncthreads();
   if (bad) atomicOr(&a.P->flags, kFlagNonfinite);
   for (int i = tid; i < a.nsym; i += blockDim.x)
@@ -396,8 +419,10 @@ struct LaneLenArgs {
 
 // Bit length of every lane stream and per-unit totals. One work-group per
 // block: thread t < 7m owns column j = t mod m of the block's class t/m + 1.
+// With zero chunks, a chunk (M_y consecutive rows of the column) whose
+// symbols are all R costs the token Z's code instead.
 __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
-  __shared__ uint8_t L[2 * kMaxRadius];
+  __shared__ uint8_t L[kMaxAlphabet];
   __shared__ uint32_t bits_s[256], out_s[256];
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
   const int m = (a.g.B >> a.logs) >> 1;
@@ -411,7 +436,39 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
     const UnitGeo ug = unit_geo(a.g, u, a.logs);
     const uint32_t rows = uint32_t(ug.M[0]) * ug.M[1];
     Mx = ug.M[2];
-    if (j < Mx) {
+    if (j < Mx && a.g.Z >= 0) {
+      const uint16_t* col = a.sym + uint64_t(unit_sym_off(a.g, a.logs, u)) + uint64_t(j) * rows;
+      const uint32_t My = uint32_t(ug.M[1]), R = uint32_t(a.g.R), LZ = L[a.g.Z];
+      const bool vec = (reinterpret_cast<uintptr_t>(col) & 15) == 0 && (My & 7) == 0;
+      for (uint32_t t0 = 0; t0 < rows; t0 += My) {
+        uint32_t cb = 0, co = 0;
+        bool all = true;
+        if (vec) {
+          const uint4* c4 = reinterpret_cast<const uint4*>(col + t0);
+          for (uint32_t k8 = 0; k8 < (My >> 3); ++k8) {
+            const uint4 w = c4[k8];
+            const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t s0 = v[k] & 0xFFFFu, s1 = v[k] >> 16;
+              cb += L[s0] + L[s1];
+              co += (s0 == 0) + (s1 == 0);
+              all = all && s0 == R && s1 == R;
+            }
+          }
+        } else {
+          for (uint32_t t = t0; t < t0 + My; ++t) {
+            const uint16_t s = col[t];
+            cb += L[s];
+            co += (s == 0);
+            all = all && s == R;
+          }
+        }
+        bits += all ? LZ : cb;
+        no += co;
+      }
+      a.lane_len[unit_lane_off(a.g, a.logs, u) + j] = uint16_t(bits);
+    } else if (j < Mx) {
       const uint16_t* col = a.sym + uint64_t(unit_sym_off(a.g, a.logs, u)) + uint64_t(j) * rows;
       uint32_t t = 0;
       if ((reinterpret_cast<uintptr_t>(col) & 15) == 0) {
@@ -569,7 +626,7 @@ __device__ inline void layout_body(const LayoutArgs& a) {
   if (threadIdx.x != 0) return;
   DevParams* P = a.P;
   const int L = a.g.L;
-  const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(2 * a.g.R));
+  const uint64_t anchor_off = kHeaderBytes + align16(uint64_t(alphabet(a.g)));
   const uint64_t vb = uint64_t(a.vb);
   uint64_t pos = anchor_off + align16(vb * a.n_anchor);
   for (int l = 1; l <= L; ++l) {
@@ -605,6 +662,7 @@ __device__ inline void layout_body(const LayoutArgs& a) {
   st64(o + 88, kHeaderBytes);
   st64(o + 96, anchor_off);
   st64(o + 104, a.n_anchor);
+  st32(o + 112, a.g.Z >= 0 ? 2u : 1u);  // coding: 1 Huffman only, 2 zero chunks
   for (int l = 1; l <= L; ++l) {
     uint8_t* e = o + kLevelTable + kLevelRec * uint64_t(l - 1);
     st64(e + 0, P->sec[l]);
@@ -698,8 +756,8 @@ __device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_
 __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   const DevParams* P = a.P;
   if (P->flags) return;
-  __shared__ uint8_t Ls[2 * kMaxRadius];
-  __shared__ uint16_t Cs[2 * kMaxRadius];
+  __shared__ uint8_t Ls[kMaxAlphabet];
+  __shared__ uint16_t Cs[kMaxAlphabet];
   __shared__ uint32_t lb_s[256];
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) {
     Ls[i] = a.lens[i];
@@ -750,9 +808,27 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   const uint64_t segmask = (m >= 64 ? ~uint64_t(0) : ((uint64_t(1) << m) - 1)) << (lane - j);
   const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
   const uint16_t* col = a.sym + base + uint64_t(j) * rows;
+  // zero chunks: at the first row of each chunk (M_y rows) the lane checks the
+  // chunk; a chunk of all-R symbols emits Z there and nothing for its rows
+  const bool zc = a.g.Z >= 0;
+  const uint32_t Rs = uint32_t(a.g.R);
+  uint32_t vyc = 0;     // row within the current chunk
+  bool zrun = false;    // the current chunk is all R
   auto step = [&](uint32_t s, uint32_t t) {
-    if (act) {
-      const uint32_t len = Ls[s], cw = Cs[s];
+    uint32_t len = Ls[s], cw = Cs[s];
+    if (zc) {
+      if (vyc == 0) {
+        bool all = act;
+        for (uint32_t k = 0; k < M1 && all; ++k) all = col[t + k] == Rs;
+        zrun = all;
+      }
+      if (zrun) {
+        len = vyc == 0 ? Ls[a.g.Z] : 0u;
+        cw = Cs[a.g.Z];
+      }
+      if (++vyc == M1) vyc = 0;
+    }
+    if (act && len) {
       const uint32_t o = uint32_t(pos & 31);
       if (o + len <= 32) {
         cur |= cw << (32 - o - len);
@@ -837,8 +913,9 @@ __device__ inline uint32_t block_excl_scan32(uint32_t v, uint32_t* total) {
 __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   const DevParams* P = a.P;
   if (P->flags) return;
-  __shared__ uint32_t LC[2 * kMaxRadius];  // code | length << 16
+  __shared__ uint32_t LC[kMaxAlphabet];  // code | length << 16
   __shared__ uint16_t us[kPackChunk];
+  __shared__ uint8_t zf[kPackChunk];      // zero-chunk flags of the buffer
   __shared__ uint32_t wb[kPackWords];
   __shared__ uint32_t u_rows[8], u_mx[8], u_my[8];
   __shared__ uint64_t u_src[8];
@@ -885,18 +962,43 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
     uint32_t wdone = 0;  // whole words of the unit written so far
     uint32_t sk = 0;     // bits carried in the partial word
     uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < n_u; c0 += kPackChunk) {
-      const int n = int(min<uint32_t>(kPackChunk, n_u - c0));
+    // Zero chunks: chunk k of the unit = symbols [k*M_y, (k+1)*M_y) (one v_z of
+    // one column). Buffers hold whole chunks, so each buffer flags its own.
+    const uint32_t My = u_my[c];
+    const bool zc = a.g.Z >= 0 && My > 0;
+    const uint32_t bstep = zc ? (kPackChunk / My) * My : kPackChunk;
+    const uint32_t lcz = zc ? LC[a.g.Z] : 0u;
+    for (uint32_t c0 = 0; c0 < n_u; c0 += bstep) {
+      const int n = int(min<uint32_t>(bstep, n_u - c0));
       for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
       __syncthreads();
-      // this thread's run of kPackPer symbols: (code, length) in registers
+      if (zc) {
+        const int nch = n / int(My);
+        for (int k = tid; k < nch; k += 256) {
+          bool all = true;
+          for (uint32_t v = 0; v < My && all; ++v) all = us[k * My + v] == uint16_t(a.g.R);
+          zf[k] = all ? 1 : 0;
+        }
+        __syncthreads();
+      }
+      // this thread's run of kPackPer symbols: (code, length) in registers; a
+      // zero chunk's first symbol carries Z's code, its others nothing
       const int i0 = tid * kPackPer;
       uint32_t lc[kPackPer];
       uint32_t mine = 0;
+      uint32_t q = zc ? uint32_t(i0) / My : 0u, r = zc ? uint32_t(i0) - q * My : 0u;
 #pragma unroll
       for (int k = 0; k < kPackPer; ++k) {
-        lc[k] = i0 + k < n ? LC[us[i0 + k]] : 0u;
-        mine += lc[k] >> 16;
+        uint32_t v = i0 + k < n ? LC[us[i0 + k]] : 0u;
+        if (zc && i0 + k < n) {
+          if (zf[q]) v = r == 0 ? lcz : 0u;
+          if (++r == My) {
+            r = 0;
+            ++q;
+          }
+        }
+        lc[k] = v;
+        mine += v >> 16;
       }
       uint32_t total;
       const uint32_t off = block_excl_scan32(mine, &total);
@@ -1008,7 +1110,7 @@ __host__ __device__ inline PredSlabArgs pred_args(const CompressArgs& a, int l) 
   p.sym = a.sym[l];
   p.P = a.params;
   p.hist = a.hist;
-  p.nsym = 2 * g.R;
+  p.nsym = alphabet(g);
   return p;
 }
 
@@ -1020,7 +1122,7 @@ __host__ __device__ inline LaneLenArgs lanelen_args(const CompressArgs& a, int l
   q.sym = a.sym[l];
   q.nu = nu;
   q.lens = a.lens;
-  q.nsym = 2 * a.geo.R;
+  q.nsym = alphabet(a.geo);
   q.lane_len = a.lane_len + a.lane_base[l];
   q.cnt_words = a.cnt + uint64_t(2 * (l - 1)) * nu;
   q.cnt_outl = a.cnt + uint64_t(2 * (l - 1) + 1) * nu;
@@ -1056,7 +1158,7 @@ __host__ __device__ inline PackArgs pack_args(const CompressArgs& a, int l) {
   p.nu = nu;
   p.lens = a.lens;
   p.codes = a.codes;
-  p.nsym = 2 * a.geo.R;
+  p.nsym = alphabet(a.geo);
   p.lane_len = a.lane_len + a.lane_base[l];
   p.scan_words = a.scan + uint64_t(2 * (l - 1)) * (nu + 1);
   p.scan_outl = a.scan + uint64_t(2 * (l - 1) + 1) * (nu + 1);
@@ -1100,7 +1202,7 @@ __global__ void kb_init(const CompressArgs* J, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    init_body(a.params, a.hist, 2 * a.geo.R);
+    init_body(a.params, a.hist, alphabet(a.geo));
   }
 }
 
@@ -1200,7 +1302,8 @@ __global__ void kb_fill_head(const CompressArgs* J, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    fill_head_body(a.out, a.lens, 2 * a.geo.R, a.rec[0], a.vb, a.n_anchor, a.params, loc, cnt);
+    fill_head_body(a.out, a.lens, alphabet(a.geo), a.rec[0], a.vb, a.n_anchor, a.params, loc,
+                   cnt);
   }
 }
 
@@ -1284,7 +1387,7 @@ template <class T>
 hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   const Geo& g = a.geo;
   const int L = g.L;
-  const int nsym = 2 * g.R;
+  const int nsym = alphabet(g);
   const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
   const uint64_t nu = a.lc[1].nu;
   prof_begin(st, "init", -1);

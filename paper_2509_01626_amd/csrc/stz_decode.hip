@@ -250,6 +250,8 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
         pf[k] = (alive && idx < a.words) ? a.pay[idx] : 0u;
       }
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
+      const int Zt = a.g.Z, Rc = a.g.R;  // zero-chunk token (-1: off), centre symbol
+      int zr = 0;                        // rows left in the current zero chunk
       int vy = 0;                        // row r = vz*My + vy, advanced incrementally
       int so = (c - 1) * S::SCP + j;     // LDS slot of the row's symbol
       uint32_t nw = ring[rk * NL + tid];  // next stream word (word wi)
@@ -265,9 +267,16 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
         rk = rk == RB ? 0 : rk;
         nw = ring[rk * NL + tid];
         const uint16_t e = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
-        const int len = e >> 12;
-        const int sy = e & 4095;
-        bad |= len == 0;  // not a code of the book; lane totals are checked at the end
+        // Inside a zero chunk a row takes R and no bits; a Z token (only at a
+        // chunk's first row) starts one.
+        const bool inz = zr > 0;
+        const int le = e >> 12, se = e & 4095;
+        const bool isz = !inz && se == Zt && le != 0;
+        bad |= !inz && le == 0;  // not a code of the book; lane totals are checked at the end
+        bad |= isz && vy != 0;
+        const int len = inz ? 0 : le;
+        const int sy = inz || isz ? Rc : se;
+        zr = isz ? My - 1 : (inz ? zr - 1 : 0);
         buf <<= len;
         nb -= len;
         used += len;

@@ -16,7 +16,8 @@ constexpr uint64_t kHeaderBytes = 512;
 constexpr int kLmax = 12;             // longest Huffman code
 constexpr int kLutBits = kLmax;       // decoder table indexed by the next 12 bits
 constexpr int kMaxLevels = 6;         // B <= 64
-constexpr int kMaxRadius = 1024;      // alphabet 2R <= 2048
+constexpr int kMaxRadius = 1024;      // quantization symbols 2R <= 2048
+constexpr int kMaxAlphabet = 2 * kMaxRadius + 1;  // plus the zero-chunk token
 constexpr uint64_t kLevelTable = 128;
 constexpr uint64_t kLevelRec = 48;
 
@@ -34,7 +35,12 @@ struct Geo {
   int64_t n[3];    // nz, ny, nx
   int64_t nb[3];   // blocks per axis
   int32_t B, logB, L, R;
+  int32_t Z;       // zero-chunk token (2R), or -1 when that stage is off
+  int32_t pad;
 };
+
+// Code alphabet: the 2R quantization symbols, plus the zero-chunk token.
+__host__ __device__ inline int alphabet(const Geo& g) { return 2 * g.R + (g.Z >= 0 ? 1 : 0); }
 
 // Class sub-grid extent along axis d of block b, class parity o, stride 2^logs.
 __host__ __device__ inline int64_t axis_M(const Geo& g, int d, int64_t b, int o, int logs) {

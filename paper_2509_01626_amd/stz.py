@@ -18,14 +18,15 @@ EB_ABS, EB_REL = 0, 1
 
 class Config(C.Structure):
     _fields_ = [("block", C.c_uint32), ("levels", C.c_uint32), ("radius", C.c_uint32),
-                ("reserved", C.c_uint32), ("eb_ratio", C.c_double)]
+                ("coding", C.c_uint32), ("eb_ratio", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("dims", C.c_uint64 * 3), ("block", C.c_uint32), ("levels", C.c_uint32),
                 ("radius", C.c_uint32), ("lmax", C.c_uint32), ("eb_mode", C.c_uint32),
                 ("dtype", C.c_uint32), ("eb", C.c_double), ("eb_abs", C.c_double),
-                ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64)]
+                ("eb_ratio", C.c_double), ("total_bytes", C.c_uint64),
+                ("coding", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Job(C.Structure):
@@ -130,8 +131,11 @@ def stz_trim():
         raise StzError(st, "stz_trim")
 
 
-def config(block=32, levels=0, radius=0, eb_ratio=0.0):
-    return Config(block, levels, radius, 0, eb_ratio)
+CODING_DEFAULT, CODING_HUFFMAN, CODING_ZERO_CHUNKS = 0, 1, 2
+
+
+def config(block=32, levels=0, radius=0, eb_ratio=0.0, coding=CODING_DEFAULT):
+    return Config(block, levels, radius, coding, eb_ratio)
 
 
 def _check_dev(t, dtype):
