@@ -48,8 +48,10 @@ def parse():
                     help="offered loads, requests per second")
     ap.add_argument("--f64-dims", default="256,256,2048",
                     help="dims of the float64 field (empty = skip)")
+    ap.add_argument("--coding-n", type=int, default=512,
+                    help="edge of the smooth field of the coding section (0 = skip)")
     ap.add_argument("--only", default="",
-                    help="comma list of sections to run: plain,batch,scale,serve,f64")
+                    help="comma list of sections to run: plain,batch,scale,serve,f64,coding")
     return ap.parse_args()
 
 
@@ -333,6 +335,8 @@ def main():
         res["serving"] = bench_serve(args, dev)
     if args.f64_dims and want("f64"):
         res["f64"] = bench_f64(args, dev, oracle_check=not args.no_cpu_baseline)
+    if args.coding_n > 0 and want("coding"):
+        res["coding"] = bench_coding(args, dev, oracle_check=not args.no_cpu_baseline)
     print(json.dumps(res), flush=True)
 
 
@@ -510,6 +514,62 @@ def bench_f64(args, dev, oracle_check=True):
     torch.cuda.empty_cache()
     stz.stz_trim()
     return res
+
+
+def bench_coding(args, dev, oracle_check=True):
+    """Entropy-coding stages on a smooth field (sum of 32 Gaussian bumps plus
+    1e-3 noise, n^3), where most chunks are all-centre: compression ratio and
+    rates of Huffman only vs zero chunks + Huffman, rel eb 1e-2 and 1e-3,
+    B = 32. Both reconstruct the same values."""
+    import torch
+
+    from paper_2509_01626_amd import fields, stz
+    n = args.coding_n
+    dims = (n, n, n)
+    x = fields.bumps_t(dims, 31, dev)
+    torch.cuda.synchronize()
+    fbytes = 4 * x.numel()
+    rows = []
+    for eb in (1e-2, 1e-3):
+        recs = []
+        for coding in (stz.CODING_HUFFMAN, stz.CODING_ZERO_CHUNKS):
+            cfg = stz.config(block=32, coding=coding)
+            out = torch.empty(stz.stz_compress_bound(dims, cfg), dtype=torch.uint8, device=dev)
+            rec = torch.empty_like(x)
+            holder = {}
+
+            def comp():
+                holder["c"] = stz.stz_compress(x, stz.EB_REL, eb, cfg, out=out)
+
+            comp()
+            t_c = _sync_time(comp, args.steps)
+            c = holder["c"]
+            inf = stz.stz_info(c)
+
+            def decomp():
+                stz.stz_decompress(c, out=rec, info=inf)
+
+            decomp()
+            t_d = _sync_time(decomp, args.steps)
+            recs.append(rec)
+            rows.append({"eb_rel": eb, "coding": "huffman" if coding == 1 else "zero_chunks",
+                         "compression_ratio": round(fbytes / c.numel(), 2),
+                         "compress_gbps": round(fbytes / t_c / 1e9, 2),
+                         "decompress_gbps": round(fbytes / t_d / 1e9, 2)})
+        rows[-1]["same_reconstruction"] = bool(
+            torch.equal(recs[0].view(torch.int32), recs[1].view(torch.int32)))
+    oracle_ok = None
+    if oracle_check:
+        from oracle import oracle as O
+        crop = x[:64, :64, :64].contiguous()
+        want = O.compress(crop.cpu().numpy(), O.EB_REL, 1e-2, O.config(block=32))
+        oracle_ok = stz.stz_compress(crop, stz.EB_REL, 1e-2,
+                                     stz.config(block=32)).cpu().numpy().tobytes() == want
+    del x
+    torch.cuda.empty_cache()
+    stz.stz_trim()
+    return {"workload": f"{n}^3 float32 sum of 32 Gaussian bumps + N(0,1e-6) noise, B=32",
+            "runs": rows, "oracle_crop_equal": oracle_ok}
 
 
 def bench_scale(args, dev):

@@ -54,26 +54,24 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   __shared__ int s_m, s_max;
   const int t = threadIdx.x;
   uint8_t* lens = lens_k + size_t(k) * nsym;
-  int np2 = 1;
-  while (np2 < nsym) np2 <<= 1;
   if (t == 0) {
     s_m = 0;
     s_max = 0;
   }
   __syncthreads();
+  // the used symbols' keys, compacted (any order: the sort orders them)
   const uint64_t add = (uint64_t(1) << k) - 1;
-  for (int i = t; i < np2; i += blockDim.x) {
-    const uint64_t c = i < nsym ? uint64_t(hist[i]) : 0;
-    if (c) {
-      W[i] = (((c + add) >> k) << kSymBits) | uint64_t(i);
-      atomicAdd(&s_m, 1);
-    } else {
-      W[i] = kInf;
-    }
+  for (int i = t; i < nsym; i += blockDim.x) {
+    const uint64_t c = uint64_t(hist[i]);
+    if (c) W[atomicAdd(&s_m, 1)] = (((c + add) >> k) << kSymBits) | uint64_t(i);
+    lens[i] = 0;
   }
-  for (int i = t; i < nsym; i += blockDim.x) lens[i] = 0;
-  bitonic_sort(W, np2);
+  __syncthreads();
   const int m = s_m;
+  int np2 = 1;
+  while (np2 < m) np2 <<= 1;
+  for (int i = m + t; i < np2; i += blockDim.x) W[i] = kInf;
+  bitonic_sort(W, np2);
   if (m <= 1) {
     if (m == 1 && t == 0) lens[W[0] & kSymMask] = 1;
     if (t == 0) maxlen_k[k] = m;
@@ -170,7 +168,7 @@ __device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k,
                                      uint8_t* lens_out, uint16_t* codes_out) {
   __shared__ uint64_t key[kCbMax];
   __shared__ uint32_t bl[kLmax + 2], first[kLmax + 1], start[kLmax + 1];
-  __shared__ int s_k;
+  __shared__ int s_k, s_n;
   const int t = threadIdx.x;
   if (t == 0) {
     int kk = kCbScales - 1;
@@ -182,19 +180,23 @@ __device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k,
     s_k = kk;
   }
   if (t < kLmax + 2) bl[t] = 0;
+  if (t == 0) s_n = 0;
   __syncthreads();
   const uint8_t* lens = lens_k + size_t(s_k) * nsym;
-  int np2 = 1;
-  while (np2 < nsym) np2 <<= 1;
-  for (int i = t; i < np2; i += blockDim.x) {
-    const int l = i < nsym ? lens[i] : 0;
-    key[i] = l ? ((uint64_t(l) << kSymBits) | uint64_t(i)) : kInf;
-    if (l) atomicAdd(&bl[l], 1u);
-    if (i < nsym) {
-      lens_out[i] = uint8_t(l);
-      codes_out[i] = 0;
+  for (int i = t; i < nsym; i += blockDim.x) {
+    const int l = lens[i];
+    if (l) {
+      key[atomicAdd(&s_n, 1)] = (uint64_t(l) << kSymBits) | uint64_t(i);
+      atomicAdd(&bl[l], 1u);
     }
+    lens_out[i] = uint8_t(l);
+    codes_out[i] = 0;
   }
+  __syncthreads();
+  const int nk = s_n;
+  int np2 = 1;
+  while (np2 < nk) np2 <<= 1;
+  for (int i = nk + t; i < np2; i += blockDim.x) key[i] = kInf;
   bitonic_sort(key, np2);
   if (t == 0) {
     uint32_t code = 0, st = 0;

@@ -355,7 +355,9 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
         if (a0 + vzl >= Mz || j >= Mx || My == 0) continue;
         const uint16_t* q = ssym + (c - 1) * S::SCP + (vzl * m) * S::SP + j;
         bool all = true;
-        for (int vy = 0; vy < My; ++vy) all = all && q[vy * S::SP] == uint16_t(R);
+#pragma unroll
+        for (int vy = 0; vy < m; ++vy)
+          if (vy < My) all &= q[vy * S::SP] == uint16_t(R);
         if (all) {
           ++n_zero;
           n_cover += uint32_t(My);
@@ -915,7 +917,7 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   if (P->flags) return;
   __shared__ uint32_t LC[kMaxAlphabet];  // code | length << 16
   __shared__ uint16_t us[kPackChunk];
-  __shared__ uint8_t zf[kPackChunk];      // zero-chunk flags of the buffer
+  __shared__ uint32_t zf[kPackChunk / 32];  // zero-chunk flags of the buffer (bits)
   __shared__ uint32_t wb[kPackWords];
   __shared__ uint32_t u_rows[8], u_mx[8], u_my[8];
   __shared__ uint64_t u_src[8];
@@ -968,16 +970,24 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
     const bool zc = a.g.Z >= 0 && My > 0;
     const uint32_t bstep = zc ? (kPackChunk / My) * My : kPackChunk;
     const uint32_t lcz = zc ? LC[a.g.Z] : 0u;
+    // How a thread finds its zero chunks: 1 = M_y divides its run of kPackPer
+    // symbols (chunks inside the run), 2 = M_y is two runs (the chunk is this
+    // run and its pair's), 3 = other M_y (edge blocks): flags in LDS.
+    const int zmode = !zc ? 0
+                      : ((kPackPer % My) == 0 ? 1 : (My == 2 * kPackPer ? 2 : 3));
     for (uint32_t c0 = 0; c0 < n_u; c0 += bstep) {
       const int n = int(min<uint32_t>(bstep, n_u - c0));
       for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
       __syncthreads();
-      if (zc) {
+      if (zmode == 3) {
         const int nch = n / int(My);
+        for (int k = tid; k < (nch + 31) / 32; k += 256) zf[k] = 0;
+        __syncthreads();
         for (int k = tid; k < nch; k += 256) {
           bool all = true;
-          for (uint32_t v = 0; v < My && all; ++v) all = us[k * My + v] == uint16_t(a.g.R);
-          zf[k] = all ? 1 : 0;
+#pragma unroll 8
+          for (uint32_t v = 0; v < My; ++v) all &= us[k * My + v] == uint16_t(a.g.R);
+          if (all) atomicOr(&zf[k >> 5], 1u << (k & 31));
         }
         __syncthreads();
       }
@@ -985,21 +995,48 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       // zero chunk's first symbol carries Z's code, its others nothing
       const int i0 = tid * kPackPer;
       uint32_t lc[kPackPer];
-      uint32_t mine = 0;
-      uint32_t q = zc ? uint32_t(i0) / My : 0u, r = zc ? uint32_t(i0) - q * My : 0u;
+      uint32_t rm = 0;  // bit k: symbol k of the run is R
 #pragma unroll
       for (int k = 0; k < kPackPer; ++k) {
-        uint32_t v = i0 + k < n ? LC[us[i0 + k]] : 0u;
-        if (zc && i0 + k < n) {
-          if (zf[q]) v = r == 0 ? lcz : 0u;
-          if (++r == My) {
-            r = 0;
-            ++q;
+        const bool ok = i0 + k < n;
+        const uint32_t sy = ok ? us[i0 + k] : 0u;
+        lc[k] = ok ? LC[sy] : 0u;
+        rm |= uint32_t(ok && sy == uint32_t(a.g.R)) << k;
+      }
+      if (zmode == 1) {
+        // bit k of f: symbols k..k+M_y-1 all R (M_y a power of two)
+        uint32_t f = rm;
+        for (uint32_t sft = 1; sft < My; sft <<= 1) f &= f >> sft;
+#pragma unroll
+        for (int k = 0; k < kPackPer; ++k) {
+          const uint32_t base = uint32_t(k) & ~(My - 1);
+          if ((f >> base) & 1u) lc[k] = uint32_t(k) == base ? lcz : 0u;
+        }
+      } else if (zmode == 2) {
+        const bool mine_all = rm == (1u << kPackPer) - 1;
+        // every lane takes part in the shuffle (no short circuit around it)
+        const int pair_all = __shfl_xor(int(mine_all), 1, kWave);
+        const bool all = mine_all && pair_all != 0;
+        if (all) {
+#pragma unroll
+          for (int k = 0; k < kPackPer; ++k) lc[k] = (k == 0 && (tid & 1) == 0) ? lcz : 0u;
+        }
+      } else if (zmode == 3) {
+        uint32_t q = uint32_t(i0) / My, r = uint32_t(i0) - q * My;
+#pragma unroll
+        for (int k = 0; k < kPackPer; ++k) {
+          if (i0 + k < n) {
+            if ((zf[q >> 5] >> (q & 31)) & 1u) lc[k] = r == 0 ? lcz : 0u;
+            if (++r == My) {
+              r = 0;
+              ++q;
+            }
           }
         }
-        lc[k] = v;
-        mine += v >> 16;
       }
+      uint32_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < kPackPer; ++k) mine += lc[k] >> 16;
       uint32_t total;
       const uint32_t off = block_excl_scan32(mine, &total);
       const uint32_t nw = (sk + total + 31) >> 5;
@@ -1082,7 +1119,13 @@ __device__ inline void pack_body(const PackArgs& a, int64_t wg) {
     pack_lanes_body(a, wg);
 }
 
-__global__ __launch_bounds__(256) void k_pack(PackArgs a) { pack_body(a, blockIdx.x); }
+// Plain launches take the packer of their block edge: separate kernels keep
+// each one's LDS to its own buffers.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pack_units(
+    PackArgs a) {
+  pack_units_body(a, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k_pack_lanes(PackArgs a) { pack_lanes_body(a, blockIdx.x); }
 
 }  // namespace
 
@@ -1451,7 +1494,10 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   prof_end(st);
   for (int l = 1; l <= L; ++l) {
     prof_begin(st, "pack", l);
-    hipLaunchKernelGGL(k_pack, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
+    if ((g.B >> (L - l)) >= 32)
+      hipLaunchKernelGGL(k_pack_units, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
+    else
+      hipLaunchKernelGGL(k_pack_lanes, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
     prof_end(st);
   }
   return hipGetLastError();

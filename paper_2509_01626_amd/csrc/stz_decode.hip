@@ -64,6 +64,12 @@ struct DecRows {
 // over the extra slab passes.
 constexpr int dec_slab_h(int E) { return E == 32 ? 2 : default_slab_h(E); }
 
+constexpr int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
 // Value of one point of class C (0 = copy of a coarse point).
 template <class T, int E, int H, int C, bool INT>
 __device__ inline T dec_point(const DecRows<T>& x, int lz, int ly, int lx, int srow,
@@ -116,9 +122,9 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   // Stream words a lane can touch while decoding one slab: at most HZ*m codes
   // of <= kLmax bits, plus the bit window's lookahead (< 2 words).
   constexpr int WPL = (S::HZ * m * kLmax + 31) / 32 + 2;
-  // Per-lane ring of 2*WPL stream words, [slot][lane]: the words of the
-  // current slab plus the prefetched words of the next one.
-  constexpr int RB = 2 * WPL;
+  // Per-lane ring of RB >= 2*WPL stream words (a power of two), [slot][lane]:
+  // the words of the current slab plus the prefetched words of the next one.
+  constexpr int RB = pow2_ceil(2 * WPL);
   __shared__ uint16_t lut[1 << kLutBits];
   __shared__ uint16_t symb[7 * S::SCP];
   __shared__ T tile[S::TILE];
@@ -200,7 +206,8 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   }
   // Bit window: `buf` holds `nb` valid bits, left aligned; `wi` = next stream
   // word, found in ring slot `rk`. Slot of word w = (w - first word) mod RB.
-  // Before each slab the ring holds the WPL words from `wi` on.
+  // Before each slab the ring holds the WPL words from `wi` on. Bits consumed
+  // so far = 32*wi - pos - nb.
   uint64_t wi = pos >> 5, buf = 0;
   int nb = 0, rk = 0;
   if (lane_active) {
@@ -215,7 +222,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     ++wi;
     rk = 1;
   }
-  uint32_t used = 0, run = 0;
+  uint32_t run = 0;
   bool bad = false;
   // Lanes of this unit inside the wave (units never straddle a wave).
   const int seg = lane - j;
@@ -251,6 +258,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
       }
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
       const int Zt = a.g.Z, Rc = a.g.R;  // zero-chunk token (-1: off), centre symbol
+      const uint32_t eR = uint32_t(Rc);  // table entry of a zero-chunk row: R, no bits
       int zr = 0;                        // rows left in the current zero chunk
       int vy = 0;                        // row r = vz*My + vy, advanced incrementally
       int so = (c - 1) * S::SCP + j;     // LDS slot of the row's symbol
@@ -262,24 +270,21 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
         const int sh = rf ? 32 - nb : 0;
         buf |= uint64_t(rf ? nw : 0u) << sh;
         nb += rf ? 32 : 0;
-        wi += rf ? 1 : 0;
-        rk += rf ? 1 : 0;
-        rk = rk == RB ? 0 : rk;
+        rk = (rk + (rf ? 1 : 0)) & (RB - 1);
         nw = ring[rk * NL + tid];
-        const uint16_t e = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
-        // Inside a zero chunk a row takes R and no bits; a Z token (only at a
-        // chunk's first row) starts one.
-        const bool inz = zr > 0;
-        const int le = e >> 12, se = e & 4095;
-        const bool isz = !inz && se == Zt && le != 0;
-        bad |= !inz && le == 0;  // not a code of the book; lane totals are checked at the end
-        bad |= isz && vy != 0;
-        const int len = inz ? 0 : le;
-        const int sy = inz || isz ? Rc : se;
-        zr = isz ? My - 1 : (inz ? zr - 1 : 0);
+        // Inside a zero chunk a row takes R and no bits; a Z token starts one
+        // (valid only at a chunk's first row: checked when the chunk ends).
+        const bool inz = zr != 0;
+        const uint32_t ei = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
+        const uint32_t e = inz ? eR : ei;
+        const int len = int(e >> 12);
+        const int se = int(e & 4095);
+        bad |= e == 0;  // not a code of the book; lane totals are checked at the end
+        const bool isz = se == Zt;
+        const int sy = isz ? Rc : se;
+        zr = isz ? My - 1 : zr - (inz ? 1 : 0);
         buf <<= len;
         nb -= len;
-        used += len;
         const bool is_out = sy == 0 && len != 0;
         const uint64_t wm = __ballot(is_out);
         uint16_t st = uint16_t(sy);
@@ -293,15 +298,12 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
         if (++vy == My) {
           vy = 0;
           so += (m - My) * S::SP;
+          bad |= zr != 0;  // a token after a chunk's first row runs past its end
         }
       }
-      int sl = rb + WPL;
-      if (sl >= RB) sl -= RB;
+      wi = wb + uint64_t((rk - rb) & (RB - 1));  // words merged: fewer than RB per slab
 #pragma unroll
-      for (int k = 0; k < WPL; ++k) {
-        ring[sl * NL + tid] = pf[k];
-        if (++sl == RB) sl = 0;
-      }
+      for (int k = 0; k < WPL; ++k) ring[((rb + WPL + k) & (RB - 1)) * NL + tid] = pf[k];
     }
     tile_store<S, T>(tile, tr);
     __syncthreads();
@@ -351,14 +353,19 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     __syncthreads();
   }
   if (lane_active && alive && complete) {
-    if (used != lb) bad = true;
+    if (32 * wi - pos - uint64_t(nb) != uint64_t(lb)) bad = true;
     if (j == 0 && uok[c] && run != uo1[c] - uo0[c]) bad = true;
   }
   if (bad && lane_active && alive) atomicOr(a.flags, kFlagCorrupt);
 }
 
+// Waves per SIMD the decoder is compiled for: 5 for 32^3-point blocks (96
+// VGPRs; the decode chains are latency-bound, so occupancy pays).
+constexpr int dec_waves(int E) { return E == 32 ? 5 : 1; }
+
 template <class T, int E>
-__global__ __launch_bounds__(256) void k_dec_slab(DecSlabArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dec_waves(E))))
+void k_dec_slab(DecSlabArgs a) {
   dec_body<T, E, dec_slab_h(E)>(a, blockIdx.x);
 }
 

@@ -95,3 +95,29 @@ def test_batch_with_both_codings(gpu, oracle):
     want = oracle.compress(xs[1].cpu().numpy(), oracle.EB_REL, 1e-2,
                            oracle.config(block=16, coding=2))
     assert views[1].cpu().numpy().tobytes() == want
+
+
+def test_corrupt_zero_chunk_streams_match_oracle_status(gpu, oracle):
+    """Bit flips in the payload of a stream full of zero-chunk tokens: the GPU
+    decoder reports corruption exactly when the oracle does (a token that is
+    not at a chunk's first row included), and equal values otherwise."""
+    import torch
+
+    from paper_2509_01626_amd import stz
+    x = fields.bumps((24, 24, 24), seed=3, n_bumps=4)
+    want = oracle.compress(x, oracle.EB_REL, 1e-2, oracle.config(block=8))
+    assert oracle.info(want).coding == 2
+    rng = np.random.default_rng(5)
+    payload_from = len(want) // 3
+    for i in range(60):
+        c = bytearray(want)
+        k = int(rng.integers(payload_from, len(c)))
+        c[k] ^= 1 << int(rng.integers(0, 8))
+        print(f"[corrupt] byte {k}", flush=True)
+        d = torch.frombuffer(bytearray(c), dtype=torch.uint8).to(gpu)
+        st_gpu = stz.decode_status(d)
+        st_ref = oracle.decode_status(bytes(c))
+        assert (st_gpu == stz.OK) == (st_ref == oracle.OK), (k, st_gpu, st_ref)
+        if st_ref == oracle.OK:
+            got = stz.stz_decompress(d).cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), oracle.decompress(bytes(c)).view(np.uint32))
