@@ -717,9 +717,8 @@ void build_decode_maps(const std::vector<DecodePlan>& pl, const std::vector<uint
   for (uint32_t k = 0; k < n; ++k) maxk = std::max(maxk, pl[live[k]].a.level_out);
   b->max_level = maxk;
   for (int k = 1; k <= maxk; ++k) {
-    b->n_check[k] = maps->add(&b->check[k], per_req([&](const DecodeArgs& a) {
-      return a.level_out >= k ? 1u : 0u;
-    }));
+    b->n_check[k] = 0;
+    for (uint32_t r = 0; r < n; ++r) b->n_check[k] += pl[live[r]].a.level_out >= k ? 1u : 0u;
     for (uint32_t r = 0; r < n; ++r) {
       const DecodeArgs& a = pl[live[r]].a;
       if (a.level_out < k) continue;

@@ -59,15 +59,23 @@ struct DecRows {
 
 // Slab height of the decoder: for 32^3-point blocks, 2 planes keep the LDS
 // footprint (code table, slab symbols, coarse tile, stream ring) at 26 KB and
-// the registers under 100, for five work-groups per CU: the per-symbol decode
-// chains (one per lane stream) are latency-bound, so more blocks in flight win
-// over the extra slab passes.
-constexpr int dec_slab_h(int E) { return E == 32 ? 2 : default_slab_h(E); }
+// the registers under 100, for five work-groups per CU; 16^3-point blocks
+// take 4 planes (17 KB, 79 VGPRs, six per CU). The per-symbol decode chains
+// (one per lane stream) are latency-bound, so more blocks in flight win over
+// the extra slab passes.
+constexpr int dec_slab_h(int E) { return E == 32 ? 2 : (E == 16 ? 4 : default_slab_h(E)); }
 
 constexpr int pow2_ceil(int v) {
   int p = 1;
   while (p < v) p <<= 1;
   return p;
+}
+
+// Sentinel entries of a level's unit index (first offsets 0, last = totals).
+__device__ inline void dec_check_body(const DecSlabArgs& d) {
+  if (threadIdx.x == 0 && (d.unit_word[0] != 0 || d.unit_outl[0] != 0 ||
+                           d.unit_word[d.nu] != d.words || d.unit_outl[d.nu] != d.noutl))
+    atomicOr(d.flags, kFlagCorrupt);
 }
 
 // Value of one point of class C (0 = copy of a coarse point).
@@ -125,7 +133,12 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   // Per-lane ring of RB >= 2*WPL stream words (a power of two), [slot][lane]:
   // the words of the current slab plus the prefetched words of the next one.
   constexpr int RB = pow2_ceil(2 * WPL);
-  __shared__ uint16_t lut[1 << kLutBits];
+  // Blocks of 16^3 level points and more copy the code table into LDS; for
+  // smaller ones (a few symbols per lane) the copy would cost more than it
+  // saves, and the table is read through the cache.
+  constexpr bool kLdsLut = E >= 16;
+  __shared__ uint16_t lut_s[kLdsLut ? (1 << kLutBits) : 1];
+  const uint16_t* lut = kLdsLut ? lut_s : a.lut;
   __shared__ uint16_t symb[7 * S::SCP];
   __shared__ T tile[S::TILE];
   __shared__ uint32_t ring[RB * NL];
@@ -133,7 +146,9 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   __shared__ uint32_t uo0[8], uo1[8];
   __shared__ int uok[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut[i] = a.lut[i];
+  if constexpr (kLdsLut)
+    for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut_s[i] = a.lut[i];
+  if (wg == 0 && tid == 0) dec_check_body(a);  // the level's unit-index sentinels
 
   const int64_t nblk = a.bb_n[0] * a.bb_n[1] * a.bb_n[2];
   const int64_t bl = wg_block(wg, nblk, a.xcd_remap);
@@ -172,9 +187,14 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   }
   const bool lane_active = is_lane && needed && j < Mx;
   const int64_t u = blk * 7 + (c - 1);
-  uint32_t lb = 0;
+  uint32_t lb = 0, w0 = 0, w1 = 0, o0 = 0, o1 = 0;
   uint64_t pos = 0;
   if (lane_active) {
+    // the unit's index entries load alongside the lane length
+    w0 = a.unit_word[u];
+    w1 = a.unit_word[u + 1];
+    o0 = a.unit_outl[u];
+    o1 = a.unit_outl[u + 1];
     const uint64_t lane0 = uint64_t(unit_lane_off(a.g, a.logs, u));
     lb = lane0 + j < a.nlanes ? a.lane_len[lane0 + j] : 0;
   }
@@ -189,8 +209,6 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
       if (k < j) pre += v;
       tot += v;
     }
-    const uint32_t w0 = a.unit_word[u], w1 = a.unit_word[u + 1];
-    const uint32_t o0 = a.unit_outl[u], o1 = a.unit_outl[u + 1];
     const bool ok = w0 <= w1 && w1 <= a.words && o0 <= o1 && o1 <= a.noutl &&
                     (uint64_t(tot) + 31) / 32 == uint64_t(w1 - w0);
     if (j == 0) {
@@ -391,13 +409,6 @@ __global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, T*
   dec_anchor_body<T>(comp, anchor_off, g, rec0, g0, blockIdx.x, gridDim.x);
 }
 
-// Sentinel entries of a level's unit index (first offsets 0, last = totals).
-__device__ inline void dec_check_body(const DecSlabArgs& d) {
-  if (threadIdx.x == 0 && (d.unit_word[0] != 0 || d.unit_outl[0] != 0 ||
-                           d.unit_word[d.nu] != d.words || d.unit_outl[d.nu] != d.noutl))
-    atomicOr(d.flags, kFlagCorrupt);
-}
-
 // Level-k argument block of a decode, built the same way on the host (plain
 // launches) and on the device (batched launches, from the request table).
 __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
@@ -440,7 +451,6 @@ __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
   return d;
 }
 
-__global__ void k_dec_check(DecSlabArgs d) { dec_check_body(d); }
 
 template <class T, int E>
 void launch_slab(const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
@@ -491,13 +501,6 @@ __global__ void kb_dec_anchor(const DecodeArgs* R, ItemMap m) {
 
 // Per-level argument blocks of a batch are built on the host (the same
 // builder as the plain launches) and read here through restrict pointers.
-__global__ void kb_dec_check(const DecSlabArgs* __restrict__ D, ItemMap m) {
-  STZ_FOR_ITEMS(m) {
-    uint32_t loc, cnt;
-    dec_check_body(D[map_find_d(m, it_, &loc, &cnt)]);
-  }
-}
-
 template <int E, int H>
 __global__ __launch_bounds__(256) void kb_dec(const DecSlabArgs* __restrict__ D, ItemMap m) {
   STZ_FOR_ITEMS(m) {
@@ -612,9 +615,6 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
   prof_end(st);
   for (int k = 1; k <= a.level_out; ++k) {
     const DecSlabArgs d = dec_args(a, k);
-    prof_begin(st, "dec_check", k);
-    hipLaunchKernelGGL(k_dec_check, dim3(1), dim3(64), 0, st, d);
-    prof_end(st);
     const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
     const int E = g.B >> (L - k);
     prof_begin(st, d.xcd_remap ? "decode" : "rdecode", k);
@@ -667,8 +667,6 @@ hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
     }
     if (!b.n_check[k]) continue;
     const DecSlabArgs* D = reinterpret_cast<const DecSlabArgs*>(b.args) + uint64_t(k - 1) * b.nreq;
-    hipLaunchKernelGGL(kb_dec_check, dim3(grid(b.grid, b.n_check[k])), dim3(64), 0, st, D,
-                       b.check[k]);
     for (int e = 1; e < kBatchEdges; ++e) {
       if (!b.n_dec[k][e]) continue;
       const unsigned gd = grid(b.grid_dec[e], b.n_dec[k][e]);

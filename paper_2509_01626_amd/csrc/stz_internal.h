@@ -290,8 +290,7 @@ struct DecodeBatch {
   int max_level;
   ItemMap anchor;
   uint32_t n_anchor;
-  ItemMap check[kMaxLevels + 1];
-  uint32_t n_check[kMaxLevels + 1];
+  uint32_t n_check[kMaxLevels + 1];           // requests that decode level k
   ItemMap dec[kMaxLevels + 1][kBatchEdges];   // blocks of each request's box at level k
   uint32_t n_dec[kMaxLevels + 1][kBatchEdges];
 };
