@@ -477,7 +477,8 @@ stz_status params_status(const DevParams& P) {
 struct CompressPlan {
   CompressArgs a;
   uint64_t o_part = 0, o_rec[kMaxLevels] = {}, o_sym[kMaxLevels + 1] = {}, o_lane = 0,
-           o_hist = 0, o_lens = 0, o_codes = 0, o_cb = 0, o_cnt = 0, o_scan = 0, o_spart = 0;
+           o_hist = 0, o_hpart = 0, o_lens = 0, o_codes = 0, o_cb = 0, o_cnt = 0, o_scan = 0,
+           o_spart = 0;
 
   stz_status init(const void* x, int vb, const uint64_t dims[3], int eb_mode, double eb,
                   const stz_config* cfg, void* out, uint64_t out_cap) {
@@ -518,6 +519,8 @@ struct CompressPlan {
     }
     o_lane = ws.take<uint16_t>(lanes);
     o_hist = ws.take<unsigned long long>(nsym);
+    a.nslots = uint32_t(std::min<uint64_t>(kHistSlots, uint64_t(g.nb[0] * g.nb[1] * g.nb[2])));
+    o_hpart = ws.take<uint32_t>(uint64_t(nsym) * a.nslots);
     o_lens = ws.take<uint8_t>(nsym);
     o_codes = ws.take<uint16_t>(nsym);
     o_cb = ws.take<uint8_t>(codebook_scratch_bytes(nsym));
@@ -536,6 +539,7 @@ struct CompressPlan {
     for (int l = 1; l <= L; ++l) a.sym[l] = ws.at<uint16_t>(o_sym[l]);
     a.lane_len = ws.at<uint16_t>(o_lane);
     a.hist = ws.at<unsigned long long>(o_hist);
+    a.hpart = ws.at<uint32_t>(o_hpart);
     a.lens = ws.at<uint8_t>(o_lens);
     a.codes = ws.at<uint16_t>(o_codes);
     a.cb_scratch = ws.at<uint8_t>(o_cb);
@@ -662,6 +666,12 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
   }));
   b->n_anchor = maps->add(&b->anchor, per_job([](const CompressArgs& a) {
     return cap_items(a.n_anchor, 256, 4096);
+  }));
+  b->n_hzero = maps->add(&b->hzero, per_job([](const CompressArgs& a) {
+    return cap_items(uint64_t(alphabet(a.geo)) * a.nslots, 256 * 16, 1024);
+  }));
+  b->n_hred = maps->add(&b->hred, per_job([](const CompressArgs& a) {
+    return uint32_t((alphabet(a.geo) + 255) / 256);
   }));
   int maxL = 0;
   for (uint32_t k = 0; k < n; ++k) maxL = std::max(maxL, pl[live[k]].a.geo.L);

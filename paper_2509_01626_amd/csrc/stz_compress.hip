@@ -17,17 +17,50 @@ namespace {
 // Every kernel is a device body run by one work-group (`wg` of `ngrid` for
 // grid-stride bodies) plus a plain launch; the batched launches run the same
 // bodies over a work map of many jobs.
-__device__ inline void init_body(DevParams* P, unsigned long long* hist, int nsym) {
-  const int t = threadIdx.x;
-  if (t == 0) {
+__device__ inline void init_body(DevParams* P) {
+  if (threadIdx.x == 0) {
     P->flags = 0;
     P->total = 0;
   }
-  for (int i = t; i < nsym; i += blockDim.x) hist[i] = 0;
 }
 
-__global__ void k_init(DevParams* P, unsigned long long* hist, int nsym) {
-  init_body(P, hist, nsym);
+__global__ void k_init(DevParams* P) { init_body(P); }
+
+// Clear the partial histograms (n words), grid-stride.
+__device__ inline void hzero_body(uint32_t* hpart, uint64_t n, uint64_t wg, uint64_t ngrid) {
+  const uint64_t n4 = n >> 2;
+  uint4* p4 = reinterpret_cast<uint4*>(hpart);
+  for (uint64_t i = wg * blockDim.x + threadIdx.x; i < n4; i += ngrid * blockDim.x)
+    p4[i] = make_uint4(0, 0, 0, 0);
+  for (uint64_t i = (n4 << 2) + wg * blockDim.x + threadIdx.x; i < n; i += ngrid * blockDim.x)
+    hpart[i] = 0;
+}
+
+__global__ void k_hzero(uint32_t* hpart, uint64_t n) { hzero_body(hpart, n, blockIdx.x, gridDim.x); }
+
+// hist[bin] = sum over the slots; work-group `wg` covers 256 bins.
+__device__ inline void hred_body(const uint32_t* hpart, uint32_t nslots, int nsym,
+                                 unsigned long long* hist, int wg) {
+  const int bin = wg * 256 + int(threadIdx.x);
+  if (bin >= nsym) return;
+  // 32 independent loads in flight per round (the slots are few and the
+  // loads latency-bound)
+  unsigned long long v = 0;
+  uint32_t s = 0;
+  for (; s + 32 <= nslots; s += 32) {
+    uint32_t w[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) w[k] = hpart[uint64_t(s + k) * nsym + bin];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) v += w[k];
+  }
+  for (; s < nslots; ++s) v += hpart[uint64_t(s) * nsym + bin];
+  hist[bin] = v;
+}
+
+__global__ __launch_bounds__(256) void k_hred(const uint32_t* hpart, uint32_t nslots, int nsym,
+                                              unsigned long long* hist) {
+  hred_body(hpart, nslots, nsym, hist, blockIdx.x);
 }
 
 template <class T>
@@ -195,7 +228,8 @@ struct PredSlabArgs {
   void* cur;         // level-l grid; null at the finest level
   uint16_t* sym;
   DevParams* P;
-  unsigned long long* hist;
+  uint32_t* hpart;   // [nsym][nslots] partial histograms
+  uint32_t nslots;
   int nsym;
 };
 
@@ -239,13 +273,13 @@ __device__ inline void pred_point(const PredRows<T>& c, int lz, int ly, int lx, 
 }
 
 // This wave's rows of parity type (ZP, YP); classes fixed at compile time.
-template <class T, int E, int H, int ZP, int YP, bool INT>
+template <class T, int E, int H, int NW, int ZP, int YP, bool INT>
 __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave, int lane,
                                  uint32_t* n_center, bool* bad) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
-  for_type_rows<E, ZP, YP>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
+  for_type_rows<E, ZP, YP, NW>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
     T* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
     const T* xrow =
         c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);
@@ -263,10 +297,12 @@ __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave,
 // Predict and quantize every level-l point of one block (format 2.2, 2.3);
 // also writes the block's part of the level-l grid (coarse points copied,
 // level points reconstructed) for the next level's prediction.
-template <class T, int E, int H>
+// NT = threads of the work-group (256, or 64 for small blocks).
+template <class T, int E, int H, int NT = 256>
 __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_remap) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
+  constexpr int NW = NT / 64;
   __shared__ uint32_t h[kMaxAlphabet];
   __shared__ T tile[S::TILE];
   __shared__ uint16_t ssym[7 * S::SCP];  // slab symbols, [class][v_z][v_y][v_x] (padded)
@@ -329,15 +365,15 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     ctx.chk = chk;
     ctx.R = R;
     if (interior) {
-      pred_type<T, E, H, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     } else {
-      pred_type<T, E, H, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
     }
     __syncthreads();
     const int a0 = z0 >> 1;
@@ -398,13 +434,19 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   if (n_zero) atomicAdd(&h[a.g.Z], n_zero);
   __syncthreads();
   if (bad) atomicOr(&a.P->flags, kFlagNonfinite);
+  const uint64_t slot = uint64_t(wg) % a.nslots;
   for (int i = tid; i < a.nsym; i += blockDim.x)
-    if (h[i]) atomicAdd(&a.hist[i], (unsigned long long)h[i]);
+    if (h[i]) atomicAdd(&a.hpart[slot * uint64_t(a.nsym) + i], h[i]);
 }
 
+// Threads per work-group of the plain launches: blocks of at most 4^3 level
+// points take one wave, so that four times as many fit on a CU (8^3 blocks
+// are faster with four waves sharing the block's points).
+constexpr int pred_threads(int E) { return E <= 4 ? 64 : 256; }
+
 template <class T, int E>
-__global__ __launch_bounds__(256) void k_pred_slab(PredSlabArgs a) {
-  pred_body<T, E, default_slab_h(E)>(a, blockIdx.x, true);
+__global__ __launch_bounds__(pred_threads(E)) void k_pred_slab(PredSlabArgs a) {
+  pred_body<T, E, default_slab_h(E), pred_threads(E)>(a, blockIdx.x, true);
 }
 
 struct LaneLenArgs {
@@ -1152,7 +1194,8 @@ __host__ __device__ inline PredSlabArgs pred_args(const CompressArgs& a, int l) 
   p.cur = l < g.L ? a.rec[l] : nullptr;
   p.sym = a.sym[l];
   p.P = a.params;
-  p.hist = a.hist;
+  p.hpart = a.hpart;
+  p.nslots = a.nslots;
   p.nsym = alphabet(g);
   return p;
 }
@@ -1245,7 +1288,23 @@ __global__ void kb_init(const CompressArgs* J, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
-    init_body(a.params, a.hist, alphabet(a.geo));
+    init_body(a.params);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_hzero(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    hzero_body(a.hpart, uint64_t(alphabet(a.geo)) * a.nslots, loc, cnt);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_hred(const CompressArgs* J, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const CompressArgs& a = J[map_find(m, it_, &loc, &cnt)];
+    hred_body(a.hpart, a.nslots, alphabet(a.geo), a.hist, int(loc));
   }
 }
 
@@ -1359,7 +1418,7 @@ __global__ __launch_bounds__(256) void kb_pack(const PackArgs* __restrict__ Q, I
 
 template <class T, int E>
 void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_pred_slab<T, E>), dim3(unsigned(nblk)), dim3(256), 0, st, p);
+  hipLaunchKernelGGL((k_pred_slab<T, E>), dim3(unsigned(nblk)), dim3(pred_threads(E)), 0, st, p);
 }
 
 template <int E, int H>
@@ -1434,7 +1493,9 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
   const uint64_t nu = a.lc[1].nu;
   prof_begin(st, "init", -1);
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, a.params, a.hist, nsym);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, a.params);
+  const uint64_t nh = uint64_t(nsym) * a.nslots;
+  hipLaunchKernelGGL(k_hzero, dim3(grid_for(nh, 256 * 16, 1024)), dim3(256), 0, st, a.hpart, nh);
   prof_end(st);
   if (a.eb_mode == 1) {
     prof_begin(st, "minmax", -1);
@@ -1465,6 +1526,10 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
     }
     prof_end(st);
   }
+  prof_begin(st, "hist", -1);
+  hipLaunchKernelGGL(k_hred, dim3((nsym + 255) / 256), dim3(256), 0, st, a.hpart, a.nslots, nsym,
+                     a.hist);
+  prof_end(st);
   launch_codebook(a.hist, nsym, a.lens, a.codes, a.cb_scratch, st);
   for (int l = 1; l <= L; ++l) {
     prof_begin(st, "lanelen", l);
@@ -1559,6 +1624,7 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
   };
   prof_begin(st, "b_init", -1);
   hipLaunchKernelGGL(kb_init, grid(b.jobs1, b.n_jobs1), dim3(256), 0, st, b.J, b.jobs1);
+  hipLaunchKernelGGL(kb_hzero, grid(b.hzero, b.n_hzero), dim3(256), 0, st, b.J, b.hzero);
   prof_end(st);
   if (b.n_minmax) {
     prof_begin(st, "b_minmax", -1);
@@ -1591,6 +1657,9 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
       prof_end(st);
     }
   }
+  prof_begin(st, "b_hist", -1);
+  hipLaunchKernelGGL(kb_hred, grid(b.hred, b.n_hred), dim3(256), 0, st, b.J, b.hred);
+  prof_end(st);
   launch_codebook_batch(b.J, b.njobs, st);
   for (int l = 1; l <= b.max_levels; ++l) {
     prof_begin(st, "b_lanelen", l);

@@ -102,12 +102,12 @@ __device__ inline T dec_point(const DecRows<T>& x, int lz, int ly, int lx, int s
 
 // Reconstruct this wave's rows of parity type (ZP, YP): classes 4ZP+2YP (even
 // x) and 4ZP+2YP+1 (odd x), both fixed at compile time.
-template <class T, int E, int H, int ZP, int YP, bool INT>
+template <class T, int E, int H, int NW, int ZP, int YP, bool INT>
 __device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, int lane) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
-  for_type_rows<E, ZP, YP>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
+  for_type_rows<E, ZP, YP, NW>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
     if (lz < x.rz0 || lz >= x.rz1 || ly < x.ry0 || ly >= x.ry1) return;
     T* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + ly - x.of[1])) * x.oc[2] +
                   (x.ox - x.of[2]);
@@ -122,11 +122,14 @@ __device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, i
   });
 }
 
-template <class T, int E, int H>
+// NT = threads of the work-group (256, or 64 for small blocks).
+template <class T, int E, int H, int NT = 256>
 __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
+  constexpr int NW = NT / 64;
   constexpr int NL = 7 * m;  // decoding lanes: one per (class, x column)
+  static_assert(NL <= NT, "a work-group holds every decoding lane");
   // Stream words a lane can touch while decoding one slab: at most HZ*m codes
   // of <= kLmax bits, plus the bit window's lookahead (< 2 words).
   constexpr int WPL = (S::HZ * m * kLmax + 31) / 32 + 2;
@@ -259,8 +262,8 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     const int a0 = z0 >> 1;
     // ---- coarse tile of the slab (global loads in flight during decoding) ----
     const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;  // level coords, even
-    TileRegs<S, T> tr;
-    tile_fetch<S, T>(tr, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1,
+    TileRegs<S, T, NT> tr;
+    tile_fetch<S, T, NT>(tr, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, tz0 >> 1, ty0 >> 1,
                      tx0 >> 1);
     // ---- decode this slab's rows into LDS -----------------------------------
     if (lane_active) {
@@ -323,7 +326,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
 #pragma unroll
       for (int k = 0; k < WPL; ++k) ring[((rb + WPL + k) & (RB - 1)) * NL + tid] = pf[k];
     }
-    tile_store<S, T>(tile, tr);
+    tile_store<S, T, NT>(tile, tr);
     __syncthreads();
     // ---- reconstruct the slab ------------------------------------------------------
     const int hs = min(S::H, Ez - z0);
@@ -358,15 +361,15 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
       ctx.E2 = a.E2d;
     ctx.R = a.g.R;
     if (interior) {
-      dec_type<T, E, H, 0, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, 0, 1, true>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, 1, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, 1, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 0, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 1, true>(ctx, hs, Ey, wave, lane);
     } else {
-      dec_type<T, E, H, 0, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, 0, 1, false>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, 1, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, 1, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 0, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 1, false>(ctx, hs, Ey, wave, lane);
     }
     __syncthreads();
   }
@@ -380,11 +383,15 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
 // Waves per SIMD the decoder is compiled for: 5 for 32^3-point blocks (96
 // VGPRs; the decode chains are latency-bound, so occupancy pays).
 constexpr int dec_waves(int E) { return E == 32 ? 5 : 1; }
+// Threads per work-group of the plain launches: blocks of at most 8^3 level
+// points (at most 28 decoding lanes, a few hundred points) take one wave, so
+// four times as many blocks fit on a CU; their latency chains overlap.
+constexpr int slab_threads(int E) { return E <= 8 ? 64 : 256; }
 
 template <class T, int E>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dec_waves(E))))
+__global__ __launch_bounds__(slab_threads(E)) __attribute__((amdgpu_waves_per_eu(dec_waves(E))))
 void k_dec_slab(DecSlabArgs a) {
-  dec_body<T, E, dec_slab_h(E)>(a, blockIdx.x);
+  dec_body<T, E, dec_slab_h(E), slab_threads(E)>(a, blockIdx.x);
 }
 
 // Anchors of the box R_0 from the stream into the level-0 box grid.
@@ -454,7 +461,7 @@ __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
 
 template <class T, int E>
 void launch_slab(const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_dec_slab<T, E>), dim3(unsigned(nblk)), dim3(256), 0, st, d);
+  hipLaunchKernelGGL((k_dec_slab<T, E>), dim3(unsigned(nblk)), dim3(slab_threads(E)), 0, st, d);
 }
 
 // Plain launch of one level of a decode, by level block edge.

@@ -174,7 +174,9 @@ struct CompressArgs {
   void* rec[kMaxLevels];   // compact grids of levels 0..L-1 (value type)
   uint16_t* sym[kMaxLevels + 1];
   LevelConst lc[kMaxLevels + 1];
-  unsigned long long* hist;   // 2R counters
+  unsigned long long* hist;   // token counts (alphabet entries)
+  uint32_t* hpart;            // [nslots][alphabet] partial counts of the predictor
+  uint32_t nslots;            // histogram slots: min(blocks, kHistSlots)
   uint8_t* lens;              // 2R
   uint16_t* codes;            // 2R
   void* cb_scratch;           // codebook_scratch_bytes(2R)
@@ -199,6 +201,13 @@ struct ItemMap {
 
 constexpr int kBatchEdges = 7;  // level block edge E = 2^e, e = 1..6
 
+// The predictor's work-groups add their block histograms into one of
+// kHistSlots partial histograms (chosen by work-group index, so concurrent
+// work-groups rarely meet on an address; a slot's bins are contiguous); a
+// reduction sums the slots. A slot holds at most 2^40 / 128 counts, within
+// 32 bits.
+constexpr uint32_t kHistSlots = 128;
+
 // One batched compression: the job table (device) and the work map of every
 // launch; n_* are the item totals (host copies of first[n]).
 struct CompressBatch {
@@ -208,8 +217,8 @@ struct CompressBatch {
   unsigned grid;                               // persistent work-groups per launch
   unsigned grid_pred[kBatchEdges];             // per level block edge
   int max_levels;
-  ItemMap jobs1, minmax, anchor, scan_ac, scan_b, zero, head;
-  uint32_t n_jobs1, n_minmax, n_anchor, n_scan_ac, n_scan_b, n_zero, n_head;
+  ItemMap jobs1, minmax, anchor, scan_ac, scan_b, zero, head, hzero, hred;
+  uint32_t n_jobs1, n_minmax, n_anchor, n_scan_ac, n_scan_b, n_zero, n_head, n_hzero, n_hred;
   ItemMap pred[kMaxLevels + 1][kBatchEdges];   // blocks of level l with edge 2^e
   uint32_t n_pred[kMaxLevels + 1][kBatchEdges];
   ItemMap level[kMaxLevels + 1];               // blocks of every job with L >= l

@@ -66,24 +66,24 @@ __device__ inline void load_tile(V* tile, const V* __restrict__ src, const int64
 }
 
 // The same tile in two halves: fetch this thread's share of the tile into
-// registers (256 threads), then store it, so that other work can run while
+// registers (NT threads), then store it, so that other work can run while
 // the loads are in flight.
-template <class S, class V>
+template <class S, class V, int NT = 256>
 struct TileRegs {
   static constexpr int N = S::TZ * S::T * S::T;
-  static constexpr int K = (N + 255) / 256;
+  static constexpr int K = (N + NT - 1) / NT;
   V v[K];
 };
 
-template <class S, class V>
-__device__ inline void tile_fetch(TileRegs<S, V>& r, const V* __restrict__ src,
+template <class S, class V, int NT = 256>
+__device__ inline void tile_fetch(TileRegs<S, V, NT>& r, const V* __restrict__ src,
                                   const int64_t sf[3], const int64_t sc[3], int64_t cz0,
                                   int64_t cy0, int64_t cx0) {
 #pragma unroll
-  for (int k = 0; k < TileRegs<S, V>::K; ++k) {
-    const int i = threadIdx.x + 256 * k;
+  for (int k = 0; k < TileRegs<S, V, NT>::K; ++k) {
+    const int i = threadIdx.x + NT * k;
     V v = V(0);
-    if (i < TileRegs<S, V>::N) {
+    if (i < TileRegs<S, V, NT>::N) {
       const int tx = i % S::T, t = i / S::T, ty = t % S::T, tz = t / S::T;
       const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
       if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
@@ -93,12 +93,12 @@ __device__ inline void tile_fetch(TileRegs<S, V>& r, const V* __restrict__ src,
   }
 }
 
-template <class S, class V>
-__device__ inline void tile_store(V* tile, const TileRegs<S, V>& r) {
+template <class S, class V, int NT = 256>
+__device__ inline void tile_store(V* tile, const TileRegs<S, V, NT>& r) {
 #pragma unroll
-  for (int k = 0; k < TileRegs<S, V>::K; ++k) {
-    const int i = threadIdx.x + 256 * k;
-    if (i < TileRegs<S, V>::N) tile[(i / S::T) * S::TP + i % S::T] = r.v[k];
+  for (int k = 0; k < TileRegs<S, V, NT>::K; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < TileRegs<S, V, NT>::N) tile[(i / S::T) * S::TP + i % S::T] = r.v[k];
   }
 }
 
@@ -255,16 +255,17 @@ namespace dev {
 namespace {
 
 // Rows of parity type (ZP, YP) in the slab [z0, z0 + hs) assigned to this
-// wave: calls f(lz, ly, q) for the thread's (even, odd) x pair q of each row.
-// Every type has the same number of rows, so the four waves stay balanced.
-template <int E, int ZP, int YP, class F>
+// wave (of NW): calls f(lz, ly, q) for the thread's (even, odd) x pair q of
+// each row. Every type has the same number of rows, so the waves stay
+// balanced.
+template <int E, int ZP, int YP, int NW, class F>
 __device__ inline void for_type_rows(int z0, int hs, int Ey, int wave, int lane, F f) {
   using S = SlabShape<E>;
   const int nz = (hs - ZP + 1) >> 1;  // planes of parity ZP in the slab
   const int ntask = nz * S::G;
   const int r = lane / S::P, q = lane % S::P;
   if (r >= S::RW) return;
-  for (int t = wave; t < ntask; t += 4) {
+  for (int t = wave; t < ntask; t += NW) {
     const int iz = t / S::G, g = t - iz * S::G;
     const int lz = z0 + ZP + 2 * iz;
     const int ly = YP + 2 * (g * S::RW + r);
