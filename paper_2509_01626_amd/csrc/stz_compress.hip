@@ -932,6 +932,7 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
 constexpr int kPackChunk = 4096;                     // symbols per chunk
 constexpr int kPackPer = kPackChunk / 256;           // per thread
 constexpr int kPackWords = kPackChunk * kLmax / 32 + 2;
+constexpr int kPackRows = 32 * 32;  // rows (M_z * M_y) of a unit, E <= 64
 
 // 32-bit exclusive scan over the work-group (256 threads).
 __device__ inline uint32_t block_excl_scan32(uint32_t v, uint32_t* total) {
@@ -961,6 +962,7 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   __shared__ uint16_t us[kPackChunk];
   __shared__ uint32_t zf[kPackChunk / 32];  // zero-chunk flags of the buffer (bits)
   __shared__ uint32_t wb[kPackWords];
+  __shared__ uint32_t rmask[kPackRows];  // per unit row: columns holding an outlier
   __shared__ uint32_t u_rows[8], u_mx[8], u_my[8];
   __shared__ uint64_t u_src[8];
   const int tid = threadIdx.x;
@@ -1017,6 +1019,12 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
     // run and its pair's), 3 = other M_y (edge blocks): flags in LDS.
     const int zmode = !zc ? 0
                       : ((kPackPer % My) == 0 ? 1 : (My == 2 * kPackPer ? 2 : 3));
+    // Outliers: while the symbols pass through LDS, each outlier sets its
+    // column's bit in its row's mask; ranks (row-major) come from the masks.
+    const uint32_t uo = a.scan_outl[u], n_out = a.scan_outl[u + 1] - uo;
+    const uint32_t Mx = u_mx[c];
+    if (n_out)
+      for (uint32_t i = tid; i < rows; i += 256) rmask[i] = 0;
     for (uint32_t c0 = 0; c0 < n_u; c0 += bstep) {
       const int n = int(min<uint32_t>(bstep, n_u - c0));
       for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
@@ -1045,6 +1053,12 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
         lc[k] = ok ? LC[sy] : 0u;
         rm |= uint32_t(ok && sy == uint32_t(a.g.R)) << k;
       }
+      if (n_out)  // symbol p of the unit: column p / rows, row p % rows
+        for (int i = tid; i < n; i += 256)
+          if (us[i] == 0) {
+            const uint32_t p = c0 + uint32_t(i), jj = p / rows;
+            atomicOr(&rmask[p - jj * rows], 1u << jj);
+          }
       if (zmode == 1) {
         // bit k of f: symbols k..k+M_y-1 all R (M_y a power of two)
         uint32_t f = rm;
@@ -1122,32 +1136,33 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       __syncthreads();
     }
     if (sk && tid == 0) dst[wdone] = carry;
-    // outliers in rank order (row-major: row t, then column j)
-    const uint32_t uo = a.scan_outl[u], n_out = a.scan_outl[u + 1] - uo;
+    // outliers in rank order (row-major: row t, then column j): thread tid
+    // owns rows [tid*rpt, (tid+1)*rpt); a block scan of its outlier count
+    // gives the rank of its first one
     if (n_out) {
       const UnitGeo ug = unit_geo(a.g, u, a.logs);
-      const uint32_t Mx = u_mx[c], M1 = u_my[c];
-      uint32_t run = 0;
-      for (uint32_t r0 = 0; r0 < n_u; r0 += 256) {
-        const uint32_t r = r0 + tid;
-        bool isz = false;
-        uint32_t t = 0, j = 0;
-        if (r < n_u) {
-          t = r / Mx;
-          j = r - t * Mx;
-          isz = src[uint64_t(j) * rows + t] == 0;
+      const uint32_t M1 = u_my[c];
+      const uint32_t rpt = (rows + 255) / 256, t0 = tid * rpt;
+      uint32_t cnt = 0;
+      for (uint32_t t = t0; t < t0 + rpt && t < rows; ++t) cnt += __popc(rmask[t]);
+      uint32_t tot;
+      uint32_t rank = block_excl_scan32(cnt, &tot);
+      for (uint32_t t = t0; t < t0 + rpt && t < rows; ++t) {
+        uint32_t mk = rmask[t];
+        while (mk) {
+          const uint32_t jj = __ffs(mk) - 1;
+          mk &= mk - 1;
+          if (rank < n_out && jj < Mx) {
+            const uint32_t vy = t % M1, vz = t / M1;
+            const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
+            const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
+            const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * jj + ug.o[2]) << a.logs);
+            put_outlier(outv, a.vb, uo + rank, a.x, (pz * a.g.n[1] + py) * a.g.n[2] + px);
+          }
+          ++rank;
         }
-        uint32_t cnt;
-        const uint32_t rank = run + block_excl_scan32(isz ? 1u : 0u, &cnt);
-        if (isz && rank < n_out) {
-          const uint32_t vy = t % M1, vz = t / M1;
-          const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
-          const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
-          const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * j + ug.o[2]) << a.logs);
-          put_outlier(outv, a.vb, uo + rank, a.x, (pz * a.g.n[1] + py) * a.g.n[2] + px);
-        }
-        run += cnt;
       }
+      __syncthreads();  // the masks are cleared for the next unit
     }
   }
 }
