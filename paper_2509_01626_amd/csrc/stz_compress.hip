@@ -439,6 +439,10 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     if (h[i]) atomicAdd(&a.hpart[slot * uint64_t(a.nsym) + i], h[i]);
 }
 
+// Slab height of the plain predictor launches: 4 planes for 32^3-point blocks
+// (24 KB of LDS, six work-groups per CU against four with 8 planes).
+constexpr int pred_slab_h(int E) { return E == 32 ? 4 : default_slab_h(E); }
+
 // Threads per work-group of the plain launches: blocks of at most 4^3 level
 // points take one wave, so that four times as many fit on a CU (8^3 blocks
 // are faster with four waves sharing the block's points).
@@ -446,7 +450,7 @@ constexpr int pred_threads(int E) { return E <= 4 ? 64 : 256; }
 
 template <class T, int E>
 __global__ __launch_bounds__(pred_threads(E)) void k_pred_slab(PredSlabArgs a) {
-  pred_body<T, E, default_slab_h(E), pred_threads(E)>(a, blockIdx.x, true);
+  pred_body<T, E, pred_slab_h(E), pred_threads(E)>(a, blockIdx.x, true);
 }
 
 struct LaneLenArgs {
