@@ -688,6 +688,15 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
       const Geo& g = a.geo;
       return g.L < l ? 0u : uint32_t(g.nb[0] * g.nb[1] * g.nb[2]);
     }));
+    for (int units = 0; units < 2; ++units) {
+      ItemMap* m = units ? &b->pack_u[l] : &b->pack_l[l];
+      uint32_t* n = units ? &b->n_pack_u[l] : &b->n_pack_l[l];
+      *n = maps->add(m, per_job([&](const CompressArgs& a) {
+        const Geo& g = a.geo;
+        if (g.L < l || ((g.B >> (g.L - l)) >= 32) != (units == 1)) return 0u;
+        return uint32_t(g.nb[0] * g.nb[1] * g.nb[2]);
+      }));
+    }
   }
   b->n_scan_ac = maps->add(&b->scan_ac, per_job([](const CompressArgs& a) {
     return uint32_t((a.lc[1].nu + 2047) / 2048) * uint32_t(2 * a.geo.L);

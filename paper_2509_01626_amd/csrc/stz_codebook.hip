@@ -16,9 +16,12 @@ namespace {
 
 constexpr int kCbThreads = 1024;
 constexpr int kCbMax = 4096;            // power of two >= the largest alphabet
+constexpr int kCbNodes = 2 * kMaxAlphabet;  // >= max(kCbMax, 2 * alphabet - 1)
+constexpr int kCbPer = (kCbNodes + kCbThreads - 1) / kCbThreads;
 constexpr int kSymBits = 12;            // symbol field of the sort keys
 constexpr uint64_t kSymMask = (uint64_t(1) << kSymBits) - 1;
 static_assert(kMaxAlphabet <= kCbMax && kCbMax <= (1 << kSymBits), "alphabet too large");
+static_assert(kCbNodes >= kCbMax && kCbNodes >= 2 * kMaxAlphabet - 1, "node arrays too small");
 constexpr int kCbScales = 42;           // k = 0..41
 constexpr uint64_t kInf = ~uint64_t(0);
 
@@ -47,9 +50,11 @@ __device__ void bitonic_sort(uint64_t* key, int n) {
 // creation order; depths by pointer jumping.
 __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, uint8_t* lens_k,
                                      int* maxlen_k, int k) {
-  __shared__ uint64_t W[2 * kCbMax];
-  __shared__ uint16_t par[2 * kCbMax];
-  __shared__ uint16_t dep[2 * kCbMax];
+  // nodes: the sorted leaves (padded to a power of two while sorting) and then
+  // the m - 1 merged nodes: at most kCbNodes entries
+  __shared__ uint64_t W[kCbNodes];
+  __shared__ uint16_t par[kCbNodes];
+  __shared__ uint16_t dep[kCbNodes];
   __shared__ uint16_t leaf[kCbMax];
   __shared__ int s_m, s_max;
   const int t = threadIdx.x;
@@ -133,7 +138,7 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   for (int i = t; i < nn; i += blockDim.x) dep[i] = (i == nn - 1) ? 0 : 1;
   __syncthreads();
   for (int round = 0; (1 << round) < nn; ++round) {
-    uint16_t nd[2 * kCbMax / kCbThreads], np[2 * kCbMax / kCbThreads];
+    uint16_t nd[kCbPer], np[kCbPer];
     int j = 0;
     for (int i = t; i < nn; i += blockDim.x, ++j) {
       const int p = par[i];
@@ -231,14 +236,23 @@ __host__ __device__ inline int* cb_maxlen_k(void* scratch, int nsym) {
                                 ((size_t(kCbScales) * nsym + 15) & ~size_t(15)));
 }
 
-// Batched code books, one job per blockIdx.y. Scale k0 + blockIdx.x; scales
-// above 0 are skipped when scale 0 already fits (the common case), so a batch
-// pays for one tree per field unless a field needs the length limit.
+// Batched code books, one job per blockIdx.y, scale k0 + blockIdx.x. The
+// scales run in three launches: 0; 1..7 unless 0 fits; 8..41 unless one of
+// 0..7 fits. A field pays for one tree unless it needs the length limit,
+// and then rarely for more than eight. (Scales a launch skips keep stale
+// longest-code entries, which the final pick never reaches: it stops at the
+// first scale that fits.)
+constexpr int kCbFirst = 8;
 __global__ __launch_bounds__(kCbThreads) void kb_cb_build(const CompressArgs* J, int k0) {
   const CompressArgs& a = J[blockIdx.y];
   const int nsym = alphabet(a.geo);
   int* mk = cb_maxlen_k(a.cb_scratch, nsym);
-  if (k0 > 0 && mk[0] <= kLmax) return;
+  if (k0 > 0) {
+    bool fits = mk[0] <= kLmax;
+    if (k0 >= kCbFirst)
+      for (int k = 1; k < kCbFirst; ++k) fits = fits || mk[k] <= kLmax;
+    if (fits) return;
+  }
   cb_build_body(a.hist, nsym, cb_lens_k(a.cb_scratch), mk, k0 + int(blockIdx.x));
 }
 
@@ -269,7 +283,9 @@ void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, ui
 void launch_codebook_batch(const CompressArgs* J, uint32_t njobs, hipStream_t st) {
   prof_begin(st, "b_cb_build", -1);
   hipLaunchKernelGGL(kb_cb_build, dim3(1, njobs), dim3(kCbThreads), 0, st, J, 0);
-  hipLaunchKernelGGL(kb_cb_build, dim3(kCbScales - 1, njobs), dim3(kCbThreads), 0, st, J, 1);
+  hipLaunchKernelGGL(kb_cb_build, dim3(kCbFirst - 1, njobs), dim3(kCbThreads), 0, st, J, 1);
+  hipLaunchKernelGGL(kb_cb_build, dim3(kCbScales - kCbFirst, njobs), dim3(kCbThreads), 0, st, J,
+                     kCbFirst);
   prof_end(st);
   prof_begin(st, "b_cb_final", -1);
   hipLaunchKernelGGL(kb_cb_final, dim3(njobs), dim3(kCbThreads), 0, st, J);

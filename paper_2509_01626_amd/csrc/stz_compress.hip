@@ -1171,14 +1171,6 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   }
 }
 
-// Units of 16^3 symbols and more take the chunked encoder, smaller ones the
-// lane encoder (both write the same bytes).
-__device__ inline void pack_body(const PackArgs& a, int64_t wg) {
-  if ((a.g.B >> a.logs) >= 32)
-    pack_units_body(a, wg);
-  else
-    pack_lanes_body(a, wg);
-}
 
 // Plain launches take the packer of their block edge: separate kernels keep
 // each one's LDS to its own buffers.
@@ -1428,10 +1420,21 @@ __global__ void kb_fill_head(const CompressArgs* J, ItemMap m) {
   }
 }
 
-__global__ __launch_bounds__(256) void kb_pack(const PackArgs* __restrict__ Q, ItemMap m) {
+// Batched packers, one per packer kind (separate kernels keep each one's LDS
+// and registers to its own): the work maps hold jobs whose level edge is
+// >= 32 (units) or < 32 (lanes).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void kb_pack_units(
+    const PackArgs* __restrict__ Q, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
-    pack_body(Q[map_find(m, it_, &loc, &cnt)], loc);
+    pack_units_body(Q[map_find(m, it_, &loc, &cnt)], loc);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_pack_lanes(const PackArgs* __restrict__ Q, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    pack_lanes_body(Q[map_find(m, it_, &loc, &cnt)], loc);
   }
 }
 
@@ -1700,10 +1703,14 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
   prof_end(st);
   for (int l = 1; l <= b.max_levels; ++l) {
     prof_begin(st, "b_pack", l);
-    hipLaunchKernelGGL(kb_pack, grid(b.level[l], b.n_level[l]), dim3(256), 0, st,
-                       reinterpret_cast<const PackArgs*>(b.args + lay.pack) +
-                           uint64_t(l - 1) * b.njobs,
-                       b.level[l]);
+    const PackArgs* K = reinterpret_cast<const PackArgs*>(b.args + lay.pack) +
+                        uint64_t(l - 1) * b.njobs;
+    if (b.n_pack_u[l])
+      hipLaunchKernelGGL(kb_pack_units, grid(b.pack_u[l], b.n_pack_u[l]), dim3(256), 0, st, K,
+                         b.pack_u[l]);
+    if (b.n_pack_l[l])
+      hipLaunchKernelGGL(kb_pack_lanes, grid(b.pack_l[l], b.n_pack_l[l]), dim3(256), 0, st, K,
+                         b.pack_l[l]);
     prof_end(st);
   }
   return hipGetLastError();

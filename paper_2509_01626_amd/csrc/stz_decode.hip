@@ -509,7 +509,9 @@ __global__ void kb_dec_anchor(const DecodeArgs* R, ItemMap m) {
 // Per-level argument blocks of a batch are built on the host (the same
 // builder as the plain launches) and read here through restrict pointers.
 template <int E, int H>
-__global__ __launch_bounds__(256) void kb_dec(const DecSlabArgs* __restrict__ D, ItemMap m) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(H == dec_slab_h(E) ? dec_waves(E) : 1)))
+void kb_dec(const DecSlabArgs* __restrict__ D, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const DecSlabArgs d = uniform_load(D + map_find_d(m, it_, &loc, &cnt));

@@ -223,6 +223,8 @@ struct CompressBatch {
   uint32_t n_pred[kMaxLevels + 1][kBatchEdges];
   ItemMap level[kMaxLevels + 1];               // blocks of every job with L >= l
   uint32_t n_level[kMaxLevels + 1];
+  ItemMap pack_u[kMaxLevels + 1], pack_l[kMaxLevels + 1];  // the same, by packer:
+  uint32_t n_pack_u[kMaxLevels + 1], n_pack_l[kMaxLevels + 1];  // level edge >= 32 / < 32
   int pred_h[kBatchEdges];                     // predictor slab height per edge
 };
 
