@@ -45,6 +45,87 @@ __device__ void bitonic_sort(uint64_t* key, int n) {
   __syncthreads();
 }
 
+// Two-queue merge (leaves W[0..m) ascending; merged nodes appended from W[m]
+// in creation order; ties go to the leaf queue): parent of every node into
+// par, node ids = positions. Run by one thread. 64-bit weights, with a
+// two-deep register lookahead on both queues.
+__device__ inline void merge64(uint64_t* W, int m, uint16_t* par) {
+  // leaves are W[li..m), merged nodes W[ii..next)
+  int li = 0, ii = m, next = m;
+  uint64_t l0 = W[0], l1 = W[1], i0 = kInf, i1 = kInf;
+  for (int it = 0; it < m - 1; ++it) {
+    int a, b;
+    uint64_t wa, wb;
+    if (li < m && (ii == next || l0 <= i0)) {
+      a = li;
+      wa = l0;
+      ++li;
+      l0 = l1;
+      l1 = li + 1 < m ? W[li + 1] : kInf;
+    } else {
+      a = ii;
+      wa = i0;
+      ++ii;
+      i0 = i1;
+      i1 = ii + 1 < next ? W[ii + 1] : kInf;
+    }
+    if (li < m && (ii == next || l0 <= i0)) {
+      b = li;
+      wb = l0;
+      ++li;
+      l0 = l1;
+      l1 = li + 1 < m ? W[li + 1] : kInf;
+    } else {
+      b = ii;
+      wb = i0;
+      ++ii;
+      i0 = i1;
+      i1 = ii + 1 < next ? W[ii + 1] : kInf;
+    }
+    const uint64_t nw = wa + wb;
+    W[next] = nw;
+    par[a] = uint16_t(next);
+    par[b] = uint16_t(next);
+    if (ii == next)
+      i0 = nw;
+    else if (ii + 1 == next)
+      i1 = nw;
+    ++next;
+  }
+  par[2 * m - 2] = uint16_t(2 * m - 2);
+  }
+
+// The same merge with 32-bit weights (the total weight is below 2^32 - 1, so
+// ~0 marks an empty queue slot): each step takes the two lightest of the next
+// two leaves l0 <= l1 and the next two merged nodes i0 <= i1 (two leaves when
+// l1 <= i0, two merged nodes when i1 < l0, else one of each). Layout in W:
+// leaves [0, m), two ~0 pads, merged nodes from m + 2 (node k at Wi[k]) with
+// ~0 in the m + 1 slots before the merge, so every load is unconditional.
+__device__ inline void merge32(uint32_t* W, int m, uint16_t* par) {
+  const uint32_t* Wl = W;
+  uint32_t* Wi = W + m + 2;
+  int li = 0, ii = 0;
+  uint32_t l0 = Wl[0], l1 = Wl[1], i0 = ~0u, i1 = ~0u;
+  for (int ni = 0; ni < m - 1; ++ni) {
+    const bool LL = l1 <= i0;
+    const bool II = !LL && i1 < l0;
+    const int ida = II ? m + ii : li;
+    const int idb = LL ? li + 1 : m + ii + (II ? 1 : 0);
+    const uint32_t wsum = LL ? l0 + l1 : (II ? i0 + i1 : l0 + i0);
+    const int dl = LL ? 2 : (II ? 0 : 1);
+    Wi[ni] = wsum;
+    par[ida] = uint16_t(m + ni);
+    par[idb] = uint16_t(m + ni);
+    li += dl;
+    ii += 2 - dl;
+    l0 = Wl[li];
+    l1 = Wl[li + 1];
+    i0 = Wi[ii];
+    i1 = Wi[ii + 1];
+  }
+  par[2 * m - 2] = uint16_t(2 * m - 2);
+}
+
 // Code lengths for counts ceil(hist / 2^k), k = blockIdx.x: two queues over the
 // leaves sorted by (count, symbol), ties to the leaf queue, merged nodes in
 // creation order; depths by pointer jumping.
@@ -57,6 +138,7 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   __shared__ uint16_t dep[kCbNodes];
   __shared__ uint16_t leaf[kCbMax];
   __shared__ int s_m, s_max;
+  __shared__ unsigned long long s_tot;
   const int t = threadIdx.x;
   uint8_t* lens = lens_k + size_t(k) * nsym;
   if (t == 0) {
@@ -82,56 +164,31 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
     if (t == 0) maxlen_k[k] = m;
     return;
   }
+  unsigned long long tot = 0;  // total weight (the root's)
   for (int i = t; i < m; i += blockDim.x) {
     leaf[i] = uint16_t(W[i] & kSymMask);
     W[i] = W[i] >> kSymBits;
+    tot += W[i];
   }
+  if (t == 0) s_tot = 0;
   __syncthreads();
-  if (t == 0) {
-    // Two-queue merge with a two-deep register lookahead on both queues:
-    // leaves are W[li..m), merged nodes W[ii..next).
-    int li = 0, ii = m, next = m;
-    uint64_t l0 = W[0], l1 = W[1], i0 = kInf, i1 = kInf;
-    for (int it = 0; it < m - 1; ++it) {
-      int a, b;
-      uint64_t wa, wb;
-      if (li < m && (ii == next || l0 <= i0)) {
-        a = li;
-        wa = l0;
-        ++li;
-        l0 = l1;
-        l1 = li + 1 < m ? W[li + 1] : kInf;
-      } else {
-        a = ii;
-        wa = i0;
-        ++ii;
-        i0 = i1;
-        i1 = ii + 1 < next ? W[ii + 1] : kInf;
-      }
-      if (li < m && (ii == next || l0 <= i0)) {
-        b = li;
-        wb = l0;
-        ++li;
-        l0 = l1;
-        l1 = li + 1 < m ? W[li + 1] : kInf;
-      } else {
-        b = ii;
-        wb = i0;
-        ++ii;
-        i0 = i1;
-        i1 = ii + 1 < next ? W[ii + 1] : kInf;
-      }
-      const uint64_t nw = wa + wb;
-      W[next] = nw;
-      par[a] = uint16_t(next);
-      par[b] = uint16_t(next);
-      if (ii == next)
-        i0 = nw;
-      else if (ii + 1 == next)
-        i1 = nw;
-      ++next;
-    }
-    par[2 * m - 2] = uint16_t(2 * m - 2);
+  if (tot) atomicAdd(&s_tot, tot);
+  __syncthreads();
+  if (s_tot < 0xFFFFFFFFull) {
+    // 32-bit weights: repack W in place as u32 (2m + 3 words, within W's
+    // storage) and run the narrow merge
+    uint32_t wv[kCbPer];
+    int j = 0;
+    for (int i = t; i < m; i += blockDim.x, ++j) wv[j] = uint32_t(W[i]);
+    __syncthreads();
+    uint32_t* W32 = reinterpret_cast<uint32_t*>(W);
+    j = 0;
+    for (int i = t; i < m; i += blockDim.x, ++j) W32[i] = wv[j];
+    for (int i = m + t; i < 2 * m + 3; i += blockDim.x) W32[i] = ~0u;
+    __syncthreads();
+    if (t == 0) merge32(W32, m, par);
+  } else if (t == 0) {
+    merge64(W, m, par);
   }
   __syncthreads();
   const int nn = 2 * m - 1;
@@ -237,22 +294,20 @@ __host__ __device__ inline int* cb_maxlen_k(void* scratch, int nsym) {
 }
 
 // Batched code books, one job per blockIdx.y, scale k0 + blockIdx.x. The
-// scales run in three launches: 0; 1..7 unless 0 fits; 8..41 unless one of
-// 0..7 fits. A field pays for one tree unless it needs the length limit,
-// and then rarely for more than eight. (Scales a launch skips keep stale
-// longest-code entries, which the final pick never reaches: it stops at the
-// first scale that fits.)
-constexpr int kCbFirst = 8;
+// scales run in launches of growing k: 0, then 1..7, then groups of eight;
+// a launch skips a job when one of its scales below k0 already fits. A field
+// pays for one tree unless it needs the length limit, and then for the
+// groups up to the first scale that fits. (Scales a launch skips keep stale
+// longest-code entries; the final pick never reaches them, as it stops at the
+// first scale that fits, and every scale before that one was built.)
+constexpr int kCbGroup = 8;
 __global__ __launch_bounds__(kCbThreads) void kb_cb_build(const CompressArgs* J, int k0) {
   const CompressArgs& a = J[blockIdx.y];
   const int nsym = alphabet(a.geo);
   int* mk = cb_maxlen_k(a.cb_scratch, nsym);
-  if (k0 > 0) {
-    bool fits = mk[0] <= kLmax;
-    if (k0 >= kCbFirst)
-      for (int k = 1; k < kCbFirst; ++k) fits = fits || mk[k] <= kLmax;
-    if (fits) return;
-  }
+  bool fits = false;
+  for (int k = 0; k < k0; ++k) fits = fits || mk[k] <= kLmax;
+  if (fits) return;
   cb_build_body(a.hist, nsym, cb_lens_k(a.cb_scratch), mk, k0 + int(blockIdx.x));
 }
 
@@ -282,10 +337,11 @@ void launch_codebook(const unsigned long long* hist, int nsym, uint8_t* lens, ui
 
 void launch_codebook_batch(const CompressArgs* J, uint32_t njobs, hipStream_t st) {
   prof_begin(st, "b_cb_build", -1);
-  hipLaunchKernelGGL(kb_cb_build, dim3(1, njobs), dim3(kCbThreads), 0, st, J, 0);
-  hipLaunchKernelGGL(kb_cb_build, dim3(kCbFirst - 1, njobs), dim3(kCbThreads), 0, st, J, 1);
-  hipLaunchKernelGGL(kb_cb_build, dim3(kCbScales - kCbFirst, njobs), dim3(kCbThreads), 0, st, J,
-                     kCbFirst);
+  for (int k0 = 0; k0 < kCbScales;) {
+    const int n = k0 == 0 ? 1 : k0 == 1 ? kCbGroup - 1 : std::min(kCbGroup, kCbScales - k0);
+    hipLaunchKernelGGL(kb_cb_build, dim3(n, njobs), dim3(kCbThreads), 0, st, J, k0);
+    k0 += n;
+  }
   prof_end(st);
   prof_begin(st, "b_cb_final", -1);
   hipLaunchKernelGGL(kb_cb_final, dim3(njobs), dim3(kCbThreads), 0, st, J);
