@@ -1,0 +1,92 @@
+"""GPU parity of the code book's length limit (format 2.4: the smallest k
+whose Huffman code for the counts ceil(c / 2^k) has no code longer than 12
+bits). Fields are built so that the finest-level symbol histogram is known
+exactly: a zero field whose finest-level points (those with an odd
+coordinate, predicted from the all-zero coarser grid) carry offsets q * 2e
+with 2e = 2^-9, so each takes symbol R + q. Geometric counts 2^j on symbols
+R+1..R+J+1 put the first fitting scale at k = 0, in 1..7 and in 8..15, the
+first three groups of scales the batched code book builds; the plain and
+batched streams must equal the oracle's byte for byte."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+EB = 2.0 ** -10  # 2e = 2^-9: the finest level's quantizer is exact
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2509_01626_amd import stz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    stz.lib()
+    return torch.device("cuda:0")
+
+
+def _field(n, J, seed):
+    """n^3 zeros; 2^j finest-level points (random, seeded) get offset j + 1
+    bins, j = 0..J."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    fine = np.flatnonzero(((z | y | x) & 1).ravel())
+    need = (1 << (J + 1)) - 1
+    assert need <= fine.size
+    pick = rng.permutation(fine)[:need]
+    v = np.zeros(n ** 3, dtype=np.float32)
+    start = 0
+    for j in range(J + 1):
+        v[pick[start:start + (1 << j)]] = np.float32((j + 1) * 2.0 ** -9)
+        start += 1 << j
+    return v.reshape(n, n, n)
+
+
+def _first_fitting_scale(oracle, x, cfg):
+    sym, _, lvl = oracle.symbols(x, oracle.EB_ABS, EB, cfg)
+    hist = np.bincount(sym[lvl > 0].ravel(), minlength=1025).astype(np.uint64)
+    for k in range(42):
+        c = np.where(hist > 0, (hist + (np.uint64(1) << np.uint64(k)) - np.uint64(1))
+                     >> np.uint64(k), 0).astype(np.uint64)
+        if oracle.huffman_lengths(c, 60).max() <= 12:
+            return k
+    raise AssertionError("no scale fits")
+
+
+# (edge, J, first fitting scale with Huffman-only coding)
+CASES = [(64, 10, 0), (96, 15, 5), (160, 20, 10)]
+
+
+def test_length_limit_plain_and_batched(gpu, oracle):
+    import torch
+
+    from paper_2509_01626_amd import stz
+    xs, cfgs, wants = [], [], []
+    for i, (n, J, k_want) in enumerate(CASES):
+        for coding in (1, 2):
+            print(f"[case] n={n} J={J} coding={coding}", flush=True)
+            x = _field(n, J, seed=10 + i)
+            ocfg = oracle.config(block=16, coding=coding)
+            if coding == 1:
+                assert _first_fitting_scale(oracle, x, ocfg) == k_want
+            want = oracle.compress(x, oracle.EB_ABS, EB, ocfg)
+            xd = torch.from_numpy(x).to(gpu)
+            cfg = stz.config(block=16, coding=coding)
+            got = stz.stz_compress(xd, stz.EB_ABS, EB, cfg)
+            assert got.cpu().numpy().tobytes() == want, (n, J, coding)
+            assert np.array_equal(stz.stz_decompress(got).cpu().numpy(), oracle.decompress(want))
+            xs.append(xd)
+            cfgs.append(cfg)
+            wants.append(want)
+    # one batch over all six fields: every scale group runs for some job
+    outs = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8, device=gpu)
+            for x, c in zip(xs, cfgs)]
+    # the second call runs the jobs in reverse order, so each job slot's
+    # code-book scratch still holds another field's scales from the first
+    for rep, order in enumerate((list(range(len(xs))), list(range(len(xs)))[::-1])):
+        views, _ = stz.stz_compress_batch([xs[i] for i in order], [stz.EB_ABS] * len(xs),
+                                          [EB] * len(xs), [cfgs[i] for i in order],
+                                          [outs[i] for i in order])
+        for v, i in zip(views, order):
+            assert v.cpu().numpy().tobytes() == wants[i], (rep, i)
