@@ -102,6 +102,55 @@ __device__ inline void tile_store(V* tile, const TileRegs<S, V, NT>& r) {
   }
 }
 
+// Rolling coarse window: slabs of one block read overlapping coarse planes
+// (TZ per slab, HZ of them new), so a block keeps them in LDS and loads only
+// the new ones. Plane P (counted from the block's first coarse plane) is
+// stored twice, in slots P mod TZ and P mod TZ + TZ, so the TZ planes of any
+// slab are contiguous from slot (first plane) mod TZ and the stencils keep
+// their compile-time tap offsets. NP = planes one load brings.
+template <class S, class V, int NP, int NT>
+struct PlaneRegs {
+  static constexpr int N = NP * S::T * S::T;
+  static constexpr int K = (N + NT - 1) / NT;
+  V v[K];
+};
+
+// Load NP coarse planes from coarse plane cz0 on (zero outside the source box).
+template <class S, class V, int NP, int NT>
+__device__ inline void planes_fetch(PlaneRegs<S, V, NP, NT>& r, const V* __restrict__ src,
+                                    const int64_t sf[3], const int64_t sc[3], int64_t cz0,
+                                    int64_t cy0, int64_t cx0) {
+#pragma unroll
+  for (int k = 0; k < PlaneRegs<S, V, NP, NT>::K; ++k) {
+    const int i = threadIdx.x + NT * k;
+    V v = V(0);
+    if (i < PlaneRegs<S, V, NP, NT>::N) {
+      const int tx = i % S::T, t = i / S::T, ty = t % S::T, tz = t / S::T;
+      const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
+      if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
+        v = src[(cz * sc[1] + cy) * sc[2] + cx];
+    }
+    r.v[k] = v;
+  }
+}
+
+// Store planes p0 .. p0+NP-1 (block-relative) into both of their slots.
+template <class S, class V, int NP, int NT>
+__device__ inline void planes_store(V* win, const PlaneRegs<S, V, NP, NT>& r, int p0) {
+  constexpr int PL = S::T * S::TP;  // one plane of the window
+#pragma unroll
+  for (int k = 0; k < PlaneRegs<S, V, NP, NT>::K; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < PlaneRegs<S, V, NP, NT>::N) {
+      const int t = i / (S::T * S::T), rem = i - t * (S::T * S::T);
+      const int off = (rem / S::T) * S::TP + rem % S::T;
+      const int slot = (p0 + t) % S::TZ;
+      win[slot * PL + off] = r.v[k];
+      win[(slot + S::TZ) * PL + off] = r.v[k];
+    }
+  }
+}
+
 // True when every odd level coordinate of the block has full cubic support
 // (offsets -3..+3 inside the level grid) on every axis: M3, P1 and P3 hold
 // for all its points, so each class uses its Eq. 6 / 7 / 8 form.
