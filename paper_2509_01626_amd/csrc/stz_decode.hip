@@ -143,11 +143,13 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   __shared__ uint16_t lut_s[kLdsLut ? (1 << kLutBits) : 1];
   const uint16_t* lut = kLdsLut ? lut_s : a.lut;
   __shared__ uint16_t symb[7 * S::SCP];
-  // Blocks decoded in several slabs keep a rolling window of coarse planes
-  // (each slab loads only its HZ new planes); single-slab blocks and the
-  // largest blocks, whose doubled window would not fit, load whole tiles.
-  constexpr bool kRoll = (E == 16 || E == 32) && S::H < E;
-  __shared__ T tile[kRoll ? 2 * S::TILE : S::TILE];
+  // Blocks of 16^3 and 32^3 level points decoded in several slabs slide a
+  // window of coarse planes: the waves that hold no decoding lane move it and
+  // load the slab's HZ new planes while the other waves decode. Other blocks
+  // load each slab's whole coarse tile.
+  constexpr int NLW = (NL + 63) / 64;  // waves holding decoding lanes
+  constexpr bool kSlide = (E == 16 || E == 32) && S::H < E && NLW * 64 < NT;
+  __shared__ T tile[S::TILE];
   __shared__ uint32_t ring[RB * NL];
   __shared__ uint32_t lanelen_s[NL];
   __shared__ uint32_t uo0[8], uo1[8];
@@ -260,12 +262,11 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   bool complete = true;
   // block origin of the coarse window (level coordinates, even)
   const int64_t cz00 = (oz - 2) >> 1, cy0 = (oy - 2) >> 1, cx0 = (ox - 2) >> 1;
-  if constexpr (kRoll) {
-    // the first slab's TZ planes; later slabs add HZ planes each
-    PlaneRegs<S, T, S::TZ, NT> r0;
-    planes_fetch<S, T, S::TZ, NT>(r0, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, cz00,
-                                  cy0, cx0);
-    planes_store<S, T, S::TZ, NT>(tile, r0, 0);
+  if constexpr (kSlide) {
+    // the first slab's TZ planes; later slabs slide the window by HZ
+    TileRegs<S, T, NT> r0;
+    tile_fetch<S, T, NT>(r0, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, cz00, cy0, cx0);
+    tile_store<S, T, NT>(tile, r0);
   }
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     if (z0 >= zlast) {
@@ -275,14 +276,14 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     const int a0 = z0 >> 1;
     // ---- coarse planes of the slab (global loads in flight during decoding) ----
     TileRegs<S, T, NT> tr;
-    PlaneRegs<S, T, S::HZ, NT> pr;
-    if constexpr (kRoll) {
-      if (z0 > 0)
-        planes_fetch<S, T, S::HZ, NT>(pr, static_cast<const T*>(a.prev), a.in_first, a.in_cnt,
-                                      cz00 + a0 + S::TZ - S::HZ, cy0, cx0);
-    } else {
+    if constexpr (!kSlide)
       tile_fetch<S, T, NT>(tr, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, cz00 + a0, cy0,
                            cx0);
+    if constexpr (kSlide) {
+      if (z0 > 0 && wave >= NLW)
+        slide_window<S, T, NT - NLW * 64>(tile, static_cast<const T*>(a.prev), a.in_first,
+                                          a.in_cnt, cz00 + a0 + S::TZ - S::HZ, cy0, cx0,
+                                          tid - NLW * 64);
     }
     // ---- decode this slab's rows into LDS -----------------------------------
     if (lane_active) {
@@ -345,16 +346,12 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
 #pragma unroll
       for (int k = 0; k < WPL; ++k) ring[((rb + WPL + k) & (RB - 1)) * NL + tid] = pf[k];
     }
-    if constexpr (kRoll) {
-      if (z0 > 0) planes_store<S, T, S::HZ, NT>(tile, pr, a0 + S::TZ - S::HZ);
-    } else {
-      tile_store<S, T, NT>(tile, tr);
-    }
+    if constexpr (!kSlide) tile_store<S, T, NT>(tile, tr);
     __syncthreads();
     // ---- reconstruct the slab ------------------------------------------------------
     const int hs = min(S::H, Ez - z0);
     DecRows<T> ctx;
-    ctx.tile = kRoll ? tile + (a0 % S::TZ) * (S::T * S::TP) : tile;
+    ctx.tile = tile;
     ctx.symb = symb;
     ctx.uo0 = uo0;
     ctx.uo1 = uo1;

@@ -102,51 +102,39 @@ __device__ inline void tile_store(V* tile, const TileRegs<S, V, NT>& r) {
   }
 }
 
-// Rolling coarse window: slabs of one block read overlapping coarse planes
-// (TZ per slab, HZ of them new), so a block keeps them in LDS and loads only
-// the new ones. Plane P (counted from the block's first coarse plane) is
-// stored twice, in slots P mod TZ and P mod TZ + TZ, so the TZ planes of any
-// slab are contiguous from slot (first plane) mod TZ and the stencils keep
-// their compile-time tap offsets. NP = planes one load brings.
-template <class S, class V, int NP, int NT>
-struct PlaneRegs {
-  static constexpr int N = NP * S::T * S::T;
-  static constexpr int K = (N + NT - 1) / NT;
-  V v[K];
-};
-
-// Load NP coarse planes from coarse plane cz0 on (zero outside the source box).
-template <class S, class V, int NP, int NT>
-__device__ inline void planes_fetch(PlaneRegs<S, V, NP, NT>& r, const V* __restrict__ src,
-                                    const int64_t sf[3], const int64_t sc[3], int64_t cz0,
-                                    int64_t cy0, int64_t cx0) {
+// Sliding coarse window: consecutive slabs of a block read overlapping coarse
+// planes (TZ per slab, the last HZ of them new). Between two slabs the window
+// moves down by HZ planes in LDS and the new planes are loaded into its top.
+// NS threads (index st) do it, each owning the same (row, column) positions
+// in every plane, so the moves need no barrier among them; nothing else may
+// touch the window meanwhile. cz_new = coarse plane of the first new plane.
+template <class S, class V, int NS>
+__device__ inline void slide_window(V* tile, const V* __restrict__ src, const int64_t sf[3],
+                                    const int64_t sc[3], int64_t cz_new, int64_t cy0,
+                                    int64_t cx0, int st) {
+  constexpr int PE = S::T * S::T, PL = S::T * S::TP, KE = (PE + NS - 1) / NS;
+  V nv[KE][S::HZ];
 #pragma unroll
-  for (int k = 0; k < PlaneRegs<S, V, NP, NT>::K; ++k) {
-    const int i = threadIdx.x + NT * k;
-    V v = V(0);
-    if (i < PlaneRegs<S, V, NP, NT>::N) {
-      const int tx = i % S::T, t = i / S::T, ty = t % S::T, tz = t / S::T;
-      const int64_t cz = cz0 + tz - sf[0], cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
-      if (cz >= 0 && cz < sc[0] && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2])
-        v = src[(cz * sc[1] + cy) * sc[2] + cx];
+  for (int k = 0; k < KE; ++k) {
+    const int e = st + NS * k;
+    const int ty = e / S::T, tx = e % S::T;
+    const int64_t cy = cy0 + ty - sf[1], cx = cx0 + tx - sf[2];
+    const bool in_yx = e < PE && cy >= 0 && cy < sc[1] && cx >= 0 && cx < sc[2];
+#pragma unroll
+    for (int j = 0; j < S::HZ; ++j) {
+      const int64_t cz = cz_new + j - sf[0];
+      nv[k][j] = (in_yx && cz >= 0 && cz < sc[0]) ? src[(cz * sc[1] + cy) * sc[2] + cx] : V(0);
     }
-    r.v[k] = v;
   }
-}
-
-// Store planes p0 .. p0+NP-1 (block-relative) into both of their slots.
-template <class S, class V, int NP, int NT>
-__device__ inline void planes_store(V* win, const PlaneRegs<S, V, NP, NT>& r, int p0) {
-  constexpr int PL = S::T * S::TP;  // one plane of the window
 #pragma unroll
-  for (int k = 0; k < PlaneRegs<S, V, NP, NT>::K; ++k) {
-    const int i = threadIdx.x + NT * k;
-    if (i < PlaneRegs<S, V, NP, NT>::N) {
-      const int t = i / (S::T * S::T), rem = i - t * (S::T * S::T);
-      const int off = (rem / S::T) * S::TP + rem % S::T;
-      const int slot = (p0 + t) % S::TZ;
-      win[slot * PL + off] = r.v[k];
-      win[(slot + S::TZ) * PL + off] = r.v[k];
+  for (int k = 0; k < KE; ++k) {
+    const int e = st + NS * k;
+    if (e < PE) {
+      const int off = (e / S::T) * S::TP + e % S::T;
+#pragma unroll
+      for (int q = 0; q + S::HZ < S::TZ; ++q) tile[q * PL + off] = tile[(q + S::HZ) * PL + off];
+#pragma unroll
+      for (int j = 0; j < S::HZ; ++j) tile[(S::TZ - S::HZ + j) * PL + off] = nv[k][j];
     }
   }
 }
