@@ -339,9 +339,14 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   uint32_t n_center = 0;  // the zero-residual symbol is counted in a register
   uint32_t n_zero = 0, n_cover = 0;  // zero chunks found, centre symbols they cover
   bool bad = false;
+  // Blocks walked in several slabs slide their window of coarse planes
+  // between slabs (once the slab's predictions are done) instead of loading
+  // every slab's whole tile: each slab adds HZ of its TZ planes.
+  constexpr bool kSlide = S::H < E;
+  const int64_t cz00 = (oz - 2) >> 1, cy0 = (oy - 2) >> 1, cx0 = (ox - 2) >> 1;
+  if constexpr (kSlide) load_tile<S, T>(tile, prev, sf, a.nc, cz00, cy0, cx0);
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
-    const int64_t tz0 = oz + z0 - 2, ty0 = oy - 2, tx0 = ox - 2;
-    load_tile<S, T>(tile, prev, sf, a.nc, tz0 >> 1, ty0 >> 1, tx0 >> 1);
+    if constexpr (!kSlide) load_tile<S, T>(tile, prev, sf, a.nc, cz00 + (z0 >> 1), cy0, cx0);
     __syncthreads();
     const int hs = min(S::H, Ez - z0);
     PredRows<T> ctx;
@@ -377,6 +382,9 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     }
     __syncthreads();
     const int a0 = z0 >> 1;
+    if constexpr (kSlide)
+      if (z0 + S::H < Ez)
+        slide_window<S, T, NT>(tile, prev, sf, a.nc, cz00 + a0 + S::TZ, cy0, cx0, tid);
     // Zero chunks (format 2.4): a chunk is the M_y symbols of one (class,
     // v_z, v_x); one whose symbols are all R becomes one token Z, so the
     // histogram counts Z once and those symbols not at all. Slabs hold whole
