@@ -279,7 +279,7 @@ __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave,
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
-  for_type_rows<E, ZP, YP, NW>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
+  for_type_rows<E, ZP, YP, NW>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q, int) {
     T* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
     const T* xrow =
         c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);

@@ -107,10 +107,13 @@ __device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, i
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
-  for_type_rows<E, ZP, YP, NW>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q) {
+  // the lane's row offset from its wave's first row (lanes of one row group
+  // are 2*(lane / P) rows apart)
+  const int64_t lane_row = int64_t(2 * (lane / S::P)) * x.oc[2];
+  for_type_rows<E, ZP, YP, NW>(x.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q, int lyu) {
     if (lz < x.rz0 || lz >= x.rz1 || ly < x.ry0 || ly >= x.ry1) return;
-    T* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + ly - x.of[1])) * x.oc[2] +
-                  (x.ox - x.of[2]);
+    T* orow = x.cur + ((x.oz + lz - x.of[0]) * x.oc[1] + (x.oy + lyu - x.of[1])) * x.oc[2] +
+                  (x.ox - x.of[2]) + lane_row;
     const int srow = (((lz >> 1) - x.a0) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {x.oz + lz, x.oy + ly, x.ox + l0};
@@ -154,7 +157,8 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   __shared__ uint32_t lanelen_s[NL];
   __shared__ uint32_t uo0[8], uo1[8];
   __shared__ int uok[8];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
   if constexpr (kLdsLut)
     for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut_s[i] = a.lut[i];
   if (wg == 0 && tid == 0) dec_check_body(a);  // the level's unit-index sentinels

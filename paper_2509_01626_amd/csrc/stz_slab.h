@@ -292,8 +292,10 @@ namespace dev {
 namespace {
 
 // Rows of parity type (ZP, YP) in the slab [z0, z0 + hs) assigned to this
-// wave (of NW): calls f(lz, ly, q) for the thread's (even, odd) x pair q of
-// each row. Every type has the same number of rows, so the waves stay
+// wave (of NW): calls f(lz, ly, q, lyu) for the thread's (even, odd) x pair
+// q of each row; lyu = the first row of the wave's task (ly - lyu depends on
+// the lane only), so row addresses can be split into a scalar part and a
+// per-lane offset. Every type has the same number of rows, so the waves stay
 // balanced.
 template <int E, int ZP, int YP, int NW, class F>
 __device__ inline void for_type_rows(int z0, int hs, int Ey, int wave, int lane, F f) {
@@ -305,8 +307,9 @@ __device__ inline void for_type_rows(int z0, int hs, int Ey, int wave, int lane,
   for (int t = wave; t < ntask; t += NW) {
     const int iz = t / S::G, g = t - iz * S::G;
     const int lz = z0 + ZP + 2 * iz;
-    const int ly = YP + 2 * (g * S::RW + r);
-    if (ly < Ey) f(lz, ly, q);
+    const int lyu = YP + 2 * g * S::RW;  // the wave's first row: uniform
+    const int ly = lyu + 2 * r;
+    if (ly < Ey) f(lz, ly, q, lyu);
   }
 }
 
