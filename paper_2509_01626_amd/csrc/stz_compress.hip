@@ -1108,9 +1108,8 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       uint32_t total;
       const uint32_t off = block_excl_scan32(mine, &total);
       const uint32_t nw = (sk + total + 31) >> 5;
-      for (uint32_t i = tid; i < nw; i += 256) wb[i] = 0;
-      __syncthreads();
-      if (tid == 0) wb[0] = carry;
+      for (uint32_t i = tid; i < nw; i += 256) wb[i] = i == 0 ? carry : 0u;
+      if (nw == 0 && tid == 0) wb[0] = carry;
       __syncthreads();
       // codes of the run into the word buffer (chunk-relative bit positions)
       uint32_t pos = sk + off;
