@@ -477,12 +477,92 @@ struct LaneLenArgs {
 // block: thread t < 7m owns column j = t mod m of the block's class t/m + 1.
 // With zero chunks, a chunk (M_y consecutive rows of the column) whose
 // symbols are all R costs the token Z's code instead.
+// Full blocks of 32^3 level points, every unit's symbols 16-byte aligned:
+// all threads read the units' symbols in coalesced 8-symbol groups
+// (a lane's rows = TPL consecutive groups, a zero chunk of M_y = CT*8 rows =
+// CT groups) and sum each lane's code lengths over its TPL threads.
+template <int M>
+__device__ inline void lanelen_full(const LaneLenArgs& a, const uint8_t* L, const int64_t* usym,
+                                   const int64_t* ulane, uint32_t* ub, uint32_t* uo) {
+  constexpr int rows = M * M, TPL = rows / 8, CT = M / 8, NG = rows * M / 8;
+  static_assert(TPL <= 64 && (64 % TPL) == 0 && (CT == 1 || CT == 2) && NG % 256 == 0,
+                "lane groups");
+  const int tid = threadIdx.x;
+  const bool zc = a.g.Z >= 0;
+  const uint32_t R = uint32_t(a.g.R), LZ = zc ? L[a.g.Z] : 0u;
+  for (int c = 1; c <= 7; ++c) {
+    const uint4* g4 = reinterpret_cast<const uint4*>(a.sym + usym[c]);
+    const int64_t lane0 = ulane[c];
+    for (int s8 = tid; s8 < NG; s8 += 256) {  // whole waves take part
+      uint32_t cb = 0, co = 0;
+      bool all = true;
+      {
+        const uint4 w = g4[s8];
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t s0 = v[k] & 0xFFFFu, s1 = v[k] >> 16;
+          cb += L[s0] + L[s1];
+          co += (s0 == 0) + (s1 == 0);
+          all = all && s0 == R && s1 == R;
+        }
+      }
+      uint32_t bits = cb;
+      if (zc) {
+        if constexpr (CT == 1) {
+          bits = all ? LZ : cb;
+        } else {
+          const bool pair = __shfl_xor(int(all), 1, kWave) != 0;  // every lane shuffles
+          bits = (all && pair) ? ((s8 & 1) == 0 ? LZ : 0u) : cb;
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < TPL; o <<= 1) {
+        bits += __shfl_xor(bits, o, kWave);
+        co += __shfl_xor(co, o, kWave);
+      }
+      if ((s8 % TPL) == 0) {
+        a.lane_len[lane0 + s8 / TPL] = uint16_t(bits);
+        atomicAdd(&ub[c], bits);
+        atomicAdd(&uo[c], co);
+      }
+    }
+  }
+}
+
 __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
   __shared__ uint8_t L[kMaxAlphabet];
   __shared__ uint32_t bits_s[256], out_s[256];
+  __shared__ uint32_t ub[8], uo[8];
+  __shared__ int64_t usym[8], ulane[8];
+  __shared__ int s_fast;
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
   const int m = (a.g.B >> a.logs) >> 1;
   const int tid = threadIdx.x, c = tid / m + 1, j = tid % m;
+  if (m == 16) {
+    // a full block (every class sub-grid m^3) with aligned unit symbols?
+    if (tid == 0) s_fast = 1;
+    if (tid < 8) ub[tid] = uo[tid] = 0;
+    __syncthreads();
+    if (tid < 7) {
+      const UnitGeo ug = unit_geo(a.g, wg * 7 + tid, a.logs);
+      usym[tid + 1] = unit_sym_off(a.g, a.logs, wg * 7 + tid);
+      ulane[tid + 1] = unit_lane_off(a.g, a.logs, wg * 7 + tid);
+      if (ug.M[0] != m || ug.M[1] != m || ug.M[2] != m || (usym[tid + 1] & 7) != 0 ||
+          (reinterpret_cast<uintptr_t>(a.sym) & 15) != 0)
+        s_fast = 0;
+    }
+    __syncthreads();
+    if (s_fast) {
+      lanelen_full<16>(a, L, usym, ulane, ub, uo);
+      __syncthreads();
+      if (tid < 7) {
+        a.cnt_words[wg * 7 + tid] = (ub[tid + 1] + 31) >> 5;
+        a.cnt_outl[wg * 7 + tid] = uo[tid + 1];
+      }
+      return;
+    }
+  }
   const bool is_lane = tid < 7 * m;
   const int64_t u = wg * 7 + (c - 1);
   uint32_t bits = 0, no = 0;
