@@ -252,13 +252,12 @@ struct PredRows {
 // Predict and quantize one point of class C (0 = coarse copy only).
 template <class T, int E, int H, int C, bool INT>
 __device__ inline void pred_point(const PredRows<T>& c, int lz, int ly, int lx, int srow,
-                                  const T* xrow, T* grow, const int64_t p[3],
+                                  const T xv, T* grow, const int64_t p[3],
                                   uint32_t* n_center, bool* bad) {
   using S = SlabShape<E, H>;
   if constexpr (C == 0) {
     if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
-    const T xv = xrow[lx << c.ls];
     *bad |= !isfinite(xv);
     const T pred = tile_pred<T, E, C, INT>(c.tile, lz - c.z0, ly, lx, p, c.n);
     T rv;
@@ -272,26 +271,56 @@ __device__ inline void pred_point(const PredRows<T>& c, int lz, int ly, int lx, 
   }
 }
 
+// The field values of this wave's rows of parity type (ZP, YP) in the slab
+// at z0: xs[k] = the (even x, odd x) pair of the wave's k-th row (the even
+// one is not needed for type (0, 0), whose even-x points are coarse copies).
+// Loaded for the next slab while the current one finishes.
+template <class T, int E, int H, int NW, int ZP, int YP, int KT>
+__device__ inline void pred_fetch_x(const PredRows<T>& c, int z0, int hs, int Ey, int wave,
+                                    int lane, T (&xs)[KT][2]) {
+  for_type_rows_k<E, H, ZP, YP, NW>(z0, hs, Ey, wave, lane, [&](int k, int lz, int ly, int q, int) {
+    const T* xrow =
+        c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);
+    const int l0 = 2 * q, l1 = 2 * q + 1;
+    if constexpr (ZP != 0 || YP != 0) xs[k][0] = l0 < c.Ex ? xrow[l0 << c.ls] : T(0);
+    xs[k][1] = l1 < c.Ex ? xrow[l1 << c.ls] : T(0);
+  });
+}
+
 // This wave's rows of parity type (ZP, YP); classes fixed at compile time.
-template <class T, int E, int H, int NW, int ZP, int YP, bool INT>
+// PRE: xs = the rows' field values (pred_fetch_x); else they are loaded here.
+template <class T, int E, int H, int NW, int ZP, int YP, bool INT, bool PRE, int KT>
 __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave, int lane,
-                                 uint32_t* n_center, bool* bad) {
+                                 const T (&xs)[KT][2], uint32_t* n_center, bool* bad) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
-  for_type_rows<E, ZP, YP, NW>(c.z0, hs, Ey, wave, lane, [&](int lz, int ly, int q, int) {
+  auto row = [&](int k, int lz, int ly, int q) {
     T* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
-    const T* xrow =
-        c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] + (c.ox << c.ls);
     const int srow = (((lz - c.z0) >> 1) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {c.oz + lz, c.oy + ly, c.ox + l0};
     const int64_t p1[3] = {c.oz + lz, c.oy + ly, c.ox + l1};
-    if (l0 < c.Ex)
-      pred_point<T, E, H, C0, INT>(c, lz, ly, l0, srow, xrow, grow, p0, n_center, bad);
+    T x0, x1;
+    if constexpr (PRE) {
+      x0 = xs[k][0];
+      x1 = xs[k][1];
+    } else {
+      const T* xrow = c.x + ((((c.oz + lz) << c.ls) * c.fn[1]) + ((c.oy + ly) << c.ls)) * c.fn[2] +
+                      (c.ox << c.ls);
+      x0 = (C0 != 0 && l0 < c.Ex) ? xrow[l0 << c.ls] : T(0);
+      x1 = l1 < c.Ex ? xrow[l1 << c.ls] : T(0);
+    }
+    if (l0 < c.Ex) pred_point<T, E, H, C0, INT>(c, lz, ly, l0, srow, x0, grow, p0, n_center, bad);
     if (l1 < c.Ex)
-      pred_point<T, E, H, C0 + 1, INT>(c, lz, ly, l1, srow, xrow, grow, p1, n_center, bad);
-  });
+      pred_point<T, E, H, C0 + 1, INT>(c, lz, ly, l1, srow, x1, grow, p1, n_center, bad);
+  };
+  if constexpr (PRE)
+    for_type_rows_k<E, H, ZP, YP, NW>(c.z0, hs, Ey, wave, lane,
+                                      [&](int k, int lz, int ly, int q, int) { row(k, lz, ly, q); });
+  else
+    for_type_rows<E, ZP, YP, NW>(c.z0, hs, Ey, wave, lane,
+                                 [&](int lz, int ly, int q, int) { row(0, lz, ly, q); });
 }
 
 // Predict and quantize every level-l point of one block (format 2.2, 2.3);
@@ -345,41 +374,58 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   constexpr bool kSlide = S::H < E;
   const int64_t cz00 = (oz - 2) >> 1, cy0 = (oy - 2) >> 1, cx0 = (ox - 2) >> 1;
   if constexpr (kSlide) load_tile<S, T>(tile, prev, sf, a.nc, cz00, cy0, cx0);
+  PredRows<T> ctx;
+  ctx.x = xv;
+  ctx.tile = tile;
+  ctx.ssym = ssym;
+  ctx.h = h;
+  ctx.cur = cur;
+  ctx.oz = oz;
+  ctx.oy = oy;
+  ctx.ox = ox;
+  ctx.Ex = Ex;
+  ctx.ls = ls;
+  for (int d = 0; d < 3; ++d) {
+    ctx.n[d] = a.n[d];
+    ctx.fn[d] = a.g.n[d];
+  }
+  ctx.E2 = E2;
+  ctx.INV = INV;
+  ctx.chk = chk;
+  ctx.R = R;
+  // Field values of the thread's points, per parity type: for float fields
+  // in 16^3 and 32^3 blocks loaded for the next slab while the current one
+  // finishes (16 registers); other blocks load them where they are used.
+  constexpr bool kPre = sizeof(T) == 4 && (E == 16 || E == 32);
+  constexpr int KT = kPre ? type_tasks_per_wave<E, H, NW>() : 1;
+  T x00[KT][2], x01[KT][2], x10[KT][2], x11[KT][2];
+  auto fetch_x = [&](int zs) {
+    if constexpr (kPre) {
+      const int hn = min(S::H, Ez - zs);
+      pred_fetch_x<T, E, H, NW, 0, 0>(ctx, zs, hn, Ey, wave, lane, x00);
+      pred_fetch_x<T, E, H, NW, 0, 1>(ctx, zs, hn, Ey, wave, lane, x01);
+      pred_fetch_x<T, E, H, NW, 1, 0>(ctx, zs, hn, Ey, wave, lane, x10);
+      pred_fetch_x<T, E, H, NW, 1, 1>(ctx, zs, hn, Ey, wave, lane, x11);
+    }
+  };
+  fetch_x(0);
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     if constexpr (!kSlide) load_tile<S, T>(tile, prev, sf, a.nc, cz00 + (z0 >> 1), cy0, cx0);
     __syncthreads();
     const int hs = min(S::H, Ez - z0);
-    PredRows<T> ctx;
-    ctx.x = xv;
-    ctx.tile = tile;
-    ctx.ssym = ssym;
-    ctx.h = h;
-    ctx.cur = cur;
-    ctx.oz = oz;
-    ctx.oy = oy;
-    ctx.ox = ox;
     ctx.z0 = z0;
-    ctx.Ex = Ex;
-    ctx.ls = ls;
-    for (int d = 0; d < 3; ++d) {
-      ctx.n[d] = a.n[d];
-      ctx.fn[d] = a.g.n[d];
-    }
-    ctx.E2 = E2;
-    ctx.INV = INV;
-    ctx.chk = chk;
-    ctx.R = R;
     if (interior) {
-      pred_type<T, E, H, NW, 0, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, NW, 0, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 0, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 1, true>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, true, kPre>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 1, true, kPre>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 0, true, kPre>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 1, true, kPre>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
     } else {
-      pred_type<T, E, H, NW, 0, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, NW, 0, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 0, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 1, false>(ctx, hs, Ey, wave, lane, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, false, kPre>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 1, false, kPre>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 0, false, kPre>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 1, false, kPre>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
     }
+    if (z0 + S::H < Ez) fetch_x(z0 + S::H);
     __syncthreads();
     const int a0 = z0 >> 1;
     if constexpr (kSlide)
@@ -456,8 +502,16 @@ constexpr int pred_slab_h(int E) { return E == 32 ? 4 : default_slab_h(E); }
 // are faster with four waves sharing the block's points).
 constexpr int pred_threads(int E) { return E <= 4 ? 64 : 256; }
 
+// Waves per SIMD the predictor is compiled for: the occupancy its LDS
+// allows for float fields (6 work-groups per CU for 32^3-point blocks, 7 for
+// 16^3), so the registers holding the next slab's field values do not cost
+// resident blocks.
+template <class T>
+constexpr int pred_waves(int E) { return sizeof(T) != 4 ? 1 : (E == 32 ? 6 : (E == 16 ? 7 : 1)); }
+
 template <class T, int E>
-__global__ __launch_bounds__(pred_threads(E)) void k_pred_slab(PredSlabArgs a) {
+__global__ __launch_bounds__(pred_threads(E)) __attribute__((amdgpu_waves_per_eu(pred_waves<T>(E))))
+void k_pred_slab(PredSlabArgs a) {
   pred_body<T, E, pred_slab_h(E), pred_threads(E)>(a, blockIdx.x, true);
 }
 
@@ -1437,7 +1491,9 @@ __global__ void kb_anchor(const CompressArgs* J, ItemMap m) {
 // Per-level argument blocks of a batch are built on the host (the same
 // builders as the plain launches) and read here through restrict pointers.
 template <int E, int H>
-__global__ __launch_bounds__(256) void kb_pred(const PredSlabArgs* __restrict__ P, ItemMap m) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(H == pred_slab_h(E) ? pred_waves<float>(E) : 1)))
+void kb_pred(const PredSlabArgs* __restrict__ P, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
     const PredSlabArgs& a = P[map_find(m, it_, &loc, &cnt)];

@@ -313,6 +313,37 @@ __device__ inline void for_type_rows(int z0, int hs, int Ey, int wave, int lane,
   }
 }
 
+
+// Tasks (rows) of one parity type a wave can get in a slab of H planes.
+template <int E, int H, int NW>
+constexpr int type_tasks_per_wave() {
+  return (((H + 1) / 2) * SlabShape<E>::G + NW - 1) / NW;
+}
+
+// for_type_rows with the wave's task number k (0 .. type_tasks_per_wave - 1)
+// unrolled at compile time, so per-task values can live in registers:
+// calls f(k, lz, ly, q, lyu) in the same order.
+template <int E, int H, int ZP, int YP, int NW, class F>
+__device__ inline void for_type_rows_k(int z0, int hs, int Ey, int wave, int lane, F f) {
+  using S = SlabShape<E>;
+  constexpr int KT = type_tasks_per_wave<E, H, NW>();
+  const int nz = (hs - ZP + 1) >> 1;
+  const int ntask = nz * S::G;
+  const int r = lane / S::P, q = lane % S::P;
+  if (r >= S::RW) return;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int t = wave + k * NW;
+    if (t < ntask) {
+      const int iz = t / S::G, g = t - iz * S::G;
+      const int lz = z0 + ZP + 2 * iz;
+      const int lyu = YP + 2 * g * S::RW;
+      const int ly = lyu + 2 * r;
+      if (ly < Ey) f(k, lz, ly, q, lyu);
+    }
+  }
+}
+
 }  // namespace
 }  // namespace dev
 }  // namespace stz
