@@ -206,6 +206,8 @@ def test_autotuned_shapes_keep_outputs(gpu):
     report = stz.stz_autotune_batch(jobs)
     print(report, flush=True)
     assert "compress tuned" in report and "decode tuned" in report
+    # every candidate shape must reproduce the default output exactly
+    assert "changed the output" not in report
     comps2, jobs2 = stz.stz_compress_batch(xs, [stz.EB_REL] * len(xs), [eb for _, eb, _ in batch],
                                            cfgs, outs)
     torch.cuda.synchronize()
