@@ -313,7 +313,6 @@ __device__ inline void for_type_rows(int z0, int hs, int Ey, int wave, int lane,
   }
 }
 
-
 // Tasks (rows) of one parity type a wave can get in a slab of H planes.
 template <int E, int H, int NW>
 constexpr int type_tasks_per_wave() {
