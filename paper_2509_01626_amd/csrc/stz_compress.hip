@@ -1245,31 +1245,33 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       for (uint32_t i = tid; i < nw; i += 256) wb[i] = i == 0 ? carry : 0u;
       if (nw == 0 && tid == 0) wb[0] = carry;
       __syncthreads();
-      // codes of the run into the word buffer (chunk-relative bit positions)
-      uint32_t pos = sk + off;
-      uint32_t cw_i = pos >> 5, cur = 0;
+      // codes of the run into the word buffer (chunk-relative bit positions):
+      // a 64-bit accumulator holds the word being filled (high half) and the
+      // next; words wholly inside the run are stored, its first and last
+      // words (shared with the neighbouring runs) OR-ed in
+      {
+        uint32_t w = (sk + off) >> 5, fill = (sk + off) & 31;
+        uint64_t acc = 0;
+        bool first = true;
 #pragma unroll
-      for (int k = 0; k < kPackPer; ++k) {
-        const uint32_t len = lc[k] >> 16, code = lc[k] & 0xFFFFu;
-        if (len == 0) continue;
-        if ((pos >> 5) != cw_i) {
-          if (cur) atomicOr(&wb[cw_i], cur);
-          cur = 0;
-          cw_i = pos >> 5;
+        for (int k = 0; k < kPackPer; ++k) {
+          const uint32_t len = lc[k] >> 16, code = lc[k] & 0xFFFFu;
+          acc |= (uint64_t(code) << 20) << (44 - fill - len);  // code < 2^12: no overflow
+          fill += len;
+          if (fill >= 32) {
+            const uint32_t word = uint32_t(acc >> 32);
+            if (first)
+              atomicOr(&wb[w], word);
+            else
+              wb[w] = word;
+            first = false;
+            acc <<= 32;
+            fill -= 32;
+            ++w;
+          }
         }
-        const uint32_t o = pos & 31;
-        if (o + len <= 32) {
-          cur |= code << (32 - o - len);
-        } else {
-          const uint32_t hi = o + len - 32;
-          cur |= code >> hi;
-          atomicOr(&wb[cw_i], cur);
-          cw_i += 1;
-          cur = code << (32 - hi);
-        }
-        pos += len;
+        if (fill) atomicOr(&wb[w], uint32_t(acc >> 32));
       }
-      if (cur) atomicOr(&wb[cw_i], cur);
       __syncthreads();
       // complete words out; the partial last word carries over
       const uint32_t end = sk + total;
