@@ -1004,12 +1004,17 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   const uint32_t Rs = uint32_t(a.g.R);
   uint32_t vyc = 0;     // row within the current chunk
   bool zrun = false;    // the current chunk is all R
-  auto step = [&](uint32_t s, uint32_t t) {
+  // zk: whether the chunk starting at this row is all R when the caller
+  // knows it (-1: read the chunk's symbols here)
+  auto step = [&](uint32_t s, uint32_t t, int zk) {
     uint32_t len = Ls[s], cw = Cs[s];
     if (zc) {
       if (vyc == 0) {
         bool all = act;
-        for (uint32_t k = 0; k < M1 && all; ++k) all = col[t + k] == Rs;
+        if (zk >= 0)
+          all = all && zk != 0;
+        else
+          for (uint32_t k = 0; k < M1 && all; ++k) all = col[t + k] == Rs;
         zrun = all;
       }
       if (zrun) {
@@ -1057,14 +1062,23 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
       const uint4 w = act ? c4[t >> 3] : make_uint4(0x00010001u, 0x00010001u, 0x00010001u,
                                                     0x00010001u);
       const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+      // chunks of M_y rows dividing the 8 loaded rows: their all-R flags
+      // come from these symbols (bit i: row t + i is R)
+      uint32_t r8 = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        r8 |= (uint32_t((v[k] & 0xFFFFu) == Rs) << (2 * k)) | (uint32_t((v[k] >> 16) == Rs) << (2 * k + 1));
+      const bool known = (8 % M1) == 0;
+      const uint32_t cm = (1u << M1) - 1;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        step(v[k] & 0xFFFFu, t + 2 * k);
-        step(v[k] >> 16, t + 2 * k + 1);
+        const int i0 = 2 * k, i1 = 2 * k + 1;
+        step(v[k] & 0xFFFFu, t + i0, known ? int(((r8 >> i0) & cm) == cm) : -1);
+        step(v[k] >> 16, t + i1, known ? int(((r8 >> i1) & cm) == cm) : -1);
       }
     }
   }
-  for (; t < rows; ++t) step(act ? col[t] : uint16_t(1), t);
+  for (; t < rows; ++t) step(act ? col[t] : uint16_t(1), t, -1);
   if (act && (pos & 31)) emit_word(pay, pos >> 5, cur, start, end);
 }
 
