@@ -939,6 +939,159 @@ __device__ inline void emit_word(uint32_t* pay, uint64_t wi, uint32_t w, uint64_
     atomicOr(&pay[wi], w);
 }
 
+// Full blocks of 16^3 level points (units of 8^3 = 512 symbols, chunks of
+// M_y = 8 rows) whose symbols are 16-byte aligned: the block's 7 units, one
+// after the other in the level's symbol array, are encoded together. Thread
+// t < 224 takes 16 consecutive symbols of unit t / 32 (two 16-byte loads);
+// bit offsets come from a scan over the unit's 32 threads (half a wave) plus
+// the unit's first word; codes go into an LDS buffer of the block's words,
+// written out coalesced; outlier ranks (row-major) from per-row column masks.
+// Returns false (nothing written) when the block does not qualify.
+__device__ inline bool pack_block16(const PackArgs& a, int64_t wg, const uint8_t* Ls,
+                                    const uint16_t* Cs, uint32_t* unit_word, uint32_t* unit_outl,
+                                    uint16_t* lane_arr, uint32_t* pay, uint8_t* outv) {
+  constexpr int kU = 512, kRows = 64, kTPU = 32, kWords = 7 * (kU * kLmax / 32) + 8;
+  __shared__ uint32_t wb[kWords];
+  __shared__ uint32_t rmask[7 * kRows];  // per unit row: columns holding an outlier
+  __shared__ int64_t usym0;
+  __shared__ int s_ok, s_out;
+  const int tid = threadIdx.x;
+  const int64_t u0 = wg * 7;
+  if (tid == 0) {
+    s_ok = (reinterpret_cast<uintptr_t>(a.sym) & 15) == 0;
+    s_out = 0;
+    usym0 = unit_sym_off(a.g, a.logs, u0);
+    if (usym0 & 7) s_ok = 0;
+  }
+  if (tid < 7 * kRows) rmask[tid] = 0;
+  for (int i = tid + 256; i < 7 * kRows; i += 256) rmask[i] = 0;
+  __syncthreads();
+  if (tid < 7) {
+    const UnitGeo ug = unit_geo(a.g, u0 + tid, a.logs);
+    if (ug.M[0] != 8 || ug.M[1] != 8 || ug.M[2] != 8) s_ok = 0;
+  }
+  __syncthreads();
+  if (!s_ok) return false;
+  // unit index entries and lane lengths
+  if (tid < 56) {
+    const int c = tid / 8, j = tid % 8;
+    const int64_t u = u0 + c;
+    const uint64_t li = uint64_t(unit_lane_off(a.g, a.logs, u)) + j;
+    lane_arr[li] = a.lane_len[li];
+    if (j == 0) {
+      unit_word[u] = a.scan_words[u];
+      unit_outl[u] = a.scan_outl[u];
+      if (a.scan_outl[u + 1] != a.scan_outl[u]) s_out = 1;
+      if (u == int64_t(a.nu) - 1) {
+        unit_word[a.nu] = a.scan_words[a.nu];
+        unit_outl[a.nu] = a.scan_outl[a.nu];
+      }
+    }
+  }
+  const uint32_t w0 = a.scan_words[u0];
+  const uint32_t nw = a.scan_words[u0 + 7] - w0;
+  for (uint32_t i = tid; i < nw; i += 256) wb[i] = 0;
+  const int cu = tid / kTPU, r = tid % kTPU;  // unit, run within the unit
+  const bool act = tid < 7 * kTPU;
+  const bool zc = a.g.Z >= 0;
+  const uint32_t R = uint32_t(a.g.R);
+  const uint32_t lcz = zc ? (uint32_t(Cs[a.g.Z]) | (uint32_t(Ls[a.g.Z]) << 16)) : 0u;
+  uint32_t lc[16];
+  uint32_t mine = 0;
+  if (act) {
+    const uint4* g4 = reinterpret_cast<const uint4*>(a.sym + usym0 + cu * kU + r * 16);
+    const uint4 q0 = g4[0], q1 = g4[1];
+    const uint32_t v[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    uint32_t rm = 0;  // bit k: symbol k of the run is R
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t sy = (v[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+      lc[k] = uint32_t(Cs[sy]) | (uint32_t(Ls[sy]) << 16);
+      rm |= uint32_t(sy == R) << k;
+      if (sy == 0) {  // outlier: symbol p of the unit is row p mod 64 of column p / 64
+        const int p = r * 16 + k;
+        atomicOr(&rmask[cu * kRows + (p & (kRows - 1))], 1u << (p / kRows));
+      }
+    }
+    if (zc) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (((rm >> (8 * h)) & 0xFFu) == 0xFFu) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) lc[8 * h + k] = k == 0 ? lcz : 0u;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) mine += lc[k] >> 16;
+  }
+  // exclusive scan of the bit counts over the unit's 32 threads
+  uint32_t inc = mine;
+#pragma unroll
+  for (int o = 1; o < kTPU; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o, kTPU);
+    if (r >= o) inc += t;
+  }
+  __syncthreads();  // buffer cleared, masks complete
+  if (act) {
+    const uint32_t pos = (a.scan_words[u0 + cu] - w0) * 32 + (inc - mine);
+    uint32_t w = pos >> 5, fill = pos & 31;
+    uint64_t acc = 0;
+    bool first = true;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t len = lc[k] >> 16, code = lc[k] & 0xFFFFu;
+      acc |= (uint64_t(code) << 20) << (44 - fill - len);  // code < 2^12: no overflow
+      fill += len;
+      if (fill >= 32) {
+        const uint32_t word = uint32_t(acc >> 32);
+        if (first)
+          atomicOr(&wb[w], word);
+        else
+          wb[w] = word;
+        first = false;
+        acc <<= 32;
+        fill -= 32;
+        ++w;
+      }
+    }
+    if (fill) atomicOr(&wb[w], uint32_t(acc >> 32));
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < nw; i += 256) pay[w0 + i] = wb[i];
+  // outliers in rank order per unit (row-major: row t, then column): wave 0,
+  // one row per lane
+  if (s_out && tid < kRows) {
+    for (int c = 0; c < 7; ++c) {
+      const int64_t u = u0 + c;
+      const uint32_t uo = a.scan_outl[u], n_out = a.scan_outl[u + 1] - uo;
+      if (n_out == 0) continue;
+      uint32_t mk = rmask[c * kRows + tid];
+      const uint32_t cnt = __popc(mk);
+      uint32_t incl = cnt;
+#pragma unroll
+      for (int o = 1; o < kRows; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, kWave);
+        if (tid >= o) incl += t;
+      }
+      uint32_t rank = incl - cnt;
+      const UnitGeo ug = unit_geo(a.g, u, a.logs);
+      const uint32_t vy = tid % 8, vz = tid / 8;
+      const int64_t pz = (ug.b[0] << a.g.logB) + (int64_t(2 * vz + ug.o[0]) << a.logs);
+      const int64_t py = (ug.b[1] << a.g.logB) + (int64_t(2 * vy + ug.o[1]) << a.logs);
+      while (mk) {
+        const uint32_t jj = __ffs(mk) - 1;
+        mk &= mk - 1;
+        if (rank < n_out) {
+          const int64_t px = (ug.b[2] << a.g.logB) + (int64_t(2 * jj + ug.o[2]) << a.logs);
+          put_outlier(outv, a.vb, uo + rank, a.x, (pz * a.g.n[1] + py) * a.g.n[2] + px);
+        }
+        ++rank;
+      }
+    }
+  }
+  return true;
+}
+
 // Small units (block edge at this level below 32): one lane per column
 // stream packs its codes directly (same block mapping as k_lanelen); a unit's
 // lanes sit inside one wave, so the rank order of its outliers comes from a
@@ -1336,6 +1489,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   pack_units_body(a, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void k_pack_lanes(PackArgs a) { pack_lanes_body(a, blockIdx.x); }
+
+// Levels with 16^3-point blocks: the whole-block encoder, the lane packer
+// for blocks it does not take (domain edges).
+__global__ __launch_bounds__(256) void k_pack_blocks16(PackArgs a) {
+  const DevParams* P = a.P;
+  if (P->flags) return;
+  __shared__ uint8_t Ls[kMaxAlphabet];
+  __shared__ uint16_t Cs[kMaxAlphabet];
+  for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) {
+    Ls[i] = a.lens[i];
+    Cs[i] = a.codes[i];
+  }
+  __syncthreads();
+  const int l = a.level;
+  if (pack_block16(a, blockIdx.x, Ls, Cs, reinterpret_cast<uint32_t*>(a.out + P->sec[l]),
+                   reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]),
+                   reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]),
+                   reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]), a.out + P->off_out[l]))
+    return;
+  pack_lanes_body(a, blockIdx.x);
+}
 
 }  // namespace
 
@@ -1742,6 +1916,9 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
     prof_begin(st, "pack", l);
     if ((g.B >> (L - l)) >= 32)
       hipLaunchKernelGGL(k_pack_units, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
+    else if ((g.B >> (L - l)) == 16)
+      hipLaunchKernelGGL(k_pack_blocks16, dim3(unsigned(nu / 7)), dim3(256), 0, st,
+                         pack_args(a, l));
     else
       hipLaunchKernelGGL(k_pack_lanes, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
     prof_end(st);
