@@ -584,6 +584,44 @@ __device__ inline void lanelen_full(const LaneLenArgs& a, const uint8_t* L, cons
   }
 }
 
+// Full blocks of 16^3 level points (units of 512 symbols, lanes of 64 rows,
+// chunks of 8): the 7 units and their lanes are consecutive, so the block's
+// 448 groups of 8 symbols are taken as one array, 8 groups per lane.
+__device__ inline void lanelen_block16(const LaneLenArgs& a, const uint8_t* L, int64_t usym1,
+                                       int64_t ulane1, uint32_t* ub, uint32_t* uo) {
+  constexpr int TPL = 8, NG = 7 * 64;
+  const int tid = threadIdx.x;
+  const bool zc = a.g.Z >= 0;
+  const uint32_t R = uint32_t(a.g.R), LZ = zc ? L[a.g.Z] : 0u;
+  const uint4* g4 = reinterpret_cast<const uint4*>(a.sym + usym1);
+  for (int s8 = tid; s8 < 512; s8 += 256) {  // whole waves take part
+    uint32_t cb = 0, co = 0;
+    bool all = true;
+    if (s8 < NG) {
+      const uint4 w = g4[s8];
+      const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t s0 = v[k] & 0xFFFFu, s1 = v[k] >> 16;
+        cb += L[s0] + L[s1];
+        co += (s0 == 0) + (s1 == 0);
+        all = all && s0 == R && s1 == R;
+      }
+    }
+    uint32_t bits = (zc && all && s8 < NG) ? LZ : cb;
+#pragma unroll
+    for (int o = 1; o < TPL; o <<= 1) {
+      bits += __shfl_xor(bits, o, kWave);
+      co += __shfl_xor(co, o, kWave);
+    }
+    if (s8 < NG && (s8 % TPL) == 0) {
+      a.lane_len[ulane1 + s8 / TPL] = uint16_t(bits);
+      atomicAdd(&ub[s8 / 64 + 1], bits);
+      atomicAdd(&uo[s8 / 64 + 1], co);
+    }
+  }
+}
+
 __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
   __shared__ uint8_t L[kMaxAlphabet];
   __shared__ uint32_t bits_s[256], out_s[256];
@@ -593,7 +631,7 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
   for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
   const int m = (a.g.B >> a.logs) >> 1;
   const int tid = threadIdx.x, c = tid / m + 1, j = tid % m;
-  if (m == 16) {
+  if (m == 16 || m == 8) {
     // a full block (every class sub-grid m^3) with aligned unit symbols?
     if (tid == 0) s_fast = 1;
     if (tid < 8) ub[tid] = uo[tid] = 0;
@@ -608,7 +646,10 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
     }
     __syncthreads();
     if (s_fast) {
-      lanelen_full<16>(a, L, usym, ulane, ub, uo);
+      if (m == 16)
+        lanelen_full<16>(a, L, usym, ulane, ub, uo);
+      else
+        lanelen_block16(a, L, usym[1], ulane[1], ub, uo);
       __syncthreads();
       if (tid < 7) {
         a.cnt_words[wg * 7 + tid] = (ub[tid + 1] + 31) >> 5;
