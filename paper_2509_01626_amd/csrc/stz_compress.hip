@@ -1929,7 +1929,10 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   launch_codebook(a.hist, nsym, a.lens, a.codes, a.cb_scratch, st);
   for (int l = 1; l <= L; ++l) {
     prof_begin(st, "lanelen", l);
-    hipLaunchKernelGGL(k_lanelen, dim3(unsigned(nu / 7)), dim3(256), 0, st, lanelen_args(a, l));
+    // blocks of at most 8^3 level points (at most 28 lanes): one-wave
+    // work-groups, four times as many per CU
+    const unsigned nt = (g.B >> (L - l)) <= 8 ? 64u : 256u;
+    hipLaunchKernelGGL(k_lanelen, dim3(unsigned(nu / 7)), dim3(nt), 0, st, lanelen_args(a, l));
     prof_end(st);
   }
   const int nblk = scan_blocks(a);
@@ -1960,8 +1963,8 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
     else if ((g.B >> (L - l)) == 16)
       hipLaunchKernelGGL(k_pack_blocks16, dim3(unsigned(nu / 7)), dim3(256), 0, st,
                          pack_args(a, l));
-    else
-      hipLaunchKernelGGL(k_pack_lanes, dim3(unsigned(nu / 7)), dim3(256), 0, st, pack_args(a, l));
+    else  // at most 28 lanes: one-wave work-groups
+      hipLaunchKernelGGL(k_pack_lanes, dim3(unsigned(nu / 7)), dim3(64), 0, st, pack_args(a, l));
     prof_end(st);
   }
   return hipGetLastError();
