@@ -225,13 +225,18 @@ __global__ __launch_bounds__(kCbThreads) void k_cb_build(const unsigned long lon
   cb_build_body(hist, nsym, lens_k, maxlen_k, blockIdx.x);
 }
 
-// Pick the first scale whose code fits in kLmax bits; canonical codes.
+// Pick the first scale whose code fits in kLmax bits; canonical codes (by
+// length, then symbol): a symbol's code = the first code of its length + the
+// number of smaller symbols with the same length, counted with per-wave
+// ballots and per-wave totals (no sort).
 __device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k, int nsym,
                                      uint8_t* lens_out, uint16_t* codes_out) {
-  __shared__ uint64_t key[kCbMax];
-  __shared__ uint32_t bl[kLmax + 2], first[kLmax + 1], start[kLmax + 1];
-  __shared__ int s_k, s_n;
-  const int t = threadIdx.x;
+  constexpr int kW = kCbThreads / 64;     // waves
+  constexpr int kPass = kCbMax / kCbThreads;  // symbols per thread, one per pass
+  __shared__ uint32_t wcnt[kPass][kW][kLmax + 1];  // per pass and wave: symbols per length
+  __shared__ uint32_t bl[kLmax + 2], first[kLmax + 1];
+  __shared__ int s_k;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t == 0) {
     int kk = kCbScales - 1;
     for (int k = 0; k < kCbScales; ++k)
@@ -241,40 +246,54 @@ __device__ inline void cb_final_body(const uint8_t* lens_k, const int* maxlen_k,
       }
     s_k = kk;
   }
-  if (t < kLmax + 2) bl[t] = 0;
-  if (t == 0) s_n = 0;
   __syncthreads();
   const uint8_t* lens = lens_k + size_t(s_k) * nsym;
-  for (int i = t; i < nsym; i += blockDim.x) {
-    const int l = lens[i];
-    if (l) {
-      key[atomicAdd(&s_n, 1)] = (uint64_t(l) << kSymBits) | uint64_t(i);
-      atomicAdd(&bl[l], 1u);
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  int len[kPass];
+  uint32_t rank[kPass];
+#pragma unroll
+  for (int p = 0; p < kPass; ++p) {
+    const int i = p * kCbThreads + t;
+    len[p] = i < nsym ? int(lens[i]) : 0;
+    rank[p] = 0;
+    for (int l = 1; l <= kLmax; ++l) {
+      const uint64_t m = __ballot(len[p] == l);
+      if (len[p] == l) rank[p] = __popcll(m & below);
+      if (lane == 0) wcnt[p][w][l] = __popcll(m);
     }
-    lens_out[i] = uint8_t(l);
-    codes_out[i] = 0;
   }
   __syncthreads();
-  const int nk = s_n;
-  int np2 = 1;
-  while (np2 < nk) np2 <<= 1;
-  for (int i = nk + t; i < np2; i += blockDim.x) key[i] = kInf;
-  bitonic_sort(key, np2);
+  if (t <= kLmax) {  // symbols per length, then the first code of each length
+    uint32_t n = 0;
+    for (int p = 0; p < kPass; ++p)
+      for (int ww = 0; ww < kW; ++ww) n += t == 0 ? 0u : wcnt[p][ww][t];
+    bl[t] = n;
+  }
+  __syncthreads();
   if (t == 0) {
-    uint32_t code = 0, st = 0;
+    uint32_t code = 0;
+    bl[kLmax + 1] = 0;
     for (int l = 1; l <= kLmax; ++l) {
       code = (code + bl[l - 1]) << 1;
       first[l] = code;
-      start[l] = st;
-      st += bl[l];
     }
   }
   __syncthreads();
-  for (int i = t; i < np2; i += blockDim.x) {
-    const uint64_t k = key[i];
-    if (k == kInf) continue;
-    const int l = int(k >> kSymBits), sy = int(k & kSymMask);
-    codes_out[sy] = uint16_t(first[l] + (uint32_t(i) - start[l]));
+#pragma unroll
+  for (int p = 0; p < kPass; ++p) {
+    const int i = p * kCbThreads + t;
+    if (i >= nsym) continue;
+    const int l = len[p];
+    uint32_t code = 0;
+    if (l) {
+      uint32_t r = rank[p];
+      for (int q = 0; q < p; ++q)
+        for (int ww = 0; ww < kW; ++ww) r += wcnt[q][ww][l];
+      for (int ww = 0; ww < w; ++ww) r += wcnt[p][ww][l];
+      code = first[l] + r;
+    }
+    lens_out[i] = uint8_t(l);
+    codes_out[i] = uint16_t(code);
   }
 }
 
