@@ -907,20 +907,27 @@ __device__ inline void layout_body(const LayoutArgs& a) {
 
 __global__ void k_layout(LayoutArgs a) { layout_body(a); }
 
-// Zero [from, total) of the stream (padding and the words packed with atomics).
+// Zero [from, total) of the stream (padding and the words packed with atomics),
+// except the payload of level `skip` (-1: none), which the unit packer writes
+// word by word in full (its last, partly padded 16 bytes are still cleared).
 __device__ inline void zero_body(uint8_t* out, uint64_t from, const DevParams* P, uint64_t wg,
-                                 uint64_t ngrid) {
+                                 uint64_t ngrid, int skip = -1) {
   if (P->flags) return;
   const uint64_t to = P->total;
+  uint64_t s0 = 0, s1 = 0;  // skipped range, in 16-byte units
+  if (skip >= 0) {
+    s0 = P->off_pay[skip] / 16;
+    s1 = (P->off_pay[skip] + 4 * P->words[skip]) / 16;
+  }
   uint4* p = reinterpret_cast<uint4*>(out);
   const uint4 z = make_uint4(0, 0, 0, 0);
   for (uint64_t i = from / 16 + wg * blockDim.x + threadIdx.x; i < to / 16;
        i += ngrid * blockDim.x)
-    p[i] = z;
+    if (i < s0 || i >= s1) p[i] = z;
 }
 
-__global__ void k_zero(uint8_t* out, uint64_t from, const DevParams* P) {
-  zero_body(out, from, P, blockIdx.x, gridDim.x);
+__global__ void k_zero(uint8_t* out, uint64_t from, const DevParams* P, int skip) {
+  zero_body(out, from, P, blockIdx.x, gridDim.x, skip);
 }
 
 // Code lengths and anchors into the stream.
@@ -1950,7 +1957,9 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_layout, dim3(1), dim3(64), 0, st, layout_args(a));
   prof_end(st);
   prof_begin(st, "zero", -1);
-  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, a.out, kHeaderBytes, a.params);
+  // the finest level's payload, when the unit packer writes it, needs no clearing
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, st, a.out, kHeaderBytes, a.params,
+                     g.B >= 32 ? L : -1);
   prof_end(st);
   prof_begin(st, "fill_head", -1);
   hipLaunchKernelGGL(k_fill_head, dim3(grid_for(a.n_anchor + nsym, 256, 4096)), dim3(256), 0, st,

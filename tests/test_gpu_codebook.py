@@ -90,3 +90,19 @@ def test_length_limit_plain_and_batched(gpu, oracle):
                                           [outs[i] for i in order])
         for v, i in zip(views, order):
             assert v.cpu().numpy().tobytes() == wants[i], (rep, i)
+
+
+@pytest.mark.parametrize("B", [32, 64, 16])
+def test_stream_bytes_independent_of_output_buffer_contents(gpu, oracle, B):
+    """The stream is fully written: an output buffer filled with 0xFF bytes
+    beforehand gives the same bytes as the oracle (no word, padding or
+    section is left to the buffer's previous contents)."""
+    import torch
+
+    from paper_2509_01626_amd import fields, stz
+    x = fields.spectral((70, 64, 96), 5 / 3, seed=B)
+    cfg = stz.config(block=B)
+    want = oracle.compress(x, oracle.EB_REL, 1e-3, oracle.config(block=B))
+    out = torch.full((stz.stz_compress_bound(x.shape, cfg),), 0xFF, dtype=torch.uint8, device=gpu)
+    got = stz.stz_compress(torch.from_numpy(x).to(gpu), stz.EB_REL, 1e-3, cfg, out=out)
+    assert got.cpu().numpy().tobytes() == want
