@@ -143,7 +143,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   // smaller ones (a few symbols per lane) the copy would cost more than it
   // saves, and the table is read through the cache.
   constexpr bool kLdsLut = E >= 16;
-  __shared__ uint16_t lut_s[kLdsLut ? (1 << kLutBits) : 1];
+  __shared__ __align__(16) uint16_t lut_s[kLdsLut ? (1 << kLutBits) : 1];
   const uint16_t* lut = kLdsLut ? lut_s : a.lut;
   __shared__ uint16_t symb[7 * S::SCP];
   // Blocks of 16^3 and 32^3 level points decoded in several slabs slide a
@@ -159,8 +159,16 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   __shared__ int uok[8];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
-  if constexpr (kLdsLut)
-    for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut_s[i] = a.lut[i];
+  if constexpr (kLdsLut) {
+    // 16-byte copies when the table is aligned (8 entries per thread and pass)
+    if ((reinterpret_cast<uintptr_t>(a.lut) & 15) == 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(a.lut);
+      uint4* dst = reinterpret_cast<uint4*>(lut_s);
+      for (int i = tid; i < (1 << kLutBits) / 8; i += blockDim.x) dst[i] = src[i];
+    } else {
+      for (int i = tid; i < (1 << kLutBits); i += blockDim.x) lut_s[i] = a.lut[i];
+    }
+  }
   if (wg == 0 && tid == 0) dec_check_body(a);  // the level's unit-index sentinels
 
   const int64_t nblk = a.bb_n[0] * a.bb_n[1] * a.bb_n[2];
