@@ -843,11 +843,15 @@ int compress_impl(const T* x, const uint64_t dims[3], int eb_mode, double eb,
   for (int l = 1; l <= c.L; ++l) {
     const LevelOut& L_ = lv[l];
     uint8_t* base = o + sec[l];
-    std::memcpy(base + L_.ll.off_unit_word, L_.unit_word.data(), 4 * L_.unit_word.size());
-    std::memcpy(base + L_.ll.off_unit_outl, L_.unit_outl.data(), 4 * L_.unit_outl.size());
-    std::memcpy(base + L_.ll.off_lane, L_.lane_len.data(), 2 * L_.lane_len.size());
-    std::memcpy(base + L_.ll.off_payload, L_.payload.data(), 4 * L_.payload.size());
-    std::memcpy(base + L_.ll.off_outl, outl[l].data(), VB * outl[l].size());
+    // (an empty vector may hold no storage: copy only nonempty arrays)
+    auto put = [](uint8_t* dst, const void* src, size_t bytes) {
+      if (bytes) std::memcpy(dst, src, bytes);
+    };
+    put(base + L_.ll.off_unit_word, L_.unit_word.data(), 4 * L_.unit_word.size());
+    put(base + L_.ll.off_unit_outl, L_.unit_outl.data(), 4 * L_.unit_outl.size());
+    put(base + L_.ll.off_lane, L_.lane_len.data(), 2 * L_.lane_len.size());
+    put(base + L_.ll.off_payload, L_.payload.data(), 4 * L_.payload.size());
+    put(base + L_.ll.off_outl, outl[l].data(), VB * outl[l].size());
   }
   return OK;
 }

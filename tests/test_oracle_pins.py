@@ -213,6 +213,50 @@ def test_huffman_length_limit(oracle):
     assert unl.max() > 12
 
 
+def test_huffman_length_limit_worked_examples(oracle):
+    """Hand-worked lengths for counts that need one and two halvings to fit
+    the 12-bit limit (tests/golden/huffman_length_limit.txt)."""
+    n = 0
+    with open(os.path.join(GOLDEN, "huffman_length_limit.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            a, b = line.split(";")
+            counts = np.array([int(v) for v in a.split()], dtype=np.uint64)
+            want = [int(v) for v in b.split()]
+            assert list(oracle.huffman_lengths(counts, 12)) == want, (list(counts), want)
+            n += 1
+    assert n == 3
+
+
+def _first_fitting_halving(oracle, counts, lmax):
+    """k and ceil(c / 2^k) for the first k whose unlimited code fits lmax."""
+    c = counts.astype(np.uint64)
+    k = 0
+    while oracle.huffman_lengths(c, 64).max() > lmax:
+        c = np.where(c > 0, (c + 1) >> np.uint64(1), c).astype(np.uint64)
+        k += 1
+        assert k < 64
+    return k, c
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_huffman_length_limit_is_halving_rebuild(oracle, seed):
+    """The limited lengths are the unlimited lengths of ceil(c / 2^k) at the
+    first k that fits (the rule restated: k halvings, each c -> ceil(c/2)),
+    on skewed random histograms that exceed 12 bits."""
+    rng = np.random.default_rng(100 + seed)
+    counts = np.zeros(1024, dtype=np.uint64)
+    m = int(rng.integers(20, 60))
+    idx = rng.choice(1024, size=m, replace=False)
+    counts[idx] = np.floor(1.6 ** rng.uniform(0, 45, size=m)).astype(np.uint64) + 1
+    k, c = _first_fitting_halving(oracle, counts, 12)
+    assert k >= 1, "the case must exercise the limit"
+    # repeated ceil halving equals one division by 2^k, rounded up
+    assert np.array_equal(c, (counts + np.uint64((1 << k) - 1)) >> np.uint64(k))
+    assert np.array_equal(oracle.huffman_lengths(counts, 12), oracle.huffman_lengths(c, 64))
+
+
 def test_huffman_degenerate(oracle):
     counts = np.zeros(16, dtype=np.uint64)
     assert np.all(oracle.huffman_lengths(counts) == 0)
