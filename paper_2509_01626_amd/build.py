@@ -7,6 +7,7 @@ packed-fp32 instruction selection disabled.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -25,12 +26,28 @@ FLAGS = [
 ]
 
 
+OBJDIR = os.path.join(HERE, "_build")
+
+
 def build(verbose=False):
+    """Compile every source to an object in parallel, then link the library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SOURCES
+    os.makedirs(OBJDIR, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+    objs = [os.path.join(OBJDIR, os.path.basename(f) + ".o") for f in SOURCES]
+    cmds = [[hipcc] + cflags + ["-I", os.path.join(ROOT, "include"), "-c", "-o", o, f]
+            for f, o in zip(SOURCES, objs)]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        for r in ex.map(lambda c: subprocess.run(c, check=True), cmds):
+            pass
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -2,7 +2,8 @@
 ABI. Every job of a batch must produce the same bytes as the plain call (and,
 for the small fields checked here, as the CPU oracle); every request of a
 batch must produce what the plain region / level decode of the same stream
-produces; launch shapes chosen by the autotuner must not change any output."""
+produces and what the oracle's region decode produces; launch shapes chosen by
+the autotuner must not change any output."""
 import numpy as np
 import pytest
 
@@ -112,11 +113,12 @@ def _random_requests(rng, flds, n):
     return items
 
 
-def test_batch_decode_matches_plain_region(gpu):
+def test_batch_decode_matches_plain_region_and_oracle(gpu, oracle):
     import torch
     stz = _stz()
     batch = _uneven_batch(10, seed=300, lo=6, hi=40)
     _, _, _, comps, _ = _compress_batch(gpu, batch)
+    hosts = [c.cpu().numpy().tobytes() for c in comps]
     flds = [stz.Field(c) for c in comps]
     rng = np.random.default_rng(5)
     reqs = _random_requests(rng, flds, 60)
@@ -142,6 +144,8 @@ def test_batch_decode_matches_plain_region(gpu):
         got = outs[i][:n].cpu().numpy()
         assert np.array_equal(got.view(np.uint32), want.reshape(-1).cpu().numpy().view(np.uint32)), \
             (i, k, lo, hi, lv)
+        ref = oracle.decompress_region(hosts[k], lo, hi, lv).reshape(-1)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), ("oracle", i, k, lo, hi, lv)
     for f in flds:
         f.close()
 

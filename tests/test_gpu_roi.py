@@ -45,14 +45,17 @@ def test_roi_matches_oracle(gpu, oracle, unit, stat):
     f.close()
 
 
-def test_roi_blocks_decode_as_batch(gpu):
+def test_roi_blocks_decode_as_batch(gpu, oracle):
     import torch
 
     from paper_2509_01626_amd import stz
     x = fields.spectral((64, 48, 80), 5 / 3, seed=12)
     comp = stz.stz_compress(torch.from_numpy(x).to(gpu), stz.EB_REL, 1e-3, stz.config(block=16))
+    host = comp.cpu().numpy().tobytes()
     f = stz.Field(comp)
     sel, _ = stz.stz_roi_select(f, 2, stz.ROI_BLOCKS, stz.ROI_RANGE, stz.ROI_TOP_FRACTION, 0.25)
+    osel, _ = oracle.roi_select(host, 2, stz.ROI_BLOCKS, stz.ROI_RANGE, stz.ROI_TOP_FRACTION, 0.25)
+    assert np.array_equal(sel, osel)
     boxes = stz.roi_block_boxes(f.info, sel)
     assert len(boxes) == int(np.ceil(0.25 * 4 * 3 * 5))
     items, outs = [], []
@@ -65,4 +68,6 @@ def test_roi_blocks_decode_as_batch(gpu):
     for (lo, hi), o in zip(boxes, outs):
         want = stz.stz_decompress_region(comp, lo, hi, f.info.levels).reshape(-1)
         assert torch.equal(o[:want.numel()].view(torch.int32), want.view(torch.int32))
+        ref = oracle.decompress_region(host, lo, hi, f.info.levels).reshape(-1)
+        assert np.array_equal(o[:ref.size].cpu().numpy().view(np.uint32), ref.view(np.uint32))
     f.close()
