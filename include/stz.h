@@ -127,6 +127,30 @@ stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t
                                  const uint64_t hi[3], uint32_t level, float* out,
                                  uint64_t out_cap_elems, uint64_t out_dims[3], void* stream);
 
+/* Size in bytes of the fixed device scratch of stz_decompress_region_noalloc. */
+#define STZ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* stz_decompress_region for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, layouts, results and errors, but the call allocates nothing.
+ * Its scratch (the dependency cone's coarse level grids, the decoder table and
+ * a flag word) is a fixed device array of STZ_NOALLOC_SCRATCH_BYTES that each
+ * GPU holds from the library's load until the process ends; the stream header
+ * and the table pass through host stack buffers (pageable copies). A decode
+ * whose scratch would exceed that size returns STZ_ERR_NOMEM and does nothing
+ * (for float32 fields, about sum over levels k < level of 4 * (cone points at
+ * level k): a 256^3 box at the finest level of a 512^3 field needs ~12 MB, a
+ * full 512^3 decode ~77 MB, too much). float32 streams only (STZ_ERR_ARG for
+ * others). Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (different streams or host threads) race; calls on one
+ * stream from one thread are safe. The call synchronizes `stream` twice (the
+ * header, then the status). With the stage profiler on it still creates
+ * timing events. */
+stz_status stz_decompress_region_noalloc(const void* comp, uint64_t size, const uint64_t lo[3],
+                                         const uint64_t hi[3], uint32_t level, float* out,
+                                         uint64_t out_cap_elems, uint64_t out_dims[3],
+                                         void* stream);
+
 /* ---- float64 fields -------------------------------------------------------
  * Double-precision fields (the paper's WarpX data are float64, Sec. 4.1,
  * Table 2) use the same format with value type 1 in the header: prediction

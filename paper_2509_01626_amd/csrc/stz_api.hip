@@ -223,7 +223,8 @@ struct Header {
   uint64_t off_outl[kMaxLevels + 1], off_lane[kMaxLevels + 1], off_pay[kMaxLevels + 1],
       off_out[kMaxLevels + 1];
   LevelConst lc[kMaxLevels + 1];
-  std::vector<uint8_t> lens;
+  uint8_t lens[kMaxAlphabet];  // code lengths of the alphabet (nsym entries)
+  int nsym = 0;
 };
 
 template <class T>
@@ -233,15 +234,9 @@ T rd(const uint8_t* p) {
   return v;
 }
 
-stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* h) {
-  if (!comp || size < kHeaderBytes) return STZ_ERR_CORRUPT;
-  const uint64_t want = std::min<uint64_t>(size, Staging::kHdrBytes);
-  Staging* stage = staging();
-  if (!stage) return STZ_ERR_NOMEM;
-  if (hipMemcpyAsync(stage->hdr, comp, want, hipMemcpyDeviceToHost, st) != hipSuccess)
-    return STZ_ERR_DEVICE;
-  if (hipStreamSynchronize(st) != hipSuccess) return STZ_ERR_DEVICE;
-  const uint8_t* p = stage->hdr;
+// Parse the first `want` = min(size, kHdrBytes) bytes of a stream of `size`
+// bytes, already copied to host memory at p.
+stz_status parse_header(const uint8_t* p, uint64_t want, uint64_t size, Header* h) {
   if (rd<uint32_t>(p) != kMagic || rd<uint32_t>(p + 4) != kVersion) return STZ_ERR_CORRUPT;
   uint64_t dims[3] = {rd<uint64_t>(p + 8), rd<uint64_t>(p + 16), rd<uint64_t>(p + 24)};
   stz_config cf;
@@ -270,8 +265,9 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
   h->n_anchor = rd<uint64_t>(p + 104);
   if (h->anchor_off != kHeaderBytes + align16(nsym)) return STZ_ERR_CORRUPT;
   if (h->n_anchor != grid_count(h->g, h->g.L)) return STZ_ERR_CORRUPT;
-  if (kHeaderBytes + nsym > want) return STZ_ERR_CORRUPT;
-  h->lens.assign(p + kHeaderBytes, p + kHeaderBytes + nsym);
+  if (kHeaderBytes + nsym > want || nsym > uint64_t(kMaxAlphabet)) return STZ_ERR_CORRUPT;
+  std::memcpy(h->lens, p + kHeaderBytes, nsym);
+  h->nsym = int(nsym);
   level_consts(h->g, h->lc);
   const uint64_t vb = uint64_t(h->vb);
   uint64_t pos = h->anchor_off + align16(vb * h->n_anchor);
@@ -296,11 +292,23 @@ stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* 
   return STZ_OK;
 }
 
+// Copy the header of a device stream to the calling thread's pinned staging
+// (one synchronization) and parse it.
+stz_status read_header(const void* comp, uint64_t size, hipStream_t st, Header* h) {
+  if (!comp || size < kHeaderBytes) return STZ_ERR_CORRUPT;
+  const uint64_t want = std::min<uint64_t>(size, Staging::kHdrBytes);
+  Staging* stage = staging();
+  if (!stage) return STZ_ERR_NOMEM;
+  if (hipMemcpyAsync(stage->hdr, comp, want, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return STZ_ERR_DEVICE;
+  return parse_header(stage->hdr, want, size, h);
+}
+
 // Decoder table: entry for every 12-bit window = symbol | length << 12, or 0
 // when no code is a prefix of the window. Fails when the lengths do not form a
 // prefix code.
-bool build_lut(const std::vector<uint8_t>& lens, std::vector<uint16_t>* lut) {
-  const int nsym = int(lens.size());
+bool build_lut(const uint8_t* lens, int nsym, uint16_t* lut) {
   uint32_t bl[kLmax + 1] = {0};
   uint64_t kraft = 0;  // in units of 2^-kLmax
   for (int i = 0; i < nsym; ++i) {
@@ -317,13 +325,13 @@ bool build_lut(const std::vector<uint8_t>& lens, std::vector<uint16_t>* lut) {
     code = (code + bl[l - 1]) << 1;
     next[l] = code;
   }
-  lut->assign(size_t(1) << kLutBits, 0);
+  std::memset(lut, 0, sizeof(uint16_t) << kLutBits);
   for (int i = 0; i < nsym; ++i) {
     const int l = lens[i];
     if (!l) continue;
     const uint32_t c = next[l]++;
     const uint32_t lo = c << (kLutBits - l), n = 1u << (kLutBits - l);
-    for (uint32_t k = 0; k < n; ++k) (*lut)[lo + k] = uint16_t(i | (l << 12));
+    for (uint32_t k = 0; k < n; ++k) lut[lo + k] = uint16_t(i | (l << 12));
   }
   return true;
 }
@@ -440,21 +448,19 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   if (out_dims)
     for (int d = 0; d < 3; ++d) out_dims[d] = pl.od[d];
   if (s != STZ_OK || pl.cnt == 0) return s;
-  std::vector<uint16_t> lut;
-  if (!build_lut(h.lens, &lut)) return STZ_ERR_CORRUPT;
-  Workspace ws(st);
-  pl.take(ws);
-  const uint64_t o_lut = ws.take<uint8_t>(lut.size() * 2 + 16);
-  if (!ws.commit()) return STZ_ERR_NOMEM;
-  uint16_t* dlut = ws.at<uint16_t>(o_lut);
-  uint32_t* dflags = reinterpret_cast<uint32_t*>(dlut + lut.size());
-  pl.bind(ws, dlut, dflags);
   Staging* stage = staging();
   if (!stage) return STZ_ERR_NOMEM;
-  std::memcpy(stage->lut, lut.data(), lut.size() * 2);
-  std::memset(stage->lut + lut.size(), 0, 16);
-  if (hipMemcpyAsync(dlut, stage->lut, lut.size() * 2 + 16, hipMemcpyHostToDevice, st) !=
-      hipSuccess)
+  constexpr uint64_t nlut = uint64_t(1) << kLutBits;
+  if (!build_lut(h.lens, h.nsym, stage->lut)) return STZ_ERR_CORRUPT;
+  Workspace ws(st);
+  pl.take(ws);
+  const uint64_t o_lut = ws.take<uint8_t>(nlut * 2 + 16);
+  if (!ws.commit()) return STZ_ERR_NOMEM;
+  uint16_t* dlut = ws.at<uint16_t>(o_lut);
+  uint32_t* dflags = reinterpret_cast<uint32_t*>(dlut + nlut);
+  pl.bind(ws, dlut, dflags);
+  std::memset(stage->lut + nlut, 0, 16);
+  if (hipMemcpyAsync(dlut, stage->lut, nlut * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
     return STZ_ERR_DEVICE;
   if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
   if (hipMemcpyAsync(stage->flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -462,6 +468,61 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
     return STZ_ERR_DEVICE;
   prof_flush();
   return *stage->flags ? STZ_ERR_CORRUPT : STZ_OK;
+}
+
+// ---- decoding without allocation --------------------------------------------
+// Device address of the file-scope scratch array on the current device
+// (set up once per device with that device current), or null.
+void* noalloc_scratch();
+
+// A box decode like decode_box (float32 streams) whose scratch (level grids,
+// decoder table, corruption flag) lives in the fixed scratch array: no device
+// or pinned allocation, the header and table pass through stack buffers.
+stz_status decode_box_noalloc(const void* comp, uint64_t size, const Box* boxp, int level,
+                              float* out, uint64_t out_cap, uint64_t out_dims[3], hipStream_t st) {
+  if (out_dims)
+    for (int d = 0; d < 3; ++d) out_dims[d] = 0;
+  uint8_t* base = static_cast<uint8_t*>(noalloc_scratch());
+  if (!base) return STZ_ERR_DEVICE;
+  if (!comp || size < kHeaderBytes) return STZ_ERR_CORRUPT;
+  uint8_t hb[kHeaderBytes + kMaxAlphabet];
+  const uint64_t want = std::min<uint64_t>(size, sizeof(hb));
+  if (hipMemcpyAsync(hb, comp, want, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  Header h;
+  stz_status s = parse_header(hb, want, size, &h);
+  if (s != STZ_OK) return s;
+  if (h.vb != 4) return STZ_ERR_ARG;
+  DecodePlan pl;
+  s = pl.init(h, comp, size, boxp, level, out, out_cap);
+  if (out_dims)
+    for (int d = 0; d < 3; ++d) out_dims[d] = pl.od[d];
+  if (s != STZ_OK || pl.cnt == 0) return s;
+  // layout: the cone's level grids, then the table with the flag word behind it
+  constexpr uint64_t nlut = uint64_t(1) << kLutBits;
+  uint64_t used = 0;
+  for (int k = 0; k < pl.a.level_out; ++k) {
+    pl.a.rec[k] = base + used;
+    used += (uint64_t(h.vb) * std::max<uint64_t>(box_points(pl.a.box[k], h.g.L - k), 1) + 255) &
+            ~uint64_t(255);
+  }
+  const uint64_t o_lut = used;
+  used += nlut * 2 + 16;
+  if (used > uint64_t(STZ_NOALLOC_SCRATCH_BYTES)) return STZ_ERR_NOMEM;
+  uint16_t lut[nlut + 8];
+  if (!build_lut(h.lens, h.nsym, lut)) return STZ_ERR_CORRUPT;
+  std::memset(lut + nlut, 0, 16);  // clears the flag word
+  pl.a.lut = reinterpret_cast<const uint16_t*>(base + o_lut);
+  pl.a.flags = reinterpret_cast<uint32_t*>(base + o_lut + nlut * 2);
+  if (hipMemcpyAsync(base + o_lut, lut, sizeof(lut), hipMemcpyHostToDevice, st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
+  uint32_t flag = 0;
+  if (hipMemcpyAsync(&flag, pl.a.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return STZ_ERR_DEVICE;
+  return flag ? STZ_ERR_CORRUPT : STZ_OK;
 }
 
 // ---- compression plan of one field ----------------------------------------
@@ -944,23 +1005,22 @@ stz_status stz_open(const void* comp, uint64_t size, stz_field* field, void* str
   auto* f = new (std::nothrow) stz_field_s;
   if (!f) return STZ_ERR_NOMEM;
   stz_status s = read_header(comp, size, st, &f->h);
-  std::vector<uint16_t> lut;
-  if (s == STZ_OK && !build_lut(f->h.lens, &lut)) s = STZ_ERR_CORRUPT;
+  Staging* stage = staging();
+  if (s == STZ_OK && !stage) s = STZ_ERR_NOMEM;
+  if (s == STZ_OK && !build_lut(f->h.lens, f->h.nsym, stage->lut)) s = STZ_ERR_CORRUPT;
   if (s != STZ_OK) {
     delete f;
     return s;
   }
   f->comp = static_cast<const uint8_t*>(comp);
   f->size = size;
-  f->lut_entries = lut.size();
-  Staging* stage = staging();
-  if (!stage || hipGetDevice(&f->device) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&f->lut), lut.size() * 2) != hipSuccess) {
+  f->lut_entries = uint64_t(1) << kLutBits;
+  if (hipGetDevice(&f->device) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&f->lut), f->lut_entries * 2) != hipSuccess) {
     delete f;
     return STZ_ERR_NOMEM;
   }
-  std::memcpy(stage->lut, lut.data(), lut.size() * 2);
-  if (hipMemcpyAsync(f->lut, stage->lut, lut.size() * 2, hipMemcpyHostToDevice, st) !=
+  if (hipMemcpyAsync(f->lut, stage->lut, f->lut_entries * 2, hipMemcpyHostToDevice, st) !=
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     (void)hipFree(f->lut);
@@ -1487,9 +1547,48 @@ stz_status level_one(const void* comp, uint64_t size, uint32_t level, void* out,
 }
 
 }  // namespace
+
+// Scratch of stz_decompress_region_noalloc. Each GPU holds its own copy from
+// module load until the process ends. In host code the name is only a
+// stand-in: every use goes through the address from hipGetSymbolAddress.
+__device__ __align__(256) uint8_t scratch[STZ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+void* noalloc_scratch() {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    addr[dev] = p;
+  }
+  return addr[dev];
+}
+
+}  // namespace
 }  // namespace stz
 
 extern "C" {
+
+stz_status stz_decompress_region_noalloc(const void* comp, uint64_t size, const uint64_t lo[3],
+                                         const uint64_t hi[3], uint32_t level, float* out,
+                                         uint64_t out_cap_elems, uint64_t out_dims[3],
+                                         void* stream) {
+  if (!lo || !hi) return STZ_ERR_ARG;
+  Box b;
+  for (int d = 0; d < 3; ++d) {
+    if (lo[d] > (uint64_t(1) << 32) || hi[d] > (uint64_t(1) << 32)) return STZ_ERR_ARG;
+    b.lo[d] = int64_t(lo[d]);
+    b.hi[d] = int64_t(hi[d]);
+  }
+  if (level > uint32_t(kMaxLevels)) return STZ_ERR_ARG;
+  return decode_box_noalloc(comp, size, &b, int(level), out, out_cap_elems, out_dims,
+                            static_cast<hipStream_t>(stream));
+}
 
 stz_status stz_decompress_region(const void* comp, uint64_t size, const uint64_t lo[3],
                                  const uint64_t hi[3], uint32_t level, float* out,

@@ -80,6 +80,10 @@ def lib():
             f.restype = C.c_int
             f.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p, C.c_uint32, C.c_void_p,
                           C.c_uint64, u64p, C.c_void_p]
+        L.stz_decompress_region_noalloc.restype = C.c_int
+        L.stz_decompress_region_noalloc.argtypes = [C.c_void_p, C.c_uint64, u64p, u64p,
+                                                    C.c_uint32, C.c_void_p, C.c_uint64, u64p,
+                                                    C.c_void_p]
         L.stz_info.restype = C.c_int
         L.stz_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Info), C.c_void_p]
         L.stz_compress_batch.restype = C.c_int
@@ -267,6 +271,20 @@ def stz_decompress_region(comp, lo, hi, level, out=None, stream=None, info=None)
         raise StzError(st, "stz_decompress_region" + sfx)
     assert tuple(od) == shape, (tuple(od), shape)
     return out.reshape(-1)[:n].view(shape)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # STZ_NOALLOC_SCRATCH_BYTES
+
+
+def stz_decompress_region_noalloc(comp, lo, hi, level, out, stream=None):
+    """The allocation-free region decode (float32 streams) into the caller's
+    `out` (device float32); returns (status, out_dims) and never raises."""
+    _check_dev(out, torch.float32)
+    od = (C.c_uint64 * 3)()
+    st = lib().stz_decompress_region_noalloc(
+        C.c_void_p(comp.data_ptr()), comp.numel(), _dims(lo), _dims(hi), level,
+        C.c_void_p(out.data_ptr()), out.numel(), od, _stream(stream))
+    return st, tuple(int(v) for v in od)
 
 
 def decode_status(comp, fn="decompress", level=0, lo=None, hi=None, stream=None,
