@@ -95,35 +95,101 @@ __device__ inline void merge64(uint64_t* W, int m, uint16_t* par) {
   par[2 * m - 2] = uint16_t(2 * m - 2);
   }
 
-// The same merge with 32-bit weights (the total weight is below 2^32 - 1, so
-// ~0 marks an empty queue slot): each step takes the two lightest of the next
-// two leaves l0 <= l1 and the next two merged nodes i0 <= i1 (two leaves when
-// l1 <= i0, two merged nodes when i1 < l0, else one of each). Layout in W:
-// leaves [0, m), two ~0 pads, merged nodes from m + 2 (node k at Wi[k]) with
-// ~0 in the m + 1 slots before the merge, so every load is unconditional.
-__device__ inline void merge32(uint32_t* W, int m, uint16_t* par) {
-  const uint32_t* Wl = W;
-  uint32_t* Wi = W + m + 2;
-  int li = 0, ii = 0;
-  uint32_t l0 = Wl[0], l1 = Wl[1], i0 = ~0u, i1 = ~0u;
-  for (int ni = 0; ni < m - 1; ++ni) {
-    const bool LL = l1 <= i0;
-    const bool II = !LL && i1 < l0;
-    const int ida = II ? m + ii : li;
-    const int idb = LL ? li + 1 : m + ii + (II ? 1 : 0);
-    const uint32_t wsum = LL ? l0 + l1 : (II ? i0 + i1 : l0 + i0);
-    const int dl = LL ? 2 : (II ? 0 : 1);
-    Wi[ni] = wsum;
-    par[ida] = uint16_t(m + ni);
-    par[idb] = uint16_t(m + ni);
-    li += dl;
-    ii += 2 - dl;
-    l0 = Wl[li];
-    l1 = Wl[li + 1];
-    i0 = Wi[ii];
-    i1 = Wi[ii + 1];
+// Orders LDS accesses of one wave: what a lane wrote before the call is seen
+// by every lane of the same wave after it.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// First index in [lo, hi) of the ascending array A whose value exceeds t (hi
+// if none), found by one wave in 64-way steps; every lane returns it.
+__device__ inline int wave_upper_bound(const uint32_t* A, int lo, int hi, uint32_t t) {
+  const int lane = threadIdx.x & 63;
+  while (hi - lo > 64) {
+    const int step = (hi - lo + 63) >> 6;
+    const int idx = lo + lane * step;
+    const int c = __popcll(__ballot(idx < hi && A[idx] <= t));
+    if (c == 0) return lo;
+    lo += (c - 1) * step;
+    hi = min(hi, lo + step);
   }
-  par[2 * m - 2] = uint16_t(2 * m - 2);
+  const int idx = lo + lane;
+  return lo + __popcll(__ballot(idx < hi && A[idx] <= t));
+}
+
+// Number of entries of the ascending A[lo, hi) below t (strict) or at most t,
+// by binary search in one lane.
+template <bool STRICT>
+__device__ inline int count_before(const uint32_t* A, int lo, int hi, uint32_t t) {
+  const int base = lo;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const bool go = STRICT ? A[mid] < t : A[mid] <= t;
+    lo = go ? mid + 1 : lo;
+    hi = go ? hi : mid;
+  }
+  return lo - base;
+}
+
+// The two-queue merge with 32-bit weights (total below 2^32 - 1), by one wave,
+// in phases that reproduce the serial merge exactly. The serial merge removes
+// nodes in the order S = the merge of the leaf queue and the merged-node queue
+// (a leaf first on equal weights, merged nodes in creation order), and merged
+// node k is S[2k] + S[2k+1]. Let t be the weight of the next merged node to be
+// created. Every remaining node of weight <= t precedes it (and every later
+// one) in S, so a phase appends all of them to S at once, placed by the merge
+// rule, and then creates every merged node whose two children are in S. The
+// threshold at least doubles every two phases, so there are at most about
+// 2*log2(total) phases (about 26 on these histograms).
+// LDS layout: LW = leaves [0, m) plus two ~0 pads; IW = merged nodes
+// [0, m - 1); SW = weights of S [0, 2m - 2); Sid = node ids of S (leaf i = i,
+// merged node k = m + k); par = parent of each node id.
+__device__ inline void merge_phased(const uint32_t* LW, uint32_t* IW, uint32_t* SW, uint16_t* Sid,
+                                    int m, uint16_t* par) {
+  const int lane = threadIdx.x & 63;
+  int li = 0, ki = 0, q = 0, p = 0;  // next leaf, next merged node, merged count, |S|
+  while (q < m - 1) {
+    const uint32_t a0 = LW[li], a1 = LW[li + 1];
+    const uint32_t b0 = ki < q ? IW[ki] : ~0u, b1 = ki + 1 < q ? IW[ki + 1] : ~0u;
+    uint32_t t;
+    if (p & 1) {
+      t = SW[p - 1] + min(a0, b0);
+    } else {
+      const uint32_t s1 = min(a0, b0);
+      const uint32_t s2 = a0 <= b0 ? min(a1, b0) : min(a0, b1);
+      t = s1 + s2;
+    }
+    const int cl = wave_upper_bound(LW, li, m, t) - li;
+    const int ci = wave_upper_bound(IW, ki, q, t) - ki;
+    for (int e = lane; e < cl + ci; e += 64) {
+      if (e < cl) {
+        const uint32_t w = LW[li + e];
+        const int pos = e + count_before<true>(IW, ki, ki + ci, w);
+        SW[p + pos] = w;
+        Sid[p + pos] = uint16_t(li + e);
+      } else {
+        const int b = e - cl;
+        const uint32_t w = IW[ki + b];
+        const int pos = b + count_before<false>(LW, li, li + cl, w);
+        SW[p + pos] = w;
+        Sid[p + pos] = uint16_t(m + ki + b);
+      }
+    }
+    wave_sync();
+    p += cl + ci;
+    const int q1 = p >> 1;
+    for (int k = q + lane; k < q1; k += 64) {
+      IW[k] = SW[2 * k] + SW[2 * k + 1];
+      par[Sid[2 * k]] = uint16_t(m + k);
+      par[Sid[2 * k + 1]] = uint16_t(m + k);
+    }
+    wave_sync();
+    li += cl;
+    ki += ci;
+    q = q1;
+  }
+  if (lane == 0) par[2 * m - 2] = uint16_t(2 * m - 2);
 }
 
 // Code lengths for counts ceil(hist / 2^k), k = blockIdx.x: two queues over the
@@ -133,7 +199,7 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
                                      int* maxlen_k, int k) {
   // nodes: the sorted leaves (padded to a power of two while sorting) and then
   // the m - 1 merged nodes: at most kCbNodes entries
-  __shared__ uint64_t W[kCbNodes];
+  __shared__ uint64_t W[kCbNodes + 2];
   __shared__ uint16_t par[kCbNodes];
   __shared__ uint16_t dep[kCbNodes];
   __shared__ uint16_t leaf[kCbMax];
@@ -175,18 +241,20 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   if (tot) atomicAdd(&s_tot, tot);
   __syncthreads();
   if (s_tot < 0xFFFFFFFFull) {
-    // 32-bit weights: repack W in place as u32 (2m + 3 words, within W's
-    // storage) and run the narrow merge
+    // 32-bit weights: repack the leaves in place as u32 (LW), then merged
+    // nodes (IW) and the removal order (SW) behind them, within W's storage
+    // (4m + 3 words); the removal order's node ids go to dep until the depths
+    // are computed
     uint32_t wv[kCbPer];
     int j = 0;
     for (int i = t; i < m; i += blockDim.x, ++j) wv[j] = uint32_t(W[i]);
     __syncthreads();
-    uint32_t* W32 = reinterpret_cast<uint32_t*>(W);
+    uint32_t* LW = reinterpret_cast<uint32_t*>(W);
     j = 0;
-    for (int i = t; i < m; i += blockDim.x, ++j) W32[i] = wv[j];
-    for (int i = m + t; i < 2 * m + 3; i += blockDim.x) W32[i] = ~0u;
+    for (int i = t; i < m; i += blockDim.x, ++j) LW[i] = wv[j];
+    if (t < 2) LW[m + t] = ~0u;
     __syncthreads();
-    if (t == 0) merge32(W32, m, par);
+    if (t < 64) merge_phased(LW, LW + m + 2, LW + 2 * m + 1, dep, m, par);
   } else if (t == 0) {
     merge64(W, m, par);
   }
