@@ -58,9 +58,9 @@ struct DecRows {
 };
 
 // Slab height of the decoder: for 32^3-point blocks, 2 planes keep the LDS
-// footprint (code table, slab symbols, coarse tile, stream ring) at 26 KB and
-// the registers under 100, for five work-groups per CU; 16^3-point blocks
-// take 4 planes (17 KB, 79 VGPRs, six per CU). The per-symbol decode chains
+// footprint (code table, slab symbols, coarse tile, stream ring) at 26 KB, for
+// six work-groups per CU; 16^3-point blocks take 4 planes (17 KB, 72 VGPRs,
+// seven per CU). The per-symbol decode chains
 // (one per lane stream) are latency-bound, so more blocks in flight win over
 // the extra slab passes.
 constexpr int dec_slab_h(int E) { return E == 32 ? 2 : (E == 16 ? 4 : default_slab_h(E)); }
@@ -270,6 +270,8 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
 
   const int64_t org[3] = {oz, oy, ox};
   const bool interior = block_interior(org, E, a.n);
+  constexpr bool kFullPath = m >= 8;
+  const bool full_rows = Ez == E && Ey == E;
   const int zlast = min(Ez, rz1);  // no output needed beyond this level plane
   bool complete = true;
   // block origin of the coarse window (level coordinates, even)
@@ -312,46 +314,94 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
       const int Zt = a.g.Z, Rc = a.g.R;  // zero-chunk token (-1: off), centre symbol
       const uint32_t eR = uint32_t(Rc);  // table entry of a zero-chunk row: R, no bits
-      int zr = 0;                        // rows left in the current zero chunk
-      int vy = 0;                        // row r = vz*My + vy, advanced incrementally
-      int so = (c - 1) * S::SCP + j;     // LDS slot of the row's symbol
       uint32_t nw = ring[rk * NL + tid];  // next stream word (word wi)
-      for (int r = r0; r < r1; ++r) {
-        // Branch-free refill: merge the next word when fewer than kLmax
-        // bits are left, then read the following one from the ring.
-        const bool rf = nb < kLmax;
-        const int sh = rf ? 32 - nb : 0;
-        buf |= uint64_t(rf ? nw : 0u) << sh;
-        nb += rf ? 32 : 0;
-        rk = (rk + (rf ? 1 : 0)) & (RB - 1);
-        nw = ring[rk * NL + tid];
-        // Inside a zero chunk a row takes R and no bits; a Z token starts one
-        // (valid only at a chunk's first row: checked when the chunk ends).
-        const bool inz = zr != 0;
-        const uint32_t ei = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
-        const uint32_t e = inz ? eR : ei;
-        const int len = int(e >> 12);
-        const int se = int(e & 4095);
-        bad |= e == 0;  // not a code of the book; lane totals are checked at the end
-        const bool isz = se == Zt;
-        const int sy = isz ? Rc : se;
-        zr = isz ? My - 1 : zr - (inz ? 1 : 0);
-        buf <<= len;
-        nb -= len;
-        const bool is_out = sy == 0 && len != 0;
-        const uint64_t wm = __ballot(is_out);
-        uint16_t st = uint16_t(sy);
-        if (wm != 0) {  // wave-uniform: outliers are rare
-          const uint64_t mk = wm & segmask;
-          if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
-          run += __popcll(mk);
+      if (kFullPath && full_rows) {
+        // Full blocks: every unit has M_y = m rows per chunk and HZ chunks in
+        // the slab, so the row loop unrolls completely. The bit window is
+        // topped up to at least 32 bits before every two codes (of at most
+        // kLmax bits each); a chunk's first token decides whether it is a zero
+        // chunk; codes that are not in the book give symbol 0 with no bits and
+        // are caught in the (rare) outlier branch.
+        bool zmid = false;  // a Z token after a chunk's first row
+#pragma unroll
+        for (int hz = 0; hz < S::HZ; ++hz) {
+          bool inz = false;
+#pragma unroll
+          for (int vy = 0; vy < m; vy += 2) {
+            const bool rf = nb < 32;
+            const int sh = rf ? 32 - nb : 0;
+            buf |= uint64_t(rf ? nw : 0u) << sh;
+            nb += rf ? 32 : 0;
+            rk = (rk + (rf ? 1 : 0)) & (RB - 1);
+            nw = ring[rk * NL + tid];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const uint32_t ei = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
+              const uint32_t e = inz ? eR : ei;
+              const int len = int(e >> 12);
+              int sy = int(e & 4095);
+              buf <<= len;
+              nb -= len;
+              if (vy + u == 0) {
+                inz = sy == Zt;
+                sy = inz ? Rc : sy;
+              } else {
+                zmid |= sy == Zt;
+              }
+              uint16_t st = uint16_t(sy);
+              if (__ballot(sy == 0) != 0) {  // wave-uniform: outliers are rare
+                const bool is_out = sy == 0 && len != 0;
+                bad |= sy == 0 && len == 0;  // not a code of the book
+                const uint64_t mk = __ballot(is_out) & segmask;
+                if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
+                run += __popcll(mk);
+              }
+              symb[(c - 1) * S::SCP + (hz * m + vy + u) * S::SP + j] = st;
+            }
+          }
         }
-        symb[so] = st;
-        so += S::SP;
-        if (++vy == My) {
-          vy = 0;
-          so += (m - My) * S::SP;
-          bad |= zr != 0;  // a token after a chunk's first row runs past its end
+        bad |= zmid;
+      } else {
+        int zr = 0;                        // rows left in the current zero chunk
+        int vy = 0;                        // row r = vz*My + vy, advanced incrementally
+        int so = (c - 1) * S::SCP + j;     // LDS slot of the row's symbol
+        for (int r = r0; r < r1; ++r) {
+          // Branch-free refill: merge the next word when fewer than kLmax
+          // bits are left, then read the following one from the ring.
+          const bool rf = nb < kLmax;
+          const int sh = rf ? 32 - nb : 0;
+          buf |= uint64_t(rf ? nw : 0u) << sh;
+          nb += rf ? 32 : 0;
+          rk = (rk + (rf ? 1 : 0)) & (RB - 1);
+          nw = ring[rk * NL + tid];
+          // Inside a zero chunk a row takes R and no bits; a Z token starts one
+          // (valid only at a chunk's first row: checked when the chunk ends).
+          const bool inz = zr != 0;
+          const uint32_t ei = lut[uint32_t(buf >> 32) >> (32 - kLutBits)];
+          const uint32_t e = inz ? eR : ei;
+          const int len = int(e >> 12);
+          const int se = int(e & 4095);
+          bad |= e == 0;  // not a code of the book; lane totals are checked at the end
+          const bool isz = se == Zt;
+          const int sy = isz ? Rc : se;
+          zr = isz ? My - 1 : zr - (inz ? 1 : 0);
+          buf <<= len;
+          nb -= len;
+          const bool is_out = sy == 0 && len != 0;
+          const uint64_t wm = __ballot(is_out);
+          uint16_t st = uint16_t(sy);
+          if (wm != 0) {  // wave-uniform: outliers are rare
+            const uint64_t mk = wm & segmask;
+            if (is_out) st = uint16_t(0x8000u | ((run + __popcll(mk & ltmask)) & 0x7FFFu));
+            run += __popcll(mk);
+          }
+          symb[so] = st;
+          so += S::SP;
+          if (++vy == My) {
+            vy = 0;
+            so += (m - My) * S::SP;
+            bad |= zr != 0;  // a token after a chunk's first row runs past its end
+          }
         }
       }
       wi = wb + uint64_t((rk - rb) & (RB - 1));  // words merged: fewer than RB per slab
@@ -412,16 +462,19 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   if (bad && lane_active && alive) atomicOr(a.flags, kFlagCorrupt);
 }
 
-// Waves per SIMD the decoder is compiled for: 5 for 32^3-point blocks (96
-// VGPRs; the decode chains are latency-bound, so occupancy pays).
-constexpr int dec_waves(int E) { return E == 32 ? 5 : 1; }
+// Waves per SIMD the decoder is compiled for: 6 for float fields in 32^3-point
+// blocks (at most 80 VGPRs, no spills), so six work-groups of 26 KB LDS share
+// a CU (the decode chains are latency-bound, so occupancy pays); 5 for double
+// fields, whose wider values need more registers.
+template <class T>
+constexpr int dec_waves(int E) { return E == 32 ? (sizeof(T) == 4 ? 6 : 5) : 1; }
 // Threads per work-group of the plain launches: blocks of at most 8^3 level
 // points (at most 28 decoding lanes, a few hundred points) take one wave, so
 // four times as many blocks fit on a CU; their latency chains overlap.
 constexpr int slab_threads(int E) { return E <= 8 ? 64 : 256; }
 
 template <class T, int E>
-__global__ __launch_bounds__(slab_threads(E)) __attribute__((amdgpu_waves_per_eu(dec_waves(E))))
+__global__ __launch_bounds__(slab_threads(E)) __attribute__((amdgpu_waves_per_eu(dec_waves<T>(E))))
 void k_dec_slab(DecSlabArgs a) {
   dec_body<T, E, dec_slab_h(E), slab_threads(E)>(a, blockIdx.x);
 }
@@ -542,7 +595,7 @@ __global__ void kb_dec_anchor(const DecodeArgs* R, ItemMap m) {
 // builder as the plain launches) and read here through restrict pointers.
 template <int E, int H>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(H == dec_slab_h(E) ? dec_waves(E) : 1)))
+__attribute__((amdgpu_waves_per_eu(H == dec_slab_h(E) ? dec_waves<float>(E) : 1)))
 void kb_dec(const DecSlabArgs* __restrict__ D, ItemMap m) {
   STZ_FOR_ITEMS(m) {
     uint32_t loc, cnt;
