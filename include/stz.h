@@ -249,6 +249,43 @@ typedef struct {
 stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_flags,
                                 void* stream);
 
+/* ---- Captured batches (HIP graphs) ----------------------------------------
+ * The batching pattern with persistent kernels captured once (Sec. 3.3's
+ * many-field workflows: in-situ compression of successive time steps, repeated
+ * region decodes). A plan fixes a job array (or request array): pointers,
+ * extents, bounds, configurations and output buffers. Planning validates it,
+ * lays out and allocates the plan's own scratch once, uploads the job tables
+ * once and captures the whole launch sequence of stz_compress_batch
+ * (stz_decompress_batch) into a HIP graph. Every device-side clear inside the
+ * graph is a kernel. stz_batch_run replays the graph on `stream` with no host
+ * work, no allocation and no synchronization; the contents of the inputs may
+ * change between runs (the outputs are then exactly those of the eager call
+ * on the new data). Statuses and compressed sizes stay on the device until
+ * stz_batch_status reads them. Runs of one plan must not overlap (they share
+ * its scratch); resident fields of a decode plan must stay open. Invalid
+ * entries are left out of the graph and keep their validation status. */
+typedef struct stz_batch_s* stz_batch;
+
+/* Plan and capture a compression batch; `jobs` (host, njobs <= STZ_MAX_BATCH)
+ * is read during the call only. */
+stz_status stz_compress_batch_plan(const stz_job* jobs, uint64_t njobs, stz_batch* plan,
+                                   void* stream);
+/* Plan and capture a decode batch of `n` requests (host array, read during
+ * the call only; out_dims and status are not written here). */
+stz_status stz_decompress_batch_plan(const stz_request* reqs, uint64_t n, stz_batch* plan,
+                                     void* stream);
+/* Enqueue one replay of the plan's graph on `stream` (asynchronous). */
+stz_status stz_batch_run(stz_batch plan, void* stream);
+/* Synchronize `stream` and report the last run: for a compression plan
+ * jobs[i].status and out_size, for a decode plan reqs[i].status (corruption
+ * found on the device gives STZ_ERR_CORRUPT); n must equal the planned count
+ * and the other array pointer may be NULL. Returns the first failing status. */
+stz_status stz_batch_status(stz_batch plan, stz_job* jobs, stz_request* reqs, uint64_t n,
+                            void* stream);
+/* Synchronizes the plan's device, then frees the graph and its scratch. */
+void stz_batch_destroy(stz_batch plan);
+
+
 /* ---- ROI selection (Sec. 3.3, flexible scientific workflow) ---------------
  * Decodes the resident field at progressive level `level` (cheap at coarse
  * levels), computes for every unit the maximum (stat 0) or the value range

@@ -1169,6 +1169,308 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
 
 }  // extern "C"
 
+// ---- captured batches (HIP graphs) -------------------------------------------
+namespace stz {
+namespace {
+
+// Fills n words with v: the only way a captured graph clears memory (no
+// memset nodes).
+__global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Scratch owned by a plan: laid out by a Workspace, allocated once.
+bool own_workspace(Workspace& ws, char** owned) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<uint64_t>(ws.size, 256)) != hipSuccess) return false;
+  *owned = static_cast<char*>(p);
+  ws.base = *owned;
+  return true;
+}
+
+// Capture whatever `launch` enqueues into an executable graph, on a private
+// stream (the caller's may be the legacy stream, which cannot capture).
+template <class F>
+stz_status capture_graph(F launch, hipGraph_t* g, hipGraphExec_t* x) {
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STZ_ERR_DEVICE;
+  stz_status s = STZ_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    s = STZ_ERR_DEVICE;
+  } else {
+    const bool ok = launch(cs);
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(cs, &graph) != hipSuccess || !ok || !graph) {
+      s = STZ_ERR_DEVICE;
+      if (graph) (void)hipGraphDestroy(graph);
+    } else if (hipGraphInstantiate(x, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      s = STZ_ERR_DEVICE;
+    } else {
+      *g = graph;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  return s;
+}
+
+}  // namespace
+}  // namespace stz
+
+struct stz_batch_s {
+  int kind = 0;  // 0 compression, 1 decoding
+  int device = 0;
+  uint64_t n = 0;                  // jobs or requests
+  std::vector<int32_t> status;     // validation status per entry
+  std::vector<uint32_t> live;      // entries in the graph
+  char* scratch = nullptr;         // plan-owned device memory
+  stz::DevParams* dpar = nullptr;  // compression: per-live-job parameters
+  uint32_t* flags = nullptr;       // decoding: per-live-request corruption flag
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace stz {
+namespace {
+
+void destroy_plan(stz_batch_s* b) {
+  if (!b) return;
+  int cur = 0;
+  const bool sw = hipGetDevice(&cur) == hipSuccess && cur != b->device;
+  if (sw) (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->scratch) (void)hipFree(b->scratch);
+  if (sw) (void)hipSetDevice(cur);
+  delete b;
+}
+
+}  // namespace
+}  // namespace stz
+
+extern "C" {
+
+stz_status stz_compress_batch_plan(const stz_job* jobs, uint64_t njobs, stz_batch* plan,
+                                   void* stream) {
+  if (!plan) return STZ_ERR_ARG;
+  *plan = nullptr;
+  if ((!jobs && njobs) || njobs > STZ_MAX_BATCH) return STZ_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto* B = new (std::nothrow) stz_batch_s;
+  if (!B) return STZ_ERR_NOMEM;
+  B->kind = 0;
+  B->n = njobs;
+  B->status.assign(njobs, STZ_OK);
+  if (hipGetDevice(&B->device) != hipSuccess) {
+    delete B;
+    return STZ_ERR_DEVICE;
+  }
+  std::vector<CompressPlan> pl(njobs);
+  for (uint64_t i = 0; i < njobs; ++i) {
+    B->status[i] = jobs[i].reserved ? STZ_ERR_ARG
+                                    : pl[i].init(jobs[i].x, 4, jobs[i].dims, jobs[i].eb_mode,
+                                                 jobs[i].eb, &jobs[i].cfg, jobs[i].out,
+                                                 jobs[i].out_cap);
+    if (B->status[i] == STZ_OK) B->live.push_back(uint32_t(i));
+  }
+  const uint32_t nl = uint32_t(B->live.size());
+  if (nl == 0) {
+    *plan = B;
+    return STZ_OK;
+  }
+  Workspace ws(st);
+  const uint64_t o_params = ws.take<DevParams>(nl);
+  for (uint32_t k = 0; k < nl; ++k) pl[B->live[k]].take(ws);
+  const uint64_t o_jobs = ws.take<CompressArgs>(nl);
+  BatchMaps maps;
+  CompressBatch b;
+  build_compress_maps(pl, B->live, &maps, &b);
+  const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
+  const uint64_t ab = compress_batch_args_bytes(nl, b.max_levels);
+  const uint64_t o_args = ws.take<uint8_t>(ab);
+  if (!own_workspace(ws, &B->scratch)) {
+    destroy_plan(B);
+    return STZ_ERR_NOMEM;
+  }
+  B->dpar = ws.at<DevParams>(o_params);
+  for (uint32_t k = 0; k < nl; ++k) pl[B->live[k]].bind(ws, B->dpar + k);
+  std::vector<CompressArgs> hj(nl);
+  for (uint32_t k = 0; k < nl; ++k) hj[k] = pl[B->live[k]].a;
+  std::vector<uint8_t> ha(ab);
+  build_compress_batch_args(hj.data(), nl, b.max_levels, ha.data());
+  CompressArgs* dj = ws.at<CompressArgs>(o_jobs);
+  uint32_t* dm = ws.at<uint32_t>(o_maps);
+  uint8_t* da = ws.at<uint8_t>(o_args);
+  if (hipMemcpy(dj, hj.data(), nl * sizeof(CompressArgs), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dm, maps.buf.data(), maps.buf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(da, ha.data(), ab, hipMemcpyHostToDevice) != hipSuccess) {
+    destroy_plan(B);
+    return STZ_ERR_DEVICE;
+  }
+  b.J = dj;
+  b.args = da;
+  maps.bind(dm);
+  const stz_status s = capture_graph(
+      [&](hipStream_t cs) { return launch_compress_batch(b, cs) == hipSuccess; }, &B->graph,
+      &B->exec);
+  if (s != STZ_OK) {
+    destroy_plan(B);
+    return s;
+  }
+  *plan = B;
+  return STZ_OK;
+}
+
+stz_status stz_decompress_batch_plan(const stz_request* reqs, uint64_t n, stz_batch* plan,
+                                     void* stream) {
+  if (!plan) return STZ_ERR_ARG;
+  *plan = nullptr;
+  if ((!reqs && n) || n > STZ_MAX_BATCH) return STZ_ERR_ARG;
+  (void)stream;
+  auto* B = new (std::nothrow) stz_batch_s;
+  if (!B) return STZ_ERR_NOMEM;
+  B->kind = 1;
+  B->n = n;
+  B->status.assign(n, STZ_OK);
+  if (hipGetDevice(&B->device) != hipSuccess) {
+    delete B;
+    return STZ_ERR_DEVICE;
+  }
+  std::vector<DecodePlan> pl(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    const stz_request& r = reqs[i];
+    if (!r.field || r.reserved) {
+      B->status[i] = STZ_ERR_ARG;
+      continue;
+    }
+    Box box;
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+      ok = ok && r.lo[d] < (uint64_t(1) << 40) && r.hi[d] < (uint64_t(1) << 40);
+      box.lo[d] = int64_t(r.lo[d]);
+      box.hi[d] = int64_t(r.hi[d]);
+    }
+    if (!ok || r.level > 64 || r.field->h.vb != 4) {
+      B->status[i] = STZ_ERR_ARG;
+      continue;
+    }
+    B->status[i] = pl[i].init(r.field->h, r.field->comp, r.field->size, &box, int(r.level),
+                              r.out, r.out_cap_elems);
+    if (B->status[i] == STZ_OK && pl[i].cnt) B->live.push_back(uint32_t(i));
+  }
+  const uint32_t nl = uint32_t(B->live.size());
+  if (nl == 0) {
+    *plan = B;
+    return STZ_OK;
+  }
+  Workspace ws(nullptr);
+  for (uint32_t k = 0; k < nl; ++k) pl[B->live[k]].take(ws);
+  const uint64_t o_req = ws.take<DecodeArgs>(nl);
+  const uint64_t o_flags = ws.take<uint32_t>(nl);
+  BatchMaps maps;
+  DecodeBatch b;
+  std::vector<DirectItem> direct;
+  build_decode_maps(pl, B->live, &maps, &b, &direct);
+  const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
+  const uint64_t ab = decode_batch_args_bytes(nl, b.max_level);
+  const uint64_t o_args = ws.take<uint8_t>(ab);
+  if (!own_workspace(ws, &B->scratch)) {
+    destroy_plan(B);
+    return STZ_ERR_NOMEM;
+  }
+  B->flags = ws.at<uint32_t>(o_flags);
+  std::vector<DecodeArgs> hr(nl);
+  for (uint32_t k = 0; k < nl; ++k) {
+    pl[B->live[k]].bind(ws, reqs[B->live[k]].field->lut, B->flags + k);
+    hr[k] = pl[B->live[k]].a;
+  }
+  std::vector<uint8_t> ha(ab);
+  build_decode_batch_args(hr.data(), nl, b.max_level, ha.data());
+  DecodeArgs* dr = ws.at<DecodeArgs>(o_req);
+  uint32_t* dm = ws.at<uint32_t>(o_maps);
+  uint8_t* da = ws.at<uint8_t>(o_args);
+  if (hipMemcpy(dr, hr.data(), nl * sizeof(DecodeArgs), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dm, maps.buf.data(), maps.buf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(da, ha.data(), ab, hipMemcpyHostToDevice) != hipSuccess) {
+    destroy_plan(B);
+    return STZ_ERR_DEVICE;
+  }
+  b.R = dr;
+  b.args = da;
+  b.host_R = hr.data();
+  b.direct = direct.data();
+  b.n_direct = uint32_t(direct.size());
+  maps.bind(dm);
+  uint32_t* flags = B->flags;
+  const stz_status s = capture_graph(
+      [&](hipStream_t cs) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(std::min<uint32_t>((nl + 255) / 256, 1024)),
+                           dim3(256), 0, cs, flags, nl, 0u);
+        return launch_decode_batch(b, cs) == hipSuccess;
+      },
+      &B->graph, &B->exec);
+  if (s != STZ_OK) {
+    destroy_plan(B);
+    return s;
+  }
+  *plan = B;
+  return STZ_OK;
+}
+
+stz_status stz_batch_run(stz_batch plan, void* stream) {
+  if (!plan) return STZ_ERR_ARG;
+  if (!plan->exec) return STZ_OK;
+  return hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? STZ_OK
+             : STZ_ERR_DEVICE;
+}
+
+stz_status stz_batch_status(stz_batch plan, stz_job* jobs, stz_request* reqs, uint64_t n,
+                            void* stream) {
+  if (!plan || n != plan->n) return STZ_ERR_ARG;
+  if (plan->kind == 0 ? !jobs && n : !reqs && n) return STZ_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t nl = uint32_t(plan->live.size());
+  std::vector<DevParams> hp(plan->kind == 0 ? nl : 0);
+  std::vector<uint32_t> hf(plan->kind == 1 ? nl : 0);
+  if (nl) {
+    const hipError_t e =
+        plan->kind == 0
+            ? hipMemcpyAsync(hp.data(), plan->dpar, nl * sizeof(DevParams), hipMemcpyDeviceToHost,
+                             st)
+            : hipMemcpyAsync(hf.data(), plan->flags, nl * 4, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return STZ_ERR_DEVICE;
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    if (plan->kind == 0) {
+      jobs[i].status = plan->status[i];
+      jobs[i].out_size = 0;
+    } else {
+      reqs[i].status = plan->status[i];
+    }
+  }
+  for (uint32_t k = 0; k < nl; ++k) {
+    const uint32_t i = plan->live[k];
+    if (plan->kind == 0) {
+      jobs[i].out_size = hp[k].total;
+      jobs[i].status = params_status(hp[k]);
+    } else if (hf[k]) {
+      reqs[i].status = STZ_ERR_CORRUPT;
+    }
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    const int32_t v = plan->kind == 0 ? jobs[i].status : reqs[i].status;
+    if (v != STZ_OK) return static_cast<stz_status>(v);
+  }
+  return STZ_OK;
+}
+
+void stz_batch_destroy(stz_batch plan) { stz::destroy_plan(plan); }
+
+}  // extern "C"
+
 namespace stz {
 namespace {
 

@@ -62,10 +62,16 @@ bool on(Prof& p) {
 
 }  // namespace
 
+// Streams being captured into a graph get no timing events.
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 void prof_begin(hipStream_t st, const char* name, int level) {
   Prof& p = prof();
   std::lock_guard<std::mutex> lk(p.mu);
-  if (!on(p)) return;
+  if (!on(p) || capturing(st)) return;
   Pending q;
   char buf[64];
   std::snprintf(buf, sizeof(buf), level >= 0 ? "%s@%d" : "%s", name, level);
@@ -80,7 +86,7 @@ void prof_begin(hipStream_t st, const char* name, int level) {
 void prof_end(hipStream_t st) {
   Prof& p = prof();
   std::lock_guard<std::mutex> lk(p.mu);
-  if (!p.enabled || p.pending.empty()) return;
+  if (!p.enabled || p.pending.empty() || capturing(st)) return;
   (void)hipEventRecord(p.pending.back().e1, st);
 }
 

@@ -97,6 +97,19 @@ def lib():
         L.stz_decompress_batch.restype = C.c_int
         L.stz_decompress_batch.argtypes = [C.POINTER(Request), C.c_uint64, C.c_void_p,
                                            C.c_void_p]
+        L.stz_compress_batch_plan.restype = C.c_int
+        L.stz_compress_batch_plan.argtypes = [C.POINTER(Job), C.c_uint64, C.POINTER(C.c_void_p),
+                                              C.c_void_p]
+        L.stz_decompress_batch_plan.restype = C.c_int
+        L.stz_decompress_batch_plan.argtypes = [C.POINTER(Request), C.c_uint64,
+                                                C.POINTER(C.c_void_p), C.c_void_p]
+        L.stz_batch_run.restype = C.c_int
+        L.stz_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+        L.stz_batch_status.restype = C.c_int
+        L.stz_batch_status.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                       C.c_void_p]
+        L.stz_batch_destroy.restype = None
+        L.stz_batch_destroy.argtypes = [C.c_void_p]
         L.stz_autotune_batch.restype = C.c_int
         L.stz_autotune_batch.argtypes = [C.POINTER(Job), C.c_uint64, C.c_char_p, C.c_uint64,
                                          C.c_void_p]
@@ -405,6 +418,50 @@ def stz_decompress_batch(reqs, flags=None, stream=None, check=True):
     if check and st != OK:
         raise StzError(st, "stz_decompress_batch")
     return st
+
+
+# ---- captured batches (HIP graphs) ------------------------------------------
+class BatchPlan:
+    """A compression plan over a job array (stz_compress_batch_plan) or a
+    decode plan over a request array (stz_decompress_batch_plan): run()
+    replays the captured graph asynchronously, status() reads the last run."""
+
+    def __init__(self, jobs=None, reqs=None, stream=None):
+        h = C.c_void_p()
+        if (jobs is None) == (reqs is None):
+            raise ValueError("give exactly one of jobs, reqs")
+        self.jobs, self.reqs = jobs, reqs
+        if jobs is not None:
+            st = lib().stz_compress_batch_plan(jobs, len(jobs), C.byref(h), _stream(stream))
+            what = "stz_compress_batch_plan"
+        else:
+            st = lib().stz_decompress_batch_plan(reqs, len(reqs), C.byref(h), _stream(stream))
+            what = "stz_decompress_batch_plan"
+        if st != OK:
+            raise StzError(st, what)
+        self.handle = h
+
+    def run(self, stream=None):
+        st = lib().stz_batch_run(self.handle, _stream(stream))
+        if st != OK:
+            raise StzError(st, "stz_batch_run")
+
+    def status(self, stream=None):
+        """Synchronize and write the last run's statuses (and sizes) into the
+        planned array; returns the first failing status."""
+        n = len(self.jobs) if self.jobs is not None else len(self.reqs)
+        return lib().stz_batch_status(self.handle, self.jobs, self.reqs, n, _stream(stream))
+
+    def close(self):
+        if self.handle:
+            lib().stz_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass
 
 
 # ---- ROI selection ------------------------------------------------------------

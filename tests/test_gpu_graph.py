@@ -1,0 +1,177 @@
+"""GPU: captured batches (stz_compress_batch_plan / stz_decompress_batch_plan
+and stz_batch_run). Every replay of a plan's HIP graph must give exactly the
+bytes (decoded values) of the eager batched call on the same data, and, for
+the fields checked here, the CPU oracle's; replays alternate with eager work
+and synchronizations, the input contents change between replays (the plan
+keeps only pointers and shapes), and statuses come back only through
+stz_batch_status."""
+import numpy as np
+import pytest
+
+from paper_2509_01626_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2509_01626_amd import stz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    stz.lib()
+    return torch.device("cuda:0")
+
+
+def _batch(n, seed, lo=8, hi=56):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        dims = tuple(int(v) for v in rng.integers(lo, hi + 1, size=3))
+        x = fields.bumps(dims, seed=seed + i, n_bumps=6) if i % 2 == 0 else \
+            fields.spectral(dims, 5 / 3, seed=seed + i)
+        eb = float(10 ** rng.uniform(-4, -2))
+        B = int(rng.choice([4, 8, 16, 32]))
+        out.append((x, eb, B))
+    return out
+
+
+def test_compress_plan_replays_match_eager_and_oracle(gpu, oracle):
+    import torch
+
+    from paper_2509_01626_amd import stz
+    batch = _batch(12, seed=900)
+    xs = [torch.from_numpy(x).to(gpu) for x, _, _ in batch]
+    cfgs = [stz.config(block=B) for _, _, B in batch]
+    ebs = [eb for _, eb, _ in batch]
+    outs_e = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8, device=gpu)
+              for x, c in zip(xs, cfgs)]
+    outs_g = [torch.zeros_like(o) for o in outs_e]
+    jobs_g = stz.make_jobs(xs, [stz.EB_REL] * len(xs), ebs, cfgs, outs_g)
+    plan = stz.BatchPlan(jobs=jobs_g)
+    for rep in range(4):
+        if rep == 2:  # new contents, same shapes: the plan must follow the data
+            for i, x in enumerate(xs):
+                x.mul_(1.5).add_(0.25)
+        print(f"[graph] compress replay {rep}", flush=True)
+        plan.run()
+        assert plan.status() == stz.OK
+        comps_e, jobs_e = stz.stz_compress_batch(xs, [stz.EB_REL] * len(xs), ebs, cfgs, outs_e)
+        torch.cuda.synchronize()
+        for i in range(len(xs)):
+            assert jobs_g[i].status == stz.OK
+            assert jobs_g[i].out_size == jobs_e[i].out_size, (rep, i)
+            got = outs_g[i][:jobs_g[i].out_size].cpu().numpy().tobytes()
+            assert got == comps_e[i].cpu().numpy().tobytes(), (rep, i)
+            if rep in (0, 3) and i < 4:
+                want = oracle.compress(xs[i].cpu().numpy(), oracle.EB_REL, ebs[i],
+                                       oracle.config(block=batch[i][2]))
+                assert got == want, (rep, i)
+    plan.close()
+
+
+def test_compress_plan_statuses(gpu):
+    import torch
+
+    from paper_2509_01626_amd import stz
+    x = torch.from_numpy(fields.spectral((20, 21, 22), 5 / 3, seed=4)).to(gpu)
+    bad = x.clone()
+    bad[3, 4, 5] = float("nan")
+    cfg = stz.config(block=8)
+    cap = stz.stz_compress_bound(x.shape, cfg)
+    outs = [torch.empty(cap, dtype=torch.uint8, device=gpu) for _ in range(4)]
+    outs[2] = torch.empty(64, dtype=torch.uint8, device=gpu)
+    jobs = stz.make_jobs([x, bad, x, x], [stz.EB_REL] * 4, [1e-3, 1e-3, 1e-3, -1.0],
+                         [cfg] * 4, outs)
+    plan = stz.BatchPlan(jobs=jobs)
+    plan.run()
+    st = plan.status()
+    assert [jobs[i].status for i in range(4)] == [stz.OK, stz.ERR_NONFINITE, stz.ERR_BUFFER,
+                                                  stz.ERR_ARG]
+    assert st == stz.ERR_NONFINITE
+    ref = stz.stz_compress(x, stz.EB_REL, 1e-3, cfg).cpu().numpy().tobytes()
+    assert outs[0][:jobs[0].out_size].cpu().numpy().tobytes() == ref
+    plan.close()
+
+
+def test_decode_plan_replays_match_eager_and_oracle(gpu, oracle):
+    import torch
+
+    from paper_2509_01626_amd import stz
+    batch = _batch(6, seed=950, lo=10, hi=48)
+    comps, hosts = [], []
+    for x, eb, B in batch:
+        c = stz.stz_compress(torch.from_numpy(x).to(gpu), stz.EB_REL, eb, stz.config(block=B))
+        comps.append(c)
+        hosts.append(c.cpu().numpy().tobytes())
+    flds = [stz.Field(c) for c in comps]
+    rng = np.random.default_rng(17)
+    reqs = []
+    for _ in range(30):
+        k = int(rng.integers(0, len(flds)))
+        dims = [int(v) for v in flds[k].info.dims]
+        lo = [int(rng.integers(0, d)) for d in dims]
+        hi = [int(rng.integers(a + 1, d + 1)) for a, d in zip(lo, dims)]
+        reqs.append((k, lo, hi, int(rng.integers(0, flds[k].info.levels + 1))))
+    for k in (0, 1):
+        reqs.append((k, [0, 0, 0], [int(v) for v in flds[k].info.dims], flds[k].info.levels))
+    items_g, items_e, outs_g, outs_e = [], [], [], []
+    for k, lo, hi, lv in reqs:
+        shp = stz.region_shape(flds[k].info, lo, hi, lv)
+        n = max(1, shp[0] * shp[1] * shp[2])
+        og = torch.full((n,), -5.0, dtype=torch.float32, device=gpu)
+        oe = torch.full((n,), -5.0, dtype=torch.float32, device=gpu)
+        outs_g.append(og)
+        outs_e.append(oe)
+        items_g.append((flds[k], lo, hi, lv, og))
+        items_e.append((flds[k], lo, hi, lv, oe))
+    arr_g = stz.make_requests(items_g)
+    plan = stz.BatchPlan(reqs=arr_g)
+    arr_e = stz.make_requests(items_e)
+    for rep in range(3):
+        for o in outs_g + outs_e:
+            o.fill_(-5.0)
+        print(f"[graph] decode replay {rep}", flush=True)
+        plan.run()
+        assert plan.status() == stz.OK
+        stz.stz_decompress_batch(arr_e)
+        torch.cuda.synchronize()
+        for i, (k, lo, hi, lv) in enumerate(reqs):
+            assert torch.equal(outs_g[i].view(torch.int32), outs_e[i].view(torch.int32)), (rep, i)
+            if rep == 1:
+                ref = oracle.decompress_region(hosts[k], lo, hi, lv).reshape(-1)
+                got = outs_g[i][:ref.size].cpu().numpy()
+                assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (i, k, lo, hi, lv)
+    plan.close()
+    for f in flds:
+        f.close()
+
+
+def test_decode_plan_reports_corruption(gpu):
+    import torch
+
+    from paper_2509_01626_amd import stz
+    x = torch.from_numpy(fields.spectral((32, 32, 32), 5 / 3, seed=9)).to(gpu)
+    comp = stz.stz_compress(x, stz.EB_REL, 1e-3, stz.config(block=8))
+    bad = comp.clone()
+    f_ok, f_bad = stz.Field(comp), stz.Field(bad)
+    L = f_ok.info.levels
+    o1 = torch.empty(32 ** 3, dtype=torch.float32, device=gpu)
+    o2 = torch.empty(32 ** 3, dtype=torch.float32, device=gpu)
+    arr = stz.make_requests([(f_ok, [0, 0, 0], [32, 32, 32], L, o1),
+                             (f_bad, [0, 0, 0], [32, 32, 32], L, o2)])
+    plan = stz.BatchPlan(reqs=arr)
+    plan.run()
+    assert plan.status() == stz.OK
+    tail = bad[-4096:]
+    tail ^= 0x5A   # payload bits of the finest level change after planning
+    plan.run()
+    st = plan.status()
+    assert arr[0].status == stz.OK
+    assert arr[1].status == stz.decode_status(bad, "decompress")
+    assert st == arr[1].status
+    assert torch.equal(o1.view(torch.int32), stz.stz_decompress(comp).reshape(-1).view(torch.int32))
+    plan.close()
+    f_ok.close()
+    f_bad.close()
