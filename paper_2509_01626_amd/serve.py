@@ -14,6 +14,16 @@ time. The loop
 3. polls the in-flight batches' events; a finished batch hands each result to
    ``on_done`` and frees its arena space, which lets more requests in.
 
+Nothing allocates or frees device or pinned memory inside the loop: each
+slot's flag words (device and pinned host) are allocated once, the status
+words come back by an asynchronous copy on the slot's own stream (no call on
+the default stream, which would wait for every slot), and ``prewarm`` sizes
+the library's per-stream scratch and staging for the largest batch up front.
+A result view handed to ``on_done`` is valid only until the callback returns;
+work the callback enqueues on the current stream (a copy of the view, say) is
+ordered before the region is reused: the region goes back to the arena only
+once an event recorded on that stream after the callbacks has completed.
+
 So requests arriving while others are on the GPU join the next batch as soon
 as a slot and memory free up, and batches on different slots overlap on the
 device. Latency = time the host sees the batch finished - arrival time.
@@ -90,15 +100,37 @@ class Server:
         self.fields = fields
         self.arena = Arena(arena_bytes // 4, device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
-        self.busy = [None] * slots        # per slot: (event, batch, flags) or None
+        self.busy = [None] * slots        # per slot: batch in flight, or None
+        self.events = [torch.cuda.Event() for _ in range(slots)]
+        self.dflags = [torch.empty(max_batch, dtype=torch.int32, device=device)
+                       for _ in range(slots)]
+        self.hflags = [torch.empty(max_batch, dtype=torch.int32, pin_memory=True)
+                       for _ in range(slots)]
         self.max_batch = max_batch
         self.device = device
         self.on_done = on_done
         self.waiting = collections.deque()
         self.admitted = []
         self.done = []
+        self.releasing = collections.deque()  # (event, [(off, cap)]) after on_done
         self.batches = 0
         self.batch_sizes = []
+
+    def prewarm(self, field, lo, hi, level):
+        """Decode a full batch of the largest expected request on every slot
+        (into a temporary buffer), so the library's per-stream scratch and
+        pinned staging reach their final size before serving starts."""
+        f = self.fields[field]
+        shp = stz.region_shape(f.info, lo, hi, level)
+        n = max(1, shp[0] * shp[1] * shp[2])
+        tmp = torch.empty(n * self.max_batch, dtype=torch.float32, device=self.device)
+        for s, st in enumerate(self.streams):
+            items = [(f, lo, hi, level, tmp[i * n:(i + 1) * n]) for i in range(self.max_batch)]
+            arr = stz.make_requests(items)
+            with torch.cuda.stream(st):
+                stz.stz_decompress_batch(arr, flags=self.dflags[s], stream=st, check=False)
+            st.synchronize()
+        del tmp
 
     # -- request intake ---------------------------------------------------------------
     def submit(self, req):
@@ -113,6 +145,9 @@ class Server:
         self.waiting.append(req)
 
     def _admit(self):
+        while self.releasing and self.releasing[0][0].query():
+            for o, n in self.releasing.popleft()[1]:
+                self.arena.release(o, n)
         while self.waiting:
             r = self.waiting[0]
             got = self.arena.alloc(max(r.n, 1))
@@ -132,34 +167,41 @@ class Server:
             items = [(self.fields[r.field], r.lo, r.hi, r.level,
                       self.arena.view(r.off, r.cap)) for r in batch]
             arr = stz.make_requests(items)
-            flags = torch.empty(len(batch), dtype=torch.int32, device=self.device)
             st = self.streams[s]
+            nb = len(batch)
             with torch.cuda.stream(st):
-                stz.stz_decompress_batch(arr, flags=flags, stream=st, check=False)
-                ev = torch.cuda.Event()
-                ev.record(st)
+                stz.stz_decompress_batch(arr, flags=self.dflags[s], stream=st, check=False)
+                self.hflags[s][:nb].copy_(self.dflags[s][:nb], non_blocking=True)
+                self.events[s].record(st)
             for i, r in enumerate(batch):
                 r.status = arr[i].status
-            self.busy[s] = (ev, batch, flags)
+            self.busy[s] = batch
             self.batches += 1
-            self.batch_sizes.append(len(batch))
+            self.batch_sizes.append(nb)
 
     def _reap(self):
         for s in range(len(self.streams)):
-            b = self.busy[s]
-            if b is None or not b[0].query():
+            batch = self.busy[s]
+            if batch is None or not self.events[s].query():
                 continue
-            ev, batch, flags = b
             t = time.perf_counter()
-            fl = flags.cpu().tolist()
+            fl = self.hflags[s][:len(batch)].tolist()
+            regions = []
             for r, f in zip(batch, fl):
                 if r.status == stz.OK and f:
                     r.status = stz.ERR_CORRUPT
                 r.t_done = t
                 if self.on_done is not None:
                     self.on_done(r, self.arena.view(r.off, max(r.n, 1))[:r.n].view(r.shape))
-                self.arena.release(r.off, r.cap)
+                regions.append((r.off, r.cap))
                 self.done.append(r)
+            if self.on_done is not None:
+                ev = torch.cuda.Event()
+                ev.record(torch.cuda.current_stream(self.device))
+                self.releasing.append((ev, regions))
+            else:
+                for o, n in regions:
+                    self.arena.release(o, n)
             self.busy[s] = None
 
     def step(self):
@@ -168,7 +210,8 @@ class Server:
         self._launch()
 
     def idle(self):
-        return not self.waiting and not self.admitted and all(b is None for b in self.busy)
+        return (not self.waiting and not self.admitted and not self.releasing and
+                all(b is None for b in self.busy))
 
     # -- driver ---------------------------------------------------------------------
     def run(self, arrivals):
@@ -211,13 +254,17 @@ def poisson_arrivals(rng, n, rate, fields_info, edge=(16, 256)):
 
 
 def latency_stats(done):
+    """Latency percentiles (nearest rank on the sorted latencies), mean and
+    maximum, in ms, over the requests that succeeded."""
     lat = sorted((r.t_done - r.t_arrive) for r in done if r.status == stz.OK)
     if not lat:
-        return {"p50_ms": None, "p99_ms": None, "mean_ms": None}
+        return {"p50_ms": None, "p99_ms": None, "p999_ms": None, "max_ms": None,
+                "mean_ms": None}
 
     def pct(p):
         i = min(len(lat) - 1, max(0, int(round(p / 100.0 * (len(lat) - 1)))))
         return lat[i] * 1e3
 
     return {"p50_ms": round(pct(50), 3), "p99_ms": round(pct(99), 3),
+            "p999_ms": round(pct(99.9), 3), "max_ms": round(lat[-1] * 1e3, 3),
             "mean_ms": round(sum(lat) / len(lat) * 1e3, 3)}

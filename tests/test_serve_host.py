@@ -52,3 +52,4 @@ def test_latency_percentiles():
     st = serve.latency_stats(done)
     assert st["p50_ms"] == 51.0 or st["p50_ms"] == 50.0
     assert st["p99_ms"] == 99.0
+    assert st["p999_ms"] == 100.0 and st["max_ms"] == 100.0
