@@ -42,8 +42,10 @@ def parse():
     ap.add_argument("--scale-n", type=int, default=1024,
                     help="edge of the 4 co-located variables (0 = skip)")
     ap.add_argument("--serve-fields", type=int, default=16, help="resident fields (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=2000,
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=500,
+                    help="uncounted requests before each offered load")
     ap.add_argument("--serve-rates", default="1000,4000,16000",
                     help="offered loads, requests per second")
     ap.add_argument("--f64-dims", default="256,256,2048",
@@ -420,6 +422,27 @@ def bench_batched(args, dev, oracle_check=True):
                  for a, b in zip(recon, recon_b))
     ok_bound = all(float((r - x).abs().max()) <= f.info.eb_abs * (1 + 1e-6)
                    for r, x, f in zip(recon_b, xs, flds))
+    # the same batches captured once in HIP graphs and replayed
+    outs_g = [torch.empty_like(o) for o in outs]
+    jobs_g = stz.make_jobs(xs, modes, ebs, cfgs, outs_g)
+    plan_c = stz.BatchPlan(jobs=jobs_g)
+    plan_c.run()
+    t_gc = _sync_time(plan_c.run, args.steps)
+    same_gc = plan_c.status() == stz.OK and all(
+        jobs_g[i].out_size == sizes[i] and torch.equal(outs_g[i][:sizes[i]], comps[i])
+        for i in range(len(xs)))
+    plan_c.close()
+    del outs_g
+    recon_g = [torch.empty_like(x) for x in xs]
+    reqs_g = stz.make_requests([(f, [0, 0, 0], list(x.shape), f.info.levels, r)
+                                for f, x, r in zip(flds, xs, recon_g)])
+    plan_d = stz.BatchPlan(reqs=reqs_g)
+    plan_d.run()
+    t_gd = _sync_time(plan_d.run, args.steps)
+    same_gd = plan_d.status() == stz.OK and all(
+        torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(recon, recon_g))
+    plan_d.close()
+    del recon_g
     oracle_ok = None
     if oracle_check:
         from oracle import oracle as O
@@ -428,6 +451,9 @@ def bench_batched(args, dev, oracle_check=True):
         for i in order:
             want = O.compress(xs[i].cpu().numpy(), O.EB_REL, ebs[i], O.config(block=B))
             oracle_ok = oracle_ok and want == comps[i].cpu().numpy().tobytes()
+            ref = O.decompress(want).reshape(-1)
+            oracle_ok = oracle_ok and np.array_equal(
+                recon_b[i].reshape(-1).cpu().numpy().view(np.uint32), ref.view(np.uint32))
     for f in flds:
         f.close()
     cr = fbytes / sum(sizes)
@@ -437,12 +463,17 @@ def bench_batched(args, dev, oracle_check=True):
         "fields": len(xs), "values": nvals, "field_gb": round(fbytes / 1e9, 3),
         "compression_ratio": round(cr, 3),
         "compress_gbps": {"plain": round(fbytes / t_pc / 1e9, 2),
-                          "batched": round(fbytes / t_bc / 1e9, 2)},
+                          "batched": round(fbytes / t_bc / 1e9, 2),
+                          "graph": round(fbytes / t_gc / 1e9, 2)},
         "decompress_gbps": {"plain": round(fbytes / t_pd / 1e9, 2),
-                            "batched": round(fbytes / t_bd / 1e9, 2)},
-        "compress_ms": {"plain": round(t_pc * 1e3, 3), "batched": round(t_bc * 1e3, 3)},
-        "decompress_ms": {"plain": round(t_pd * 1e3, 3), "batched": round(t_bd * 1e3, 3)},
+                            "batched": round(fbytes / t_bd / 1e9, 2),
+                            "graph": round(fbytes / t_gd / 1e9, 2)},
+        "compress_ms": {"plain": round(t_pc * 1e3, 3), "batched": round(t_bc * 1e3, 3),
+                        "graph": round(t_gc * 1e3, 3)},
+        "decompress_ms": {"plain": round(t_pd * 1e3, 3), "batched": round(t_bd * 1e3, 3),
+                          "graph": round(t_gd * 1e3, 3)},
         "batched_bytes_equal_plain": bool(same), "batched_decode_equal_plain": bool(same_d),
+        "graph_bytes_equal_eager": bool(same_gc), "graph_decode_equal_eager": bool(same_gd),
         "within_bound": bool(ok_bound), "oracle_sample_equal": oracle_ok,
         "autotune": [ln for ln in report.splitlines() if "tuned" in ln or "default" in ln],
     }
@@ -575,6 +606,7 @@ def bench_coding(args, dev, oracle_check=True):
 def bench_scale(args, dev):
     """4 co-located variables (log-normal density, three velocity components):
     plain per-variable calls vs one batch of 4 jobs, B = 64, rel eb 1e-3."""
+    import numpy as np
     import torch
 
     from paper_2509_01626_amd import fields, stz
@@ -613,7 +645,26 @@ def bench_scale(args, dev):
     t_bc = _sync_time(batch_c, 2)
     sizes = [jobs[i].out_size for i in range(4)]
     same = sizes == sizes_p and all(torch.equal(outs[i][:sizes[i]], ref[i]) for i in range(4))
+    # the batch captured in a HIP graph and replayed into the same buffers
+    jobs_g = stz.make_jobs(xs, [stz.EB_REL] * 4, [1e-3] * 4, [cfg] * 4, outs)
+    plan_c = stz.BatchPlan(jobs=jobs_g)
+    plan_c.run()
+    t_gc = _sync_time(plan_c.run, 2)
+    same_gc = plan_c.status() == stz.OK and all(
+        jobs_g[i].out_size == sizes[i] and torch.equal(outs[i][:sizes[i]], ref[i])
+        for i in range(4))
+    plan_c.close()
     del ref
+    # oracle check on a 256^3 crop of the density (the same B and bound)
+    from oracle import oracle as O
+    crop = xs[0][:256, :256, :256].contiguous()
+    c_crop = stz.stz_compress(crop, stz.EB_REL, 1e-3, cfg)
+    want = O.compress(crop.cpu().numpy(), O.EB_REL, 1e-3, O.config(block=64))
+    oracle_ok = c_crop.cpu().numpy().tobytes() == want
+    oracle_ok = oracle_ok and np.array_equal(
+        stz.stz_decompress(c_crop).cpu().numpy().view(np.uint32),
+        O.decompress(want).view(np.uint32))
+    del crop, c_crop, want
     comps = [outs[i][:sizes[i]] for i in range(4)]
     recon = torch.empty(dims, dtype=torch.float32, device=dev)
     err_ok = True
@@ -642,6 +693,13 @@ def bench_scale(args, dev):
     t_bd = _sync_time(batch_d, 2)
     stz.stz_decompress(comps[3], out=recon)
     same_d = torch.equal(recon.view(torch.int32), outs_d[3].view(torch.int32))
+    outs_d[3].fill_(0)
+    plan_d = stz.BatchPlan(reqs=reqs)
+    plan_d.run()
+    t_gd = _sync_time(plan_d.run, 2)
+    same_gd = plan_d.status() == stz.OK and torch.equal(recon.view(torch.int32),
+                                                         outs_d[3].view(torch.int32))
+    plan_d.close()
     for f in flds:
         f.close()
     res = {
@@ -650,10 +708,14 @@ def bench_scale(args, dev):
         "field_gb": round(fbytes / 1e9, 3),
         "compression_ratio": round(fbytes / sum(sizes), 3),
         "compress_gbps": {"plain": round(fbytes / t_pc / 1e9, 2),
-                          "batched": round(fbytes / t_bc / 1e9, 2)},
+                          "batched": round(fbytes / t_bc / 1e9, 2),
+                          "graph": round(fbytes / t_gc / 1e9, 2)},
         "decompress_gbps": {"plain": round(fbytes / t_pd / 1e9, 2),
-                            "batched": round(fbytes / t_bd / 1e9, 2)},
+                            "batched": round(fbytes / t_bd / 1e9, 2),
+                            "graph": round(fbytes / t_gd / 1e9, 2)},
         "batched_bytes_equal_plain": bool(same), "batched_decode_equal_plain": bool(same_d),
+        "graph_bytes_equal_eager": bool(same_gc), "graph_decode_equal_eager": bool(same_gd),
+        "oracle_crop_256_equal": bool(oracle_ok),
         "within_bound": bool(err_ok),
         "autotune": [ln for ln in report.splitlines() if "tuned" in ln or "default" in ln],
     }
@@ -696,8 +758,11 @@ def bench_serve(args, dev):
             rng = np.random.default_rng(7)
             arr = serve.poisson_arrivals(rng, args.serve_requests, rate, infos)
             srv = serve.Server(flds, arena_bytes=8 << 30, slots=slots, max_batch=mb, device=dev)
+            # scratch and staging sized for the largest request before serving
+            srv.prewarm(0, [0, 0, 0], [256, 256, 256], infos[0].levels)
             # warm-up requests (not counted)
-            srv.run(serve.poisson_arrivals(np.random.default_rng(8), 50, rate, infos))
+            srv.run(serve.poisson_arrivals(np.random.default_rng(8), args.serve_warmup, rate,
+                                           infos))
             srv.done = []
             srv.batch_sizes = []
             srv.batches = 0
@@ -707,7 +772,8 @@ def bench_serve(args, dev):
             st = serve.latency_stats(done)
             ok = sum(1 for r in done if r.status == stz.OK)
             pt[mode] = {"completed_rps": round(ok / wall, 1), "p50_ms": st["p50_ms"],
-                        "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                        "p99_ms": st["p99_ms"], "p999_ms": st["p999_ms"],
+                        "max_ms": st["max_ms"], "mean_ms": st["mean_ms"],
                         "launch_batches": srv.batches,
                         "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)),
                                             2)}
@@ -723,6 +789,7 @@ def bench_serve(args, dev):
         "workload": f"{nf} resident compressed 512^3 k^-5/3 spectral fields (rel eb 1e-3, B=32); "
                     "Poisson requests: uniform field, level U{0..5}, box edge per axis U[16,256]",
         "requests_per_load": args.serve_requests,
+        "warmup_requests": args.serve_warmup,
         "resident_compressed_gb": round(sum(c.numel() for c in comps) / 1e9, 3),
         "load_points": points,
     }
