@@ -1292,6 +1292,7 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
 // with coalesced stores (the last partial word carries into the next chunk).
 constexpr int kPackChunk = 4096;                     // symbols per chunk
 constexpr int kPackPer = kPackChunk / 256;           // per thread
+static_assert(kPackPer % 8 == 0, "a run is whole 16-byte groups");
 constexpr int kPackWords = kPackChunk * kLmax / 32 + 2;
 constexpr int kPackRows = 32 * 32;  // rows (M_z * M_y) of a unit, E <= 64
 
@@ -1320,7 +1321,7 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
   const DevParams* P = a.P;
   if (P->flags) return;
   __shared__ uint32_t LC[kMaxAlphabet];  // code | length << 16
-  __shared__ uint16_t us[kPackChunk];
+  __shared__ __align__(16) uint16_t us[kPackChunk];
   __shared__ uint32_t zf[kPackChunk / 32];  // zero-chunk flags of the buffer (bits)
   __shared__ uint32_t wb[kPackWords];
   __shared__ uint32_t rmask[kPackRows];  // per unit row: columns holding an outlier
@@ -1388,7 +1389,14 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       for (uint32_t i = tid; i < rows; i += 256) rmask[i] = 0;
     for (uint32_t c0 = 0; c0 < n_u; c0 += bstep) {
       const int n = int(min<uint32_t>(bstep, n_u - c0));
-      for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
+      if (((reinterpret_cast<uintptr_t>(src + c0) | uint32_t(n)) & 15) == 0) {
+        // whole 16-byte groups of 8 symbols
+        const uint4* s4 = reinterpret_cast<const uint4*>(src + c0);
+        uint4* d4 = reinterpret_cast<uint4*>(us);
+        for (int i = tid; i < n / 8; i += 256) d4[i] = s4[i];
+      } else {
+        for (int i = tid; i < n; i += 256) us[i] = src[c0 + i];
+      }
       __syncthreads();
       if (zmode == 3) {
         const int nch = n / int(My);
@@ -1407,12 +1415,19 @@ __device__ inline void pack_units_body(const PackArgs& a, int64_t wg) {
       const int i0 = tid * kPackPer;
       uint32_t lc[kPackPer];
       uint32_t rm = 0;  // bit k: symbol k of the run is R
+      // the run's symbols as 16-byte LDS reads of 8 symbols each
 #pragma unroll
-      for (int k = 0; k < kPackPer; ++k) {
-        const bool ok = i0 + k < n;
-        const uint32_t sy = ok ? us[i0 + k] : 0u;
-        lc[k] = ok ? LC[sy] : 0u;
-        rm |= uint32_t(ok && sy == uint32_t(a.g.R)) << k;
+      for (int g = 0; g < kPackPer / 8; ++g) {
+        const uint4 q = reinterpret_cast<const uint4*>(us + i0)[g];
+        const uint32_t sw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+          const int k = 8 * g + h;
+          const bool ok = i0 + k < n;
+          const uint32_t sy = ok ? (sw[h >> 1] >> (16 * (h & 1))) & 0xFFFFu : 0u;
+          lc[k] = ok ? LC[sy] : 0u;
+          rm |= uint32_t(ok && sy == uint32_t(a.g.R)) << k;
+        }
       }
       if (n_out)  // symbol p of the unit: column p / rows, row p % rows
         for (int i = tid; i < n; i += 256)
