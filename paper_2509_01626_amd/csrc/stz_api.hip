@@ -937,21 +937,20 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
     Workspace ws(st);
     const uint64_t o_params = ws.take<DevParams>(nl);
     for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
-    const uint64_t o_jobs = ws.take<CompressArgs>(nl);
     BatchMaps maps;
     CompressBatch b;
     build_compress_maps(pl, live, &maps, &b);
-    const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
+    // one staging blob, laid out as on the device and sent with one copy:
+    // job table | work maps | per-level argument blocks (256-aligned)
+    const uint64_t jb = (uint64_t(nl) * sizeof(CompressArgs) + 15) & ~uint64_t(15);
+    const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
+    const uint64_t ao = (jb + mb + 255) & ~uint64_t(255);
     const uint64_t ab = compress_batch_args_bytes(nl, b.max_levels);
-    const uint64_t o_args = ws.take<uint8_t>(ab);
+    const uint64_t o_blob = ws.take<uint8_t>(ao + ab);
     if (!ws.commit()) return STZ_ERR_NOMEM;
     DevParams* dpar = ws.at<DevParams>(o_params);
     for (uint32_t k = 0; k < nl; ++k) pl[live[k]].bind(ws, dpar + k);
     HostBuf& hb = host_buf(st);
-    // staging: job table | work maps | per-level argument blocks (256-aligned)
-    const uint64_t jb = uint64_t(nl) * sizeof(CompressArgs);
-    const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
-    const uint64_t ao = (jb + mb + 255) & ~uint64_t(255);
     const uint64_t pb = uint64_t(nl) * sizeof(DevParams);
     if (!hb.reserve(std::max(ao + ab, pb))) return STZ_ERR_NOMEM;
     for (uint32_t k = 0; k < nl; ++k)
@@ -959,12 +958,11 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
     std::memcpy(hb.p + jb, maps.buf.data(), mb);
     build_compress_batch_args(reinterpret_cast<const CompressArgs*>(hb.p), nl, b.max_levels,
                               hb.p + ao);
-    CompressArgs* dj = ws.at<CompressArgs>(o_jobs);
-    uint32_t* dm = ws.at<uint32_t>(o_maps);
-    uint8_t* da = ws.at<uint8_t>(o_args);
-    if (hipMemcpyAsync(dj, hb.p, jb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(dm, hb.p + jb, mb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(da, hb.p + ao, ab, hipMemcpyHostToDevice, st) != hipSuccess)
+    uint8_t* blob = ws.at<uint8_t>(o_blob);
+    CompressArgs* dj = reinterpret_cast<CompressArgs*>(blob);
+    uint32_t* dm = reinterpret_cast<uint32_t*>(blob + jb);
+    uint8_t* da = blob + ao;
+    if (hipMemcpyAsync(blob, hb.p, ao + ab, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
     b.J = dj;
     b.args = da;
@@ -1097,31 +1095,31 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
   BatchMaps maps;
   DecodeBatch b;
   std::vector<DirectItem> direct;
-  uint64_t o_req = 0, o_flags = 0, o_maps = 0, o_args = 0;
-  if (nl) {
-    for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
-    o_req = ws.take<DecodeArgs>(nl);
-    o_flags = ws.take<uint32_t>(nl);
-    build_decode_maps(pl, live, &maps, &b, &direct);
-    o_maps = ws.take<uint32_t>(maps.buf.size());
-    o_args = ws.take<uint8_t>(decode_batch_args_bytes(nl, b.max_level));
-    if (!ws.commit()) return STZ_ERR_NOMEM;
-  }
-  // Host staging: request table | work maps | zero flags | zero caller flags |
-  // per-level argument blocks (256-aligned).
-  const uint64_t rb = uint64_t(nl) * sizeof(DecodeArgs);
+  if (nl) build_decode_maps(pl, live, &maps, &b, &direct);
+  // One staging blob, laid out as on the device and sent with one copy:
+  // request table | work maps | zero flags | per-level argument blocks
+  // (256-aligned); the caller's zero flags follow it in host memory.
+  const uint64_t rb = (uint64_t(nl) * sizeof(DecodeArgs) + 15) & ~uint64_t(15);
   const uint64_t mb = maps.buf.size() * sizeof(uint32_t);
   const uint64_t fb = uint64_t(nl) * 4;
-  const uint64_t cb = dev_flags ? n * 4 : 0;
-  const uint64_t ao = (rb + mb + fb + cb + 255) & ~uint64_t(255);
+  const uint64_t ao = (rb + mb + fb + 255) & ~uint64_t(255);
   const uint64_t ab = nl ? decode_batch_args_bytes(nl, b.max_level) : 0;
-  if (!hb.reserve(ao + ab)) return STZ_ERR_NOMEM;
-  std::memset(hb.p + rb + mb, 0, fb + cb);
+  const uint64_t cb = dev_flags ? n * 4 : 0;
+  uint64_t o_blob = 0;
+  if (nl) {
+    for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
+    o_blob = ws.take<uint8_t>(ao + ab);
+    if (!ws.commit()) return STZ_ERR_NOMEM;
+  }
+  if (!hb.reserve(ao + ab + cb)) return STZ_ERR_NOMEM;
+  std::memset(hb.p + rb + mb, 0, fb);
+  std::memset(hb.p + ao + ab, 0, cb);
   if (dev_flags &&
-      hipMemcpyAsync(dev_flags, hb.p + rb + mb + fb, cb, hipMemcpyHostToDevice, st) != hipSuccess)
+      hipMemcpyAsync(dev_flags, hb.p + ao + ab, cb, hipMemcpyHostToDevice, st) != hipSuccess)
     return STZ_ERR_DEVICE;
   if (nl) {
-    uint32_t* wflags = ws.at<uint32_t>(o_flags);
+    uint8_t* blob = ws.at<uint8_t>(o_blob);
+    uint32_t* wflags = reinterpret_cast<uint32_t*>(blob + rb + mb);
     for (uint32_t k = 0; k < nl; ++k) {
       const stz_request& r = reqs[live[k]];
       pl[live[k]].bind(ws, r.field->lut, dev_flags ? dev_flags + live[k] : wflags + k);
@@ -1131,13 +1129,10 @@ stz_status stz_decompress_batch(stz_request* reqs, uint64_t n, uint32_t* dev_fla
     std::memcpy(hb.p + rb, maps.buf.data(), mb);
     build_decode_batch_args(reinterpret_cast<const DecodeArgs*>(hb.p), nl, b.max_level,
                             hb.p + ao);
-    DecodeArgs* dr = ws.at<DecodeArgs>(o_req);
-    uint32_t* dm = ws.at<uint32_t>(o_maps);
-    uint8_t* da = ws.at<uint8_t>(o_args);
-    if (hipMemcpyAsync(dr, hb.p, rb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(dm, hb.p + rb, mb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(wflags, hb.p + rb + mb, fb, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(da, hb.p + ao, ab, hipMemcpyHostToDevice, st) != hipSuccess)
+    DecodeArgs* dr = reinterpret_cast<DecodeArgs*>(blob);
+    uint32_t* dm = reinterpret_cast<uint32_t*>(blob + rb);
+    uint8_t* da = blob + ao;
+    if (hipMemcpyAsync(blob, hb.p, ao + ab, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
     if (!hb.mark(st)) return STZ_ERR_DEVICE;
     b.R = dr;
