@@ -31,6 +31,7 @@ device. Latency = time the host sees the batch finished - arrival time.
 All decoding runs in the HIP library; this module only schedules.
 """
 import collections
+import gc
 import time
 
 import torch
@@ -101,6 +102,7 @@ class Server:
         self.arena = Arena(arena_bytes // 4, device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
         self.busy = [None] * slots        # per slot: batch in flight, or None
+        self.t_launch = [0.0] * slots
         self.events = [torch.cuda.Event() for _ in range(slots)]
         self.dflags = [torch.empty(max_batch, dtype=torch.int32, device=device)
                        for _ in range(slots)]
@@ -115,12 +117,18 @@ class Server:
         self.releasing = collections.deque()  # (event, [(off, cap)]) after on_done
         self.batches = 0
         self.batch_sizes = []
+        self.trace = []  # per batch: (launch time, time seen done, size)
 
-    def prewarm(self, field, lo, hi, level):
-        """Decode a full batch of the largest expected request on every slot
-        (into a temporary buffer), so the library's per-stream scratch and
-        pinned staging reach their final size before serving starts."""
+    def prewarm(self, field, edge, level):
+        """Decode a full batch of the largest expected request (a box of
+        `edge` points per axis in the middle of the field, whose dependency
+        cone no face clips) on every slot into a temporary buffer, so the
+        library's per-stream scratch and pinned staging reach their final
+        size before serving starts."""
         f = self.fields[field]
+        dims = [int(v) for v in f.info.dims]
+        lo = [max(0, (d - edge) // 2) for d in dims]
+        hi = [min(d, a + edge) for a, d in zip(lo, dims)]
         shp = stz.region_shape(f.info, lo, hi, level)
         n = max(1, shp[0] * shp[1] * shp[2])
         tmp = torch.empty(n * self.max_batch, dtype=torch.float32, device=self.device)
@@ -176,6 +184,7 @@ class Server:
             for i, r in enumerate(batch):
                 r.status = arr[i].status
             self.busy[s] = batch
+            self.t_launch[s] = time.perf_counter()
             self.batches += 1
             self.batch_sizes.append(nb)
 
@@ -185,6 +194,7 @@ class Server:
             if batch is None or not self.events[s].query():
                 continue
             t = time.perf_counter()
+            self.trace.append((self.t_launch[s], t, len(batch)))
             fl = self.hflags[s][:len(batch)].tolist()
             regions = []
             for r, f in zip(batch, fl):
@@ -218,16 +228,24 @@ class Server:
         """arrivals: list of (t_offset_seconds, field, lo, hi, level), sorted by time.
         Submits each at its arrival time (relative to the start) and runs the loop
         until every request is done. Returns the finished requests."""
-        t0 = time.perf_counter()
-        i = 0
-        n = len(arrivals)
-        while i < n or not self.idle():
-            now = time.perf_counter()
-            while i < n and arrivals[i][0] <= now - t0:
-                ta, f, lo, hi, lv = arrivals[i]
-                self.submit(Request(i, f, lo, hi, lv, t0 + ta))
-                i += 1
-            self.step()
+        # Python's cyclic garbage collector is paused while serving: a full
+        # collection over a long run's objects stalls the loop for tens of ms
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            t0 = time.perf_counter()
+            i = 0
+            n = len(arrivals)
+            while i < n or not self.idle():
+                now = time.perf_counter()
+                while i < n and arrivals[i][0] <= now - t0:
+                    ta, f, lo, hi, lv = arrivals[i]
+                    self.submit(Request(i, f, lo, hi, lv, t0 + ta))
+                    i += 1
+                self.step()
+        finally:
+            if gc_was_on:
+                gc.enable()
         return self.done
 
 
