@@ -39,6 +39,8 @@ def parse():
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--batch-fields", type=int, default=256,
                     help="fields in the many-field batch (0 = skip)")
+    ap.add_argument("--block-sweep", type=int, default=1,
+                    help="batched CR and speed of the many-field batch per block edge (0 = skip)")
     ap.add_argument("--scale-n", type=int, default=1024,
                     help="edge of the 4 co-located variables (0 = skip)")
     ap.add_argument("--serve-fields", type=int, default=16, help="resident fields (0 = skip)")
@@ -63,14 +65,21 @@ COPY_PROBE_BYTES = 1 << 30
 def copy_probe():
     """A plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE of
     this kernel against its 1 GiB read and 1 GiB write give the factor that
-    turns those counters into HBM bytes."""
+    turns those counters into HBM bytes. Two reductions then read only the
+    first 64 and the first 32 bytes of every 128-byte line of the same 1 GiB:
+    FETCH_SIZE equal to the copy's shows that every read fetches whole lines,
+    so the factor holds for any access pattern."""
     import torch
     src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+    rows = src.view(-1, 32)  # one 128-byte line per row
+    half = float(rows[:, :16].sum())
+    quarter = float(rows[:, :8].sum())
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES}), flush=True)
+    print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "half_line_sum": half,
+                      "quarter_line_sum": quarter}), flush=True)
 
 
 def kernel_sources_digest():
@@ -456,6 +465,45 @@ def bench_batched(args, dev, oracle_check=True):
                 recon_b[i].reshape(-1).cpu().numpy().view(np.uint32), ref.view(np.uint32))
     for f in flds:
         f.close()
+    # The block edge is part of the format (it changes the bytes), so it is the
+    # caller's choice: batched compression ratio and speed per edge, launch
+    # shapes at their defaults, to show what each choice costs.
+    sweep = []
+    if args.block_sweep:
+        for Bs in (8, 16, 32, 64):
+            cfg_s = [stz.config(block=Bs) for _ in xs]
+            outs_s = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8,
+                                  device=dev) for x, c in zip(xs, cfg_s)]
+            jobs_s = stz.make_jobs(xs, modes, ebs, cfg_s, outs_s)
+
+            def batch_s():
+                st = stz.lib().stz_compress_batch(jobs_s, len(xs), stz._stream())
+                if st != stz.OK:
+                    raise stz.StzError(st, "stz_compress_batch")
+
+            batch_s()
+            t_s = _sync_time(batch_s, args.steps)
+            comps_s = [outs_s[i][:jobs_s[i].out_size] for i in range(len(xs))]
+            flds_s = [stz.Field(c) for c in comps_s]
+            rec_s = [torch.empty_like(x) for x in xs]
+            reqs_s = stz.make_requests([(f, [0, 0, 0], list(x.shape), f.info.levels, r)
+                                        for f, x, r in zip(flds_s, xs, rec_s)])
+
+            def batch_sd():
+                stz.stz_decompress_batch(reqs_s)
+
+            batch_sd()
+            t_sd = _sync_time(batch_sd, args.steps)
+            sweep.append({"block": Bs,
+                          "compression_ratio": round(fbytes / sum(jobs_s[i].out_size
+                                                                  for i in range(len(xs))), 3),
+                          "compress_gbps": round(fbytes / t_s / 1e9, 2),
+                          "decompress_gbps": round(fbytes / t_sd / 1e9, 2)})
+            for f in flds_s:
+                f.close()
+            del outs_s, comps_s, rec_s
+            torch.cuda.empty_cache()
+            print(f"[bench] batch block sweep: {sweep[-1]}", file=sys.stderr, flush=True)
     cr = fbytes / sum(sizes)
     res = {
         "workload": f"{len(xs)} float32 fields, dims per axis U[32,256] (half Gaussian bumps, "
@@ -476,6 +524,7 @@ def bench_batched(args, dev, oracle_check=True):
         "graph_bytes_equal_eager": bool(same_gc), "graph_decode_equal_eager": bool(same_gd),
         "within_bound": bool(ok_bound), "oracle_sample_equal": oracle_ok,
         "autotune": [ln for ln in report.splitlines() if "tuned" in ln or "default" in ln],
+        "block_sweep": sweep,
     }
     del xs, outs, outs_p, recon, recon_b, comps
     torch.cuda.empty_cache()
@@ -759,16 +808,19 @@ def bench_serve(args, dev):
             arr = serve.poisson_arrivals(rng, args.serve_requests, rate, infos)
             srv = serve.Server(flds, arena_bytes=8 << 30, slots=slots, max_batch=mb, device=dev)
             # scratch and staging sized for the largest request before serving
-            srv.prewarm(0, [0, 0, 0], [256, 256, 256], infos[0].levels)
+            srv.prewarm(0, 256, infos[0].levels)
             # warm-up requests (not counted)
             srv.run(serve.poisson_arrivals(np.random.default_rng(8), args.serve_warmup, rate,
                                            infos))
             srv.done = []
             srv.batch_sizes = []
             srv.batches = 0
+            srv.trace = []
             t = time.perf_counter()
             done = srv.run(arr)
             wall = time.perf_counter() - t
+            # the batch that took longest from launch to completion seen
+            wb = max(srv.trace, key=lambda e: e[1] - e[0]) if srv.trace else (t, t, 0)
             st = serve.latency_stats(done)
             ok = sum(1 for r in done if r.status == stz.OK)
             pt[mode] = {"completed_rps": round(ok / wall, 1), "p50_ms": st["p50_ms"],
@@ -776,7 +828,9 @@ def bench_serve(args, dev):
                         "max_ms": st["max_ms"], "mean_ms": st["mean_ms"],
                         "launch_batches": srv.batches,
                         "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)),
-                                            2)}
+                                            2),
+                        "slowest_batch": {"ms": round((wb[1] - wb[0]) * 1e3, 3), "size": wb[2],
+                                          "at_s": round(wb[0] - t, 3)}}
             del srv
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
