@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--coding-n", type=int, default=512,
                     help="edge of the smooth field of the coding section (0 = skip)")
     ap.add_argument("--only", default="",
-                    help="comma list of sections to run: plain,batch,scale,serve,f64,coding")
+                    help="comma list of sections to run: plain,batch,scale,serve,f64,coding,roi")
     return ap.parse_args()
 
 
@@ -346,6 +346,8 @@ def main():
         res["serving"] = bench_serve(args, dev)
     if args.f64_dims and want("f64"):
         res["f64"] = bench_f64(args, dev, oracle_check=not args.no_cpu_baseline)
+    if want("roi"):
+        res["roi"] = bench_roi(args, dev, comp, comp_host, oracle_check=not args.no_cpu_baseline)
     if args.coding_n > 0 and want("coding"):
         res["coding"] = bench_coding(args, dev, oracle_check=not args.no_cpu_baseline)
     print(json.dumps(res), flush=True)
@@ -359,6 +361,53 @@ def _sync_time(f, reps=1):
         f()
     torch.cuda.synchronize()
     return (time.perf_counter() - t) / reps
+
+
+def bench_roi(args, dev, comp, comp_host, oracle_check=True):
+    """ROI selection (Sec. 3.3, flexible workflow) on the workload's field: per
+    progressive level, the first selection of a (level, unit, statistic)
+    decodes the level and keeps the per-unit statistics with the field; later
+    selections (other thresholds or fractions) run from the kept statistics.
+    Latency of both, host-clocked around the synchronous call."""
+    import numpy as np
+
+    from paper_2509_01626_amd import stz
+    f = stz.Field(comp)
+    L = f.info.levels
+    out = {"field": f"{args.n}^3", "block": args.block, "levels": {}}
+    for level in range(L + 1):
+        row = {}
+        for stat, sname in ((stz.ROI_MAX, "max"), (stz.ROI_RANGE, "range")):
+            t = time.perf_counter()
+            sel, st = stz.stz_roi_select(f, level, stz.ROI_BLOCKS, stat,
+                                         stz.ROI_TOP_FRACTION, 0.1)
+            first = time.perf_counter() - t
+            reps = 20
+            t = time.perf_counter()
+            for i in range(reps):
+                sel2, _ = stz.stz_roi_select(f, level, stz.ROI_BLOCKS, stat,
+                                             stz.ROI_TOP_FRACTION, 0.05 + 0.01 * i)
+            cached = (time.perf_counter() - t) / reps
+            t = time.perf_counter()
+            for i in range(reps):
+                stz.stz_roi_select(f, level, stz.ROI_BLOCKS, stat, stz.ROI_THRESHOLD,
+                                   float(st.mean()))
+            thr = (time.perf_counter() - t) / reps
+            row[sname] = {"first_ms": round(first * 1e3, 3), "cached_top_ms": round(cached * 1e3, 3),
+                          "cached_threshold_ms": round(thr * 1e3, 3), "units": int(st.size),
+                          "selected": int(sel.size)}
+        out["levels"][str(level)] = row
+    if oracle_check:
+        from oracle import oracle as ora
+        lv = max(0, L - 2)
+        osel, ost = ora.roi_select(comp_host, lv, stz.ROI_BLOCKS, stz.ROI_RANGE,
+                                   stz.ROI_TOP_FRACTION, 0.1)
+        sel, st = stz.stz_roi_select(f, lv, stz.ROI_BLOCKS, stz.ROI_RANGE,
+                                     stz.ROI_TOP_FRACTION, 0.1)
+        out["oracle_equal_level"] = lv
+        out["oracle_equal"] = bool(np.array_equal(sel, osel) and np.array_equal(st, ost))
+    f.close()
+    return out
 
 
 def bench_batched(args, dev, oracle_check=True):

@@ -299,9 +299,13 @@ void stz_batch_destroy(stz_batch plan);
  * coordinate index * 2^(L-level)). Selected indices go to `sel` (host, cap
  * entries, ascending), their number to *count (host; on STZ_ERR_BUFFER the
  * number needed); `stats` (host, may be NULL) receives every unit's statistic.
- * The statistics are computed on the device; the selection over the
- * per-unit values runs on the host. Fields of either value type. Synchronizes
- * `stream`. */
+ * The statistics are computed on the device and kept with the field: only
+ * the first selection for a (level, unit, statistic) decodes the level; later
+ * ones reuse the statistics. The selection itself (threshold, or the k largest
+ * by rank over all pairs) and the compaction of the selected indices run on
+ * the device too. The kept statistics are freed by stz_close; calls on one
+ * field from several host threads must not overlap. Fields of either value
+ * type. Synchronizes `stream`. */
 stz_status stz_roi_select(stz_field field, uint32_t level, uint32_t unit, uint32_t stat,
                           uint32_t rule, double value, uint32_t* sel, uint64_t cap,
                           uint64_t* count, double* stats, void* stream);

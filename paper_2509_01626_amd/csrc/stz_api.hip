@@ -992,6 +992,13 @@ struct stz_field_s {
   uint16_t* lut = nullptr;  // device decoder table
   uint64_t lut_entries = 0;
   int device = 0;
+  // per-unit ROI statistics already computed, by (level, unit kind, statistic)
+  struct RoiStats {
+    uint32_t key;
+    double* dev;
+    uint64_t n;
+  };
+  std::vector<RoiStats> roi;
 };
 
 extern "C" {
@@ -1054,6 +1061,7 @@ void stz_close(stz_field f) {
   if (hipGetDevice(&cur) == hipSuccess && cur != f->device) (void)hipSetDevice(f->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(f->lut);
+  for (auto& r : f->roi) (void)hipFree(r.dev);
   if (cur != f->device) (void)hipSetDevice(cur);
   delete f;
 }
@@ -1735,62 +1743,86 @@ stz_status stz_roi_select(stz_field f, uint32_t level, uint32_t unit, uint32_t s
   const uint64_t ngrid = uint64_t(gn[0]) * gn[1] * gn[2];
   const uint64_t nunits =
       unit == 0 ? uint64_t(g.nb[0] * g.nb[1] * g.nb[2]) : uint64_t(gn[unit - 1]);
-  // decode the whole domain at `level` into scratch, then the statistics; the
-  // plan is made against a placeholder output and pointed at the scratch grid
-  DecodePlan pl;
-  stz_status s = pl.init(h, f->comp, f->size, nullptr, int(level),
-                         reinterpret_cast<void*>(uintptr_t(256)), ngrid);
-  if (s != STZ_OK) return s;
-  Workspace ws(st);
-  pl.take(ws);
-  const uint64_t o_grid = ws.take<uint8_t>(uint64_t(h.vb) * ngrid);
-  const uint64_t o_stats = ws.take<double>(nunits);
-  const uint64_t o_flags = ws.take<uint32_t>(1);
-  if (!ws.commit()) return STZ_ERR_NOMEM;
-  void* grid = ws.at<uint8_t>(o_grid);
-  uint32_t* dflags = ws.at<uint32_t>(o_flags);
-  pl.a.rec[pl.a.level_out] = grid;
-  pl.bind(ws, f->lut, dflags);
-  Staging* stage = staging();
-  if (!stage) return STZ_ERR_NOMEM;
-  *stage->flags = 0;
-  if (hipMemcpyAsync(dflags, stage->flags, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-      launch_decode(pl.a, st) != hipSuccess)
-    return STZ_ERR_DEVICE;
-  double* dstats = ws.at<double>(o_stats);
-  const int64_t E = int64_t(g.B) >> logs;
-  const int64_t nb[3] = {g.nb[0], g.nb[1], g.nb[2]};
-  if (launch_roi_stats(grid, h.vb, gn, E, int(unit), int(stat), nb, nunits, dstats, st) !=
-      hipSuccess)
-    return STZ_ERR_DEVICE;
+  const uint32_t key = (level << 8) | (unit << 4) | stat;
+  double* dstats = nullptr;
+  for (auto& r : f->roi)
+    if (r.key == key) dstats = r.dev;
   HostBuf& hb = host_buf(st);
-  if (!hb.reserve(nunits * 8 + 8)) return STZ_ERR_NOMEM;
-  if (hipMemcpyAsync(hb.p, dstats, nunits * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(hb.p + nunits * 8, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (!dstats) {
+    // First selection of this kind: decode the whole domain at `level` into
+    // scratch and compute the per-unit statistics into device memory the field
+    // keeps, so later selections need no decode. The plan is made against a
+    // placeholder output and pointed at the scratch grid.
+    if (hipMalloc(reinterpret_cast<void**>(&dstats), std::max<uint64_t>(nunits, 1) * 8) !=
+        hipSuccess)
+      return STZ_ERR_NOMEM;
+    DecodePlan pl;
+    stz_status s = pl.init(h, f->comp, f->size, nullptr, int(level),
+                           reinterpret_cast<void*>(uintptr_t(256)), ngrid);
+    Workspace ws(st);
+    uint64_t o_grid = 0, o_flags = 0;
+    if (s == STZ_OK) {
+      pl.take(ws);
+      o_grid = ws.take<uint8_t>(uint64_t(h.vb) * ngrid);
+      o_flags = ws.take<uint32_t>(1);
+      if (!ws.commit()) s = STZ_ERR_NOMEM;
+    }
+    Staging* stage = staging();
+    if (s == STZ_OK && !stage) s = STZ_ERR_NOMEM;
+    if (s != STZ_OK) {
+      (void)hipFree(dstats);
+      return s;
+    }
+    void* grid = ws.at<uint8_t>(o_grid);
+    uint32_t* dflags = ws.at<uint32_t>(o_flags);
+    pl.a.rec[pl.a.level_out] = grid;
+    pl.bind(ws, f->lut, dflags);
+    *stage->flags = 0;
+    const int64_t E = int64_t(g.B) >> logs;
+    const int64_t nb[3] = {g.nb[0], g.nb[1], g.nb[2]};
+    if (hipMemcpyAsync(dflags, stage->flags, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_decode(pl.a, st) != hipSuccess ||
+        launch_roi_stats(grid, h.vb, gn, E, int(unit), int(stat), nb, nunits, dstats, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(stage->flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      (void)hipFree(dstats);
+      return STZ_ERR_DEVICE;
+    }
+    prof_flush();
+    if (*stage->flags) {
+      (void)hipFree(dstats);
+      return STZ_ERR_CORRUPT;
+    }
+    f->roi.push_back({key, dstats, nunits});
+  }
+  // selection on the device: flags, then the ascending selected indices
+  const uint64_t k =
+      rule == 1 ? std::min<uint64_t>(nunits, uint64_t(std::ceil(value * double(nunits)))) : 0;
+  Workspace ws(st);
+  const uint64_t o_scr = ws.take<uint8_t>(kRoiScratchBytes);
+  const uint64_t o_sel = ws.take<uint32_t>(nunits);
+  const uint64_t o_cnt = ws.take<uint64_t>(1);
+  if (!ws.commit()) return STZ_ERR_NOMEM;
+  uint32_t* dsel = ws.at<uint32_t>(o_sel);
+  uint64_t* dcnt = ws.at<uint64_t>(o_cnt);
+  const uint64_t hs = 8 + nunits * 4 + (stats ? nunits * 8 : 0);
+  if (!hb.reserve(hs)) return STZ_ERR_NOMEM;
+  if (launch_roi_select(dstats, nunits, int(rule), value, k, ws.at<uint8_t>(o_scr), dsel,
+                        nunits, dcnt, st) != hipSuccess ||
+      hipMemcpyAsync(hb.p, dcnt, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hb.p + 8, dsel, nunits * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      (stats && hipMemcpyAsync(hb.p + 8 + nunits * 4, dstats, nunits * 8, hipMemcpyDeviceToHost,
+                               st) != hipSuccess) ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
   prof_flush();
-  if (*reinterpret_cast<const uint32_t*>(hb.p + nunits * 8)) return STZ_ERR_CORRUPT;
-  const double* sv = reinterpret_cast<const double*>(hb.p);
-  if (stats) std::memcpy(stats, sv, nunits * 8);
-  std::vector<uint32_t> pick;
-  if (rule == 0) {
-    for (uint64_t u = 0; u < nunits; ++u)
-      if (sv[u] > value) pick.push_back(uint32_t(u));
-  } else {
-    const uint64_t k =
-        std::min<uint64_t>(nunits, uint64_t(std::ceil(value * double(nunits))));
-    std::vector<uint32_t> order(nunits);
-    for (uint64_t u = 0; u < nunits; ++u) order[u] = uint32_t(u);
-    std::partial_sort(order.begin(), order.begin() + k, order.end(), [&](uint32_t a, uint32_t b) {
-      return sv[a] > sv[b] || (sv[a] == sv[b] && a < b);
-    });
-    pick.assign(order.begin(), order.begin() + k);
-    std::sort(pick.begin(), pick.end());
-  }
-  *count = pick.size();
-  if (pick.size() > cap || (!sel && !pick.empty())) return STZ_ERR_BUFFER;
-  std::copy(pick.begin(), pick.end(), sel);
+  uint64_t n_sel = 0;
+  std::memcpy(&n_sel, hb.p, 8);
+  if (stats) std::memcpy(stats, hb.p + 8 + nunits * 4, nunits * 8);
+  *count = n_sel;
+  if (n_sel > cap || (!sel && n_sel)) return STZ_ERR_BUFFER;
+  if (n_sel) std::memcpy(sel, hb.p + 8, n_sel * 4);
   return STZ_OK;
 }
 

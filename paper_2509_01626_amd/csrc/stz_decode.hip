@@ -55,6 +55,18 @@ struct DecRows {
   int64_t of[3], oc[3], n[3];
   T E2;
   int R;
+  bool pair;  // output rows start on even elements of a grid aligned to two values
+};
+
+template <class T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
+template <>
+struct Pair2<double> {
+  using type = double2;
 };
 
 // Slab height of the decoder: for 32^3-point blocks, 2 planes keep the LDS
@@ -118,10 +130,17 @@ __device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, i
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {x.oz + lz, x.oy + ly, x.ox + l0};
     const int64_t p1[3] = {x.oz + lz, x.oy + ly, x.ox + l1};
-    if (l0 < x.Ex && l0 >= x.rx0 && l0 < x.rx1)
-      orow[l0] = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
-    if (l1 < x.Ex && l1 >= x.rx0 && l1 < x.rx1)
-      orow[l1] = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+    const bool in0 = l0 < x.Ex && l0 >= x.rx0 && l0 < x.rx1;
+    const bool in1 = l1 < x.Ex && l1 >= x.rx0 && l1 < x.rx1;
+    if (x.pair && in0 && in1) {
+      typename Pair2<T>::type w;
+      w.x = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
+      w.y = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+      *reinterpret_cast<typename Pair2<T>::type*>(orow + l0) = w;
+    } else {
+      if (in0) orow[l0] = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
+      if (in1) orow[l1] = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+    }
   });
 }
 
@@ -442,6 +461,8 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     else
       ctx.E2 = a.E2d;
     ctx.R = a.g.R;
+    ctx.pair = (a.out_cnt[2] & 1) == 0 && ((ox - a.out_first[2]) & 1) == 0 &&
+               (reinterpret_cast<uintptr_t>(a.cur) & (2 * sizeof(T) - 1)) == 0;
     if (interior) {
       dec_type<T, E, H, NW, 0, 0, true>(ctx, hs, Ey, wave, lane);
       dec_type<T, E, H, NW, 0, 1, true>(ctx, hs, Ey, wave, lane);
@@ -691,6 +712,293 @@ hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64
     hipLaunchKernelGGL(k_roi_stats<float>, dim3(unsigned(nunits)), dim3(256), 0, st,
                        static_cast<const float*>(grid), gn[0], gn[1], gn[2], E, unit, stat,
                        nb[1], nb[2], out);
+  prof_end(st);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Device-side ROI selection (Sec. 3.3, ROI workflow) over per-unit statistics.
+// rule 0 keeps the units whose statistic exceeds a threshold; rule 1 keeps the
+// k largest, ties to the smaller index. Rule 1 finds the k-th largest
+// statistic by radix selection on an order-preserving 64-bit key (eight 8-bit
+// digit passes, most significant first), so a unit is taken when its key is
+// above that key, or equal to it and among the first `need` equal ones in
+// index order. The compaction then writes the taken indices in ascending
+// order; with one chunk it runs in one work-group, else chunk counts are
+// scanned first.
+struct RoiState {
+  uint64_t prefix;  // digits of the k-th largest key fixed so far
+  uint64_t mask;    // which digits are fixed
+  uint64_t kr;      // its rank among the keys that match prefix (1-based);
+                    // after the last pass, how many keys equal to it are taken
+  uint64_t pad;
+  uint32_t hist[256];
+};
+static_assert(sizeof(RoiState) <= kRoiStateBytes, "ROI state size");
+constexpr int kRoiOneMax = 16384;  // units handled by the one-work-group path
+constexpr int kRoiChunks = 1024;   // chunks of the multi-work-group path
+
+// Order-preserving key: a > b as doubles iff key(a) > key(b); -0 and +0 equal.
+__device__ __forceinline__ uint64_t roi_key(double v) {
+  const uint64_t b = v == 0.0 ? 0ull : uint64_t(__double_as_longlong(v));
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+// Fix the next digit from a histogram of the keys matching the prefix.
+__device__ void roi_pick(const uint32_t* hist, uint64_t& prefix, uint64_t& mask, uint64_t& kr,
+                         int shift) {
+  uint64_t acc = 0;
+  int d = 255;
+  for (; d > 0; --d) {
+    if (acc + hist[d] >= kr) break;
+    acc += hist[d];
+  }
+  kr -= acc;
+  prefix |= uint64_t(d) << shift;
+  mask |= 0xffull << shift;
+}
+
+// Rule 1 threshold for n <= kRoiOneMax: one work-group, keys kept in registers.
+__global__ __launch_bounds__(1024) void k_roi_radix_one(const double* __restrict__ st,
+                                                        uint64_t n, uint64_t k,
+                                                        RoiState* __restrict__ out) {
+  constexpr int kPer = kRoiOneMax / 1024;
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix, s_mask, s_kr;
+  const int tid = threadIdx.x;
+  uint64_t key[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint64_t i = uint64_t(j) * 1024 + tid;
+    key[j] = i < n ? roi_key(st[i]) : 0;
+  }
+  if (tid == 0) {
+    s_prefix = 0;
+    s_mask = 0;
+    s_kr = k;
+  }
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    const uint64_t p = s_prefix, m = s_mask;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint64_t i = uint64_t(j) * 1024 + tid;
+      if (i < n && (key[j] & m) == p) atomicAdd(&hist[(key[j] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t pr = s_prefix, ms = s_mask, kr = s_kr;
+      roi_pick(hist, pr, ms, kr, shift);
+      s_prefix = pr;
+      s_mask = ms;
+      s_kr = kr;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out->prefix = s_prefix;
+    out->mask = s_mask;
+    out->kr = s_kr;
+  }
+}
+
+// Rule 1 threshold for large n: a grid-wide histogram and a one-group pick per digit.
+__global__ __launch_bounds__(256) void k_roi_init(RoiState* __restrict__ s, uint64_t k) {
+  s->hist[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s->prefix = 0;
+    s->mask = 0;
+    s->kr = k;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_roi_hist(const double* __restrict__ st, uint64_t n,
+                                                  RoiState* __restrict__ s, int shift) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const uint64_t p = s->prefix, m = s->mask;
+  for (uint64_t i = uint64_t(blockIdx.x) * 256 + tid; i < n; i += uint64_t(gridDim.x) * 256) {
+    const uint64_t key = roi_key(st[i]);
+    if ((key & m) == p) atomicAdd(&h[(key >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  if (h[tid]) atomicAdd(&s->hist[tid], h[tid]);
+}
+
+__global__ __launch_bounds__(256) void k_roi_pick(RoiState* __restrict__ s, int shift) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x;
+  h[tid] = s->hist[tid];
+  s->hist[tid] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t pr = s->prefix, ms = s->mask, kr = s->kr;
+    roi_pick(h, pr, ms, kr, shift);
+    s->prefix = pr;
+    s->mask = ms;
+    s->kr = kr;
+  }
+}
+
+__device__ __forceinline__ void roi_class(double v, int rule, double value, uint64_t T,
+                                          bool& gt, bool& eq) {
+  if (rule == 0) {
+    gt = v > value;
+    eq = false;
+  } else {
+    const uint64_t key = roi_key(v);
+    gt = key > T;
+    eq = key == T;
+  }
+}
+
+// Per-chunk counts of units above the threshold and equal to it.
+__global__ __launch_bounds__(1024) void k_roi_count(const double* __restrict__ st, uint64_t n,
+                                                    int rule, double value,
+                                                    const RoiState* __restrict__ s,
+                                                    uint64_t chunk, uint64_t* __restrict__ cnt) {
+  __shared__ uint32_t c_gt, c_eq;
+  const int tid = threadIdx.x;
+  if (tid == 0) c_gt = c_eq = 0;
+  __syncthreads();
+  const uint64_t T = rule == 1 ? s->prefix : 0;
+  const uint64_t lo = uint64_t(blockIdx.x) * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  uint32_t ngt = 0, neq = 0;
+  for (uint64_t u = lo + tid; u < hi; u += 1024) {
+    bool gt, eq;
+    roi_class(st[u], rule, value, T, gt, eq);
+    ngt += gt;
+    neq += eq;
+  }
+  if (ngt) atomicAdd(&c_gt, ngt);
+  if (neq) atomicAdd(&c_eq, neq);
+  __syncthreads();
+  if (tid == 0) {
+    cnt[2 * blockIdx.x] = c_gt;
+    cnt[2 * blockIdx.x + 1] = c_eq;
+  }
+}
+
+// Inclusive scan of one value per thread over a 1024-thread group.
+__device__ uint64_t roi_scan1024(uint64_t v, uint64_t* buf) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint64_t add = tid >= d ? buf[tid - d] : 0;
+    __syncthreads();
+    buf[tid] += add;
+    __syncthreads();
+  }
+  return buf[tid];
+}
+
+// Chunk offsets: where each chunk's first taken index goes, and how many
+// equal keys come before it; the total taken goes to *count.
+__global__ __launch_bounds__(1024) void k_roi_scan(const uint64_t* __restrict__ cnt, int C,
+                                                   int rule, const RoiState* __restrict__ s,
+                                                   uint64_t* __restrict__ offs,
+                                                   uint64_t* __restrict__ count) {
+  __shared__ uint64_t buf[1024];
+  const int tid = threadIdx.x;
+  const uint64_t gt = tid < C ? cnt[2 * tid] : 0, eq = tid < C ? cnt[2 * tid + 1] : 0;
+  const uint64_t need = rule == 1 ? s->kr : 0;
+  const uint64_t eq_before = roi_scan1024(eq, buf) - eq;
+  const uint64_t left = need > eq_before ? need - eq_before : 0;
+  const uint64_t take = gt + (left < eq ? left : eq);
+  const uint64_t sel_incl = roi_scan1024(take, buf);
+  if (tid < C) {
+    offs[2 * tid] = sel_incl - take;
+    offs[2 * tid + 1] = eq_before;
+  }
+  if (tid == 1023) *count = sel_incl;
+}
+
+// Ascending indices of the taken units of each chunk. Without offsets there is
+// one chunk (the whole range), and the total goes to *count.
+__global__ __launch_bounds__(1024) void k_roi_write(const double* __restrict__ st, uint64_t n,
+                                                    int rule, double value,
+                                                    const RoiState* __restrict__ s,
+                                                    uint64_t chunk,
+                                                    const uint64_t* __restrict__ offs,
+                                                    uint32_t* __restrict__ sel, uint64_t cap,
+                                                    uint64_t* __restrict__ count) {
+  __shared__ uint32_t w_eq[16], w_tk[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t lanemask = (1ull << lane) - 1;
+  const uint64_t T = rule == 1 ? s->prefix : 0;
+  const uint64_t need = rule == 1 ? s->kr : 0;
+  uint64_t sel_base = offs ? offs[2 * blockIdx.x] : 0;
+  uint64_t eq_base = offs ? offs[2 * blockIdx.x + 1] : 0;
+  const uint64_t lo = uint64_t(blockIdx.x) * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  for (uint64_t c0 = lo; c0 < hi; c0 += 1024) {
+    const uint64_t u = c0 + tid;
+    bool gt = false, eq = false;
+    if (u < hi) roi_class(st[u], rule, value, T, gt, eq);
+    const uint64_t beq = __ballot(eq);
+    if (lane == 0) w_eq[w] = uint32_t(__popcll(beq));
+    __syncthreads();
+    uint64_t eq_w = 0, eq_all = 0;
+    for (int i = 0; i < 16; ++i) {
+      eq_w += i < w ? w_eq[i] : 0u;
+      eq_all += w_eq[i];
+    }
+    const uint64_t eqrank = eq_base + eq_w + __popcll(beq & lanemask);
+    const bool take = gt || (eq && eqrank < need);
+    const uint64_t btk = __ballot(take);
+    if (lane == 0) w_tk[w] = uint32_t(__popcll(btk));
+    __syncthreads();
+    uint64_t tk_w = 0, tk_all = 0;
+    for (int i = 0; i < 16; ++i) {
+      tk_w += i < w ? w_tk[i] : 0u;
+      tk_all += w_tk[i];
+    }
+    const uint64_t pos = sel_base + tk_w + __popcll(btk & lanemask);
+    if (take && pos < cap) sel[pos] = uint32_t(u);
+    sel_base += tk_all;
+    eq_base += eq_all;
+    __syncthreads();
+  }
+  if (!offs && tid == 0) *count = sel_base;
+}
+
+}  // namespace
+
+hipError_t launch_roi_select(const double* stats, uint64_t n, int rule, double value, uint64_t k,
+                             void* scratch, uint32_t* sel, uint64_t cap, uint64_t* count,
+                             hipStream_t st) {
+  if (n > 0xffffffffull) return hipErrorInvalidValue;
+  auto* s = static_cast<RoiState*>(scratch);
+  auto* offs = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(scratch) + kRoiStateBytes);
+  prof_begin(st, "roi_select", -1);
+  if (n <= uint64_t(kRoiOneMax)) {
+    if (rule == 1)
+      hipLaunchKernelGGL(k_roi_radix_one, dim3(1), dim3(1024), 0, st, stats, n, k, s);
+    hipLaunchKernelGGL(k_roi_write, dim3(1), dim3(1024), 0, st, stats, n, rule, value, s, n,
+                       static_cast<const uint64_t*>(nullptr), sel, cap, count);
+  } else {
+    if (rule == 1) {
+      const unsigned G = unsigned(std::min<uint64_t>(1024, (n + 4095) / 4096));
+      hipLaunchKernelGGL(k_roi_init, dim3(1), dim3(256), 0, st, s, k);
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_roi_hist, dim3(G), dim3(256), 0, st, stats, n, s, shift);
+        hipLaunchKernelGGL(k_roi_pick, dim3(1), dim3(256), 0, st, s, shift);
+      }
+    }
+    const uint64_t C0 = std::min<uint64_t>(kRoiChunks, (n + 8191) / 8192);
+    const uint64_t chunk = (n + C0 - 1) / C0;
+    const int C = int((n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_roi_count, dim3(C), dim3(1024), 0, st, stats, n, rule, value, s, chunk,
+                       offs + 2 * kRoiChunks);
+    hipLaunchKernelGGL(k_roi_scan, dim3(1), dim3(1024), 0, st, offs + 2 * kRoiChunks, C, rule, s,
+                       offs, count);
+    hipLaunchKernelGGL(k_roi_write, dim3(C), dim3(1024), 0, st, stats, n, rule, value, s, chunk,
+                       static_cast<const uint64_t*>(offs), sel, cap, count);
+  }
   prof_end(st);
   return hipGetLastError();
 }

@@ -278,6 +278,15 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
 hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
                             int stat, const int64_t nb[3], uint64_t nunits, double* out,
                             hipStream_t st);
+// Device ROI selection over n per-unit statistics (n < 2^32): rule 0 keeps
+// statistics above `value`, rule 1 the k largest (ties to the smaller index).
+// The ascending selected indices go to sel (at most cap written) and their
+// number to *count (device). `scratch` holds kRoiScratchBytes.
+constexpr uint64_t kRoiStateBytes = 2048;
+constexpr uint64_t kRoiScratchBytes = kRoiStateBytes + 4 * 1024 * 8;
+hipError_t launch_roi_select(const double* stats, uint64_t n, int rule, double value, uint64_t k,
+                             void* scratch, uint32_t* sel, uint64_t cap, uint64_t* count,
+                             hipStream_t st);
 
 // One batched decode: the request table (device) and the work maps of every
 // launch. Level k of request r has edge E = B_r >> (L_r - k).

@@ -71,3 +71,43 @@ def test_roi_blocks_decode_as_batch(gpu, oracle):
         ref = oracle.decompress_region(host, lo, hi, f.info.levels).reshape(-1)
         assert np.array_equal(o[:ref.size].cpu().numpy().view(np.uint32), ref.view(np.uint32))
     f.close()
+
+
+@pytest.mark.parametrize("dtype,edge", [(np.float32, 128), (np.float64, 128),
+                                        (np.float32, 256)])
+def test_roi_many_units_ties_and_cache(gpu, oracle, dtype, edge):
+    """4096 blocks (one-work-group selection, several compaction chunks of 1024)
+    and 32768 blocks (grid-wide digit histograms and chunked compaction), a
+    field with a large constant region (many equal statistics: ties go to the
+    smaller index), selections repeated from the kept statistics, and a second
+    field whose statistics are kept apart."""
+    import torch
+
+    from paper_2509_01626_amd import stz
+    x = fields.bumps((edge, edge, edge), seed=77, n_bumps=5).astype(dtype)
+    x[:, :edge // 2, :] = 1.0
+    comp = stz.stz_compress(torch.from_numpy(x).to(gpu), stz.EB_REL, 1e-3, stz.config(block=8))
+    host = comp.cpu().numpy().tobytes()
+    y = fields.spectral((40, 40, 40), 5 / 3, seed=78).astype(dtype)
+    comp2 = stz.stz_compress(torch.from_numpy(y).to(gpu), stz.EB_REL, 1e-3, stz.config(block=8))
+    host2 = comp2.cpu().numpy().tobytes()
+    f, f2 = stz.Field(comp), stz.Field(comp2)
+    L = f.info.levels
+    for rep in range(2):
+        top = L if edge <= 128 else L - 2   # the oracle decodes this level on the CPU
+        for level, stat, rule, value in ((top, 1, 1, 0.3), (top, 1, 1, 0.75), (top, 0, 0, 1.0),
+                                         (top - 1, 0, 1, 0.5), (top, 1, 1, 1.0),
+                                         (top, 1, 1, 1e-4)):
+            print(f"[case] roi many rep={rep} {dtype.__name__} lv={level} stat={stat} "
+                  f"rule={rule} value={value}", flush=True)
+            osel, ost = oracle.roi_select(host, level, 0, stat, rule, value)
+            sel, st = stz.stz_roi_select(f, level, 0, stat, rule, value)
+            assert np.array_equal(st, ost)
+            assert np.array_equal(sel, osel)
+            osel2, _ = oracle.roi_select(host2, level if level <= f2.info.levels else
+                                         f2.info.levels, 0, stat, rule, value)
+            sel2, _ = stz.stz_roi_select(f2, level if level <= f2.info.levels else
+                                         f2.info.levels, 0, stat, rule, value)
+            assert np.array_equal(sel2, osel2)
+    f.close()
+    f2.close()
