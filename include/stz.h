@@ -97,7 +97,13 @@ uint64_t stz_compress_bound(const uint64_t dims[3], const stz_config* cfg);
  * `out_cap` bytes). `*out_size` (host) receives the stream size; on
  * STZ_ERR_BUFFER it holds the size that would have been needed. Every
  * reconstructed value differs from the input by at most the resolved absolute
- * bound. */
+ * bound (Sec. 2.1). The steps, in order: bound resolution (Sec. 2.1), anchors
+ * on the stride-B grid, then per level from coarse to fine the prediction of
+ * each point from reconstructed coarser points (Sec. 3.1, Eqs. 3-8) and its
+ * linear quantization under the level's bound (Sec. 3.1, Optimizations 3 and
+ * 5), and the Huffman coding of the symbols with per-level, per-block
+ * offsets (Sec. 3.2, 3.3), so that every level and block decodes alone.
+ * Synchronizes `stream` once (the stream size). */
 stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, double eb,
                         const stz_config* cfg, void* out, uint64_t out_cap,
                         uint64_t* out_size, void* stream);
@@ -106,11 +112,20 @@ stz_status stz_compress(const float* x, const uint64_t dims[3], int eb_mode, dou
  * (host). Copies 512 bytes to the host and synchronizes `stream`. */
 stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* stream);
 
-/* Full decompression into `out` (device, at least dims product floats). */
+/* Full decompression (Sec. 3.3, the finest level of progressive decoding)
+ * into `out` (device, at least dims product floats, raster order): anchors,
+ * then level by level the Huffman decode of the symbols and the same
+ * prediction as the compressor (Sec. 3.1, Eqs. 3-8) plus dequantization, so
+ * every value equals the compressor's reconstruction bit for bit. The call
+ * synchronizes `stream` twice: for the stream header (the launch shapes and
+ * the decoder table come from it) and for the corruption flag; a stream
+ * opened with stz_open and decoded through stz_decompress_batch or a captured
+ * decode plan needs neither round trip. */
 stz_status stz_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap_elems,
                           void* stream);
 
-/* Progressive decompression (Sec. 3.3): reconstruct levels 0..level and write
+/* Progressive decompression (Sec. 3.3, progressive decoding; the level
+ * hierarchy of Sec. 3.1-3.2): reconstruct levels 0..level and write
  * the stride-2^(L-level) grid, dims floor((n-1)/s)+1 per axis, into `out`
  * (device). `out_dims` (host) receives its shape. level == L is the full
  * field; level 0 returns the anchors. */

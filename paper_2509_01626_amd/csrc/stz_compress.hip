@@ -289,14 +289,18 @@ __device__ inline void pred_fetch_x(const PredRows<T>& c, int z0, int hs, int Ey
 
 // This wave's rows of parity type (ZP, YP); classes fixed at compile time.
 // PRE: xs = the rows' field values (pred_fetch_x); else they are loaded here.
-template <class T, int E, int H, int NW, int ZP, int YP, bool INT, bool PRE, int KT>
+// OUT: the level grid may be written (c.cur, when not null); without it (the
+// finest level) no grid addresses are formed at all.
+template <class T, int E, int H, int NW, int ZP, int YP, bool INT, bool PRE, bool OUT, int KT>
 __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave, int lane,
                                  const T (&xs)[KT][2], uint32_t* n_center, bool* bad) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
   auto row = [&](int k, int lz, int ly, int q) {
-    T* grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
+    T* grow = nullptr;
+    if constexpr (OUT)
+      grow = c.cur ? c.cur + ((c.oz + lz) * c.n[1] + (c.oy + ly)) * c.n[2] + c.ox : nullptr;
     const int srow = (((lz - c.z0) >> 1) * m + (ly >> 1)) * S::SP + q;
     const int l0 = 2 * q, l1 = 2 * q + 1;
     const int64_t p0[3] = {c.oz + lz, c.oy + ly, c.ox + l0};
@@ -326,8 +330,9 @@ __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave,
 // Predict and quantize every level-l point of one block (format 2.2, 2.3);
 // also writes the block's part of the level-l grid (coarse points copied,
 // level points reconstructed) for the next level's prediction.
-// NT = threads of the work-group (256, or 64 for small blocks).
-template <class T, int E, int H, int NT = 256>
+// NT = threads of the work-group (256, or 64 for small blocks). OUT = false:
+// the finest level, whose grid is not written (a.cur is null).
+template <class T, int E, int H, int NT = 256, bool OUT = true>
 __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_remap) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
@@ -415,15 +420,15 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     const int hs = min(S::H, Ez - z0);
     ctx.z0 = z0;
     if (interior) {
-      pred_type<T, E, H, NW, 0, 0, true, kPre>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
-      pred_type<T, E, H, NW, 0, 1, true, kPre>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 0, true, kPre>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 1, true, kPre>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 1, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 0, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 1, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
     } else {
-      pred_type<T, E, H, NW, 0, 0, false, kPre>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
-      pred_type<T, E, H, NW, 0, 1, false, kPre>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 0, false, kPre>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 1, false, kPre>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 1, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 0, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
+      pred_type<T, E, H, NW, 1, 1, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
     }
     if (z0 + S::H < Ez) fetch_x(z0 + S::H);
     __syncthreads();
@@ -509,10 +514,10 @@ constexpr int pred_threads(int E) { return E <= 4 ? 64 : 256; }
 template <class T>
 constexpr int pred_waves(int E) { return sizeof(T) != 4 ? 1 : (E == 32 ? 6 : (E == 16 ? 7 : 1)); }
 
-template <class T, int E>
+template <class T, int E, bool OUT>
 __global__ __launch_bounds__(pred_threads(E)) __attribute__((amdgpu_waves_per_eu(pred_waves<T>(E))))
 void k_pred_slab(PredSlabArgs a) {
-  pred_body<T, E, pred_slab_h(E), pred_threads(E)>(a, blockIdx.x, true);
+  pred_body<T, E, pred_slab_h(E), pred_threads(E), OUT>(a, blockIdx.x, true);
 }
 
 struct LaneLenArgs {
@@ -1836,7 +1841,12 @@ __global__ __launch_bounds__(256) void kb_pack_lanes(const PackArgs* __restrict_
 
 template <class T, int E>
 void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_pred_slab<T, E>), dim3(unsigned(nblk)), dim3(pred_threads(E)), 0, st, p);
+  if (p.cur)
+    hipLaunchKernelGGL((k_pred_slab<T, E, true>), dim3(unsigned(nblk)), dim3(pred_threads(E)), 0,
+                       st, p);
+  else
+    hipLaunchKernelGGL((k_pred_slab<T, E, false>), dim3(unsigned(nblk)), dim3(pred_threads(E)), 0,
+                       st, p);
 }
 
 template <int E, int H>

@@ -242,14 +242,16 @@ __device__ inline V tile_pred(const V* tile, int wz, int wy, int wx, const int64
     return B;
   } else if constexpr (ND == 2) {
     if (FULL || (P1[0] && M3[0] && P3[0] && P1[1] && M3[1] && P3[1])) {
-      V in = v(1, 1, 0);
-      in = in + v(1, 2, 0);
-      in = in + v(2, 1, 0);
-      in = in + v(2, 2, 0);
-      V out = v(0, 0, 0);
-      out = out + v(0, 3, 0);
-      out = out + v(3, 0, 0);
-      out = out + v(3, 3, 0);
+      const V i0 = v(1, 1, 0), i1 = v(1, 2, 0), i2 = v(2, 1, 0), i3 = v(2, 2, 0);
+      const V o0 = v(0, 0, 0), o1 = v(0, 3, 0), o2 = v(3, 0, 0), o3 = v(3, 3, 0);
+      V in = i0;
+      in = in + i1;
+      in = in + i2;
+      in = in + i3;
+      V out = o0;
+      out = out + o1;
+      out = out + o2;
+      out = out + o3;
       return ((V(9) * in) - out) * V(0.03125);
     }
     return nest_rule<V>(P1[0], M3[0], [&](int i) {
@@ -257,22 +259,18 @@ __device__ inline V tile_pred(const V* tile, int wz, int wy, int wx, const int64
     });
   } else {
     if (FULL || (P1[0] && M3[0] && P3[0] && P1[1] && M3[1] && P3[1] && P1[2] && M3[2] && P3[2])) {
-      V in = v(1, 1, 1);
-      in = in + v(1, 1, 2);
-      in = in + v(1, 2, 1);
-      in = in + v(1, 2, 2);
-      in = in + v(2, 1, 1);
-      in = in + v(2, 1, 2);
-      in = in + v(2, 2, 1);
-      in = in + v(2, 2, 2);
-      V out = v(0, 0, 0);
-      out = out + v(0, 0, 3);
-      out = out + v(0, 3, 0);
-      out = out + v(0, 3, 3);
-      out = out + v(3, 0, 0);
-      out = out + v(3, 0, 3);
-      out = out + v(3, 3, 0);
-      out = out + v(3, 3, 3);
+      // all 16 taps read before the sums (independent LDS reads in flight)
+      V t[16];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] = v(1 + (k >> 2), 1 + ((k >> 1) & 1), 1 + (k & 1));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[8 + k] = v(3 * (k >> 2), 3 * ((k >> 1) & 1), 3 * (k & 1));
+      V in = t[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) in = in + t[k];
+      V out = t[8];
+#pragma unroll
+      for (int k = 9; k < 16; ++k) out = out + t[k];
       return ((V(9) * in) - out) * V(0.015625);
     }
     return nest_rule<V>(P1[0], M3[0], [&](int i) {
