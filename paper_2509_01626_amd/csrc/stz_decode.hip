@@ -58,16 +58,27 @@ struct DecRows {
   bool pair;  // output rows start on even elements of a grid aligned to two values
 };
 
-template <class T>
-struct Pair2;
-template <>
-struct Pair2<float> {
-  using type = float2;
-};
-template <>
-struct Pair2<double> {
-  using type = double2;
-};
+// Output stores. NTS: non-temporal, for the call's final output grid, which
+// nothing in the call reads back: it streams to memory instead of displacing
+// the stream words and coarse planes other blocks still read from the caches.
+template <bool NTS, class T>
+__device__ inline void st_out(T* p, T v) {
+  if constexpr (NTS)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+template <bool NTS, class T>
+__device__ inline void st_pair(T* p, T v0, T v1) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  V2 w;
+  w.x = v0;
+  w.y = v1;
+  if constexpr (NTS)
+    __builtin_nontemporal_store(w, reinterpret_cast<V2*>(p));
+  else
+    *reinterpret_cast<V2*>(p) = w;
+}
 
 // Slab height of the decoder: for 32^3-point blocks, 2 planes keep the LDS
 // footprint (code table, slab symbols, coarse tile, stream ring) at 26 KB, for
@@ -114,7 +125,7 @@ __device__ inline T dec_point(const DecRows<T>& x, int lz, int ly, int lx, int s
 
 // Reconstruct this wave's rows of parity type (ZP, YP): classes 4ZP+2YP (even
 // x) and 4ZP+2YP+1 (odd x), both fixed at compile time.
-template <class T, int E, int H, int NW, int ZP, int YP, bool INT>
+template <class T, int E, int H, int NW, int ZP, int YP, bool INT, bool NTS>
 __device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, int lane) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
@@ -133,19 +144,19 @@ __device__ inline void dec_type(const DecRows<T>& x, int hs, int Ey, int wave, i
     const bool in0 = l0 < x.Ex && l0 >= x.rx0 && l0 < x.rx1;
     const bool in1 = l1 < x.Ex && l1 >= x.rx0 && l1 < x.rx1;
     if (x.pair && in0 && in1) {
-      typename Pair2<T>::type w;
-      w.x = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
-      w.y = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
-      *reinterpret_cast<typename Pair2<T>::type*>(orow + l0) = w;
+      const T v0 = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
+      const T v1 = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+      st_pair<NTS>(orow + l0, v0, v1);
     } else {
-      if (in0) orow[l0] = dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0);
-      if (in1) orow[l1] = dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1);
+      if (in0) st_out<NTS>(orow + l0, dec_point<T, E, H, C0, INT>(x, lz, ly, l0, srow, p0));
+      if (in1) st_out<NTS>(orow + l1, dec_point<T, E, H, C0 + 1, INT>(x, lz, ly, l1, srow, p1));
     }
   });
 }
 
-// NT = threads of the work-group (256, or 64 for small blocks).
-template <class T, int E, int H, int NT = 256>
+// NT = threads of the work-group (256, or 64 for small blocks); NTS =
+// non-temporal output stores.
+template <class T, int E, int H, int NT = 256, bool NTS = false>
 __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
@@ -464,15 +475,15 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     ctx.pair = (a.out_cnt[2] & 1) == 0 && ((ox - a.out_first[2]) & 1) == 0 &&
                (reinterpret_cast<uintptr_t>(a.cur) & (2 * sizeof(T) - 1)) == 0;
     if (interior) {
-      dec_type<T, E, H, NW, 0, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, NW, 0, 1, true>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, NW, 1, 0, true>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, NW, 1, 1, true>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 0, true, NTS>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 1, true, NTS>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 0, true, NTS>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 1, true, NTS>(ctx, hs, Ey, wave, lane);
     } else {
-      dec_type<T, E, H, NW, 0, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, NW, 0, 1, false>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, NW, 1, 0, false>(ctx, hs, Ey, wave, lane);
-      dec_type<T, E, H, NW, 1, 1, false>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 0, false, NTS>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 0, 1, false, NTS>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 0, false, NTS>(ctx, hs, Ey, wave, lane);
+      dec_type<T, E, H, NW, 1, 1, false, NTS>(ctx, hs, Ey, wave, lane);
     }
     __syncthreads();
   }
@@ -494,10 +505,10 @@ constexpr int dec_waves(int E) { return E == 32 ? (sizeof(T) == 4 ? 6 : 5) : 1; 
 // four times as many blocks fit on a CU; their latency chains overlap.
 constexpr int slab_threads(int E) { return E <= 8 ? 64 : 256; }
 
-template <class T, int E>
+template <class T, int E, bool NTS>
 __global__ __launch_bounds__(slab_threads(E)) __attribute__((amdgpu_waves_per_eu(dec_waves<T>(E))))
 void k_dec_slab(DecSlabArgs a) {
-  dec_body<T, E, dec_slab_h(E), slab_threads(E)>(a, blockIdx.x);
+  dec_body<T, E, dec_slab_h(E), slab_threads(E), NTS>(a, blockIdx.x);
 }
 
 // Anchors of the box R_0 from the stream into the level-0 box grid.
@@ -566,20 +577,26 @@ __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
 
 
 template <class T, int E>
-void launch_slab(const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_dec_slab<T, E>), dim3(unsigned(nblk)), dim3(slab_threads(E)), 0, st, d);
+void launch_slab(const DecSlabArgs& d, int64_t nblk, bool nts, hipStream_t st) {
+  if (nts)
+    hipLaunchKernelGGL((k_dec_slab<T, E, true>), dim3(unsigned(nblk)), dim3(slab_threads(E)), 0,
+                       st, d);
+  else
+    hipLaunchKernelGGL((k_dec_slab<T, E, false>), dim3(unsigned(nblk)), dim3(slab_threads(E)), 0,
+                       st, d);
 }
 
-// Plain launch of one level of a decode, by level block edge.
+// Plain launch of one level of a decode, by level block edge; nts = the level
+// writes the call's final output (non-temporal stores).
 template <class T>
-void launch_slab_e(int E, const DecSlabArgs& d, int64_t nblk, hipStream_t st) {
+void launch_slab_e(int E, const DecSlabArgs& d, int64_t nblk, bool nts, hipStream_t st) {
   switch (E) {
-    case 2: launch_slab<T, 2>(d, nblk, st); break;
-    case 4: launch_slab<T, 4>(d, nblk, st); break;
-    case 8: launch_slab<T, 8>(d, nblk, st); break;
-    case 16: launch_slab<T, 16>(d, nblk, st); break;
-    case 32: launch_slab<T, 32>(d, nblk, st); break;
-    default: launch_slab<T, 64>(d, nblk, st); break;
+    case 2: launch_slab<T, 2>(d, nblk, nts, st); break;
+    case 4: launch_slab<T, 4>(d, nblk, nts, st); break;
+    case 8: launch_slab<T, 8>(d, nblk, nts, st); break;
+    case 16: launch_slab<T, 16>(d, nblk, nts, st); break;
+    case 32: launch_slab<T, 32>(d, nblk, nts, st); break;
+    default: launch_slab<T, 64>(d, nblk, nts, st); break;
   }
 }
 
@@ -1020,7 +1037,7 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
     const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
     const int E = g.B >> (L - k);
     prof_begin(st, d.xcd_remap ? "decode" : "rdecode", k);
-    launch_slab_e<T>(E, d, nblk, st);
+    launch_slab_e<T>(E, d, nblk, k == a.level_out, st);
     prof_end(st);
   }
   return hipGetLastError();
@@ -1064,7 +1081,8 @@ hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
       const DecSlabArgs d = dec_args(b.host_R[b.direct[i].req], k);
       const int64_t nblk = d.bb_n[0] * d.bb_n[1] * d.bb_n[2];
       prof_begin(st, "b_decode_direct", k);
-      launch_slab_e<float>(d.g.B >> (d.g.L - k), d, nblk, st);
+      launch_slab_e<float>(d.g.B >> (d.g.L - k), d, nblk,
+                           k == b.host_R[b.direct[i].req].level_out, st);
       prof_end(st);
     }
     if (!b.n_check[k]) continue;
