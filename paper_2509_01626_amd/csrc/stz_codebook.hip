@@ -200,27 +200,43 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   // nodes: the sorted leaves (padded to a power of two while sorting) and then
   // the m - 1 merged nodes: at most kCbNodes entries
   __shared__ uint64_t W[kCbNodes + 2];
-  __shared__ uint16_t par[kCbNodes];
-  __shared__ uint16_t dep[kCbNodes];
+  __shared__ uint16_t par[2][kCbNodes];  // ping-pong buffers of the depth pass
+  __shared__ uint16_t dep[2][kCbNodes];
   __shared__ uint16_t leaf[kCbMax];
-  __shared__ int s_m, s_max;
+  __shared__ int s_max;
+  __shared__ int wcnt[kCbMax / 64];
   __shared__ unsigned long long s_tot;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
   uint8_t* lens = lens_k + size_t(k) * nsym;
-  if (t == 0) {
-    s_m = 0;
-    s_max = 0;
-  }
-  __syncthreads();
-  // the used symbols' keys, compacted (any order: the sort orders them)
+  if (t == 0) s_max = 0;
+  // the used symbols' keys, compacted in symbol order (any order would do:
+  // the sort orders them) with per-wave ballots
   const uint64_t add = (uint64_t(1) << k) - 1;
-  for (int i = t; i < nsym; i += blockDim.x) {
-    const uint64_t c = uint64_t(hist[i]);
-    if (c) W[atomicAdd(&s_m, 1)] = (((c + add) >> k) << kSymBits) | uint64_t(i);
-    lens[i] = 0;
+  constexpr int kPassC = kCbMax / kCbThreads;
+  uint64_t cs[kPassC];
+  uint64_t bal[kPassC];
+#pragma unroll
+  for (int q = 0; q < kPassC; ++q) {
+    const int i = q * kCbThreads + t;
+    cs[q] = i < nsym ? uint64_t(hist[i]) : 0;
+    bal[q] = __ballot(cs[q] != 0);
+    if (lane == 0) wcnt[i >> 6] = __popcll(bal[q]);
+    if (i < nsym) lens[i] = 0;
   }
   __syncthreads();
-  const int m = s_m;
+  int m = 0;
+#pragma unroll
+  for (int q = 0; q < kPassC; ++q) {
+    const int i = q * kCbThreads + t;
+    int before = 0;
+    for (int w = 0; w < kCbMax / 64; ++w) {
+      before += w < (i >> 6) ? wcnt[w] : 0;
+      m += q == 0 ? wcnt[w] : 0;
+    }
+    if (cs[q])
+      W[before + __popcll(bal[q] & ((uint64_t(1) << lane) - 1))] =
+          (((cs[q] + add) >> k) << kSymBits) | uint64_t(i);
+  }
   int np2 = 1;
   while (np2 < m) np2 <<= 1;
   for (int i = m + t; i < np2; i += blockDim.x) W[i] = kInf;
@@ -254,34 +270,35 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
     for (int i = t; i < m; i += blockDim.x, ++j) LW[i] = wv[j];
     if (t < 2) LW[m + t] = ~0u;
     __syncthreads();
-    if (t < 64) merge_phased(LW, LW + m + 2, LW + 2 * m + 1, dep, m, par);
+    if (t < 64) merge_phased(LW, LW + m + 2, LW + 2 * m + 1, dep[0], m, par[0]);
   } else if (t == 0) {
-    merge64(W, m, par);
+    merge64(W, m, par[0]);
   }
   __syncthreads();
+  // depths by pointer jumping: each round reads one buffer and writes the
+  // other, so one barrier per round
   const int nn = 2 * m - 1;
-  for (int i = t; i < nn; i += blockDim.x) dep[i] = (i == nn - 1) ? 0 : 1;
+  for (int i = t; i < nn; i += blockDim.x) dep[0][i] = (i == nn - 1) ? 0 : 1;
   __syncthreads();
+  int cur = 0;
   for (int round = 0; (1 << round) < nn; ++round) {
-    uint16_t nd[kCbPer], np[kCbPer];
-    int j = 0;
-    for (int i = t; i < nn; i += blockDim.x, ++j) {
-      const int p = par[i];
-      nd[j] = dep[i] + dep[p];
-      np[j] = par[p];
+    const uint16_t* pd = dep[cur];
+    const uint16_t* pp = par[cur];
+    uint16_t* nd = dep[cur ^ 1];
+    uint16_t* np = par[cur ^ 1];
+    for (int i = t; i < nn; i += blockDim.x) {
+      const int p = pp[i];
+      nd[i] = pd[i] + pd[p];
+      np[i] = pp[p];
     }
-    __syncthreads();
-    j = 0;
-    for (int i = t; i < nn; i += blockDim.x, ++j) {
-      dep[i] = nd[j];
-      par[i] = np[j];
-    }
+    cur ^= 1;
     __syncthreads();
   }
   int mx = 0;
   for (int i = t; i < m; i += blockDim.x) {
-    lens[leaf[i]] = uint8_t(dep[i] > 255 ? 255 : dep[i]);
-    mx = max(mx, int(dep[i]));
+    const int d = dep[cur][i];
+    lens[leaf[i]] = uint8_t(d > 255 ? 255 : d);
+    mx = max(mx, d);
   }
   atomicMax(&s_max, mx);
   __syncthreads();
