@@ -249,25 +249,33 @@ struct PredRows {
   int R;
 };
 
+// Magnitude bits of a value's top 32-bit word: infinities and NaNs have the
+// largest, so the running maximum over a block tells whether any value was
+// not finite (two vector instructions per point, no lane-mask bookkeeping).
+__device__ inline uint32_t mag_bits(float v) { return __float_as_uint(v) & 0x7fffffffu; }
+__device__ inline uint32_t mag_bits(double v) {
+  return uint32_t(uint64_t(__double_as_longlong(v)) >> 32) & 0x7fffffffu;
+}
+template <class T>
+constexpr uint32_t kMagNonfinite = sizeof(T) == 4 ? 0x7f800000u : 0x7ff00000u;
+
 // Predict and quantize one point of class C (0 = coarse copy only).
 template <class T, int E, int H, int C, bool INT>
 __device__ inline void pred_point(const PredRows<T>& c, int lz, int ly, int lx, int srow,
                                   const T xv, T* grow, const int64_t p[3],
-                                  uint32_t* n_center, bool* bad) {
+                                  uint32_t* n_center, uint32_t* mag) {
   using S = SlabShape<E, H>;
   if constexpr (C == 0) {
     if (grow) grow[lx] = c.tile[((((lz - c.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
-    *bad |= !isfinite(xv);
+    *mag = max(*mag, mag_bits(xv));
     const T pred = tile_pred<T, E, C, INT>(c.tile, lz - c.z0, ly, lx, p, c.n);
     T rv;
     const int sy = quantize<T>(xv, pred, c.E2, c.INV, c.chk, c.R, &rv);
     c.ssym[(C - 1) * S::SCP + srow] = uint16_t(sy);
     if (grow) grow[lx] = rv;
-    if (sy == c.R)
-      ++*n_center;
-    else
-      atomicAdd(&c.h[sy], 1u);
+    *n_center += sy == c.R ? 1u : 0u;
+    if (sy != c.R) atomicAdd(&c.h[sy], 1u);
   }
 }
 
@@ -293,7 +301,7 @@ __device__ inline void pred_fetch_x(const PredRows<T>& c, int z0, int hs, int Ey
 // finest level) no grid addresses are formed at all.
 template <class T, int E, int H, int NW, int ZP, int YP, bool INT, bool PRE, bool OUT, int KT>
 __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave, int lane,
-                                 const T (&xs)[KT][2], uint32_t* n_center, bool* bad) {
+                                 const T (&xs)[KT][2], uint32_t* n_center, uint32_t* mag) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int C0 = 4 * ZP + 2 * YP;
@@ -315,9 +323,9 @@ __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave,
       x0 = (C0 != 0 && l0 < c.Ex) ? xrow[l0 << c.ls] : T(0);
       x1 = l1 < c.Ex ? xrow[l1 << c.ls] : T(0);
     }
-    if (l0 < c.Ex) pred_point<T, E, H, C0, INT>(c, lz, ly, l0, srow, x0, grow, p0, n_center, bad);
+    if (l0 < c.Ex) pred_point<T, E, H, C0, INT>(c, lz, ly, l0, srow, x0, grow, p0, n_center, mag);
     if (l1 < c.Ex)
-      pred_point<T, E, H, C0 + 1, INT>(c, lz, ly, l1, srow, x1, grow, p1, n_center, bad);
+      pred_point<T, E, H, C0 + 1, INT>(c, lz, ly, l1, srow, x1, grow, p1, n_center, mag);
   };
   if constexpr (PRE)
     for_type_rows_k<E, H, ZP, YP, NW>(c.z0, hs, Ey, wave, lane,
@@ -372,7 +380,7 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   const bool interior = block_interior(org, E, a.n);
   uint32_t n_center = 0;  // the zero-residual symbol is counted in a register
   uint32_t n_zero = 0, n_cover = 0;  // zero chunks found, centre symbols they cover
-  bool bad = false;
+  uint32_t mag = 0;  // largest magnitude bits of the block's field values
   // Blocks walked in several slabs slide their window of coarse planes
   // between slabs (once the slab's predictions are done) instead of loading
   // every slab's whole tile: each slab adds HZ of its TZ planes.
@@ -420,15 +428,15 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
     const int hs = min(S::H, Ez - z0);
     ctx.z0 = z0;
     if (interior) {
-      pred_type<T, E, H, NW, 0, 0, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
-      pred_type<T, E, H, NW, 0, 1, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 0, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 1, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x00, &n_center, &mag);
+      pred_type<T, E, H, NW, 0, 1, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x01, &n_center, &mag);
+      pred_type<T, E, H, NW, 1, 0, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x10, &n_center, &mag);
+      pred_type<T, E, H, NW, 1, 1, true, kPre, OUT>(ctx, hs, Ey, wave, lane, x11, &n_center, &mag);
     } else {
-      pred_type<T, E, H, NW, 0, 0, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x00, &n_center, &bad);
-      pred_type<T, E, H, NW, 0, 1, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x01, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 0, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x10, &n_center, &bad);
-      pred_type<T, E, H, NW, 1, 1, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x11, &n_center, &bad);
+      pred_type<T, E, H, NW, 0, 0, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x00, &n_center, &mag);
+      pred_type<T, E, H, NW, 0, 1, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x01, &n_center, &mag);
+      pred_type<T, E, H, NW, 1, 0, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x10, &n_center, &mag);
+      pred_type<T, E, H, NW, 1, 1, false, kPre, OUT>(ctx, hs, Ey, wave, lane, x11, &n_center, &mag);
     }
     if (z0 + S::H < Ez) fetch_x(z0 + S::H);
     __syncthreads();
@@ -492,7 +500,7 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   if (n_center != n_cover) atomicAdd(&h[R], n_center - n_cover);  // mod 2^32, sums >= 0
   if (n_zero) atomicAdd(&h[a.g.Z], n_zero);
   __syncthreads();
-  if (bad) atomicOr(&a.P->flags, kFlagNonfinite);
+  if (mag >= kMagNonfinite<T>) atomicOr(&a.P->flags, kFlagNonfinite);
   const uint64_t slot = uint64_t(wg) % a.nslots;
   for (int i = tid; i < a.nsym; i += blockDim.x)
     if (h[i]) atomicAdd(&a.hpart[slot * uint64_t(a.nsym) + i], h[i]);

@@ -68,26 +68,24 @@ __device__ inline T fabs_t(T v) {
     return fabs(v);
 }
 
+// Every step is evaluated on every lane and the outcome selected, with no
+// branches: the same operands and order as the per-case form, so the same
+// symbols and reconstructions.
 template <class T>
 __device__ inline int quantize(T xv, T pred, T E2, T INV, double chk, int R, T* rec) {
   const T diff = xv - pred;
   const T t = rint_t(diff * INV);
-  if (fabs_t(t) <= (T)(R - 1)) {
-    const int q = (int)t;
-    const T prod = (T)q * E2;
-    const T xr = pred + prod;
-    bool ok;
-    if constexpr (sizeof(T) == 4)
-      ok = fabs((double)xv - (double)xr) <= chk;
-    else
-      ok = fabs(xv - xr) <= chk;
-    if (ok) {
-      *rec = xr;
-      return q + R;
-    }
-  }
-  *rec = xv;
-  return 0;
+  const bool inr = fabs_t(t) <= (T)(R - 1);
+  const int q = inr ? (int)t : 0;
+  const T prod = (T)q * E2;
+  const T xr = pred + prod;
+  bool ok;
+  if constexpr (sizeof(T) == 4)
+    ok = inr && fabs((double)xv - (double)xr) <= chk;
+  else
+    ok = inr && fabs(xv - xr) <= chk;
+  *rec = ok ? xr : xv;
+  return ok ? q + R : 0;
 }
 
 __device__ inline uint32_t wave_sum(uint32_t v) {
