@@ -139,6 +139,39 @@ uint64_t ws_key(hipStream_t st) {
   return (reinterpret_cast<uint64_t>(st) << 8) ^ uint64_t(dev & 255);
 }
 
+// Auxiliary streams: one per (device, caller stream), created on first use
+// with default priority, for launches that run beside the caller's stream
+// between a fork and a join event (see launch_pred).
+struct AuxCache {
+  std::mutex mu;
+  std::unordered_map<uint64_t, AuxStream> m;
+};
+
+AuxCache& aux_cache() {
+  static AuxCache* c = new AuxCache;  // never destroyed: may be used during exit
+  return *c;
+}
+
+}  // namespace
+
+const AuxStream* aux_stream(hipStream_t st) {
+  AuxCache& c = aux_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  const uint64_t key = ws_key(st);
+  auto it = c.m.find(key);
+  if (it != c.m.end()) return &it->second;
+  AuxStream a{};
+  if (hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(a.s);
+    return nullptr;
+  }
+  return &c.m.emplace(key, a).first->second;
+}
+
+namespace {
+
 // Sub-buffers are laid out first (take), then the stream's cached buffer
 // backs all of them (commit).
 struct Workspace {
@@ -839,6 +872,20 @@ stz_status stz_trim(void) {
       it = c.m.erase(it);
     } else {
       ++it;
+    }
+  }
+  {
+    AuxCache& ac = aux_cache();
+    std::lock_guard<std::mutex> lk2(ac.mu);
+    for (auto it = ac.m.begin(); it != ac.m.end();) {
+      if (int(it->first & 255) == (cur & 255)) {
+        (void)hipEventDestroy(it->second.fork);
+        (void)hipEventDestroy(it->second.join);
+        (void)hipStreamDestroy(it->second.s);
+        it = ac.m.erase(it);
+      } else {
+        ++it;
+      }
     }
   }
   return hipDeviceSynchronize() == hipSuccess ? STZ_OK : STZ_ERR_DEVICE;

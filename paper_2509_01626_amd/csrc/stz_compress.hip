@@ -339,9 +339,12 @@ __device__ inline void pred_type(const PredRows<T>& c, int hs, int Ey, int wave,
 // also writes the block's part of the level-l grid (coarse points copied,
 // level points reconstructed) for the next level's prediction.
 // NT = threads of the work-group (256, or 64 for small blocks). OUT = false:
-// the finest level, whose grid is not written (a.cur is null).
-template <class T, int E, int H, int NT = 256, bool OUT = true>
-__device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_remap) {
+// the finest level, whose grid is not written (a.cur is null). KIND: 0 = any
+// block (interior test at run time), 1 = interior blocks only, 2 = the other
+// blocks only; a kernel built for one kind holds only that kind's code.
+// `slot` = the partial histogram the block adds into.
+template <class T, int E, int H, int NT = 256, bool OUT = true, int KIND = 0>
+__device__ inline void pred_body(const PredSlabArgs& a, int64_t blk, uint64_t slot) {
   using S = SlabShape<E, H>;
   constexpr int m = S::m;
   constexpr int NW = NT / 64;
@@ -351,8 +354,6 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   __shared__ uint64_t ubase[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
-  const int64_t nblk = a.g.nb[0] * a.g.nb[1] * a.g.nb[2];
-  const int64_t blk = wg_block(wg, nblk, xcd_remap);
   const int64_t bx = blk % a.g.nb[2], by = (blk / a.g.nb[2]) % a.g.nb[1],
                 bz = blk / (a.g.nb[2] * a.g.nb[1]);
   const int64_t oz = bz * E, oy = by * E, ox = bx * E;
@@ -377,7 +378,7 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   const int64_t sf[3] = {0, 0, 0};
   const int ls = a.logs;
   const int64_t org[3] = {oz, oy, ox};
-  const bool interior = block_interior(org, E, a.n);
+  const bool interior = KIND == 1 ? true : KIND == 2 ? false : block_interior(org, E, a.n);
   uint32_t n_center = 0;  // the zero-residual symbol is counted in a register
   uint32_t n_zero = 0, n_cover = 0;  // zero chunks found, centre symbols they cover
   uint32_t mag = 0;  // largest magnitude bits of the block's field values
@@ -501,9 +502,9 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t wg, bool xcd_rem
   if (n_zero) atomicAdd(&h[a.g.Z], n_zero);
   __syncthreads();
   if (mag >= kMagNonfinite<T>) atomicOr(&a.P->flags, kFlagNonfinite);
-  const uint64_t slot = uint64_t(wg) % a.nslots;
+  const uint64_t hs0 = (slot % a.nslots) * uint64_t(a.nsym);
   for (int i = tid; i < a.nsym; i += blockDim.x)
-    if (h[i]) atomicAdd(&a.hpart[slot * uint64_t(a.nsym) + i], h[i]);
+    if (h[i]) atomicAdd(&a.hpart[hs0 + i], h[i]);
 }
 
 // Slab height of the plain predictor launches: 4 planes for 32^3-point blocks
@@ -522,10 +523,21 @@ constexpr int pred_threads(int E) { return E <= 4 ? 64 : 256; }
 template <class T>
 constexpr int pred_waves(int E) { return sizeof(T) != 4 ? 1 : (E == 32 ? 6 : (E == 16 ? 7 : 1)); }
 
-template <class T, int E, bool OUT>
+// Plain launches: KIND 1 walks the interior box of blocks, KIND 2 the shell
+// of the others, KIND 0 every block (with an empty box, the shell is all of
+// them); work-groups take contiguous runs per XCD (wg_block).
+template <class T, int E, bool OUT, int KIND>
 __global__ __launch_bounds__(pred_threads(E)) __attribute__((amdgpu_waves_per_eu(pred_waves<T>(E))))
-void k_pred_slab(PredSlabArgs a) {
-  pred_body<T, E, pred_slab_h(E), pred_threads(E), OUT>(a, blockIdx.x, true);
+void k_pred_slab(PredSlabArgs a, BlockSplit bs) {
+  const int64_t nI = box_count(bs);
+  int64_t blk;
+  if constexpr (KIND == 1) {
+    blk = box_block(bs, wg_block(blockIdx.x, nI, true));
+  } else {
+    const int64_t nS = bs.nb[0] * bs.nb[1] * bs.nb[2] - nI;
+    blk = shell_block(bs, wg_block(blockIdx.x, nS, true));
+  }
+  pred_body<T, E, pred_slab_h(E), pred_threads(E), OUT, KIND>(a, blk, blockIdx.x);
 }
 
 struct LaneLenArgs {
@@ -1766,7 +1778,7 @@ void kb_pred(const PredSlabArgs* __restrict__ P, ItemMap m) {
     const uint32_t nblk = uint32_t(a.g.nb[0] * a.g.nb[1] * a.g.nb[2]);
     // padded range (multiple of 8): contiguous blocks per XCD, padding skipped
     const uint32_t blk = uint32_t(wg_block(loc, cnt, true));
-    if (blk < nblk) pred_body<float, E, H>(a, blk, false);
+    if (blk < nblk) pred_body<float, E, H>(a, blk, blk);
   }
 }
 
@@ -1849,12 +1861,44 @@ __global__ __launch_bounds__(256) void kb_pack_lanes(const PackArgs* __restrict_
 
 template <class T, int E>
 void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
-  if (p.cur)
-    hipLaunchKernelGGL((k_pred_slab<T, E, true>), dim3(unsigned(nblk)), dim3(pred_threads(E)), 0,
-                       st, p);
-  else
-    hipLaunchKernelGGL((k_pred_slab<T, E, false>), dim3(unsigned(nblk)), dim3(pred_threads(E)), 0,
-                       st, p);
+  // Blocks of 32^3 points and more: the interior box and the shell run as two
+  // kernels, each holding only its kind's code (fewer registers and scalar
+  // spills for the interior one), the shell's on an auxiliary stream so the
+  // two overlap. Smaller blocks: one kernel for all (the launches are short;
+  // split, 16^3 blocks measured 3 % slower).
+  BlockSplit bs = block_split(p.g.nb, E, p.n);
+  const dim3 blk(pred_threads(E));
+  if constexpr (E < 32) {
+    for (int d = 0; d < 3; ++d) bs.lo[d] = bs.hi[d] = 0;  // every block in the "shell"
+    if (p.cur)
+      hipLaunchKernelGGL((k_pred_slab<T, E, true, 0>), dim3(unsigned(nblk)), blk, 0, st, p, bs);
+    else
+      hipLaunchKernelGGL((k_pred_slab<T, E, false, 0>), dim3(unsigned(nblk)), blk, 0, st, p, bs);
+  } else {
+    const int64_t nI = box_count(bs), nS = nblk - nI;
+    const AuxStream* aux = (nI && nS) ? aux_stream(st) : nullptr;
+    hipStream_t ss = st;  // the shell's stream
+    if (aux && hipEventRecord(aux->fork, st) == hipSuccess &&
+        hipStreamWaitEvent(aux->s, aux->fork, 0) == hipSuccess)
+      ss = aux->s;
+    if (p.cur) {
+      if (nS)
+        hipLaunchKernelGGL((k_pred_slab<T, E, true, 2>), dim3(unsigned(nS)), blk, 0, ss, p, bs);
+      if (nI)
+        hipLaunchKernelGGL((k_pred_slab<T, E, true, 1>), dim3(unsigned(nI)), blk, 0, st, p, bs);
+    } else {
+      if (nS)
+        hipLaunchKernelGGL((k_pred_slab<T, E, false, 2>), dim3(unsigned(nS)), blk, 0, ss, p, bs);
+      if (nI)
+        hipLaunchKernelGGL((k_pred_slab<T, E, false, 1>), dim3(unsigned(nI)), blk, 0, st, p, bs);
+    }
+    if (ss != st) {
+      // the join: st goes on only after the shell's kernel
+      if (hipEventRecord(aux->join, ss) != hipSuccess ||
+          hipStreamWaitEvent(st, aux->join, 0) != hipSuccess)
+        (void)hipStreamSynchronize(ss);
+    }
+  }
 }
 
 template <int E, int H>

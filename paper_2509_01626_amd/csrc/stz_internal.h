@@ -278,6 +278,17 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
 hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
                             int stat, const int64_t nb[3], uint64_t nunits, double* out,
                             hipStream_t st);
+// A second stream beside the caller's stream `st` (same device, default
+// priority, created on first use and kept until stz_trim), with a fork and a
+// join event: work enqueued on it after it waits for `fork` (recorded on st)
+// runs concurrently with st's, and st waits for `join` before going on.
+// nullptr when it cannot be created (run the work on st instead).
+struct AuxStream {
+  hipStream_t s;
+  hipEvent_t fork, join;
+};
+const AuxStream* aux_stream(hipStream_t st);
+
 // Device ROI selection over n per-unit statistics (n < 2^32): rule 0 keeps
 // statistics above `value`, rule 1 the k largest (ties to the smaller index).
 // The ascending selected indices go to sel (at most cap written) and their

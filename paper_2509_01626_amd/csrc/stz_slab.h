@@ -49,6 +49,65 @@ __device__ inline int64_t wg_block(int64_t wg, int64_t nblocks, bool xcd_remap) 
   return (wg & 7) * (nblocks >> 3) + (wg >> 3);
 }
 
+// The blocks of a level whose cubic stencils have full support on every axis
+// (block_interior) form one box of block indices, [lo, hi) per axis (lo = hi
+// on every axis when there is none). The predictor's plain launches for
+// large blocks take the box and the shell of remaining blocks in two kernels,
+// each compiled for its own kind of block only; these map a launch's i-th
+// work item to its block (raster order inside the box, resp. over the shell).
+struct BlockSplit {
+  int64_t nb[3];         // blocks per axis
+  int64_t lo[3], hi[3];  // the interior box
+};
+
+// The interior box of a level grid of extents n in blocks of E points:
+// block b is interior when b*E >= 2 and b*E + E + 3 <= n on every axis.
+__host__ __device__ inline BlockSplit block_split(const int64_t nb[3], int E, const int64_t n[3]) {
+  BlockSplit b;
+  bool empty = false;
+  for (int d = 0; d < 3; ++d) {
+    b.nb[d] = nb[d];
+    b.lo[d] = (2 + E - 1) / E;
+    const int64_t hi = n[d] - E - 3 >= 0 ? (n[d] - E - 3) / E + 1 : 0;
+    b.hi[d] = hi < nb[d] ? hi : nb[d];
+    empty = empty || b.hi[d] <= b.lo[d];
+  }
+  if (empty)
+    for (int d = 0; d < 3; ++d) b.lo[d] = b.hi[d] = 0;
+  return b;
+}
+
+__host__ __device__ inline int64_t box_count(const BlockSplit& b) {
+  return (b.hi[0] - b.lo[0]) * (b.hi[1] - b.lo[1]) * (b.hi[2] - b.lo[2]);
+}
+
+__device__ inline int64_t box_block(const BlockSplit& b, int64_t i) {
+  const int64_t w2 = b.hi[2] - b.lo[2], w1 = b.hi[1] - b.lo[1];
+  const int64_t ix = i % w2, t = i / w2, iy = t % w1, iz = t / w1;
+  return ((b.lo[0] + iz) * b.nb[1] + (b.lo[1] + iy)) * b.nb[2] + (b.lo[2] + ix);
+}
+
+__device__ inline int64_t shell_block(const BlockSplit& b, int64_t j) {
+  const int64_t A = b.nb[1] * b.nb[2];
+  const int64_t w1 = b.hi[1] - b.lo[1], w2 = b.hi[2] - b.lo[2];
+  if (j < b.lo[0] * A) return j;  // whole planes before the box
+  j -= b.lo[0] * A;
+  const int64_t per = A - w1 * w2;  // shell blocks of a plane through the box
+  if (j < (b.hi[0] - b.lo[0]) * per) {
+    const int64_t pz = b.lo[0] + j / per;
+    int64_t r = j % per;
+    if (r < b.lo[1] * b.nb[2]) return pz * A + r;  // whole rows before the box
+    r -= b.lo[1] * b.nb[2];
+    const int64_t rowper = b.nb[2] - w2;  // shell blocks of a row through the box
+    if (r < w1 * rowper) {
+      const int64_t py = b.lo[1] + r / rowper, c = r % rowper;
+      return pz * A + py * b.nb[2] + (c < b.lo[2] ? c : c + w2);
+    }
+    return pz * A + b.hi[1] * b.nb[2] + (r - w1 * rowper);  // rows after the box
+  }
+  return b.hi[0] * A + (j - (b.hi[0] - b.lo[0]) * per);  // planes after the box
+}
+
 // Load the coarse tile of a slab: level-(l-1) points (coarse coordinates
 // cz0 + tz, cy0 + ty, cx0 + tx) inside the source grid box; others are zero
 // and never read by a stencil whose flags allow them.
