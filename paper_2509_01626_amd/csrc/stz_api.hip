@@ -737,9 +737,12 @@ int ilog2(int v) {
   return k;
 }
 
-// Work maps of a batched compression over the live jobs (table order).
+// Work maps of a batched compression over the live jobs (table order). Jobs
+// with at least kDirectBlocks blocks of 32^3 points or more at a level are
+// left out of that level's predictor map and listed in *pdirect: they take
+// the plain launch (interior and shell kernels), which fills the device alone.
 void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<uint32_t>& live,
-                         BatchMaps* maps, CompressBatch* b) {
+                         BatchMaps* maps, CompressBatch* b, std::vector<PredDirect>* pdirect) {
   std::memset(b, 0, sizeof(*b));
   const uint32_t n = uint32_t(live.size());
   b->njobs = n;
@@ -772,11 +775,18 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
   b->max_levels = maxL;
   for (int l = 1; l <= maxL; ++l) {
     for (int e = 1; e < kBatchEdges; ++e) {
-      b->n_pred[l][e] = maps->add(&b->pred[l][e], per_job([&](const CompressArgs& a) {
-        const Geo& g = a.geo;
-        if (g.L < l || ilog2(g.B >> (g.L - l)) != e) return 0u;
-        return uint32_t(g.nb[0] * g.nb[1] * g.nb[2]);
-      }), true);
+      for (uint32_t k = 0; k < n; ++k) {
+        const Geo& g = pl[live[k]].a.geo;
+        c[k] = 0;
+        if (g.L < l || ilog2(g.B >> (g.L - l)) != e) continue;
+        const uint64_t nbk = uint64_t(g.nb[0] * g.nb[1] * g.nb[2]);
+        if ((g.B >> (g.L - l)) >= 32 && nbk >= kDirectBlocks) {
+          pdirect->push_back({k, l});
+          continue;
+        }
+        c[k] = uint32_t(nbk);
+      }
+      b->n_pred[l][e] = maps->add(&b->pred[l][e], c, true);
     }
     b->n_level[l] = maps->add(&b->level[l], per_job([&](const CompressArgs& a) {
       const Geo& g = a.geo;
@@ -986,7 +996,8 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
     for (uint32_t k = 0; k < nl; ++k) pl[live[k]].take(ws);
     BatchMaps maps;
     CompressBatch b;
-    build_compress_maps(pl, live, &maps, &b);
+    std::vector<PredDirect> pdirect;
+    build_compress_maps(pl, live, &maps, &b, &pdirect);
     // one staging blob, laid out as on the device and sent with one copy:
     // job table | work maps | per-level argument blocks (256-aligned)
     const uint64_t jb = (uint64_t(nl) * sizeof(CompressArgs) + 15) & ~uint64_t(15);
@@ -1013,6 +1024,9 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
       return STZ_ERR_DEVICE;
     b.J = dj;
     b.args = da;
+    b.host_J = reinterpret_cast<const CompressArgs*>(hb.p);
+    b.pdirect = pdirect.data();
+    b.n_pdirect = uint32_t(pdirect.size());
     maps.bind(dm);
     if (launch_compress_batch(b, st) != hipSuccess) return STZ_ERR_DEVICE;
     if (hipMemcpyAsync(hb.p, dpar, pb, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1336,7 +1350,8 @@ stz_status stz_compress_batch_plan(const stz_job* jobs, uint64_t njobs, stz_batc
   const uint64_t o_jobs = ws.take<CompressArgs>(nl);
   BatchMaps maps;
   CompressBatch b;
-  build_compress_maps(pl, B->live, &maps, &b);
+  std::vector<PredDirect> pdirect;
+  build_compress_maps(pl, B->live, &maps, &b, &pdirect);
   const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
   const uint64_t ab = compress_batch_args_bytes(nl, b.max_levels);
   const uint64_t o_args = ws.take<uint8_t>(ab);
@@ -1361,6 +1376,9 @@ stz_status stz_compress_batch_plan(const stz_job* jobs, uint64_t njobs, stz_batc
   }
   b.J = dj;
   b.args = da;
+  b.host_J = hj.data();
+  b.pdirect = pdirect.data();
+  b.n_pdirect = uint32_t(pdirect.size());
   maps.bind(dm);
   const stz_status s = capture_graph(
       [&](hipStream_t cs) { return launch_compress_batch(b, cs) == hipSuccess; }, &B->graph,

@@ -1876,7 +1876,8 @@ void launch_pred(const PredSlabArgs& p, int64_t nblk, hipStream_t st) {
       hipLaunchKernelGGL((k_pred_slab<T, E, false, 0>), dim3(unsigned(nblk)), blk, 0, st, p, bs);
   } else {
     const int64_t nI = box_count(bs), nS = nblk - nI;
-    const AuxStream* aux = (nI && nS) ? aux_stream(st) : nullptr;
+    // (under graph capture the two kernels go in stream order)
+    const AuxStream* aux = (nI && nS && !capturing(st)) ? aux_stream(st) : nullptr;
     hipStream_t ss = st;  // the shell's stream
     if (aux && hipEventRecord(aux->fork, st) == hipSuccess &&
         hipStreamWaitEvent(aux->s, aux->fork, 0) == hipSuccess)
@@ -2126,6 +2127,19 @@ hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
   hipLaunchKernelGGL(kb_anchor, grid(b.anchor, b.n_anchor), dim3(256), 0, st, b.J, b.anchor);
   prof_end(st);
   for (int l = 1; l <= b.max_levels; ++l) {
+    // jobs with many large blocks at this level: the plain launch
+    for (uint32_t i = 0; i < b.n_pdirect; ++i) {
+      if (b.pdirect[i].level != l) continue;
+      const CompressArgs& a = b.host_J[b.pdirect[i].job];
+      const PredSlabArgs p = pred_args(a, l);
+      const int64_t nblk = a.geo.nb[0] * a.geo.nb[1] * a.geo.nb[2];
+      prof_begin(st, "b_predict_direct", l);
+      if ((a.geo.B >> (a.geo.L - l)) == 32)
+        launch_pred<float, 32>(p, nblk, st);
+      else
+        launch_pred<float, 64>(p, nblk, st);
+      prof_end(st);
+    }
     for (int e = 0; e < kBatchEdges; ++e) {
       const ItemMap& m = b.pred[l][e];
       if (!b.n_pred[l][e]) continue;

@@ -210,9 +210,19 @@ constexpr uint32_t kHistSlots = 128;
 
 // One batched compression: the job table (device) and the work map of every
 // launch; n_* are the item totals (host copies of first[n]).
+// A (job, level) pair whose predictor runs as a plain launch of its own
+// inside a batched compression (many blocks of 32^3 points or more).
+struct PredDirect {
+  uint32_t job;
+  int level;
+};
+
 struct CompressBatch {
   const CompressArgs* J;
   const uint8_t* args;                         // per-level argument blocks (device)
+  const CompressArgs* host_J;                  // host copy of the job table
+  const PredDirect* pdirect;                   // host array
+  uint32_t n_pdirect;
   uint32_t njobs;
   unsigned grid;                               // persistent work-groups per launch
   unsigned grid_pred[kBatchEdges];             // per level block edge
@@ -288,6 +298,8 @@ struct AuxStream {
   hipEvent_t fork, join;
 };
 const AuxStream* aux_stream(hipStream_t st);
+// Whether `st` is being captured into a graph.
+bool capturing(hipStream_t st);
 
 // Device ROI selection over n per-unit statistics (n < 2^32): rule 0 keeps
 // statistics above `value`, rule 1 the k largest (ties to the smaller index).

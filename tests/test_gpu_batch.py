@@ -257,3 +257,32 @@ def test_batch_decode_large_request_direct_path(gpu):
     assert torch.equal(oc[:want.numel()].view(torch.int32), want.view(torch.int32))
     fa.close()
     fb.close()
+
+
+def test_batch_with_large_job_matches_plain_and_oracle(gpu, oracle):
+    """A job with 1331 blocks of 32^3 points at its finest level runs that
+    level's predictor as a plain launch inside the batch (interior and shell
+    kernels); its bytes and its neighbours' must equal the plain calls' and
+    the oracle's."""
+    import torch
+
+    from paper_2509_01626_amd import stz
+    big = fields.spectral((336, 336, 336), 5 / 3, seed=61)
+    small = [fields.bumps((40, 33, 50), seed=62, n_bumps=4), fields.spectral((70, 64, 96), 5 / 3,
+                                                                              seed=63)]
+    xs = [big] + small
+    ebs = [1e-3, 1e-2, 1e-4]
+    cfgs = [stz.config(block=32)] * 3
+    xds = [torch.from_numpy(x).to(gpu) for x in xs]
+    outs = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8, device=gpu)
+            for x, c in zip(xds, cfgs)]
+    print("[case] batch with a 336^3 job", flush=True)
+    comps, jobs = stz.stz_compress_batch(xds, [stz.EB_REL] * 3, ebs, cfgs, outs)
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert jobs[i].status == stz.OK
+        got = comps[i].cpu().numpy().tobytes()
+        plain = stz.stz_compress(xds[i], stz.EB_REL, ebs[i], cfgs[i]).cpu().numpy().tobytes()
+        assert got == plain, i
+        want = oracle.compress(xs[i], oracle.EB_REL, ebs[i], oracle.config(block=32))
+        assert got == want, i

@@ -175,3 +175,33 @@ def test_decode_plan_reports_corruption(gpu):
     plan.close()
     f_ok.close()
     f_bad.close()
+
+
+def test_compress_plan_with_large_job(gpu):
+    """A plan whose job has enough 32^3 blocks at its finest level to take the
+    plain predictor launch (interior and shell kernels, in stream order under
+    capture): every replay equals the eager batch, also after the input
+    changes."""
+    import torch
+
+    from paper_2509_01626_amd import stz
+    xs = [torch.from_numpy(fields.spectral((336, 336, 336), 5 / 3, seed=71)).to(gpu),
+          torch.from_numpy(fields.bumps((48, 40, 56), seed=72, n_bumps=5)).to(gpu)]
+    cfgs = [stz.config(block=32)] * 2
+    outs_e = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8, device=gpu)
+              for x, c in zip(xs, cfgs)]
+    outs_g = [torch.zeros_like(o) for o in outs_e]
+    jobs_g = stz.make_jobs(xs, [stz.EB_REL] * 2, [1e-3, 1e-3], cfgs, outs_g)
+    plan = stz.BatchPlan(jobs=jobs_g)
+    for rep in range(3):
+        if rep == 1:
+            xs[0].mul_(0.5).add_(2.0)
+        print(f"[graph] large-job replay {rep}", flush=True)
+        plan.run()
+        assert plan.status() == stz.OK
+        comps_e, _ = stz.stz_compress_batch(xs, [stz.EB_REL] * 2, [1e-3, 1e-3], cfgs, outs_e)
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert jobs_g[i].out_size == comps_e[i].numel(), (rep, i)
+            assert torch.equal(outs_g[i][:jobs_g[i].out_size], comps_e[i]), (rep, i)
+    plan.close()
