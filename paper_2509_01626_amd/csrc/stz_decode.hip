@@ -474,7 +474,23 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     ctx.R = a.g.R;
     ctx.pair = (a.out_cnt[2] & 1) == 0 && ((ox - a.out_first[2]) & 1) == 0 &&
                (reinterpret_cast<uintptr_t>(a.cur) & (2 * sizeof(T) - 1)) == 0;
-    if (interior) {
+    if constexpr (NW >= 16) {
+      // Wide work-groups (launches of few blocks, latency-bound): each group
+      // of NW/4 waves reconstructs one parity type, the four at once.
+      constexpr int GW = NW / 4;
+      const int g = wave / GW, wg_ = wave % GW;
+      if (interior) {
+        if (g == 0) dec_type<T, E, H, GW, 0, 0, true, NTS>(ctx, hs, Ey, wg_, lane);
+        else if (g == 1) dec_type<T, E, H, GW, 0, 1, true, NTS>(ctx, hs, Ey, wg_, lane);
+        else if (g == 2) dec_type<T, E, H, GW, 1, 0, true, NTS>(ctx, hs, Ey, wg_, lane);
+        else dec_type<T, E, H, GW, 1, 1, true, NTS>(ctx, hs, Ey, wg_, lane);
+      } else {
+        if (g == 0) dec_type<T, E, H, GW, 0, 0, false, NTS>(ctx, hs, Ey, wg_, lane);
+        else if (g == 1) dec_type<T, E, H, GW, 0, 1, false, NTS>(ctx, hs, Ey, wg_, lane);
+        else if (g == 2) dec_type<T, E, H, GW, 1, 0, false, NTS>(ctx, hs, Ey, wg_, lane);
+        else dec_type<T, E, H, GW, 1, 1, false, NTS>(ctx, hs, Ey, wg_, lane);
+      }
+    } else if (interior) {
       dec_type<T, E, H, NW, 0, 0, true, NTS>(ctx, hs, Ey, wave, lane);
       dec_type<T, E, H, NW, 0, 1, true, NTS>(ctx, hs, Ey, wave, lane);
       dec_type<T, E, H, NW, 1, 0, true, NTS>(ctx, hs, Ey, wave, lane);
@@ -576,8 +592,28 @@ __host__ __device__ inline DecSlabArgs dec_args(const DecodeArgs& a, int k) {
 }
 
 
+// Launches of fewer blocks than CUs, each block alone on its CU, are bound by
+// one block's latency: 1024-thread work-groups reconstruct the four parity
+// types of a slab at once (blocks of 16^3 points and more).
+template <class T, int E, bool NTS>
+__global__ __launch_bounds__(1024) void k_dec_slab_wide(DecSlabArgs a) {
+  dec_body<T, E, dec_slab_h(E), 1024, NTS>(a, blockIdx.x);
+}
+constexpr int64_t kWideBlocks = 256;
+
 template <class T, int E>
 void launch_slab(const DecSlabArgs& d, int64_t nblk, bool nts, hipStream_t st) {
+  if constexpr (E >= 16) {
+    if (nblk < kWideBlocks) {
+      if (nts)
+        hipLaunchKernelGGL((k_dec_slab_wide<T, E, true>), dim3(unsigned(nblk)), dim3(1024), 0, st,
+                           d);
+      else
+        hipLaunchKernelGGL((k_dec_slab_wide<T, E, false>), dim3(unsigned(nblk)), dim3(1024), 0,
+                           st, d);
+      return;
+    }
+  }
   if (nts)
     hipLaunchKernelGGL((k_dec_slab<T, E, true>), dim3(unsigned(nblk)), dim3(slab_threads(E)), 0,
                        st, d);
