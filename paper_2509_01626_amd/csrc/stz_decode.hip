@@ -680,6 +680,18 @@ void kb_dec(const DecSlabArgs* __restrict__ D, ItemMap m) {
   }
 }
 
+// Batched levels with fewer blocks than CUs (a few small requests): one
+// 1024-thread work-group per block, as the plain path's wide launches.
+template <int E>
+__global__ __launch_bounds__(1024) void kb_dec_wide(const DecSlabArgs* __restrict__ D, ItemMap m) {
+  STZ_FOR_ITEMS(m) {
+    uint32_t loc, cnt;
+    const DecSlabArgs d = uniform_load(D + map_find_d(m, it_, &loc, &cnt));
+    const int64_t blk = wg_block(loc, cnt, true);
+    if (blk < d.bb_n[0] * d.bb_n[1] * d.bb_n[2]) dec_body<float, E, dec_slab_h(E), 1024>(d, blk);
+  }
+}
+
 template <int E, int H>
 void launch_dec_b(const DecSlabArgs* D, const ItemMap& m, unsigned grid, hipStream_t st) {
   hipLaunchKernelGGL((kb_dec<E, H>), dim3(grid), dim3(256), 0, st, D, m);
@@ -1128,6 +1140,17 @@ hipError_t launch_decode_batch(const DecodeBatch& b, hipStream_t st) {
       const unsigned gd = grid(b.grid_dec[e], b.n_dec[k][e]);
       const int h = b.dec_h[e];
       prof_begin(st, "b_decode", k);
+      if (e >= 4 && b.n_dec[k][e] < kWideBlocks) {
+        const dim3 gw(b.n_dec[k][e]), tw(1024);
+        if (e == 4)
+          hipLaunchKernelGGL(kb_dec_wide<16>, gw, tw, 0, st, D, b.dec[k][e]);
+        else if (e == 5)
+          hipLaunchKernelGGL(kb_dec_wide<32>, gw, tw, 0, st, D, b.dec[k][e]);
+        else
+          hipLaunchKernelGGL(kb_dec_wide<64>, gw, tw, 0, st, D, b.dec[k][e]);
+        prof_end(st);
+        continue;
+      }
       switch (e) {
         case 1: launch_dec_bh<2>(h, D, b.dec[k][e], gd, st); break;
         case 2: launch_dec_bh<4>(h, D, b.dec[k][e], gd, st); break;
