@@ -20,7 +20,11 @@
  *     the library keeps no pointer after a call returns.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream).
  *     Host out-parameters are valid when the call returns; device outputs are
- *     valid once the stream reaches the end of the call's work. Calls that
+ *     valid once the stream reaches the end of the call's work. A call may run
+ *     part of its work on an internal stream of the library (one per caller
+ *     stream and device, default priority); that work starts after the
+ *     caller's earlier work on `stream` and `stream` waits for it before any
+ *     later work (events), so stream order is what the caller sees. Calls that
  *     return a host value (sizes, status of device-side checks) synchronize
  *     the stream once at their end.
  *   - Dims are {nz, ny, nx}, C order, x fastest.
@@ -339,9 +343,10 @@ stz_status stz_autotune_batch(stz_job* jobs, uint64_t njobs, char* report, uint6
  * library keeps per (device, stream) and grows on demand, so repeated calls
  * allocate nothing. Calls on one stream run in stream order and share that
  * stream's buffer; calls on different streams use different buffers.
- * stz_trim synchronizes the current device and releases its buffers (for a
- * process that is done with the library, or before a stream is destroyed and
- * its handle value reused by another stream would keep a large buffer alive). */
+ * stz_trim synchronizes the current device and releases its buffers and the
+ * library's internal streams (for a process that is done with the library, or
+ * before a stream is destroyed and its handle value reused by another stream
+ * would keep a large buffer alive). */
 stz_status stz_trim(void);
 
 /* Stage profiler (auxiliary; off by default, or on with STZ_PROFILE=1):
