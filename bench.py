@@ -11,6 +11,7 @@ time); per-operation rates, the dominant kernel's roofline and the CPU oracle
 baseline are reported beside it.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -219,13 +220,18 @@ def main():
 
     for _ in range(args.warmup):
         step(False)
-    # Timed region: K steps, no instrumentation.
+    # Timed region: K steps, no instrumentation. Python's cyclic garbage
+    # collector is paused meanwhile: a full collection over this process's
+    # objects stalls one host call by milliseconds.
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(args.steps):
         comp = step(True)
     torch.cuda.synchronize()
     te = time.perf_counter()
+    gc.enable()
     ms_per_step = (te - ts) * 1e3 / args.steps
     K = args.steps
     # Second timed region of K steps with the library's per-kernel HIP events
