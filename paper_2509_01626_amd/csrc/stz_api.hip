@@ -6,6 +6,7 @@
 #include <string>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -469,6 +470,68 @@ struct DecodePlan {
   }
 };
 
+// Decoder tables of plain decodes, kept in device memory per device and code
+// (the code lengths, compared in full): repeated decodes of one stream, or of
+// streams with the same code, build and upload no table. An entry is written
+// once, by the call that creates it, and used by other calls only after that
+// call has synchronized (ready). At most kLutCacheMax entries per process;
+// beyond them calls upload their table into their own scratch as before.
+// stz_trim frees a device's entries.
+struct LutEntry {
+  int device;
+  int nsym;
+  uint64_t hash;
+  std::vector<uint8_t> lens;
+  uint16_t* dev;
+  bool ready;
+};
+struct LutCache {
+  std::mutex mu;
+  std::deque<LutEntry> e;  // appending keeps references to the other entries
+};
+constexpr size_t kLutCacheMax = 64;
+
+LutCache& lut_cache() {
+  static LutCache* c = new LutCache;  // never destroyed: may be used during exit
+  return *c;
+}
+
+uint64_t lens_hash(const uint8_t* lens, int nsym) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  for (int i = 0; i < nsym; ++i) h = (h ^ lens[i]) * 1099511628211ull;
+  return h ^ uint64_t(nsym);
+}
+
+// The ready table for this code on the current device, or null. With mine
+// (a table this call has built and checked), a miss reserves a new entry for
+// the call to fill: *mine, null when the cache is full or the entry exists
+// but is not ready yet.
+const uint16_t* lut_lookup(const uint8_t* lens, int nsym, LutEntry** mine) {
+  if (mine) *mine = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  const uint64_t hh = lens_hash(lens, nsym);
+  LutCache& c = lut_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto& e : c.e)
+    if (e.device == dev && e.nsym == nsym && e.hash == hh &&
+        std::memcmp(e.lens.data(), lens, size_t(nsym)) == 0)
+      return e.ready ? e.dev : nullptr;
+  if (!mine || c.e.size() >= kLutCacheMax) return nullptr;
+  uint16_t* d = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&d), (size_t(1) << kLutBits) * 2 + 16) != hipSuccess)
+    return nullptr;
+  c.e.push_back({dev, nsym, hh, std::vector<uint8_t>(lens, lens + nsym), d, false});
+  *mine = &c.e.back();
+  return nullptr;
+}
+
+void lut_mark_ready(LutEntry* e) {
+  LutCache& c = lut_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  e->ready = true;
+}
+
 // vb = the caller's value type; a stream of the other type is rejected.
 stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int level, void* out,
                       uint64_t out_cap, uint64_t out_dims[3], int vb, hipStream_t st) {
@@ -484,21 +547,31 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   Staging* stage = staging();
   if (!stage) return STZ_ERR_NOMEM;
   constexpr uint64_t nlut = uint64_t(1) << kLutBits;
-  if (!build_lut(h.lens, h.nsym, stage->lut)) return STZ_ERR_CORRUPT;
+  LutEntry* mine = nullptr;
+  const uint16_t* cached = lut_lookup(h.lens, h.nsym, nullptr);
+  if (!cached) {
+    if (!build_lut(h.lens, h.nsym, stage->lut)) return STZ_ERR_CORRUPT;  // not a prefix code
+    cached = lut_lookup(h.lens, h.nsym, &mine);  // ready meanwhile, or reserve an entry
+  }
   Workspace ws(st);
   pl.take(ws);
-  const uint64_t o_lut = ws.take<uint8_t>(nlut * 2 + 16);
+  const uint64_t o_lut = ws.take<uint8_t>(cached || mine ? 1 : nlut * 2 + 16);
+  const uint64_t o_flags = ws.take<uint32_t>(1);
   if (!ws.commit()) return STZ_ERR_NOMEM;
-  uint16_t* dlut = ws.at<uint16_t>(o_lut);
-  uint32_t* dflags = reinterpret_cast<uint32_t*>(dlut + nlut);
+  uint16_t* dlut = cached ? const_cast<uint16_t*>(cached)
+                          : (mine ? mine->dev : ws.at<uint16_t>(o_lut));
+  uint32_t* dflags = ws.at<uint32_t>(o_flags);  // zeroed by the anchor kernel
   pl.bind(ws, dlut, dflags);
-  std::memset(stage->lut + nlut, 0, 16);
-  if (hipMemcpyAsync(dlut, stage->lut, nlut * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
-    return STZ_ERR_DEVICE;
+  if (!cached) {
+    std::memset(stage->lut + nlut, 0, 16);
+    if (hipMemcpyAsync(dlut, stage->lut, nlut * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
+      return STZ_ERR_DEVICE;
+  }
   if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
   if (hipMemcpyAsync(stage->flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
+  if (mine) lut_mark_ready(mine);  // the table's copy has completed
   prof_flush();
   return *stage->flags ? STZ_ERR_CORRUPT : STZ_OK;
 }
@@ -884,6 +957,18 @@ stz_status stz_trim(void) {
       it = c.m.erase(it);
     } else {
       ++it;
+    }
+  }
+  {
+    LutCache& lc = lut_cache();
+    std::lock_guard<std::mutex> lk3(lc.mu);
+    for (auto it = lc.e.begin(); it != lc.e.end();) {
+      if (it->device == cur) {
+        (void)hipFree(it->dev);
+        it = lc.e.erase(it);
+      } else {
+        ++it;
+      }
     }
   }
   {

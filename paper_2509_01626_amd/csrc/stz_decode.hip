@@ -545,7 +545,11 @@ __device__ inline void dec_anchor_body(const uint8_t* comp, uint64_t anchor_off,
 }
 
 template <class T>
-__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, T* rec0, Grid g0) {
+__global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, T* rec0, Grid g0,
+                             uint32_t* flags) {
+  // the call's corruption flag starts at zero (the level kernels follow in
+  // stream order)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flags = 0;
   dec_anchor_body<T>(comp, anchor_off, g, rec0, g0, blockIdx.x, gridDim.x);
 }
 
@@ -1078,7 +1082,7 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
   const uint64_t n0 = uint64_t(g0.cnt[0]) * g0.cnt[1] * g0.cnt[2];
   prof_begin(st, "dec_anchor", -1);
   hipLaunchKernelGGL(k_dec_anchor<T>, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
-                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0);
+                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0, a.flags);
   prof_end(st);
   for (int k = 1; k <= a.level_out; ++k) {
     const DecSlabArgs d = dec_args(a, k);
