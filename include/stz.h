@@ -124,7 +124,9 @@ stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* str
  * synchronizes `stream` twice: for the stream header (the launch shapes and
  * the decoder table come from it) and for the corruption flag; a stream
  * opened with stz_open and decoded through stz_decompress_batch or a captured
- * decode plan needs neither round trip. */
+ * decode plan needs neither round trip. Decoder tables are kept in device
+ * memory per code (up to 64 codes per process, freed by stz_trim), so repeated
+ * decodes of a stream upload none. */
 stz_status stz_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap_elems,
                           void* stream);
 
@@ -343,8 +345,8 @@ stz_status stz_autotune_batch(stz_job* jobs, uint64_t njobs, char* report, uint6
  * library keeps per (device, stream) and grows on demand, so repeated calls
  * allocate nothing. Calls on one stream run in stream order and share that
  * stream's buffer; calls on different streams use different buffers.
- * stz_trim synchronizes the current device and releases its buffers and the
- * library's internal streams (for a process that is done with the library, or
+ * stz_trim synchronizes the current device and releases its buffers, its kept
+ * decoder tables and the library's internal streams (for a process that is done with the library, or
  * before a stream is destroyed and its handle value reused by another stream
  * would keep a large buffer alive). */
 stz_status stz_trim(void);
