@@ -176,3 +176,35 @@ def test_corrupt_streams_match_oracle_status(gpu, oracle):
         st_gpu = stz.decode_status(d)
         st_ref = oracle.decode_status(bytes(c))
         assert (st_gpu == stz.OK) == (st_ref == oracle.OK), (k, st_gpu, st_ref)
+
+
+def test_many_codes_decode_match_oracle(gpu, oracle):
+    """Decoder tables are kept per code: 80 streams with different codes (more
+    than the 64 kept), each decoded twice in full and once as a region, must
+    give the oracle's values every time (kept tables reused, new ones filled,
+    and the calls beyond the limit uploading their own); a corrupted payload
+    decoded after its clean stream (a kept table) reports corruption."""
+    import torch
+    stz = _stz()
+    rng = np.random.default_rng(44)
+    for i in range(80):
+        dims = tuple(int(v) for v in rng.integers(10, 30, size=3))
+        x = fields.spectral(dims, float(rng.uniform(1.0, 3.0)), seed=300 + i)
+        eb = float(10 ** rng.uniform(-4, -2))
+        want = oracle.compress(x, oracle.EB_REL, eb, oracle.config(block=8))
+        ref = oracle.decompress(want)
+        d = torch.frombuffer(bytearray(want), dtype=torch.uint8).to(gpu)
+        for rep in range(2):
+            got = stz.stz_decompress(d).cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (i, rep)
+        lo, hi = [1, 2, 3], [min(9, dims[0]), min(11, dims[1]), min(13, dims[2])]
+        info = stz.stz_info(d)
+        r = stz.stz_decompress_region(d, lo, hi, info.levels, info=info).cpu().numpy()
+        assert np.array_equal(r.view(np.uint32),
+                              oracle.decompress_region(want, lo, hi, info.levels).view(np.uint32)), i
+        if i % 16 == 0:
+            c = bytearray(want)
+            c[-8] ^= 0xFF  # payload of the finest level
+            st_gpu = stz.decode_status(torch.frombuffer(bytes(c), dtype=torch.uint8).to(gpu))
+            st_ref = oracle.decode_status(bytes(c))
+            assert (st_gpu == stz.OK) == (st_ref == oracle.OK), (i, st_gpu, st_ref)
