@@ -124,9 +124,16 @@ stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* str
  * synchronizes `stream` twice: for the stream header (the launch shapes and
  * the decoder table come from it) and for the corruption flag; a stream
  * opened with stz_open and decoded through stz_decompress_batch or a captured
- * decode plan needs neither round trip. Decoder tables are kept in device
- * memory per code (up to 64 codes per process, freed by stz_trim), so repeated
- * decodes of a stream upload none. */
+ * decode plan needs neither round trip. The parsed headers of the last 16
+ * (device, comp, size) triples decoded are kept on the host: a call on a
+ * kept one skips the header round trip, and a device kernel ahead of its
+ * decode compares the stream's header bytes with the kept ones; when they
+ * differ (new contents at the same address and size) the call reads the
+ * header and decodes again, so its result and status are those of a fresh
+ * read. Decoder tables are kept in device memory per code (up to 64 codes per
+ * process, freed by stz_trim), so repeated decodes of a stream upload none.
+ * The same holds for stz_decompress_level, stz_decompress_region and the
+ * float64 variants. */
 stz_status stz_decompress(const void* comp, uint64_t size, float* out, uint64_t out_cap_elems,
                           void* stream);
 
@@ -346,7 +353,7 @@ stz_status stz_autotune_batch(stz_job* jobs, uint64_t njobs, char* report, uint6
  * allocate nothing. Calls on one stream run in stream order and share that
  * stream's buffer; calls on different streams use different buffers.
  * stz_trim synchronizes the current device and releases its buffers, its kept
- * decoder tables and the library's internal streams (for a process that is done with the library, or
+ * decoder tables and headers and the library's internal streams (for a process that is done with the library, or
  * before a stream is destroyed and its handle value reused by another stream
  * would keep a large buffer alive). */
 stz_status stz_trim(void);

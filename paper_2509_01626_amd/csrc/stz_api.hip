@@ -532,48 +532,133 @@ void lut_mark_ready(LutEntry* e) {
   e->ready = true;
 }
 
-// vb = the caller's value type; a stream of the other type is rejected.
-stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int level, void* out,
-                      uint64_t out_cap, uint64_t out_dims[3], int vb, hipStream_t st) {
+// Parsed headers of the streams plain decodes were last given, per device,
+// stream address and size, with the header bytes they were parsed from (the
+// bytes parse_header reads: the fixed part and the code lengths). A call whose
+// stream is kept launches at once: it uploads the kept bytes into its own
+// workspace, and a one-work-group kernel ahead of the decode compares them
+// with the stream's header. When they differ the call reads and parses the
+// header again and decodes again, so results and statuses are those of a
+// call that reads the header first. Kept headers only ever steer launches
+// whose reads the header's own checks bound to the stream's size. At most
+// kHdrCacheMax entries (oldest out first); stz_trim drops a device's entries.
+struct HdrEntry {
+  int device;
+  const void* comp;
+  uint64_t size;
+  std::vector<uint8_t> bytes;
   Header h;
-  stz_status s = read_header(comp, size, st, &h);
-  if (s != STZ_OK) return s;
-  if (h.vb != vb) return STZ_ERR_ARG;
+};
+struct HdrCache {
+  std::mutex mu;
+  std::deque<HdrEntry> e;
+};
+constexpr size_t kHdrCacheMax = 16;
+
+HdrCache& hdr_cache() {
+  static HdrCache* c = new HdrCache;  // never destroyed: may be used during exit
+  return *c;
+}
+
+// On a hit: the kept header in *h and its bytes in `bytes` (the calling
+// thread's pinned staging), their count in *nbytes.
+bool hdr_lookup(const void* comp, uint64_t size, Header* h, uint8_t* bytes, uint32_t* nbytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  HdrCache& c = hdr_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (const auto& e : c.e)
+    if (e.device == dev && e.comp == comp && e.size == size) {
+      *h = e.h;
+      std::memcpy(bytes, e.bytes.data(), e.bytes.size());
+      *nbytes = uint32_t(e.bytes.size());
+      return true;
+    }
+  return false;
+}
+
+// Keep (or replace) the header just parsed from `bytes`.
+void hdr_keep(const void* comp, uint64_t size, const Header& h, const uint8_t* bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  const uint64_t nb = kHeaderBytes + uint64_t(h.nsym);
+  HdrCache& c = hdr_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto it = c.e.begin(); it != c.e.end(); ++it)
+    if (it->device == dev && it->comp == comp && it->size == size) {
+      c.e.erase(it);
+      break;
+    }
+  if (c.e.size() >= kHdrCacheMax) c.e.pop_front();
+  c.e.push_back({dev, comp, size, std::vector<uint8_t>(bytes, bytes + nb), h});
+}
+
+// vb = the caller's value type; a stream of the other type is rejected.
+// use_kept = false: read the header even when it is kept.
+stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int level, void* out,
+                      uint64_t out_cap, uint64_t out_dims[3], int vb, hipStream_t st,
+                      bool use_kept = true) {
+  Staging* stage = staging();
+  if (!stage) return STZ_ERR_NOMEM;
+  Header h;
+  uint32_t nref = 0;  // kept header bytes to check the stream against (0: read here)
+  stz_status s = STZ_OK;
+  if (!use_kept || !comp || !hdr_lookup(comp, size, &h, stage->hdr, &nref)) {
+    nref = 0;
+    s = read_header(comp, size, st, &h);
+    if (s != STZ_OK) return s;
+    hdr_keep(comp, size, h, stage->hdr);
+  }
+  // A call steered by a kept header takes any outcome other than a decode
+  // from a fresh read.
+  auto reread = [&]() {
+    return decode_box(comp, size, boxp, level, out, out_cap, out_dims, vb, st, false);
+  };
+  if (h.vb != vb) return nref ? reread() : STZ_ERR_ARG;
   DecodePlan pl;
   s = pl.init(h, comp, size, boxp, level, out, out_cap);
   if (out_dims)
     for (int d = 0; d < 3; ++d) out_dims[d] = pl.od[d];
-  if (s != STZ_OK || pl.cnt == 0) return s;
-  Staging* stage = staging();
-  if (!stage) return STZ_ERR_NOMEM;
+  if (s != STZ_OK || pl.cnt == 0) return nref ? reread() : s;
   constexpr uint64_t nlut = uint64_t(1) << kLutBits;
   LutEntry* mine = nullptr;
   const uint16_t* cached = lut_lookup(h.lens, h.nsym, nullptr);
   if (!cached) {
-    if (!build_lut(h.lens, h.nsym, stage->lut)) return STZ_ERR_CORRUPT;  // not a prefix code
+    if (!build_lut(h.lens, h.nsym, stage->lut))  // not a prefix code
+      return nref ? reread() : STZ_ERR_CORRUPT;
     cached = lut_lookup(h.lens, h.nsym, &mine);  // ready meanwhile, or reserve an entry
   }
   Workspace ws(st);
   pl.take(ws);
   const uint64_t o_lut = ws.take<uint8_t>(cached || mine ? 1 : nlut * 2 + 16);
-  const uint64_t o_flags = ws.take<uint32_t>(1);
+  const uint64_t o_flags = ws.take<uint32_t>(2);
+  const uint64_t o_ref = ws.take<uint8_t>(nref ? nref : 1);
   if (!ws.commit()) return STZ_ERR_NOMEM;
   uint16_t* dlut = cached ? const_cast<uint16_t*>(cached)
                           : (mine ? mine->dev : ws.at<uint16_t>(o_lut));
-  uint32_t* dflags = ws.at<uint32_t>(o_flags);  // zeroed by the anchor kernel
+  // [0] decode flags, zeroed by the anchor kernel; [1] header check result
+  uint32_t* dflags = ws.at<uint32_t>(o_flags);
   pl.bind(ws, dlut, dflags);
   if (!cached) {
     std::memset(stage->lut + nlut, 0, 16);
     if (hipMemcpyAsync(dlut, stage->lut, nlut * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
   }
+  if (nref) {
+    uint8_t* dref = ws.at<uint8_t>(o_ref);
+    if (hipMemcpyAsync(dref, stage->hdr, nref, hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_header_check(comp, dref, nref, dflags + 1, st) != hipSuccess)
+      return STZ_ERR_DEVICE;
+  }
   if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
-  if (hipMemcpyAsync(stage->flags, dflags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(stage->flags, dflags, nref ? 8 : 4, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return STZ_ERR_DEVICE;
   if (mine) lut_mark_ready(mine);  // the table's copy has completed
   prof_flush();
-  return *stage->flags ? STZ_ERR_CORRUPT : STZ_OK;
+  if (nref && stage->flags[1]) return reread();  // the stream's header is not the kept one
+  return stage->flags[0] ? STZ_ERR_CORRUPT : STZ_OK;
 }
 
 // ---- decoding without allocation --------------------------------------------
@@ -957,6 +1042,16 @@ stz_status stz_trim(void) {
       it = c.m.erase(it);
     } else {
       ++it;
+    }
+  }
+  {
+    HdrCache& hc = hdr_cache();
+    std::lock_guard<std::mutex> lk4(hc.mu);
+    for (auto it = hc.e.begin(); it != hc.e.end();) {
+      if (it->device == cur)
+        it = hc.e.erase(it);
+      else
+        ++it;
     }
   }
   {

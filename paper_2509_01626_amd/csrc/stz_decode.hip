@@ -1097,6 +1097,24 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+__global__ __launch_bounds__(256) void k_header_check(const uint8_t* __restrict__ comp,
+                                                      const uint8_t* __restrict__ ref, uint32_t n,
+                                                      uint32_t* __restrict__ flag) {
+  bool d = false;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d |= comp[i] != ref[i];
+  const int any = __syncthreads_or(d ? 1 : 0);
+  if (threadIdx.x == 0) *flag = any ? 1u : 0u;
+}
+}  // namespace
+
+hipError_t launch_header_check(const void* comp, const uint8_t* ref, uint32_t n, uint32_t* flag,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_header_check, dim3(1), dim3(256), 0, st,
+                     static_cast<const uint8_t*>(comp), ref, n, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
   return a.vb == 8 ? launch_decode_t<double>(a, st) : launch_decode_t<float>(a, st);
 }

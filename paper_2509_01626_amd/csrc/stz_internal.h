@@ -284,6 +284,10 @@ struct DecodeArgs {
 };
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+// *flag = 1 when the n bytes at comp differ from those at ref, else 0 (one
+// work-group; both device pointers).
+hipError_t launch_header_check(const void* comp, const uint8_t* ref, uint32_t n, uint32_t* flag,
+                               hipStream_t st);
 // Per-unit ROI statistics of a level grid (see stz_roi_select).
 hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
                             int stat, const int64_t nb[3], uint64_t nunits, double* out,
