@@ -25,24 +25,67 @@ static_assert(kCbNodes >= kCbMax && kCbNodes >= 2 * kMaxAlphabet - 1, "node arra
 constexpr int kCbScales = 42;           // k = 0..41
 constexpr uint64_t kInf = ~uint64_t(0);
 
-// Ascending bitonic sort of n (power of two) 64-bit keys in LDS.
-__device__ void bitonic_sort(uint64_t* key, int n) {
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = ((lo & size) == 0);
-        const uint64_t a = key[lo], b = key[hi];
-        if ((a > b) == up) {
-          key[lo] = b;
-          key[hi] = a;
-        }
+__device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor(uint32_t(v), m, 64);
+  const uint32_t hi = __shfl_xor(uint32_t(v >> 32), m, 64);
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Number of entries of the ascending a[0, len) below t (AT_MOST: at most t),
+// by binary search.
+template <bool AT_MOST>
+__device__ inline int rank_below(const uint64_t* a, int len, uint64_t t) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (AT_MOST ? a[mid] <= t : a[mid] < t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Ascending sort of n 64-bit keys in LDS (n a power of two, 64 <= n <=
+// kCbMax): runs of 64 sorted in registers by one wave each (a bitonic network
+// over the lanes, no barriers), then merged pairwise: a key's place in the
+// merged pair is its index in its run plus the number of keys of the other
+// run below it (first run) or at most it (second run), so equal keys (the
+// padding) land on distinct places. Uses tmp (n keys); the result is in key.
+__device__ void block_sort_u64(uint64_t* key, uint64_t* tmp, int n) {
+  const int t = threadIdx.x, lane = t & 63, nw = blockDim.x >> 6;
+  for (int r = t >> 6; r < n / 64; r += nw) {
+    uint64_t v = key[r * 64 + lane];
+    for (int k = 2; k <= 64; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const uint64_t o = shfl_xor64(v, j);
+        const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+        v = keep_min ? (o < v ? o : v) : (o < v ? v : o);
       }
-    }
+    key[r * 64 + lane] = v;
   }
   __syncthreads();
+  uint64_t* src = key;
+  uint64_t* dst = tmp;
+  for (int len = 64; len < n; len <<= 1) {
+    for (int i = t; i < n; i += blockDim.x) {
+      const int base = i & ~(2 * len - 1), off = i - base;
+      const bool in_a = off < len;
+      const uint64_t v = src[i];
+      const int other = in_a ? base + len : base;
+      const int pos = in_a ? off + rank_below<false>(src + other, len, v)
+                           : off - len + rank_below<true>(src + other, len, v);
+      dst[base + pos] = v;
+    }
+    __syncthreads();
+    uint64_t* sw = src;
+    src = dst;
+    dst = sw;
+  }
+  if (src != key) {
+    for (int i = t; i < n; i += blockDim.x) key[i] = src[i];
+    __syncthreads();
+  }
 }
 
 // Two-queue merge (leaves W[0..m) ascending; merged nodes appended from W[m]
@@ -200,6 +243,7 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
   // nodes: the sorted leaves (padded to a power of two while sorting) and then
   // the m - 1 merged nodes: at most kCbNodes entries
   __shared__ uint64_t W[kCbNodes + 2];
+  __shared__ uint64_t sort_tmp[kCbMax];
   __shared__ uint16_t par[2][kCbNodes];  // ping-pong buffers of the depth pass
   __shared__ uint16_t dep[2][kCbNodes];
   __shared__ uint16_t leaf[kCbMax];
@@ -237,10 +281,11 @@ __device__ inline void cb_build_body(const unsigned long long* hist, int nsym, u
       W[before + __popcll(bal[q] & ((uint64_t(1) << lane) - 1))] =
           (((cs[q] + add) >> k) << kSymBits) | uint64_t(i);
   }
-  int np2 = 1;
+  int np2 = 64;
   while (np2 < m) np2 <<= 1;
   for (int i = m + t; i < np2; i += blockDim.x) W[i] = kInf;
-  bitonic_sort(W, np2);
+  __syncthreads();
+  block_sort_u64(W, sort_tmp, np2);
   if (m <= 1) {
     if (m == 1 && t == 0) lens[W[0] & kSymMask] = 1;
     if (t == 0) maxlen_k[k] = m;
