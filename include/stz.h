@@ -126,8 +126,8 @@ stz_status stz_info(const void* comp, uint64_t size, stz_info_t* info, void* str
  * opened with stz_open and decoded through stz_decompress_batch or a captured
  * decode plan needs neither round trip. The parsed headers of the last 16
  * (device, comp, size) triples decoded are kept on the host: a call on a
- * kept one skips the header round trip, and a device kernel ahead of its
- * decode compares the stream's header bytes with the kept ones; when they
+ * kept one skips the header round trip, and the decode's first kernel
+ * compares the stream's header bytes with the kept ones; when they
  * differ (new contents at the same address and size) the call reads the
  * header and decodes again, so its result and status are those of a fresh
  * read. Decoder tables are kept in device memory per code (up to 64 codes per

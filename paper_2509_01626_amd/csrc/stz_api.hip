@@ -536,8 +536,8 @@ void lut_mark_ready(LutEntry* e) {
 // stream address and size, with the header bytes they were parsed from (the
 // bytes parse_header reads: the fixed part and the code lengths). A call whose
 // stream is kept launches at once: it uploads the kept bytes into its own
-// workspace, and a one-work-group kernel ahead of the decode compares them
-// with the stream's header. When they differ the call reads and parses the
+// workspace, and the decode's first kernel (the anchors) compares them with
+// the stream's header before any level is decoded. When they differ the call reads and parses the
 // header again and decodes again, so results and statuses are those of a
 // call that reads the header first. Kept headers only ever steer launches
 // whose reads the header's own checks bound to the stream's size. At most
@@ -646,9 +646,10 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   }
   if (nref) {
     uint8_t* dref = ws.at<uint8_t>(o_ref);
-    if (hipMemcpyAsync(dref, stage->hdr, nref, hipMemcpyHostToDevice, st) != hipSuccess ||
-        launch_header_check(comp, dref, nref, dflags + 1, st) != hipSuccess)
+    if (hipMemcpyAsync(dref, stage->hdr, nref, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
+    pl.a.hdr_ref = dref;  // compared by the anchor kernel
+    pl.a.hdr_n = nref;
   }
   if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
   if (hipMemcpyAsync(stage->flags, dflags, nref ? 8 : 4, hipMemcpyDeviceToHost, st) !=

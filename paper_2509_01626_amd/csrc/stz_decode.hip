@@ -546,10 +546,18 @@ __device__ inline void dec_anchor_body(const uint8_t* comp, uint64_t anchor_off,
 
 template <class T>
 __global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, T* rec0, Grid g0,
-                             uint32_t* flags) {
+                             uint32_t* flags, const uint8_t* __restrict__ hdr_ref,
+                             uint32_t hdr_n) {
   // the call's corruption flag starts at zero (the level kernels follow in
   // stream order)
   if (blockIdx.x == 0 && threadIdx.x == 0) *flags = 0;
+  if (hdr_ref && blockIdx.x == 0) {
+    // a kept header: flags[1] = whether the stream's header bytes differ
+    bool d = false;
+    for (uint32_t i = threadIdx.x; i < hdr_n; i += blockDim.x) d |= comp[i] != hdr_ref[i];
+    const int any = __syncthreads_or(d ? 1 : 0);
+    if (threadIdx.x == 0) flags[1] = any ? 1u : 0u;
+  }
   dec_anchor_body<T>(comp, anchor_off, g, rec0, g0, blockIdx.x, gridDim.x);
 }
 
@@ -1082,7 +1090,8 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
   const uint64_t n0 = uint64_t(g0.cnt[0]) * g0.cnt[1] * g0.cnt[2];
   prof_begin(st, "dec_anchor", -1);
   hipLaunchKernelGGL(k_dec_anchor<T>, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
-                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0, a.flags);
+                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0, a.flags, a.hdr_ref,
+                     a.hdr_n);
   prof_end(st);
   for (int k = 1; k <= a.level_out; ++k) {
     const DecSlabArgs d = dec_args(a, k);
@@ -1096,24 +1105,6 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
 }
 
 }  // namespace
-
-namespace {
-__global__ __launch_bounds__(256) void k_header_check(const uint8_t* __restrict__ comp,
-                                                      const uint8_t* __restrict__ ref, uint32_t n,
-                                                      uint32_t* __restrict__ flag) {
-  bool d = false;
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d |= comp[i] != ref[i];
-  const int any = __syncthreads_or(d ? 1 : 0);
-  if (threadIdx.x == 0) *flag = any ? 1u : 0u;
-}
-}  // namespace
-
-hipError_t launch_header_check(const void* comp, const uint8_t* ref, uint32_t n, uint32_t* flag,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_header_check, dim3(1), dim3(256), 0, st,
-                     static_cast<const uint8_t*>(comp), ref, n, flag);
-  return hipGetLastError();
-}
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
   return a.vb == 8 ? launch_decode_t<double>(a, st) : launch_decode_t<float>(a, st);

@@ -281,13 +281,14 @@ struct DecodeArgs {
   double E2d[kMaxLevels + 1];
   const uint16_t* lut;   // 2^kLutBits entries: symbol | length << 12
   uint32_t* flags;       // device word
+  // Plain decodes launched on a kept header: the header bytes it was parsed
+  // from (device, hdr_n bytes); the anchor kernel sets flags[1] to 1 when the
+  // stream's first hdr_n bytes differ from them, else 0. Null: no check.
+  const uint8_t* hdr_ref;
+  uint32_t hdr_n;
 };
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
-// *flag = 1 when the n bytes at comp differ from those at ref, else 0 (one
-// work-group; both device pointers).
-hipError_t launch_header_check(const void* comp, const uint8_t* ref, uint32_t n, uint32_t* flag,
-                               hipStream_t st);
 // Per-unit ROI statistics of a level grid (see stz_roi_select).
 hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
                             int stat, const int64_t nb[3], uint64_t nunits, double* out,
