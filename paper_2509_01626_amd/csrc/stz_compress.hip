@@ -353,7 +353,13 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t blk, uint64_t sl
   __shared__ uint16_t ssym[7 * S::SCP];  // slab symbols, [class][v_z][v_y][v_x] (padded)
   __shared__ uint64_t ubase[8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
+  // Blocks of at most 4^3 level points (at most 56 symbols) add their symbol
+  // counts straight into their partial histogram; larger ones count in LDS
+  // and add the block's histogram once.
+  constexpr bool kGH = E <= 4;
+  const uint64_t hs0 = (slot % a.nslots) * uint64_t(a.nsym);
+  if constexpr (!kGH)
+    for (int i = tid; i < a.nsym; i += blockDim.x) h[i] = 0;
   const int64_t bx = blk % a.g.nb[2], by = (blk / a.g.nb[2]) % a.g.nb[1],
                 bz = blk / (a.g.nb[2] * a.g.nb[1]);
   const int64_t oz = bz * E, oy = by * E, ox = bx * E;
@@ -392,7 +398,7 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t blk, uint64_t sl
   ctx.x = xv;
   ctx.tile = tile;
   ctx.ssym = ssym;
-  ctx.h = h;
+  ctx.h = kGH ? a.hpart + hs0 : h;
   ctx.cur = cur;
   ctx.oz = oz;
   ctx.oy = oy;
@@ -498,13 +504,22 @@ __device__ inline void pred_body(const PredSlabArgs& a, int64_t blk, uint64_t sl
     }
     __syncthreads();
   }
-  if (n_center != n_cover) atomicAdd(&h[R], n_center - n_cover);  // mod 2^32, sums >= 0
-  if (n_zero) atomicAdd(&h[a.g.Z], n_zero);
-  __syncthreads();
-  if (mag >= kMagNonfinite<T>) atomicOr(&a.P->flags, kFlagNonfinite);
-  const uint64_t hs0 = (slot % a.nslots) * uint64_t(a.nsym);
-  for (int i = tid; i < a.nsym; i += blockDim.x)
-    if (h[i]) atomicAdd(&a.hpart[hs0 + i], h[i]);
+  if constexpr (kGH) {
+    // the centre and zero-chunk counts summed over each wave's lanes
+    const uint32_t dc = wave_sum(n_center - n_cover), dz = wave_sum(n_zero);  // mod 2^32
+    if (lane == 0) {
+      if (dc) atomicAdd(&a.hpart[hs0 + R], dc);
+      if (dz) atomicAdd(&a.hpart[hs0 + a.g.Z], dz);
+    }
+    if (mag >= kMagNonfinite<T>) atomicOr(&a.P->flags, kFlagNonfinite);
+  } else {
+    if (n_center != n_cover) atomicAdd(&h[R], n_center - n_cover);  // mod 2^32, sums >= 0
+    if (n_zero) atomicAdd(&h[a.g.Z], n_zero);
+    __syncthreads();
+    if (mag >= kMagNonfinite<T>) atomicOr(&a.P->flags, kFlagNonfinite);
+    for (int i = tid; i < a.nsym; i += blockDim.x)
+      if (h[i]) atomicAdd(&a.hpart[hs0 + i], h[i]);
+  }
 }
 
 // Slab height of the plain predictor launches: 4 planes for 32^3-point blocks
@@ -653,8 +668,12 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
   __shared__ uint32_t ub[8], uo[8];
   __shared__ int64_t usym[8], ulane[8];
   __shared__ int s_fast;
-  for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
   const int m = (a.g.B >> a.logs) >> 1;
+  // Blocks of 16^3 level points and more copy the code lengths into LDS;
+  // smaller ones (at most 16 symbols per lane) read them through the cache.
+  if (m >= 8)
+    for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) L[i] = a.lens[i];
+  const uint8_t* Lt = m >= 8 ? static_cast<const uint8_t*>(L) : a.lens;
   const int tid = threadIdx.x, c = tid / m + 1, j = tid % m;
   if (m == 16 || m == 8) {
     // a full block (every class sub-grid m^3) with aligned unit symbols?
@@ -694,7 +713,7 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
     Mx = ug.M[2];
     if (j < Mx && a.g.Z >= 0) {
       const uint16_t* col = a.sym + uint64_t(unit_sym_off(a.g, a.logs, u)) + uint64_t(j) * rows;
-      const uint32_t My = uint32_t(ug.M[1]), R = uint32_t(a.g.R), LZ = L[a.g.Z];
+      const uint32_t My = uint32_t(ug.M[1]), R = uint32_t(a.g.R), LZ = Lt[a.g.Z];
       const bool vec = (reinterpret_cast<uintptr_t>(col) & 15) == 0 && (My & 7) == 0;
       for (uint32_t t0 = 0; t0 < rows; t0 += My) {
         uint32_t cb = 0, co = 0;
@@ -707,7 +726,7 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
               const uint32_t s0 = v[k] & 0xFFFFu, s1 = v[k] >> 16;
-              cb += L[s0] + L[s1];
+              cb += Lt[s0] + Lt[s1];
               co += (s0 == 0) + (s1 == 0);
               all = all && s0 == R && s1 == R;
             }
@@ -715,7 +734,7 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
         } else {
           for (uint32_t t = t0; t < t0 + My; ++t) {
             const uint16_t s = col[t];
-            cb += L[s];
+            cb += Lt[s];
             co += (s == 0);
             all = all && s == R;
           }
@@ -735,14 +754,14 @@ __device__ inline void lanelen_body(const LaneLenArgs& a, int64_t wg) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const uint32_t s0 = v[k] & 0xFFFFu, s1 = v[k] >> 16;
-            bits += L[s0] + L[s1];
+            bits += Lt[s0] + Lt[s1];
             no += (s0 == 0) + (s1 == 0);
           }
         }
       }
       for (; t < rows; ++t) {
         const uint16_t s = col[t];
-        bits += L[s];
+        bits += Lt[s];
         no += (s == 0);
       }
       a.lane_len[unit_lane_off(a.g, a.logs, u) + j] = uint16_t(bits);
@@ -1175,17 +1194,22 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   __shared__ uint8_t Ls[kMaxAlphabet];
   __shared__ uint16_t Cs[kMaxAlphabet];
   __shared__ uint32_t lb_s[256];
-  for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) {
-    Ls[i] = a.lens[i];
-    Cs[i] = a.codes[i];
-  }
+  const int m = (a.g.B >> a.logs) >> 1;
+  // the code table in LDS for blocks of 16^3 level points; smaller ones (at
+  // most 16 symbols per lane) read it through the cache
+  if (m >= 8)
+    for (int i = threadIdx.x; i < a.nsym; i += blockDim.x) {
+      Ls[i] = a.lens[i];
+      Cs[i] = a.codes[i];
+    }
+  const uint8_t* Lt = m >= 8 ? static_cast<const uint8_t*>(Ls) : a.lens;
+  const uint16_t* Ct = m >= 8 ? static_cast<const uint16_t*>(Cs) : a.codes;
   const int l = a.level;
   uint32_t* unit_word = reinterpret_cast<uint32_t*>(a.out + P->sec[l]);
   uint32_t* unit_outl = reinterpret_cast<uint32_t*>(a.out + P->off_outl[l]);
   uint16_t* lane_arr = reinterpret_cast<uint16_t*>(a.out + P->off_lane[l]);
   uint32_t* pay = reinterpret_cast<uint32_t*>(a.out + P->off_pay[l]);
   uint8_t* outv = a.out + P->off_out[l];
-  const int m = (a.g.B >> a.logs) >> 1;
   const int tid = threadIdx.x, lane = tid & 63, c = tid / m + 1, j = tid % m;
   const bool is_lane = tid < 7 * m;
   const int64_t u = wg * 7 + (c - 1);
@@ -1233,7 +1257,7 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
   // zk: whether the chunk starting at this row is all R when the caller
   // knows it (-1: read the chunk's symbols here)
   auto step = [&](uint32_t s, uint32_t t, int zk) {
-    uint32_t len = Ls[s], cw = Cs[s];
+    uint32_t len = Lt[s], cw = Ct[s];
     if (zc) {
       if (vyc == 0) {
         bool all = act;
@@ -1244,8 +1268,8 @@ __device__ inline void pack_lanes_body(const PackArgs& a, int64_t wg) {
         zrun = all;
       }
       if (zrun) {
-        len = vyc == 0 ? Ls[a.g.Z] : 0u;
-        cw = Cs[a.g.Z];
+        len = vyc == 0 ? Lt[a.g.Z] : 0u;
+        cw = Ct[a.g.Z];
       }
       if (++vyc == M1) vyc = 0;
     }
