@@ -535,9 +535,9 @@ void lut_mark_ready(LutEntry* e) {
 // Parsed headers of the streams plain decodes were last given, per device,
 // stream address and size, with the header bytes they were parsed from (the
 // bytes parse_header reads: the fixed part and the code lengths). A call whose
-// stream is kept launches at once: it uploads the kept bytes into its own
-// workspace, and the decode's first kernel (the anchors) compares them with
-// the stream's header before any level is decoded. When they differ the call reads and parses the
+// stream is kept launches at once: the kept bytes travel as an argument of
+// the decode's first kernel (the anchors), which compares them with the
+// stream's header before any level is decoded. When they differ the call reads and parses the
 // header again and decodes again, so results and statuses are those of a
 // call that reads the header first. Kept headers only ever steer launches
 // whose reads the header's own checks bound to the stream's size. At most
@@ -632,7 +632,6 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   pl.take(ws);
   const uint64_t o_lut = ws.take<uint8_t>(cached || mine ? 1 : nlut * 2 + 16);
   const uint64_t o_flags = ws.take<uint32_t>(2);
-  const uint64_t o_ref = ws.take<uint8_t>(nref ? nref : 1);
   if (!ws.commit()) return STZ_ERR_NOMEM;
   uint16_t* dlut = cached ? const_cast<uint16_t*>(cached)
                           : (mine ? mine->dev : ws.at<uint16_t>(o_lut));
@@ -644,14 +643,10 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
     if (hipMemcpyAsync(dlut, stage->lut, nlut * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
   }
-  if (nref) {
-    uint8_t* dref = ws.at<uint8_t>(o_ref);
-    if (hipMemcpyAsync(dref, stage->hdr, nref, hipMemcpyHostToDevice, st) != hipSuccess)
-      return STZ_ERR_DEVICE;
-    pl.a.hdr_ref = dref;  // compared by the anchor kernel
-    pl.a.hdr_n = nref;
-  }
-  if (launch_decode(pl.a, st) != hipSuccess) return STZ_ERR_DEVICE;
+  HdrRef ref;  // the kept header bytes, compared by the anchor kernel
+  ref.n = nref;
+  if (nref) std::memcpy(ref.b, stage->hdr, nref);
+  if (launch_decode(pl.a, st, nref ? &ref : nullptr) != hipSuccess) return STZ_ERR_DEVICE;
   if (hipMemcpyAsync(stage->flags, dflags, nref ? 8 : 4, hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)

@@ -546,15 +546,14 @@ __device__ inline void dec_anchor_body(const uint8_t* comp, uint64_t anchor_off,
 
 template <class T>
 __global__ void k_dec_anchor(const uint8_t* comp, uint64_t anchor_off, Geo g, T* rec0, Grid g0,
-                             uint32_t* flags, const uint8_t* __restrict__ hdr_ref,
-                             uint32_t hdr_n) {
+                             uint32_t* flags, const HdrRef ref) {
   // the call's corruption flag starts at zero (the level kernels follow in
   // stream order)
   if (blockIdx.x == 0 && threadIdx.x == 0) *flags = 0;
-  if (hdr_ref && blockIdx.x == 0) {
+  if (ref.n && blockIdx.x == 0) {
     // a kept header: flags[1] = whether the stream's header bytes differ
     bool d = false;
-    for (uint32_t i = threadIdx.x; i < hdr_n; i += blockDim.x) d |= comp[i] != hdr_ref[i];
+    for (uint32_t i = threadIdx.x; i < ref.n; i += blockDim.x) d |= comp[i] != ref.b[i];
     const int any = __syncthreads_or(d ? 1 : 0);
     if (threadIdx.x == 0) flags[1] = any ? 1u : 0u;
   }
@@ -1083,15 +1082,14 @@ hipError_t launch_roi_select(const double* stats, uint64_t n, int rule, double v
 namespace {
 
 template <class T>
-hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
+hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st, const HdrRef* ref) {
   const Geo& g = a.geo;
   const int L = g.L;
   const Grid g0 = box_grid(a.box[0], L);
   const uint64_t n0 = uint64_t(g0.cnt[0]) * g0.cnt[1] * g0.cnt[2];
   prof_begin(st, "dec_anchor", -1);
   hipLaunchKernelGGL(k_dec_anchor<T>, dim3(grid_for(n0, 256, 4096)), dim3(256), 0, st, a.comp,
-                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0, a.flags, a.hdr_ref,
-                     a.hdr_n);
+                     a.anchor_off, g, static_cast<T*>(a.rec[0]), g0, a.flags, *ref);
   prof_end(st);
   for (int k = 1; k <= a.level_out; ++k) {
     const DecSlabArgs d = dec_args(a, k);
@@ -1106,8 +1104,10 @@ hipError_t launch_decode_t(const DecodeArgs& a, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_decode(const DecodeArgs& a, hipStream_t st) {
-  return a.vb == 8 ? launch_decode_t<double>(a, st) : launch_decode_t<float>(a, st);
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t st, const HdrRef* ref) {
+  static const HdrRef kNoRef = {};  // n = 0: no check
+  if (!ref) ref = &kNoRef;
+  return a.vb == 8 ? launch_decode_t<double>(a, st, ref) : launch_decode_t<float>(a, st, ref);
 }
 
 uint64_t decode_batch_args_bytes(uint32_t n, int max_level) {

@@ -281,14 +281,18 @@ struct DecodeArgs {
   double E2d[kMaxLevels + 1];
   const uint16_t* lut;   // 2^kLutBits entries: symbol | length << 12
   uint32_t* flags;       // device word
-  // Plain decodes launched on a kept header: the header bytes it was parsed
-  // from (device, hdr_n bytes); the anchor kernel sets flags[1] to 1 when the
-  // stream's first hdr_n bytes differ from them, else 0. Null: no check.
-  const uint8_t* hdr_ref;
-  uint32_t hdr_n;
 };
 
-hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+// The header bytes a plain decode launched on a kept header was parsed from,
+// passed by value to the decode's anchor kernel, which sets flags[1] to 1 when
+// the stream's first n bytes differ from them, else 0.
+struct HdrRef {
+  uint32_t n;
+  uint8_t b[kHeaderBytes + kMaxAlphabet];
+};
+
+// ref: null, or the kept header bytes to check the stream against.
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t st, const HdrRef* ref = nullptr);
 // Per-unit ROI statistics of a level grid (see stz_roi_select).
 hipError_t launch_roi_stats(const void* grid, int vb, const int64_t gn[3], int64_t E, int unit,
                             int stat, const int64_t nb[3], uint64_t nunits, double* out,
