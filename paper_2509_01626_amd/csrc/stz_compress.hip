@@ -24,8 +24,6 @@ __device__ inline void init_body(DevParams* P) {
   }
 }
 
-__global__ void k_init(DevParams* P) { init_body(P); }
-
 // Clear the partial histograms (n words), grid-stride.
 __device__ inline void hzero_body(uint32_t* hpart, uint64_t n, uint64_t wg, uint64_t ngrid) {
   const uint64_t n4 = n >> 2;
@@ -36,7 +34,12 @@ __device__ inline void hzero_body(uint32_t* hpart, uint64_t n, uint64_t wg, uint
     hpart[i] = 0;
 }
 
-__global__ void k_hzero(uint32_t* hpart, uint64_t n) { hzero_body(hpart, n, blockIdx.x, gridDim.x); }
+// The call's device parameters initialized (work-group 0) and the partial
+// histograms cleared.
+__global__ void k_init_hzero(DevParams* P, uint32_t* hpart, uint64_t n) {
+  if (blockIdx.x == 0) init_body(P);
+  hzero_body(hpart, n, blockIdx.x, gridDim.x);
+}
 
 // hist[bin] = sum over the slots; work-group `wg` covers 256 bins.
 __device__ inline void hred_body(const uint32_t* hpart, uint32_t nslots, int nsym,
@@ -1998,9 +2001,9 @@ hipError_t launch_compress_t(const CompressArgs& a, hipStream_t st) {
   const uint64_t N = uint64_t(g.n[0]) * g.n[1] * g.n[2];
   const uint64_t nu = a.lc[1].nu;
   prof_begin(st, "init", -1);
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, a.params);
   const uint64_t nh = uint64_t(nsym) * a.nslots;
-  hipLaunchKernelGGL(k_hzero, dim3(grid_for(nh, 256 * 16, 1024)), dim3(256), 0, st, a.hpart, nh);
+  hipLaunchKernelGGL(k_init_hzero, dim3(grid_for(nh, 256 * 16, 1024)), dim3(256), 0, st,
+                     a.params, a.hpart, nh);
   prof_end(st);
   if (a.eb_mode == 1) {
     prof_begin(st, "minmax", -1);
