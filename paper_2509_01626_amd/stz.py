@@ -136,9 +136,37 @@ def _dims(shape):
     return (C.c_uint64 * 3)(*[int(v) for v in shape])
 
 
+# The current stream's raw handle without building a torch Stream object
+# (the per-call cost of torch.cuda.current_stream() is ~2.5 us).
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+_cur_device = getattr(torch._C, "_cuda_getDevice", None)
+
+
 def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return C.c_void_p(stream.cuda_stream)
+    if _raw_stream is not None and _cur_device is not None:
+        return C.c_void_p(_raw_stream(_cur_device()))
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_FN = {}
+
+
+def _fn(name):
+    """Entry point `name` of the library (looked up once)."""
+    f = _FN.get(name)
+    if f is None:
+        f = _FN[name] = getattr(lib(), name)
+    return f
+
+
+def _as_shape(t, shape, n):
+    """The first n elements of t viewed as `shape` (t itself when it already
+    has that shape)."""
+    if t.shape == shape:
+        return t
+    return t.reshape(-1)[:n].view(shape)
 
 
 def stz_trim():
@@ -190,9 +218,9 @@ def stz_compress(x, eb_mode, eb, cfg, out=None, stream=None):
                           device=x.device)
     _check_dev(out, torch.uint8)
     size = C.c_uint64(0)
-    st = getattr(lib(), "stz_compress" + sfx)(
-        C.c_void_p(x.data_ptr()), _dims(x.shape), eb_mode, eb, C.byref(cfg),
-        C.c_void_p(out.data_ptr()), out.numel(), C.byref(size), _stream(stream))
+    st = _fn("stz_compress" + sfx)(
+        x.data_ptr(), _dims(x.shape), eb_mode, eb, C.byref(cfg),
+        out.data_ptr(), out.numel(), C.byref(size), _stream(stream))
     if st != OK:
         raise StzError(st, "stz_compress" + sfx)
     return out[: size.value]
@@ -228,12 +256,11 @@ def stz_decompress(comp, out=None, stream=None, info=None):
         out = torch.empty(shape, dtype=value_type(inf), device=comp.device)
     sfx = _sfx(out.dtype)
     _check_dev(out, out.dtype)
-    st = getattr(lib(), "stz_decompress" + sfx)(C.c_void_p(comp.data_ptr()), comp.numel(),
-                                                C.c_void_p(out.data_ptr()), out.numel(),
-                                                _stream(stream))
+    st = _fn("stz_decompress" + sfx)(comp.data_ptr(), comp.numel(), out.data_ptr(), out.numel(),
+                                     _stream(stream))
     if st != OK:
         raise StzError(st, "stz_decompress" + sfx)
-    return out.view(shape)
+    return out if out.shape == shape else out.view(shape)
 
 
 def level_shape(inf, level):
@@ -259,13 +286,12 @@ def stz_decompress_level(comp, level, out=None, stream=None, info=None):
     sfx = _sfx(out.dtype)
     _check_dev(out, out.dtype)
     od = (C.c_uint64 * 3)()
-    st = getattr(lib(), "stz_decompress_level" + sfx)(
-        C.c_void_p(comp.data_ptr()), comp.numel(), level, C.c_void_p(out.data_ptr()),
-        out.numel(), od, _stream(stream))
+    st = _fn("stz_decompress_level" + sfx)(
+        comp.data_ptr(), comp.numel(), level, out.data_ptr(), out.numel(), od, _stream(stream))
     if st != OK:
         raise StzError(st, "stz_decompress_level" + sfx)
     assert tuple(od) == shape
-    return out.reshape(-1)[:n].view(shape)
+    return _as_shape(out, shape, n)
 
 
 def stz_decompress_region(comp, lo, hi, level, out=None, stream=None, info=None):
@@ -277,13 +303,13 @@ def stz_decompress_region(comp, lo, hi, level, out=None, stream=None, info=None)
     sfx = _sfx(out.dtype)
     _check_dev(out, out.dtype)
     od = (C.c_uint64 * 3)()
-    st = getattr(lib(), "stz_decompress_region" + sfx)(
-        C.c_void_p(comp.data_ptr()), comp.numel(), _dims(lo), _dims(hi), level,
-        C.c_void_p(out.data_ptr()), out.numel(), od, _stream(stream))
+    st = _fn("stz_decompress_region" + sfx)(
+        comp.data_ptr(), comp.numel(), _dims(lo), _dims(hi), level, out.data_ptr(), out.numel(),
+        od, _stream(stream))
     if st != OK:
         raise StzError(st, "stz_decompress_region" + sfx)
     assert tuple(od) == shape, (tuple(od), shape)
-    return out.reshape(-1)[:n].view(shape)
+    return _as_shape(out, shape, n)
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # STZ_NOALLOC_SCRATCH_BYTES
