@@ -52,6 +52,7 @@ struct DecRows {
   T* cur;
   int64_t oz, oy, ox;
   int z0, a0, Ex, rz0, rz1, ry0, ry1, rx0, rx1;
+  int tz0;  // level plane of the coarse tile's origin (relative to the block)
   int64_t of[3], oc[3], n[3];
   T E2;
   int R;
@@ -107,7 +108,7 @@ __device__ inline T dec_point(const DecRows<T>& x, int lz, int ly, int lx, int s
                               const int64_t p[3]) {
   using S = SlabShape<E, H>;
   if constexpr (C == 0) {
-    return x.tile[((((lz - x.z0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
+    return x.tile[((((lz - x.tz0) >> 1) + 1) * S::T + (ly >> 1) + 1) * S::TP + (lx >> 1) + 1];
   } else {
     const uint16_t e = x.symb[(C - 1) * S::SCP + srow];
     if (e & 0x8000u) {
@@ -117,7 +118,7 @@ __device__ inline T dec_point(const DecRows<T>& x, int lz, int ly, int lx, int s
       return T(0);
     }
     // the quantizer's reconstruction: same operands, same order
-    const T pred = tile_pred<T, E, C, INT>(x.tile, lz - x.z0, ly, lx, p, x.n);
+    const T pred = tile_pred<T, E, C, INT>(x.tile, lz - x.tz0, ly, lx, p, x.n);
     const T prod = (T)(int(e) - x.R) * x.E2;
     return pred + prod;
   }
@@ -166,9 +167,17 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   // Stream words a lane can touch while decoding one slab: at most HZ*m codes
   // of <= kLmax bits, plus the bit window's lookahead (< 2 words).
   constexpr int WPL = (S::HZ * m * kLmax + 31) / 32 + 2;
-  // Per-lane ring of RB >= 2*WPL stream words (a power of two), [slot][lane]:
-  // the words of the current slab plus the prefetched words of the next one.
-  constexpr int RB = pow2_ceil(2 * WPL);
+  // Wide work-groups (one per CU, latency-bound launches of few blocks) of
+  // 16^3 and 32^3 level points load each lane's whole stream into its ring
+  // and the block's whole coarse tile up front, so the slabs wait on no
+  // global loads: WLW = the most words a lane stream of the block can span.
+  constexpr bool kWhole = NW >= 16 && (E == 16 || E == 32);
+  constexpr int WLW = (m * m * kLmax + 31) / 32 + 2;
+  // Per-lane ring of RB stream words (a power of two), [slot][lane]: the
+  // words of the current slab plus the prefetched words of the next one
+  // (RB >= 2*WPL), or the whole stream (kWhole: RB > WLW).
+  constexpr int RB = kWhole ? pow2_ceil(WLW + 1) : pow2_ceil(2 * WPL);
+  constexpr int WF = kWhole ? WLW : WPL;  // words loaded before the first slab, less one
   // Blocks of 16^3 level points and more copy the code table into LDS; for
   // smaller ones (a few symbols per lane) the copy would cost more than it
   // saves, and the table is read through the cache.
@@ -181,8 +190,9 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   // load the slab's HZ new planes while the other waves decode. Other blocks
   // load each slab's whole coarse tile.
   constexpr int NLW = (NL + 63) / 64;  // waves holding decoding lanes
-  constexpr bool kSlide = (E == 16 || E == 32) && S::H < E && NLW * 64 < NT;
-  __shared__ T tile[S::TILE];
+  constexpr bool kSlide = !kWhole && (E == 16 || E == 32) && S::H < E && NLW * 64 < NT;
+  using SW = SlabShape<E, E>;  // the whole block as one slab (coarse tile of m+3 planes)
+  __shared__ T tile[kWhole ? SW::TILE : S::TILE];
   __shared__ uint32_t ring[RB * NL];
   __shared__ uint32_t lanelen_s[NL];
   __shared__ uint32_t uo0[8], uo1[8];
@@ -275,15 +285,31 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
   }
   // Bit window: `buf` holds `nb` valid bits, left aligned; `wi` = next stream
   // word, found in ring slot `rk`. Slot of word w = (w - first word) mod RB.
-  // Before each slab the ring holds the WPL words from `wi` on. Bits consumed
-  // so far = 32*wi - pos - nb.
+  // Before each slab the ring holds the WPL words from `wi` on (kWhole: the
+  // whole stream). Bits consumed so far = 32*wi - pos - nb.
   uint64_t wi = pos >> 5, buf = 0;
   int nb = 0, rk = 0;
+  if constexpr (kWhole) {
+    // every thread loads (lane, word) pairs of the lanes' whole streams: the
+    // lanes' first words pass through LDS (~0u: a lane that decodes nothing)
+    __shared__ uint32_t wfirst[NL];
+    if (is_lane) wfirst[tid] = lane_active && alive ? uint32_t(wi) : ~0u;
+    __syncthreads();
+    for (int i = tid; i < NL * (WF + 1); i += NT) {
+      const int l = i % NL, k = i / NL;
+      const uint32_t w0l = wfirst[l];
+      const uint64_t idx = uint64_t(w0l) + uint64_t(k);
+      ring[k * NL + l] = (w0l != ~0u && idx < a.words) ? a.pay[idx] : 0u;
+    }
+    __syncthreads();
+  }
   if (lane_active) {
+    if constexpr (!kWhole) {
 #pragma unroll
-    for (int k = 0; k <= WPL; ++k) {
-      const uint64_t idx = wi + k;
-      ring[k * NL + tid] = (alive && idx < a.words) ? a.pay[idx] : 0u;
+      for (int k = 0; k <= WF; ++k) {
+        const uint64_t idx = wi + k;
+        ring[k * NL + tid] = (alive && idx < a.words) ? a.pay[idx] : 0u;
+      }
     }
     const int sk = int(pos & 31);
     buf = (uint64_t(ring[tid]) << 32) << sk;
@@ -312,6 +338,12 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     tile_fetch<S, T, NT>(r0, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, cz00, cy0, cx0);
     tile_store<S, T, NT>(tile, r0);
   }
+  if constexpr (kWhole) {
+    TileRegs<SW, T, NT> r0;
+    tile_fetch<SW, T, NT>(r0, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, cz00, cy0,
+                          cx0);
+    tile_store<SW, T, NT>(tile, r0);
+  }
   for (int z0 = 0; z0 < Ez; z0 += S::H) {
     if (z0 >= zlast) {
       complete = false;
@@ -320,7 +352,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     const int a0 = z0 >> 1;
     // ---- coarse planes of the slab (global loads in flight during decoding) ----
     TileRegs<S, T, NT> tr;
-    if constexpr (!kSlide)
+    if constexpr (!kSlide && !kWhole)
       tile_fetch<S, T, NT>(tr, static_cast<const T*>(a.prev), a.in_first, a.in_cnt, cz00 + a0, cy0,
                            cx0);
     if constexpr (kSlide) {
@@ -335,11 +367,13 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
       // land in the ring once the slab is decoded.
       const uint64_t wb = wi;
       const int rb = rk;
-      uint32_t pf[WPL];
+      uint32_t pf[kWhole ? 1 : WPL];
+      if constexpr (!kWhole) {
 #pragma unroll
-      for (int k = 0; k < WPL; ++k) {
-        const uint64_t idx = wb + WPL + k;
-        pf[k] = (alive && idx < a.words) ? a.pay[idx] : 0u;
+        for (int k = 0; k < WPL; ++k) {
+          const uint64_t idx = wb + WPL + k;
+          pf[k] = (alive && idx < a.words) ? a.pay[idx] : 0u;
+        }
       }
       const int r0 = a0 * My, r1 = min(a0 + S::HZ, Mz) * My;
       const int Zt = a.g.Z, Rc = a.g.R;  // zero-chunk token (-1: off), centre symbol
@@ -435,10 +469,12 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
         }
       }
       wi = wb + uint64_t((rk - rb) & (RB - 1));  // words merged: fewer than RB per slab
+      if constexpr (!kWhole) {
 #pragma unroll
-      for (int k = 0; k < WPL; ++k) ring[((rb + WPL + k) & (RB - 1)) * NL + tid] = pf[k];
+        for (int k = 0; k < WPL; ++k) ring[((rb + WPL + k) & (RB - 1)) * NL + tid] = pf[k];
+      }
     }
-    if constexpr (!kSlide) tile_store<S, T, NT>(tile, tr);
+    if constexpr (!kSlide && !kWhole) tile_store<S, T, NT>(tile, tr);
     __syncthreads();
     // ---- reconstruct the slab ------------------------------------------------------
     const int hs = min(S::H, Ez - z0);
@@ -454,6 +490,7 @@ __device__ inline void dec_body(const DecSlabArgs& a, int64_t wg) {
     ctx.oy = oy;
     ctx.ox = ox;
     ctx.z0 = z0;
+    ctx.tz0 = kWhole ? 0 : z0;
     ctx.a0 = a0;
     ctx.Ex = Ex;
     ctx.rz0 = rz0;
