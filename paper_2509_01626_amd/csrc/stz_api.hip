@@ -537,9 +537,9 @@ void lut_mark_ready(LutEntry* e) {
 // bytes parse_header reads: the fixed part and the code lengths). A call whose
 // stream is kept launches at once: the kept bytes travel as an argument of
 // the decode's first kernel (the anchors), which compares them with the
-// stream's header before any level is decoded. When they differ the call reads and parses the
-// header again and decodes again, so results and statuses are those of a
-// call that reads the header first. Kept headers only ever steer launches
+// stream's header before any level is decoded. When they differ the call
+// reads and parses the header again and decodes again, so results and
+// statuses are those of a call that reads the header first. Kept headers only ever steer launches
 // whose reads the header's own checks bound to the stream's size. At most
 // kHdrCacheMax entries (oldest out first); stz_trim drops a device's entries.
 struct HdrEntry {
@@ -560,9 +560,8 @@ HdrCache& hdr_cache() {
   return *c;
 }
 
-// On a hit: the kept header in *h and its bytes in `bytes` (the calling
-// thread's pinned staging), their count in *nbytes.
-bool hdr_lookup(const void* comp, uint64_t size, Header* h, uint8_t* bytes, uint32_t* nbytes) {
+// On a hit: the kept header in *h and the bytes it was parsed from in *ref.
+bool hdr_lookup(const void* comp, uint64_t size, Header* h, HdrRef* ref) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   HdrCache& c = hdr_cache();
@@ -570,8 +569,8 @@ bool hdr_lookup(const void* comp, uint64_t size, Header* h, uint8_t* bytes, uint
   for (const auto& e : c.e)
     if (e.device == dev && e.comp == comp && e.size == size) {
       *h = e.h;
-      std::memcpy(bytes, e.bytes.data(), e.bytes.size());
-      *nbytes = uint32_t(e.bytes.size());
+      std::memcpy(ref->b, e.bytes.data(), e.bytes.size());
+      ref->n = uint32_t(e.bytes.size());
       return true;
     }
   return false;
@@ -601,14 +600,16 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
   Staging* stage = staging();
   if (!stage) return STZ_ERR_NOMEM;
   Header h;
-  uint32_t nref = 0;  // kept header bytes to check the stream against (0: read here)
+  HdrRef ref;  // kept header bytes to check the stream against (n = 0: read here)
+  ref.n = 0;
   stz_status s = STZ_OK;
-  if (!use_kept || !comp || !hdr_lookup(comp, size, &h, stage->hdr, &nref)) {
-    nref = 0;
+  if (!use_kept || !comp || !hdr_lookup(comp, size, &h, &ref)) {
+    ref.n = 0;
     s = read_header(comp, size, st, &h);
     if (s != STZ_OK) return s;
     hdr_keep(comp, size, h, stage->hdr);
   }
+  const uint32_t nref = ref.n;
   // A call steered by a kept header takes any outcome other than a decode
   // from a fresh read.
   auto reread = [&]() {
@@ -643,9 +644,6 @@ stz_status decode_box(const void* comp, uint64_t size, const Box* boxp, int leve
     if (hipMemcpyAsync(dlut, stage->lut, nlut * 2 + 16, hipMemcpyHostToDevice, st) != hipSuccess)
       return STZ_ERR_DEVICE;
   }
-  HdrRef ref;  // the kept header bytes, compared by the anchor kernel
-  ref.n = nref;
-  if (nref) std::memcpy(ref.b, stage->hdr, nref);
   if (launch_decode(pl.a, st, nref ? &ref : nullptr) != hipSuccess) return STZ_ERR_DEVICE;
   if (hipMemcpyAsync(stage->flags, dflags, nref ? 8 : 4, hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
