@@ -896,7 +896,8 @@ int ilog2(int v) {
 // left out of that level's predictor map and listed in *pdirect: they take
 // the plain launch (interior and shell kernels), which fills the device alone.
 void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<uint32_t>& live,
-                         BatchMaps* maps, CompressBatch* b, std::vector<PredDirect>* pdirect) {
+                         BatchMaps* maps, CompressBatch* b, std::vector<PredDirect>* pdirect,
+                         std::vector<uint32_t>* whole) {
   std::memset(b, 0, sizeof(*b));
   const uint32_t n = uint32_t(live.size());
   b->njobs = n;
@@ -906,9 +907,18 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
     b->grid_pred[e] = tu.grid_pred[e];
     b->pred_h[e] = tu.pred_h[e];
   }
+  // jobs that fill the GPU by themselves run their plain launch sequence
+  std::vector<char> is_whole(n, 0);
+  for (uint32_t k = 0; k < n; ++k) {
+    const Geo& g = pl[live[k]].a.geo;
+    if (uint64_t(g.n[0]) * uint64_t(g.n[1]) * uint64_t(g.n[2]) >= kWholeJobPoints) {
+      is_whole[k] = 1;
+      whole->push_back(k);
+    }
+  }
   std::vector<uint32_t> c(n);
   auto per_job = [&](auto f) {
-    for (uint32_t k = 0; k < n; ++k) c[k] = f(pl[live[k]].a);
+    for (uint32_t k = 0; k < n; ++k) c[k] = is_whole[k] ? 0u : f(pl[live[k]].a);
     return c;
   };
   b->n_jobs1 = maps->add(&b->jobs1, per_job([](const CompressArgs&) { return 1u; }));
@@ -932,7 +942,7 @@ void build_compress_maps(const std::vector<CompressPlan>& pl, const std::vector<
       for (uint32_t k = 0; k < n; ++k) {
         const Geo& g = pl[live[k]].a.geo;
         c[k] = 0;
-        if (g.L < l || ilog2(g.B >> (g.L - l)) != e) continue;
+        if (is_whole[k] || g.L < l || ilog2(g.B >> (g.L - l)) != e) continue;
         const uint64_t nbk = uint64_t(g.nb[0] * g.nb[1] * g.nb[2]);
         if ((g.B >> (g.L - l)) >= 32 && nbk >= kDirectBlocks) {
           pdirect->push_back({k, l});
@@ -1173,7 +1183,8 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
     BatchMaps maps;
     CompressBatch b;
     std::vector<PredDirect> pdirect;
-    build_compress_maps(pl, live, &maps, &b, &pdirect);
+    std::vector<uint32_t> whole;
+    build_compress_maps(pl, live, &maps, &b, &pdirect, &whole);
     // one staging blob, laid out as on the device and sent with one copy:
     // job table | work maps | per-level argument blocks (256-aligned)
     const uint64_t jb = (uint64_t(nl) * sizeof(CompressArgs) + 15) & ~uint64_t(15);
@@ -1203,6 +1214,8 @@ stz_status stz_compress_batch(stz_job* jobs, uint64_t njobs, void* stream) {
     b.host_J = reinterpret_cast<const CompressArgs*>(hb.p);
     b.pdirect = pdirect.data();
     b.n_pdirect = uint32_t(pdirect.size());
+    b.whole = whole.data();
+    b.n_whole = uint32_t(whole.size());
     maps.bind(dm);
     if (launch_compress_batch(b, st) != hipSuccess) return STZ_ERR_DEVICE;
     if (hipMemcpyAsync(hb.p, dpar, pb, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1527,7 +1540,8 @@ stz_status stz_compress_batch_plan(const stz_job* jobs, uint64_t njobs, stz_batc
   BatchMaps maps;
   CompressBatch b;
   std::vector<PredDirect> pdirect;
-  build_compress_maps(pl, B->live, &maps, &b, &pdirect);
+  std::vector<uint32_t> whole;
+  build_compress_maps(pl, B->live, &maps, &b, &pdirect, &whole);
   const uint64_t o_maps = ws.take<uint32_t>(maps.buf.size());
   const uint64_t ab = compress_batch_args_bytes(nl, b.max_levels);
   const uint64_t o_args = ws.take<uint8_t>(ab);
@@ -1555,6 +1569,8 @@ stz_status stz_compress_batch_plan(const stz_job* jobs, uint64_t njobs, stz_batc
   b.host_J = hj.data();
   b.pdirect = pdirect.data();
   b.n_pdirect = uint32_t(pdirect.size());
+  b.whole = whole.data();
+  b.n_whole = uint32_t(whole.size());
   maps.bind(dm);
   const stz_status s = capture_graph(
       [&](hipStream_t cs) { return launch_compress_batch(b, cs) == hipSuccess; }, &B->graph,

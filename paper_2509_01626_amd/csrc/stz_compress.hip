@@ -2133,6 +2133,11 @@ hipError_t launch_hash(const void* const* ptrs, const uint64_t* bytes, uint64_t 
 }
 
 hipError_t launch_compress_batch(const CompressBatch& b, hipStream_t st) {
+  // jobs that fill the GPU by themselves: their plain launch sequence
+  for (uint32_t i = 0; i < b.n_whole; ++i) {
+    const hipError_t e = launch_compress(b.host_J[b.whole[i]], st);
+    if (e != hipSuccess) return e;
+  }
   const BatchArgLayout lay(b.njobs, b.max_levels);
   const unsigned G = b.grid;
   auto grid = [&](const ItemMap& m, uint32_t total) {

@@ -216,6 +216,7 @@ struct PredDirect {
   uint32_t job;
   int level;
 };
+constexpr uint64_t kWholeJobPoints = uint64_t(1) << 27;  // 512^3
 
 struct CompressBatch {
   const CompressArgs* J;
@@ -223,6 +224,10 @@ struct CompressBatch {
   const CompressArgs* host_J;                  // host copy of the job table
   const PredDirect* pdirect;                   // host array
   uint32_t n_pdirect;
+  // Jobs of at least kWholeJobPoints values (each fills the GPU by itself):
+  // the plain launch sequence of their own, no work items in the maps.
+  const uint32_t* whole;                       // host array of job-table indices
+  uint32_t n_whole;
   uint32_t njobs;
   unsigned grid;                               // persistent work-groups per launch
   unsigned grid_pred[kBatchEdges];             // per level block edge

@@ -286,3 +286,40 @@ def test_batch_with_large_job_matches_plain_and_oracle(gpu, oracle):
         assert got == plain, i
         want = oracle.compress(xs[i], oracle.EB_REL, ebs[i], oracle.config(block=32))
         assert got == want, i
+
+
+def test_batch_with_whole_gpu_job_matches_plain(gpu):
+    """A job of 512^3 values fills the GPU by itself and runs its plain launch
+    sequence inside the batch, eager and captured; its bytes and its small
+    neighbours' equal the plain calls' (the plain 512^3 compression equals
+    the oracle's in the full-size tests)."""
+    import torch
+
+    from paper_2509_01626_amd import stz
+    big = fields.spectral_t((512, 512, 512), 5 / 3, 5, gpu)
+    small = [torch.from_numpy(fields.bumps((40, 33, 50), seed=72, n_bumps=4)).to(gpu),
+             torch.from_numpy(fields.spectral((70, 64, 96), 5 / 3, seed=73)).to(gpu)]
+    xds = [big] + small
+    ebs = [1e-3, 1e-2, 1e-4]
+    cfgs = [stz.config(block=32)] * 3
+    plain = [stz.stz_compress(x, stz.EB_REL, eb, c).cpu().numpy().tobytes()
+             for x, eb, c in zip(xds, ebs, cfgs)]
+    outs = [torch.empty(stz.stz_compress_bound(x.shape, c), dtype=torch.uint8, device=gpu)
+            for x, c in zip(xds, cfgs)]
+    print("[case] batch with a 512^3 job", flush=True)
+    comps, jobs = stz.stz_compress_batch(xds, [stz.EB_REL] * 3, ebs, cfgs, outs)
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert jobs[i].status == stz.OK
+        assert comps[i].cpu().numpy().tobytes() == plain[i], i
+    outs_g = [torch.zeros_like(o) for o in outs]
+    jobs_g = stz.make_jobs(xds, [stz.EB_REL] * 3, ebs, cfgs, outs_g)
+    plan = stz.BatchPlan(jobs=jobs_g)
+    for rep in range(2):
+        print(f"[case] 512^3 job, captured replay {rep}", flush=True)
+        plan.run()
+        assert plan.status() == stz.OK
+        torch.cuda.synchronize()
+        for i in range(3):
+            assert outs_g[i][:jobs_g[i].out_size].cpu().numpy().tobytes() == plain[i], (rep, i)
+    plan.close()
